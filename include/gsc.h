@@ -1,0 +1,334 @@
+/* gsc.h -- C ABI of the GSCache hot path on MI355X (gfx950).
+ *
+ * GSCache (arXiv 2507.19718) caches path-space radiance of a volume path tracer in K levels of
+ * 3D Gaussians, one level per path length (Method: "A Path Space Radiance Cache").  Each frame
+ * the levels are splatted into cache images, the tracer runs with the early-termination
+ * heuristic (Algorithm 1) and writes every terminated path's attenuated radiance into the
+ * target buffer of its length (Method: "Cache Training"), and each level takes one AdamW step
+ * against those noisy targets under the HDR loss (Eq. 4) with the viewport learning-rate
+ * schedule (Eq. 5).  The renderer hands the cache only "the attenuated radiance value and the
+ * path length that produced it" (Introduction); the library is exposed through a C-style API
+ * (Method: "Implementation").
+ *
+ * Conventions
+ *   - Pointers are DEVICE pointers unless marked HOST.  The caller owns every buffer it
+ *     passes.  Opaque objects (gsc_ctx, gsc_binning, gsc_scene) are owned by the library,
+ *     draw device memory through the context's allocator, and are released by the matching
+ *     *_release / *_destroy call.
+ *   - Every call returns a gsc_status; no C++ exception crosses the ABI.  On a non-OK status
+ *     no output is valid.  Arguments are validated before anything is enqueued, so
+ *     GSC_E_INVALID_ARG leaves the device untouched.  gsc_ctx_last_error() describes the last
+ *     failure on a context.
+ *   - Device work is enqueued on the context's HIP stream (on ROCm PyTorch: the caller's
+ *     current stream).  A call synchronises only where stated.
+ *   - Layouts: a level's Gaussians are SoA, pos [n][3], rot [n][4] (w, x, y, z; need not be
+ *     normalised), log_scale [n][3], rgb [n][3], opacity_logit [n]: 14 fp32 per Gaussian
+ *     (Appendix "Memory Footprint").  Images are [K][h][w][3] fp32, row-major, level-major.
+ *   - Frames: the volume occupies the unit cube [0,1]^3.  Cameras map world to camera by
+ *     x_c = R x_w + t with camera axes x right, y down, z forward; intrinsics are in full-frame
+ *     pixels where pixel i spans [i, i+1).  (x0, y0, w, h) is the rendered window; every
+ *     per-pixel quantity is computed in full-frame coordinates, so a crop reproduces the full
+ *     frame's pixels exactly.  Tiles are 16x16 pixels laid out from (x0, y0).
+ *   - Limits: 1 <= w, h <= 16384; 1 <= K <= 8 levels per request; 0 <= n < 2^31 Gaussians per
+ *     level; 2 <= tf_points <= 64; 1 <= n_lights <= 8; instance counts are 64-bit.
+ *   - Threading: a context is used by one host thread at a time; several contexts may share a
+ *     device (one per concurrently running stream).
+ *   - Determinism: every output is deterministic except the float-atomic sums of
+ *     gsc_splat_backward (order of accumulation); gsc_ctx_set_deterministic(ctx, 1) replaces
+ *     them by a fixed-order reduction.
+ */
+#ifndef GSC_H_
+#define GSC_H_
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  GSC_OK = 0,
+  GSC_E_INVALID_ARG = 1,   /* bad pointer, size or limit; nothing was enqueued            */
+  GSC_E_CAPACITY = 2,      /* instance capacity exceeded; gsc_ctx_required_capacity() says  *
+                            * how many were needed; retry with a larger hint                */
+  GSC_E_OUT_OF_MEMORY = 3, /* the allocator returned NULL                                   */
+  GSC_E_DEVICE = 4,        /* a HIP runtime error; sticky for the context                   */
+  GSC_E_UNSUPPORTED = 5
+} gsc_status;
+
+typedef struct gsc_ctx gsc_ctx;
+typedef struct gsc_binning gsc_binning;
+typedef struct gsc_scene gsc_scene;
+
+/* Device-memory hooks.  alloc(bytes, user) returns device memory usable on the context's
+ * stream or NULL; release(ptr, user) returns it.  With no allocator the library uses
+ * hipMalloc / hipFree. */
+typedef struct {
+  void* (*alloc)(size_t bytes, void* user);
+  void (*release)(void* ptr, void* user);
+  void* user;
+} gsc_allocator;
+
+/* HOST.  Pinhole camera, see the conventions above. */
+typedef struct {
+  float R[9];              /* world -> camera rotation, row-major                          */
+  float t[3];
+  float fx, fy, cx, cy;    /* full-frame pixels                                            */
+  int32_t full_w, full_h;  /* full frame (the 1.3x frustum clamp of the EWA Jacobian)      */
+  int32_t x0, y0, w, h;    /* rendered window                                              */
+  float znear;             /* Gaussians at z <= znear are culled (0.2)                     */
+} gsc_camera;
+
+/* One cache level.  DEVICE arrays, layouts as in the conventions. */
+typedef struct {
+  const float* pos;
+  const float* rot;
+  const float* log_scale;
+  const float* rgb;
+  const float* opacity_logit;
+  int64_t n;
+} gsc_gaussians;
+
+/* Parameter gradients of one level, same shapes as gsc_gaussians.  DEVICE, overwritten. */
+typedef struct {
+  float* pos;
+  float* rot;
+  float* log_scale;
+  float* rgb;
+  float* opacity_logit;
+} gsc_grads;
+
+/* A scalar volume and its optics.  density: DEVICE [nz][ny][nx] fp32 over [0,1]^3 (trilinear,
+ * cell-centred, clamp-to-edge).  tf_rgba: HOST [tf_points][4], control point i at density
+ * i/(tf_points-1) * density_max; sigma_t = d * A(d), albedo = RGB(d); the delta-tracking
+ * majorant is density_max * max_i A_i (Evaluation: a predefined 1D transfer function per
+ * dataset).  lights: HOST [n_lights][6] point lights (position xyz, radiant intensity rgb;
+ * the paper lights its scenes with two small lights placed outside the volume). */
+typedef struct {
+  const float* density;
+  int32_t nx, ny, nz;
+  float density_max;
+  const float* tf_rgba;
+  int32_t tf_points;
+  const float* lights;
+  int32_t n_lights;
+} gsc_volume;
+
+/* HOST.  Tracer parameters.  Random numbers: Philox4x32-10 with key (lo32(seed), hi32(seed))
+ * and counter (y * full_w + x, sample, frame, j); draw k of a path is word k mod 4 of block
+ * j = k / 4; u = (word >> 8) * 2^-24.  C: the termination coefficient of Algorithm 1
+ * (C_inf != 0 disables the heuristic); eps: the epsilon of Algorithm 1 (0 by default). */
+typedef struct {
+  uint64_t seed;
+  uint32_t frame;
+  uint32_t spp;            /* >= 1; targets are the mean over samples                      */
+  uint32_t max_bounces;    /* B >= 1: paths stop after B real collisions                   */
+  uint32_t num_levels;     /* K: paths of length n >= K write level K-1                    */
+  float C;
+  int32_t C_inf;
+  float eps;
+} gsc_trace_params;
+
+/* DEVICE, one per pixel (spp == 1 only): the path's accumulated NEE radiance L, the product
+ * beta of the survival probabilities of Algorithm 1 at termination (Eq. 3), its length n
+ * (real collisions) in the low 16 bits of n_kind and the termination kind in the high 16 bits:
+ * 0 no interaction, 1 left the volume, 2 reached max_bounces, 3 terminated early. */
+typedef struct {
+  float L[3];
+  float beta;
+  uint32_t n_kind;
+} gsc_path_record;
+
+enum { GSC_KIND_ESCAPE0 = 0, GSC_KIND_ESCAPE = 1, GSC_KIND_MAXDEPTH = 2, GSC_KIND_EARLY = 3 };
+
+/* HOST.  Per-call counters and stage times (milliseconds, from HIP events). */
+typedef struct {
+  double ms_project_bin, ms_forward, ms_trace, ms_loss, ms_backward, ms_adam, ms_total;
+  uint64_t gaussians, instances, tiles, pixels, paths, path_vertices;
+  double loss;
+  int32_t adam_skipped;    /* 1 when the loss was not finite and no parameter was written  */
+} gsc_frame_stats;
+
+/* HOST.  Counts plus DEVICE pointers into a binning object, for inspection.  Per-Gaussian
+ * arrays are indexed by the concatenation of the levels (level l starts at gauss_offset[l]). */
+typedef struct {
+  uint64_t n_instances;
+  uint64_t n_tiles;        /* sum over levels of TX * TY                                   */
+  int32_t num_levels, tiles_x, tiles_y;
+  int64_t gauss_offset[9];
+  const uint32_t* values;  /* [n_instances] level-local Gaussian ids, sorted by (tile, depth, id) */
+  const uint64_t* ranges;  /* [n_tiles][2] per-tile [start, end); (0, 0) when empty          */
+  const int32_t* window;   /* [sum n][4] inclusive pixel window px0, px1, py0, py1 (0 if culled) */
+  const uint32_t* tiles_touched; /* [sum n]; 0 when culled                                  */
+  const uint32_t* depth_key; /* [sum n] bits of the camera-space z; 0xFFFFFFFF when culled   */
+  const float* screen;     /* [sum n][6] u, v, conic A, B, C, opacity                        */
+} gsc_binning_info;
+
+/* HOST.  AdamW hyper-parameters of one parameter group; lr already includes the Eq. 5 factor. */
+typedef struct {
+  float lr, beta1, beta2, eps, weight_decay;
+  int64_t step;            /* >= 1: the bias-correction step                                */
+} gsc_adam_hparams;
+
+/* HOST.  One frame of one viewer of one scene. */
+typedef struct {
+  gsc_camera cam;
+  gsc_trace_params trace;  /* num_levels must equal the scene's K                          */
+  int32_t loss;            /* 0 = L2, 1 = HDR (Eq. 4)                                      */
+  int32_t train;           /* 0: render only (no backward, no optimiser step)              */
+  uint32_t viewport_frames;/* t >= 1 of Eq. 5                                               */
+  float lr[5];             /* pos, rot, log_scale, rgb, opacity_logit (before Eq. 5)       */
+  float beta1, beta2, eps, weight_decay;
+} gsc_frame_request;
+
+/* ---- context ------------------------------------------------------------------------- */
+/* Creates a context on `device` that enqueues on `hip_stream` (NULL: the null stream).
+ * `alloc` may be NULL.  Synchronises nothing. */
+gsc_status gsc_ctx_create(int device, void* hip_stream, const gsc_allocator* alloc, gsc_ctx** out);
+void gsc_ctx_destroy(gsc_ctx* ctx);
+/* HOST string, valid until the next call on ctx. */
+const char* gsc_ctx_last_error(const gsc_ctx* ctx);
+gsc_status gsc_ctx_set_stream(gsc_ctx* ctx, void* hip_stream);
+gsc_status gsc_ctx_set_deterministic(gsc_ctx* ctx, int32_t on);
+/* After GSC_E_CAPACITY: the instance count the failed call needed. */
+uint64_t gsc_ctx_required_capacity(const gsc_ctx* ctx);
+/* Per-kernel timing: while on, every kernel launch of the context is bracketed by HIP events
+ * recorded on the stream it is launched on; turning it on clears the totals.  Costs two event
+ * records per launch. */
+gsc_status gsc_ctx_profile(gsc_ctx* ctx, int32_t on);
+/* Synchronises on the recorded events and returns kernel `index`'s name (HOST buffer of
+ * name_len bytes), total milliseconds and launch count since profiling was turned on;
+ * GSC_E_INVALID_ARG past the last index. */
+gsc_status gsc_ctx_profile_read(gsc_ctx* ctx, int32_t index, char* name, size_t name_len,
+                                double* total_ms, int64_t* launches);
+/* Instances binned and binnings run since profiling was last turned on (HOST). */
+gsc_status gsc_ctx_counters(gsc_ctx* ctx, uint64_t* instances, uint64_t* binnings);
+/* Frees the context's cached workspace (binning buffers, frame scratch). */
+gsc_status gsc_ctx_trim(gsc_ctx* ctx);
+
+/* ---- the hot path ----------------------------------------------------------------------- */
+/* Delta-tracking volume path tracer with next-event estimation to every point light
+ * (ratio-tracked shadow transmittance, isotropic phase 1/(4 pi)), Algorithm 1 early
+ * termination with the cumulative throughput reading and beta of Eq. 3, at most max_bounces
+ * real collisions; one path per pixel of the camera window per sample (Method: "Path
+ * Termination Heuristics", "Cache Sampling", "Cache Training").
+ * targets: [K][h][w][3], written completely: level min(n,K)-1 of pixel p receives the
+ * path's accumulated NEE radiance, every other level 0; mean over spp.
+ * records: [h][w] gsc_path_record, or NULL; must be NULL when spp > 1.
+ * stats: HOST or NULL; non-NULL synchronises the stream and fills ms_trace, paths and
+ * path_vertices. */
+gsc_status gsc_trace_targets(gsc_ctx* ctx, const gsc_volume* vol, const gsc_camera* cam,
+                             const gsc_trace_params* params, float* targets,
+                             gsc_path_record* records, gsc_frame_stats* stats);
+
+/* Projects every Gaussian of num_levels levels to a screen-space conic (3D Gaussian
+ * splatting, the rasteriser the paper adapts; Method: "A Path Space Radiance Cache") and bins
+ * them into 16x16 tiles: all levels share one tile-key space (level l's tiles follow level
+ * l-1's), and each tile's list is sorted by (depth, id), i.e. the instances come out sorted by
+ * the 64-bit key (tile << 32) | bits(depth) with ties broken by Gaussian id.
+ * capacity_hint: 0 sizes the instance buffer exactly (one device->host read of the count);
+ * otherwise it is used as the capacity and GSC_E_CAPACITY is returned (after synchronising)
+ * if the frame needs more.  On success *out holds a binning object that must be released
+ * with gsc_binning_release. */
+gsc_status gsc_project_bin(gsc_ctx* ctx, const gsc_gaussians* levels, int32_t num_levels,
+                           const gsc_camera* cam, uint64_t capacity_hint, gsc_binning** out);
+/* Synchronises; fills HOST counts and DEVICE pointers (valid until the object is released). */
+gsc_status gsc_binning_view(gsc_ctx* ctx, const gsc_binning* bin, gsc_binning_info* out);
+/* Writes the 64-bit sort keys [n_instances] ((global tile << 32) | bits(depth)) of the
+ * binned instances to `keys` (DEVICE, caller-owned).  The sort itself never materialises
+ * them. */
+gsc_status gsc_binning_keys(gsc_ctx* ctx, const gsc_binning* bin, uint64_t* keys);
+void gsc_binning_release(gsc_ctx* ctx, gsc_binning* bin);
+
+/* Front-to-back alpha blending of every level's tiles: per pixel, over the tile list in
+ * order, alpha = min(0.99, o exp(power)), pairs with power > 0, alpha < 1/255 or the pixel
+ * outside the Gaussian's window are skipped, and blending stops before T (1 - alpha) < 1e-4;
+ * background 0.  images [K][h][w][3], final_T [K][h][w], last_id [K][h][w] (level-local id of
+ * the last blended Gaussian, -1 when none).  The object keeps each pixel's list position of
+ * its last contributor for gsc_splat_backward. */
+gsc_status gsc_splat_forward(gsc_ctx* ctx, gsc_binning* bin, float* images, float* final_T,
+                             int32_t* last_id);
+
+/* Adjoint of gsc_splat_forward followed by the adjoint of the projection: given dL/dimages
+ * [K][h][w][3], writes the gradients of all 14 parameters of every Gaussian of every level
+ * (grads[l] has the shapes of levels[l]; overwritten).  Walks each tile back to front from
+ * the stored last contributor, recovering transmittance from final_T by division (no
+ * per-pixel lists).  levels and cam must be those given to gsc_project_bin. */
+gsc_status gsc_splat_backward(gsc_ctx* ctx, const gsc_binning* bin, const gsc_gaussians* levels,
+                              int32_t num_levels, const gsc_camera* cam, const float* final_T,
+                              const int32_t* last_id, const float* dL_dimages,
+                              const gsc_grads* grads);
+
+/* Per level l, with prediction y = images[l] and noisy target x = targets[l]: L2 (loss 0) or
+ * the HDR loss of Eq. 4, (y - x)^2 / (sg(max(y,0)) + 0.01)^2 (loss 1), averaged over the
+ * 3 w h elements of the level and summed over levels; writes dL/dimages [K][h][w][3] and the
+ * loss (DEVICE scalar, fp32).  If records is not NULL also writes the cached composite image
+ * [h][w][3]: early termination -> max(cache, 0) / beta; natural termination with nonzero
+ * radiance -> the radiance, with zero radiance -> max(cache, 0) / beta; no interaction -> 0,
+ * where cache = images[min(n,K)-1] (Method: "Natural Path Termination", Eq. 3). */
+gsc_status gsc_loss_composite(gsc_ctx* ctx, const float* images, const float* targets,
+                              const gsc_path_record* records, int32_t num_levels, int32_t w,
+                              int32_t h, int32_t loss, float* dL_dimages, float* loss_out,
+                              float* composite);
+
+/* One AdamW step over `count` elements (Method: "Regularization"): m = b1 m + (1-b1) g;
+ * v = b2 v + (1-b2) g^2; p = p (1 - lr wd); p = p - s1 m / (sqrt(v) s2 + eps) with
+ * s1 = lr / (1 - b1^step), s2 = 1 / sqrt(1 - b2^step) computed in double on the host; every
+ * fp32 operation separately rounded.  In-place on param, m, v. */
+gsc_status gsc_adam_step(gsc_ctx* ctx, float* param, float* m, float* v, const float* grad,
+                         int64_t count, const gsc_adam_hparams* hp);
+
+/* ---- scenes and frames ------------------------------------------------------------------ */
+/* A scene keeps resident on the device: a copy of the volume grid, its TF and lights, and
+ * K levels of parameters with their Adam moments and step counter (copied from init_levels). */
+gsc_status gsc_scene_create(gsc_ctx* ctx, const gsc_volume* vol, const gsc_gaussians* init_levels,
+                            int32_t K, gsc_scene** out);
+void gsc_scene_destroy(gsc_ctx* ctx, gsc_scene* scene);
+/* Replaces the TF and lights (HOST arrays; a transfer-function edit or a light move). */
+gsc_status gsc_scene_set_optics(gsc_ctx* ctx, gsc_scene* scene, const float* tf_rgba,
+                                int32_t tf_points, const float* lights, int32_t n_lights);
+/* DEVICE pointers to the scene's current parameters of level l. */
+gsc_status gsc_scene_level(const gsc_scene* scene, int32_t l, gsc_gaussians* out);
+/* DEVICE pointers to level l's optimiser state: params, m and v are each [14 n] floats laid out
+ * [pos 3n][rot 4n][log_scale 3n][rgb 3n][opacity_logit n]; *step is the number of AdamW steps
+ * taken.  Valid until the scene is destroyed. */
+gsc_status gsc_scene_state(const gsc_scene* scene, int32_t l, float** params, float** m, float** v,
+                           int64_t* n, int64_t* step);
+/* Copies parameters, moments and step counters from src to dst (same level sizes). */
+gsc_status gsc_scene_copy_state(gsc_ctx* ctx, gsc_scene* dst, const gsc_scene* src);
+/* Resident bytes: grid + 3 x 14 fp32 per Gaussian (parameters and two moments). */
+size_t gsc_scene_footprint_bytes(const gsc_scene* scene);
+/* Transient bytes one frame of w x h needs, for an instance estimate. */
+size_t gsc_frame_footprint_bytes(const gsc_scene* scene, int32_t w, int32_t h,
+                                 uint64_t instance_estimate);
+
+/* One frame (Method, per-frame protocol): splat all K levels into cache images (one key
+ * space, one launch per stage), trace the targets on a second stream meanwhile, then the
+ * loss, the cached composite into `image` ([h][w][3]), and -- when req->train -- the splat
+ * backward and one AdamW step per parameter group with lr x 1/(1 + ln t) (Eq. 5).  A
+ * non-finite loss skips the step.  stats: HOST or NULL (non-NULL synchronises). */
+gsc_status gsc_render_frame(gsc_ctx* ctx, gsc_scene* scene, const gsc_frame_request* req,
+                            float* image, gsc_frame_stats* stats);
+
+/* A batch of n frames of distinct scenes, executed stage by stage with one launch per stage
+ * over all (request, level) pairs.  The scenes must be pairwise distinct (one training step
+ * per scene per batch).  images[i] is request i's composite [h_i][w_i][3]; stats: HOST array
+ * of n or NULL.  Results equal n separate gsc_render_frame calls up to float-atomic order. */
+gsc_status gsc_render_frames(gsc_ctx* ctx, gsc_scene* const* scenes,
+                             const gsc_frame_request* reqs, float* const* images, int32_t n,
+                             gsc_frame_stats* stats);
+
+/* Enqueues a copy of `bytes` bytes between two device (or pinned host) buffers on the
+ * context's stream.  A convenience for bindings that read the DEVICE pointers of a view. */
+gsc_status gsc_copy(gsc_ctx* ctx, void* dst, const void* src, size_t bytes);
+/* Waits for all work enqueued on the context's stream. */
+gsc_status gsc_ctx_synchronize(gsc_ctx* ctx);
+
+/* HOST, side-effect free: sizes of the structs above, for bindings to check their layouts. */
+size_t gsc_abi_struct_size(int32_t which);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* GSC_H_ */

@@ -481,6 +481,12 @@ int ora_num_threads() {
 #endif
 }
 
+// The constants of the portable transcendentals, for inspection by the tests.
+void ora_constants(float* out) {
+  out[0] = O_LN2_HI; out[1] = O_LN2_LO; out[2] = O_LOG2E;
+  out[3] = O_PI.p1; out[4] = O_PI.p2; out[5] = O_PI.p3;
+}
+
 void ora_philox4x32_10(const uint32_t* ctr, const uint32_t* key, uint32_t* out) {
   Philox::block(ctr, key, out);
 }

@@ -1,0 +1,136 @@
+// gsc_internal.h -- structures shared by the host runtime and the HIP kernels of the GSCache
+// hot path (not part of the public ABI).
+//
+// A *batch* is a list of segments; a segment is one cache level of one frame request.  Every
+// kernel of the splat path runs once per stage over all segments of a batch: per-Gaussian
+// arrays are concatenated (segment s owns [g_off, g_off + n)), per-pixel arrays likewise
+// ([pix_off, pix_off + w h)), and the tiles of all segments share one key space
+// ([tile_base, tile_base + TX TY)).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/gsc.h"
+
+namespace gsc {
+
+constexpr int kTile = 16;               // 16x16 pixel tiles
+constexpr int kMaxTf = 64;
+constexpr int kMaxLights = 8;
+constexpr int kChunk = 2048;            // depth-ordered Gaussians per binning chunk
+
+struct DevCam {
+  float R[9];
+  float t[3];
+  float fx, fy, cx, cy;
+  int32_t full_w, full_h, x0, y0, w, h;
+  float znear;
+};
+
+struct Seg {
+  const float* pos;
+  const float* rot;
+  const float* ls;
+  const float* rgb;
+  const float* logit;
+  int64_t n;
+  int64_t g_off;        // per-Gaussian offset
+  int64_t tile_base;    // first global tile
+  int64_t pix_off;      // per-pixel offset (w h per segment)
+  int64_t chunk_off;    // first binning chunk (chunks of kChunk depth-ordered Gaussians)
+  int32_t n_chunks;
+  int32_t cam;
+  int32_t TX, TY;
+  int32_t level;
+  int32_t request;
+};
+
+// Per request of a trace launch.
+struct TraceDesc {
+  const float* density;
+  int32_t nx, ny, nz;
+  float dmax, majorant;
+  int32_t P, n_lights;
+  float tf[kMaxTf * 4];
+  float lights[kMaxLights * 6];
+  DevCam cam;
+  uint64_t seed;
+  uint32_t frame, spp, max_bounces, K;
+  float C;
+  int32_t C_inf;
+  float eps;
+  int64_t pix_off;      // first pixel of this request in the launch
+  float* targets;       // [K][h][w][3]
+  void* records;        // [h][w] x 20 B or NULL
+};
+
+// Per-Gaussian projected record, 48 B, gathered by the splat kernels:
+//   q0 = (u, v, A, B), q1 = (Cc, o, r, g), q2 = (b, px0|px1<<16, py0|py1<<16, id)
+struct alignas(16) SplatRec {
+  float4 q0, q1, q2;
+};
+
+// ---- launchers (all enqueue on `st`) ---------------------------------------------------------
+hipError_t launch_project(hipStream_t st, const Seg* segs, const int64_t* seg_gstart, int S,
+                          const DevCam* cams, int64_t G, SplatRec* rec, uint32_t* depth_key,
+                          uint64_t* rect, uint32_t* tiles, uint32_t* ids);
+hipError_t launch_project_backward(hipStream_t st, const Seg* segs, const int64_t* seg_gstart, int S,
+                                   const DevCam* cams, int64_t G, const float* grad2d,
+                                   float* grads14);
+hipError_t launch_fill_u32(hipStream_t st, uint32_t* p, uint32_t value, int64_t count);
+
+size_t sort_table_bytes(int n_blocks, int S);
+int sort_count_blocks(const int64_t* seg_n, int S);
+void sort_fill_table(void* host, const int64_t* seg_n, const int64_t* seg_off, int S);
+hipError_t launch_segmented_sort(hipStream_t st, const void* table_dev, int n_blocks, int S,
+                                 uint32_t* keys, uint32_t* vals, uint32_t* keys_tmp,
+                                 uint32_t* vals_tmp, uint32_t* hist);
+
+size_t bin_work_bytes(int S);
+int64_t bin_fill_work(void* host, const Seg* segs, int S, int64_t* total_chunk_tiles);
+size_t bin_scan_partials(int64_t n_tiles);
+hipError_t launch_gather_rect(hipStream_t st, const int64_t* seg_gstart, int S, int64_t G,
+                              const uint32_t* sorted_ids, const uint64_t* rect,
+                              uint64_t* rect_sorted);
+hipError_t launch_bin_count(hipStream_t st, const void* work_dev, int S, int64_t total_waves,
+                            const uint32_t* sorted_ids, const uint64_t* rect_sorted,
+                            uint32_t* counts);
+hipError_t launch_bin_scan(hipStream_t st, const void* work_dev, int S, const int64_t* seg_tstart,
+                           int64_t n_tiles, uint32_t* counts, uint32_t* tile_total,
+                           uint64_t* partial, uint64_t* tile_start, uint64_t* ranges,
+                           uint64_t* n_instances);
+hipError_t launch_bin_place(hipStream_t st, const void* work_dev, int S, int64_t total_waves,
+                            const uint32_t* sorted_ids, const uint64_t* rect_sorted,
+                            uint32_t* counts, const uint64_t* tile_start,
+                            const uint64_t* n_instances, uint64_t capacity, uint32_t* values);
+hipError_t launch_binning_keys(hipStream_t st, const int64_t* seg_tstart, int S,
+                               const int64_t* seg_goff, int64_t n_tiles, const uint64_t* tile_start,
+                               const uint64_t* n_instances, uint64_t n_host,
+                               const uint32_t* values, const uint32_t* depth_key, uint64_t* keys);
+hipError_t launch_view(hipStream_t st, int64_t G, const SplatRec* rec, const uint32_t* tiles,
+                       int32_t* window, float* screen);
+
+hipError_t launch_splat_forward(hipStream_t st, const Seg* segs, const int64_t* seg_tstart, int S,
+                                const DevCam* cams, int64_t n_tiles, const uint64_t* ranges,
+                                const uint32_t* values, const SplatRec* rec, float* images,
+                                float* final_T, int32_t* last_id, uint32_t* n_contrib);
+hipError_t launch_splat_backward(hipStream_t st, const Seg* segs, const int64_t* seg_tstart, int S,
+                                 const DevCam* cams, int64_t n_tiles, const uint64_t* ranges,
+                                 const uint32_t* values, const SplatRec* rec, const float* final_T,
+                                 const uint32_t* n_contrib, const float* dL_dimages,
+                                 float* grad2d, int64_t G, int deterministic);
+
+hipError_t launch_trace(hipStream_t st, const TraceDesc* descs, const int64_t* req_pstart, int R,
+                        int64_t total_pixels, unsigned long long* path_vertices);
+
+int loss_num_partials(int64_t pixels);
+hipError_t launch_loss_composite(hipStream_t st, const float* images, const float* targets,
+                                 const void* records, int K, int w, int h, int loss,
+                                 float* dL_dimages, double* partials, float* loss_out,
+                                 float* composite);
+hipError_t launch_adam(hipStream_t st, float* param, float* m, float* v, const float* grad,
+                       int64_t count, float b1, float b2, float omb1, float omb2, float s1,
+                       float s2, float wdf, float eps, const float* guard);
+
+}  // namespace gsc

@@ -1,0 +1,175 @@
+// k_sort.hip -- segmented least-significant-digit radix sort of 32-bit keys with 32-bit
+// values, 8-bit digits, stable.  Used to order each segment's Gaussians by the bit pattern of
+// their camera depth (positive floats order as unsigned integers); ties keep id order.  These
+// are the four low digits of the (tile << 32 | depth) instance key, sorted once per Gaussian
+// instead of once per instance; the tile digit is applied by the binning placement pass.
+//
+// Per pass: (1) per-block digit histograms, (2) per-segment digit-major exclusive scan over
+// blocks, (3) stable scatter: items are taken in index order, 256 per round, and ranked within
+// a 64-wide wavefront by eight ballots (lanes with equal digits), then across the block's four
+// wavefronts in LDS.
+#include "gsc_dev.h"
+
+namespace gsc {
+
+namespace {
+
+constexpr int kSortThreads = 256;
+constexpr int kSortRounds = 8;
+constexpr int kSortItems = kSortThreads * kSortRounds;   // 2048 items per block
+
+struct SortBlock {
+  int64_t start;      // first item (global index)
+  int64_t seg_base;   // first item of the block's segment
+  int32_t count;      // items in this block
+  int32_t seg;        // segment index
+};
+
+__global__ void __launch_bounds__(kSortThreads) sort_hist_kernel(const SortBlock* __restrict__ blocks,
+                                                                 const uint32_t* __restrict__ keys,
+                                                                 int shift, uint32_t* __restrict__ hist) {
+  __shared__ uint32_t cnt[256];
+  const SortBlock B = blocks[blockIdx.x];
+  cnt[threadIdx.x] = 0u;
+  __syncthreads();
+  for (int r = 0; r < kSortRounds; ++r) {
+    const int k = r * kSortThreads + threadIdx.x;
+    if (k < B.count) atomicAdd(&cnt[(keys[B.start + k] >> shift) & 0xffu], 1u);
+  }
+  __syncthreads();
+  hist[(int64_t)blockIdx.x * 256 + threadIdx.x] = cnt[threadIdx.x];
+}
+
+// One workgroup per segment; thread d owns digit d.
+__global__ void __launch_bounds__(256) sort_scan_kernel(const int32_t* __restrict__ seg_first_block,
+                                                        uint32_t* __restrict__ hist) {
+  __shared__ uint32_t tot[256];
+  const int s = blockIdx.x;
+  const int b0 = seg_first_block[s], b1 = seg_first_block[s + 1];
+  const int d = threadIdx.x;
+  uint32_t t = 0u;
+  for (int b = b0; b < b1; ++b) t += hist[(int64_t)b * 256 + d];
+  tot[d] = t;
+  __syncthreads();
+  // Exclusive scan over the 256 digit totals (Hillis-Steele in LDS).
+  for (int off = 1; off < 256; off <<= 1) {
+    const uint32_t v = (d >= off) ? tot[d - off] : 0u;
+    __syncthreads();
+    tot[d] += v;
+    __syncthreads();
+  }
+  uint32_t run = tot[d] - t;
+  for (int b = b0; b < b1; ++b) {
+    const uint32_t v = hist[(int64_t)b * 256 + d];
+    hist[(int64_t)b * 256 + d] = run;
+    run += v;
+  }
+}
+
+__global__ void __launch_bounds__(kSortThreads) sort_scatter_kernel(
+    const SortBlock* __restrict__ blocks, const uint32_t* __restrict__ keys_in,
+    const uint32_t* __restrict__ vals_in, int shift, const uint32_t* __restrict__ hist,
+    uint32_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out) {
+  __shared__ uint32_t run[256];
+  __shared__ uint32_t wcnt[4][256];
+  const SortBlock B = blocks[blockIdx.x];
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6;
+  const int lane = __lane_id();
+  const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  run[tid] = hist[(int64_t)blockIdx.x * 256 + tid];
+  for (int w = 0; w < 4; ++w) wcnt[w][tid] = 0u;
+  __syncthreads();
+  for (int r = 0; r < kSortRounds; ++r) {
+    const int k = r * kSortThreads + tid;
+    const bool valid = k < B.count;
+    uint32_t key = 0u, val = 0u, d = 0u;
+    if (valid) {
+      key = keys_in[B.start + k];
+      val = vals_in[B.start + k];
+      d = (key >> shift) & 0xffu;
+    }
+    uint64_t peers = __ballot(valid);
+#pragma unroll
+    for (int bit = 0; bit < 8; ++bit) {
+      const bool set = (d >> bit) & 1u;
+      const uint64_t m = __ballot(valid && set);
+      peers &= set ? m : ~m;
+    }
+    const uint32_t rank = (uint32_t)__popcll(peers & lt_mask);
+    const bool leader = valid && ((peers & lt_mask) == 0ull);
+    if (leader) wcnt[wave][d] = (uint32_t)__popcll(peers);
+    __syncthreads();
+    if (valid) {
+      uint32_t pos = run[d] + rank;
+      for (int w = 0; w < wave; ++w) pos += wcnt[w][d];
+      keys_out[B.seg_base + pos] = key;
+      vals_out[B.seg_base + pos] = val;
+    }
+    __syncthreads();
+    run[tid] += (wcnt[0][tid] + wcnt[1][tid]) + (wcnt[2][tid] + wcnt[3][tid]);
+    for (int w = 0; w < 4; ++w) wcnt[w][tid] = 0u;
+    __syncthreads();
+  }
+}
+
+}  // namespace
+
+// Host side of the sort: the block table is built from the segment sizes.
+struct SortPlan {
+  int n_blocks = 0;
+  int S = 0;
+};
+
+size_t sort_table_bytes(int n_blocks, int S) {
+  return sizeof(SortBlock) * (size_t)n_blocks + sizeof(int32_t) * (size_t)(S + 1);
+}
+
+int sort_count_blocks(const int64_t* seg_n, int S) {
+  int nb = 0;
+  for (int s = 0; s < S; ++s) nb += (int)((seg_n[s] + kSortItems - 1) / kSortItems);
+  return nb;
+}
+
+// Fills a host staging area: [SortBlock x n_blocks][int32 first_block x (S + 1)].
+void sort_fill_table(void* host, const int64_t* seg_n, const int64_t* seg_off, int S) {
+  SortBlock* blk = (SortBlock*)host;
+  int32_t* first = (int32_t*)(blk + sort_count_blocks(seg_n, S));
+  int b = 0;
+  for (int s = 0; s < S; ++s) {
+    first[s] = b;
+    for (int64_t k = 0; k < seg_n[s]; k += kSortItems) {
+      blk[b].start = seg_off[s] + k;
+      blk[b].seg_base = seg_off[s];
+      blk[b].count = (int32_t)((seg_n[s] - k) < kSortItems ? (seg_n[s] - k) : kSortItems);
+      blk[b].seg = s;
+      ++b;
+    }
+  }
+  first[S] = b;
+}
+
+// Sorts keys/vals of every segment in place (4 passes; the temporaries receive the odd passes).
+hipError_t launch_segmented_sort(hipStream_t st, const void* table_dev, int n_blocks, int S,
+                                 uint32_t* keys, uint32_t* vals, uint32_t* keys_tmp,
+                                 uint32_t* vals_tmp, uint32_t* hist) {
+  if (n_blocks == 0) return hipSuccess;
+  const SortBlock* blocks = (const SortBlock*)table_dev;
+  const int32_t* first = (const int32_t*)(blocks + n_blocks);
+  uint32_t* kin = keys; uint32_t* vin = vals;
+  uint32_t* kout = keys_tmp; uint32_t* vout = vals_tmp;
+  for (int pass = 0; pass < 4; ++pass) {
+    const int shift = 8 * pass;
+    hipLaunchKernelGGL(sort_hist_kernel, dim3(n_blocks), dim3(kSortThreads), 0, st, blocks, kin,
+                       shift, hist);
+    hipLaunchKernelGGL(sort_scan_kernel, dim3(S), dim3(256), 0, st, first, hist);
+    hipLaunchKernelGGL(sort_scatter_kernel, dim3(n_blocks), dim3(kSortThreads), 0, st, blocks,
+                       kin, vin, shift, hist, kout, vout);
+    uint32_t* t;
+    t = kin; kin = kout; kout = t;
+    t = vin; vin = vout; vout = t;
+  }
+  return hipGetLastError();
+}
+
+}  // namespace gsc

@@ -1,0 +1,288 @@
+// k_trace.hip -- the volume path tracer that produces GSCache's per-path-length training targets.
+//
+// One lane per pixel of a request, one path per sample: delta tracking against the global
+// majorant (free flight), albedo-weighted real collisions, next-event estimation to every
+// point light with ratio-tracked shadow transmittance and the isotropic phase function,
+// Algorithm 1's early termination (cumulative throughput reading: the throughput is divided
+// by the survival probability Tr and beta multiplied by it), uniform sphere directions.  The
+// NEE radiance accumulated along the path is written to the target of its length (Method:
+// "Path Termination Heuristics", "Throughput Importance Sampling", "Cascaded Cache Radiance
+// Importance Sampling", "Cache Training").  Every fp32 operation is separately rounded in a
+// fixed order, and the random numbers come from each pixel's own Philox stream, so the output
+// does not depend on the launch shape.
+#include "gsc_dev.h"
+
+namespace gsc {
+
+namespace {
+
+constexpr uint32_t kMaxSteps = 1u << 20;   // per free-flight / shadow segment (never reached)
+
+struct Vol {
+  const float* d;
+  int nx, ny, nz;
+  float dmax;
+  const float* tf;
+  int P;
+};
+
+__device__ __forceinline__ float lerpf_(float a, float b, float f) { return a + f * (b - a); }
+
+__device__ __forceinline__ float density(const Vol& V, float px, float py, float pz) {
+  const float gx = px * (float)V.nx - 0.5f, gy = py * (float)V.ny - 0.5f, gz = pz * (float)V.nz - 0.5f;
+  const float ix = floorf(gx), iy = floorf(gy), iz = floorf(gz);
+  const float fx = gx - ix, fy = gy - iy, fz = gz - iz;
+  const int x0i = (int)ix, y0i = (int)iy, z0i = (int)iz;
+  const int x0 = min(max(x0i, 0), V.nx - 1), x1 = min(max(x0i + 1, 0), V.nx - 1);
+  const int y0 = min(max(y0i, 0), V.ny - 1), y1 = min(max(y0i + 1, 0), V.ny - 1);
+  const int z0 = min(max(z0i, 0), V.nz - 1), z1 = min(max(z0i + 1, 0), V.nz - 1);
+  const int64_t sy = V.nx, sz = (int64_t)V.nx * V.ny;
+  const float* p00 = V.d + z0 * sz + y0 * sy;
+  const float* p10 = V.d + z0 * sz + y1 * sy;
+  const float* p01 = V.d + z1 * sz + y0 * sy;
+  const float* p11 = V.d + z1 * sz + y1 * sy;
+  const float c00 = lerpf_(p00[x0], p00[x1], fx);
+  const float c10 = lerpf_(p10[x0], p10[x1], fx);
+  const float c01 = lerpf_(p01[x0], p01[x1], fx);
+  const float c11 = lerpf_(p11[x0], p11[x1], fx);
+  const float c0 = lerpf_(c00, c10, fy), c1 = lerpf_(c01, c11, fy);
+  return lerpf_(c0, c1, fz);
+}
+
+__device__ __forceinline__ void transfer(const Vol& V, float d, float* r, float* g, float* b, float* a) {
+  float s = d / V.dmax;
+  s = fminf(fmaxf(s, 0.0f), 1.0f) * (float)(V.P - 1);
+  const int i = min((int)floorf(s), V.P - 2);
+  const float f = s - (float)i;
+  const float* c0 = V.tf + 4 * i;
+  const float* c1 = c0 + 4;
+  *r = lerpf_(c0[0], c1[0], f);
+  *g = lerpf_(c0[1], c1[1], f);
+  *b = lerpf_(c0[2], c1[2], f);
+  *a = lerpf_(c0[3], c1[3], f);
+}
+
+__device__ __forceinline__ float opacity_only(const Vol& V, float d) {
+  float s = d / V.dmax;
+  s = fminf(fmaxf(s, 0.0f), 1.0f) * (float)(V.P - 1);
+  const int i = min((int)floorf(s), V.P - 2);
+  const float f = s - (float)i;
+  return lerpf_(V.tf[4 * i + 3], V.tf[4 * i + 7], f);
+}
+
+__device__ __forceinline__ bool inside_cube(float x, float y, float z) {
+  return x >= 0.0f && x <= 1.0f && y >= 0.0f && y <= 1.0f && z >= 0.0f && z <= 1.0f;
+}
+
+// sigma_t = d A(d) inside the unit cube, 0 outside; also returns d.
+__device__ __forceinline__ float sigma_t(const Vol& V, float x, float y, float z, float* dout) {
+  if (!inside_cube(x, y, z)) { *dout = 0.0f; return 0.0f; }
+  const float d = density(V, x, y, z);
+  *dout = d;
+  return d * opacity_only(V, d);
+}
+
+// Slab test against [0,1]^3.
+__device__ __forceinline__ bool box(float ox, float oy, float oz, float wx, float wy, float wz,
+                                    float* t0, float* t1) {
+  float tmin = -__int_as_float(0x7f800000), tmax = __int_as_float(0x7f800000);
+  const float o[3] = {ox, oy, oz}, w[3] = {wx, wy, wz};
+#pragma unroll
+  for (int a = 0; a < 3; ++a) {
+    if (w[a] != 0.0f) {
+      const float inv = 1.0f / w[a];
+      const float ta = (0.0f - o[a]) * inv, tb = (1.0f - o[a]) * inv;
+      tmin = fmaxf(tmin, fminf(ta, tb));
+      tmax = fminf(tmax, fmaxf(ta, tb));
+    } else if (o[a] < 0.0f || o[a] > 1.0f) {
+      return false;
+    }
+  }
+  const float lo = fmaxf(tmin, 0.0f);
+  if (!(tmax > lo)) return false;
+  *t0 = lo;
+  *t1 = tmax;
+  return true;
+}
+
+struct PathResult {
+  float L0, L1, L2, beta;
+  uint32_t n, kind;
+};
+
+__device__ PathResult trace_path(const TraceDesc& D, const Vol& V, int px, int py, uint32_t sample) {
+  PathResult res{0.0f, 0.0f, 0.0f, 1.0f, 0u, 0u};
+  const DevCam& cam = D.cam;
+  PathStream rng(D.seed, (uint32_t)py * (uint32_t)cam.full_w + (uint32_t)px, sample, D.frame);
+  float d0 = ((float)px + 0.5f - cam.cx) / cam.fx;
+  float d1 = ((float)py + 0.5f - cam.cy) / cam.fy;
+  float d2 = 1.0f;
+  const float nrm = sqrtf((d0 * d0 + d1 * d1) + d2 * d2);
+  d0 = d0 / nrm; d1 = d1 / nrm; d2 = d2 / nrm;
+  const float* R = cam.R;
+  float wx = (R[0] * d0 + R[3] * d1) + R[6] * d2;
+  float wy = (R[1] * d0 + R[4] * d1) + R[7] * d2;
+  float wz = (R[2] * d0 + R[5] * d1) + R[8] * d2;
+  float ox = -((R[0] * cam.t[0] + R[3] * cam.t[1]) + R[6] * cam.t[2]);
+  float oy = -((R[1] * cam.t[0] + R[4] * cam.t[1]) + R[7] * cam.t[2]);
+  float oz = -((R[2] * cam.t[0] + R[5] * cam.t[1]) + R[8] * cam.t[2]);
+  float t0, t1;
+  if (!box(ox, oy, oz, wx, wy, wz, &t0, &t1)) return res;
+  const float sb = D.majorant;
+  float tr0 = 1.0f, tr1 = 1.0f, tr2 = 1.0f;
+  float raw0 = 1.0f, raw1 = 1.0f, raw2 = 1.0f;
+  float beta = 1.0f;
+  float L0 = 0.0f, L1 = 0.0f, L2 = 0.0f;
+  uint32_t n = 0u;
+  uint32_t kind = GSC_KIND_ESCAPE0;
+  for (;;) {
+    float t = t0;
+    bool collided = false;
+    float x = 0.0f, y = 0.0f, z = 0.0f, dcol = 0.0f;
+    for (uint32_t step = 0; step < kMaxSteps; ++step) {
+      const float u = rng.uniform();
+      t = t - glog(1.0f - u) / sb;
+      if (t >= t1) break;
+      x = ox + t * wx; y = oy + t * wy; z = oz + t * wz;
+      const float u2 = rng.uniform();
+      float dd;
+      const float st = sigma_t(V, x, y, z, &dd);
+      if (u2 < st / sb) { collided = true; dcol = dd; break; }
+    }
+    if (!collided) { kind = (n == 0u) ? GSC_KIND_ESCAPE0 : GSC_KIND_ESCAPE; break; }
+    n += 1u;
+    float ar, ag, ab, aa;
+    transfer(V, dcol, &ar, &ag, &ab, &aa);
+    raw0 = raw0 * ar; raw1 = raw1 * ag; raw2 = raw2 * ab;
+    tr0 = tr0 * ar; tr1 = tr1 * ag; tr2 = tr2 * ab;
+    for (int l = 0; l < D.n_lights; ++l) {
+      const float* lp = D.lights + 6 * l;
+      const float dl0 = lp[0] - x, dl1 = lp[1] - y, dl2 = lp[2] - z;
+      const float dist2 = (dl0 * dl0 + dl1 * dl1) + dl2 * dl2;
+      const float dist = sqrtf(dist2);
+      const float l0 = dl0 / dist, l1 = dl1 / dist, l2 = dl2 / dist;
+      float b0, b1;
+      float texit;
+      if (box(x, y, z, l0, l1, l2, &b0, &b1)) texit = fminf(dist, b1);
+      else texit = 0.0f;
+      float Tsh = 1.0f, ts = 0.0f;
+      for (uint32_t step = 0; step < kMaxSteps; ++step) {
+        const float u = rng.uniform();
+        ts = ts - glog(1.0f - u) / sb;
+        if (ts >= texit) break;
+        float dd;
+        const float st = sigma_t(V, x + ts * l0, y + ts * l1, z + ts * l2, &dd);
+        Tsh = Tsh * (1.0f - st / sb);
+      }
+      const float g = (Tsh / dist2) * kInv4Pi;
+      L0 = L0 + tr0 * (lp[3] * g);
+      L1 = L1 + tr1 * (lp[4] * g);
+      L2 = L2 + tr2 * (lp[5] * g);
+    }
+    if (n >= D.max_bounces) { kind = GSC_KIND_MAXDEPTH; break; }
+    if (!D.C_inf) {
+      const float lum = (0.2126f * raw0 + 0.7152f * raw1) + 0.0722f * raw2;
+      const float Tr = fminf(fmaxf(D.C * lum, 0.0f), 1.0f);
+      if (Tr < 0.9f) {
+        const float q = rng.uniform();
+        if (q < 1.0f - Tr) { kind = GSC_KIND_EARLY; break; }
+        tr0 = tr0 / (Tr + D.eps);
+        tr1 = tr1 / (Tr + D.eps);
+        tr2 = tr2 / (Tr + D.eps);
+        beta = beta * Tr;
+      }
+    }
+    const float u1 = rng.uniform(), u2 = rng.uniform();
+    const float cz = 1.0f - 2.0f * u1;
+    const float r = sqrtf(fmaxf(0.0f, 1.0f - cz * cz));
+    float sp, cp;
+    gsincos(kTwoPi * u2, &sp, &cp);
+    wx = r * cp; wy = r * sp; wz = cz;
+    ox = x; oy = y; oz = z;
+    float bb0, bb1;
+    if (!box(ox, oy, oz, wx, wy, wz, &bb0, &bb1)) { kind = GSC_KIND_ESCAPE; break; }
+    t0 = 0.0f;
+    t1 = bb1;
+  }
+  res.L0 = L0; res.L1 = L1; res.L2 = L2;
+  res.beta = beta;
+  res.n = n;
+  res.kind = kind;
+  return res;
+}
+
+__global__ void __launch_bounds__(256) trace_kernel(const TraceDesc* __restrict__ descs,
+                                                    const int64_t* __restrict__ req_pstart, int R,
+                                                    int64_t total, unsigned long long* path_vertices) {
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= total) return;
+  const int r = find_segment(req_pstart, R, p);
+  const TraceDesc& D = descs[r];
+  const Vol V{D.density, D.nx, D.ny, D.nz, D.dmax, D.tf, D.P};
+  const int64_t lp = p - D.pix_off;
+  const int W = D.cam.w, H = D.cam.h;
+  const int lx = (int)(lp % W), ly = (int)(lp / W);
+  const int px = D.cam.x0 + lx, py = D.cam.y0 + ly;
+  const int64_t plane = (int64_t)W * H;
+  const uint32_t K = D.K;
+  uint64_t verts = 0;
+  if (D.spp == 1u) {
+    const PathResult pr = trace_path(D, V, px, py, 0u);
+    verts = pr.n;
+    const uint32_t lvl = pr.n ? (min(pr.n, K) - 1u) : 0xFFFFFFFFu;
+    for (uint32_t l = 0; l < K; ++l) {
+      float* o = D.targets + 3 * (l * plane + lp);
+      const bool mine = (l == lvl);
+      o[0] = mine ? pr.L0 : 0.0f;
+      o[1] = mine ? pr.L1 : 0.0f;
+      o[2] = mine ? pr.L2 : 0.0f;
+    }
+    if (D.records) {
+      uint32_t* rec = (uint32_t*)D.records + 5 * lp;
+      rec[0] = __float_as_uint(pr.L0);
+      rec[1] = __float_as_uint(pr.L1);
+      rec[2] = __float_as_uint(pr.L2);
+      rec[3] = __float_as_uint(pr.beta);
+      rec[4] = pr.n | (pr.kind << 16);
+    }
+  } else {
+    for (uint32_t l = 0; l < K; ++l) {
+      float* o = D.targets + 3 * (l * plane + lp);
+      o[0] = 0.0f; o[1] = 0.0f; o[2] = 0.0f;
+    }
+    for (uint32_t smp = 0; smp < D.spp; ++smp) {
+      const PathResult pr = trace_path(D, V, px, py, smp);
+      verts += pr.n;
+      if (pr.n) {
+        float* o = D.targets + 3 * ((min(pr.n, K) - 1u) * plane + lp);
+        o[0] = o[0] + pr.L0;
+        o[1] = o[1] + pr.L1;
+        o[2] = o[2] + pr.L2;
+      }
+    }
+    const float fs = (float)D.spp;
+    for (uint32_t l = 0; l < K; ++l) {
+      float* o = D.targets + 3 * (l * plane + lp);
+      o[0] = o[0] / fs; o[1] = o[1] / fs; o[2] = o[2] / fs;
+    }
+  }
+  if (path_vertices) {
+    // Wave-level pre-reduction before the single 64-bit atomic.
+    unsigned long long v = verts;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+    if (__lane_id() == 0) atomicAdd(path_vertices, v);
+  }
+}
+
+}  // namespace
+
+hipError_t launch_trace(hipStream_t st, const TraceDesc* descs, const int64_t* req_pstart, int R,
+                        int64_t total_pixels, unsigned long long* path_vertices) {
+  if (total_pixels == 0) return hipSuccess;
+  hipLaunchKernelGGL(trace_kernel, dim3((unsigned)((total_pixels + 255) / 256)), dim3(256), 0, st,
+                     descs, req_pstart, R, total_pixels, path_vertices);
+  return hipGetLastError();
+}
+
+}  // namespace gsc

@@ -1,0 +1,136 @@
+// k_train.hip -- per-pixel loss and its gradient (Eq. 4 or L2), the cached composite, and the
+// AdamW step (Method: "Optimization and Hyperparameters", "Natural Path Termination",
+// "Cascaded Cache Radiance Importance Sampling", Eq. 3).
+#include "gsc_dev.h"
+
+namespace gsc {
+
+namespace {
+
+constexpr int kLossThreads = 256;
+
+// One lane per pixel, all K levels and three channels.  Per-block loss partials in fp64,
+// summed afterwards in a fixed order.
+__global__ void __launch_bounds__(kLossThreads) loss_composite_kernel(
+    const float* __restrict__ images, const float* __restrict__ targets,
+    const uint32_t* __restrict__ records, int K, int64_t P, int loss, float inv_k,
+    float* __restrict__ dL, double* __restrict__ partials, float* __restrict__ composite) {
+  __shared__ double red[kLossThreads];
+  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  double acc = 0.0;
+  if (p < P) {
+    for (int l = 0; l < K; ++l) {
+      const int64_t base = 3 * ((int64_t)l * P + p);
+#pragma unroll
+      for (int c = 0; c < 3; ++c) {
+        const float y = images[base + c], x = targets[base + c];
+        const float diff = y - x;
+        float g;
+        if (loss == 1) {
+          const float dn = fmaxf(y, 0.0f) + 0.01f;
+          const float den = dn * dn;
+          acc += (double)((diff * diff) / den);
+          g = ((2.0f * diff) / den) * inv_k;
+        } else {
+          acc += (double)(diff * diff);
+          g = (2.0f * diff) * inv_k;
+        }
+        dL[base + c] = g;
+      }
+    }
+    if (composite) {
+      const uint32_t* rec = records + 5 * p;
+      const float L0 = __uint_as_float(rec[0]), L1 = __uint_as_float(rec[1]),
+                  L2 = __uint_as_float(rec[2]), beta = __uint_as_float(rec[3]);
+      const uint32_t n = rec[4] & 0xffffu, kind = rec[4] >> 16;
+      float o0 = 0.0f, o1 = 0.0f, o2 = 0.0f;
+      if (n >= 1u) {
+        const float lum = (0.2126f * L0 + 0.7152f * L1) + 0.0722f * L2;
+        const bool use_cache = (kind == (uint32_t)GSC_KIND_EARLY) || !(lum > 0.0f);
+        if (use_cache) {
+          const uint32_t lvl = (n < (uint32_t)K ? n : (uint32_t)K) - 1u;
+          const float* cv = images + 3 * ((int64_t)lvl * P + p);
+          o0 = fmaxf(cv[0], 0.0f) / beta;
+          o1 = fmaxf(cv[1], 0.0f) / beta;
+          o2 = fmaxf(cv[2], 0.0f) / beta;
+        } else {
+          o0 = L0; o1 = L1; o2 = L2;
+        }
+      }
+      composite[3 * p + 0] = o0;
+      composite[3 * p + 1] = o1;
+      composite[3 * p + 2] = o2;
+    }
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int off = kLossThreads / 2; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partials[blockIdx.x] = red[0];
+}
+
+__global__ void __launch_bounds__(256) loss_final_kernel(const double* __restrict__ partials, int n,
+                                                         float scale, float* __restrict__ loss_out) {
+  __shared__ double red[256];
+  double acc = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) acc += partials[i];
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int off = 128; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *loss_out = (float)(red[0] * (double)scale);
+}
+
+// AdamW, every operation separately rounded; skipped entirely when *guard is not finite.
+__global__ void __launch_bounds__(256) adam_kernel(float* __restrict__ param, float* __restrict__ m,
+                                                   float* __restrict__ v, const float* __restrict__ grad,
+                                                   int64_t n, float b1, float b2, float omb1,
+                                                   float omb2, float s1, float s2, float wdf,
+                                                   float eps, const float* __restrict__ guard) {
+  if (guard && !isfinite(*guard)) return;
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const float g = grad[i];
+  const float mn = b1 * m[i] + omb1 * g;
+  const float vn = b2 * v[i] + omb2 * (g * g);
+  float p = param[i] * wdf;
+  const float den = sqrtf(vn) * s2 + eps;
+  p = p - (s1 * mn) / den;
+  m[i] = mn;
+  v[i] = vn;
+  param[i] = p;
+}
+
+}  // namespace
+
+int loss_num_partials(int64_t pixels) { return (int)((pixels + kLossThreads - 1) / kLossThreads); }
+
+hipError_t launch_loss_composite(hipStream_t st, const float* images, const float* targets,
+                                 const void* records, int K, int w, int h, int loss,
+                                 float* dL_dimages, double* partials, float* loss_out,
+                                 float* composite) {
+  const int64_t P = (int64_t)w * h;
+  if (P == 0) return hipSuccess;
+  const int nb = loss_num_partials(P);
+  const float kf = (float)(3.0 * (double)P);
+  const float inv_k = 1.0f / kf;
+  hipLaunchKernelGGL(loss_composite_kernel, dim3(nb), dim3(kLossThreads), 0, st, images, targets,
+                     (const uint32_t*)records, K, P, loss, inv_k, dL_dimages, partials, composite);
+  hipLaunchKernelGGL(loss_final_kernel, dim3(1), dim3(256), 0, st, partials, nb, inv_k, loss_out);
+  return hipGetLastError();
+}
+
+hipError_t launch_adam(hipStream_t st, float* param, float* m, float* v, const float* grad,
+                       int64_t count, float b1, float b2, float omb1, float omb2, float s1,
+                       float s2, float wdf, float eps, const float* guard) {
+  if (count == 0) return hipSuccess;
+  hipLaunchKernelGGL(adam_kernel, dim3((unsigned)((count + 255) / 256)), dim3(256), 0, st, param, m,
+                     v, grad, count, b1, b2, omb1, omb2, s1, s2, wdf, eps, guard);
+  return hipGetLastError();
+}
+
+}  // namespace gsc

@@ -1,0 +1,1257 @@
+// runtime.hip -- host runtime behind the C ABI in include/gsc.h: contexts, device memory via the
+// caller's allocator hook, argument validation, descriptor tables, stage orchestration.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "gsc_internal.h"
+
+using namespace gsc;
+
+namespace {
+
+// ---------------------------------------------------------------------------------------------
+// Memory
+// ---------------------------------------------------------------------------------------------
+struct Alloc {
+  gsc_allocator hook{};
+  bool has = false;
+  void* get(size_t bytes) const {
+    if (bytes == 0) bytes = 256;
+    if (has) return hook.alloc(bytes, hook.user);
+    void* p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) return nullptr;
+    return p;
+  }
+  void put(void* p) const {
+    if (!p) return;
+    if (has) hook.release(p, hook.user);
+    else (void)hipFree(p);
+  }
+};
+
+struct DevBuf {
+  void* p = nullptr;
+  size_t cap = 0;
+  // Grow-only; contents are not preserved.
+  bool ensure(const Alloc& a, size_t bytes) {
+    if (bytes <= cap && p) return true;
+    a.put(p);
+    p = nullptr;
+    cap = 0;
+    size_t want = std::max<size_t>(bytes, 256);
+    p = a.get(want);
+    if (!p) return false;
+    cap = want;
+    return true;
+  }
+  void release(const Alloc& a) { a.put(p); p = nullptr; cap = 0; }
+  template <typename T> T* as() const { return (T*)p; }
+};
+
+struct Fail {
+  gsc_status st;
+};
+
+}  // namespace
+
+// ---------------------------------------------------------------------------------------------
+// Opaque objects
+// ---------------------------------------------------------------------------------------------
+struct gsc_binning {
+  Alloc alloc;
+  int S = 0;
+  int R = 0;                       // requests
+  std::vector<Seg> segs;
+  std::vector<DevCam> cams;
+  std::vector<int64_t> seg_gstart, seg_tstart;
+  int64_t G = 0, n_tiles = 0, pixels = 0;
+  int n_sort_blocks = 0;
+  int64_t bin_waves = 0, chunk_tiles = 0;
+  // device tables: [Seg x S][DevCam x R][int64 gstart x S][int64 tstart x S][sort table][bin work]
+  DevBuf tables;
+  size_t off_cams = 0, off_gstart = 0, off_tstart = 0, off_sort = 0, off_work = 0;
+  DevBuf rec, depth_key, rect, tiles, ids, keys_tmp, ids_tmp, hist, rect_sorted;
+  DevBuf counts, tile_total, partial, tile_start, ranges, scalars, values, n_contrib, grad2d;
+  uint64_t n_instances = 0;
+  uint64_t capacity = 0;
+  bool forward_done = false;
+  int K = 0;
+  int TX = 0, TY = 0;
+  // views
+  DevBuf view_window, view_screen;
+
+  const Seg* d_segs() const { return tables.as<Seg>(); }
+  const DevCam* d_cams() const { return (const DevCam*)((char*)tables.p + off_cams); }
+  const int64_t* d_gstart() const { return (const int64_t*)((char*)tables.p + off_gstart); }
+  const int64_t* d_tstart() const { return (const int64_t*)((char*)tables.p + off_tstart); }
+  const void* d_sort() const { return (char*)tables.p + off_sort; }
+  const void* d_work() const { return (char*)tables.p + off_work; }
+  uint64_t* d_ninst() const { return scalars.as<uint64_t>(); }
+
+  void free_all() {
+    DevBuf* all[] = {&tables, &rec, &depth_key, &rect, &tiles, &ids, &keys_tmp, &ids_tmp, &hist,
+                     &rect_sorted, &counts, &tile_total, &partial, &tile_start, &ranges, &scalars,
+                     &values, &n_contrib, &grad2d, &view_window, &view_screen};
+    for (DevBuf* b : all) b->release(alloc);
+  }
+};
+
+struct gsc_scene {
+  Alloc alloc;
+  int K = 0;
+  std::vector<int64_t> n;
+  std::vector<float*> params;      // per level: [pos 3n][rot 4n][ls 3n][rgb 3n][logit n]
+  std::vector<float*> m, v;
+  std::vector<int64_t> step;       // Adam steps taken per level
+  float* density = nullptr;
+  int32_t nx = 0, ny = 0, nz = 0;
+  float dmax = 1.0f;
+  std::vector<float> tf, lights;
+};
+
+struct gsc_ctx {
+  int device = 0;
+  hipStream_t stream = nullptr;
+  hipStream_t side = nullptr;      // tracer stream (default priority)
+  Alloc alloc;
+  std::string err;
+  bool sticky = false;
+  uint64_t required = 0;
+  int deterministic = 0;
+  // pinned staging ring for descriptor uploads
+  char* pinned = nullptr;
+  size_t pinned_cap = 0, pinned_head = 0;
+  hipEvent_t upload_ev = nullptr;
+  bool upload_pending = false;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  hipEvent_t tev[8] = {};
+  // frame workspace
+  gsc_binning* frame_bin = nullptr;
+  DevBuf targets, records, dL, partials, losses, grads14, images, final_T, last_id, trace_tab,
+      vertices, composite_tmp;
+  uint64_t* host_u64 = nullptr;    // pinned scalars for readback
+  // per-kernel event timing (gsc_ctx_profile)
+  bool prof_on = false;
+  struct ProfRec { int id; hipEvent_t a, b; };
+  std::vector<ProfRec> prof_pending;
+  std::vector<hipEvent_t> ev_pool;
+  double prof_ms[16] = {};
+  int64_t prof_n[16] = {};
+  uint64_t acc_instances = 0, acc_frames = 0;
+};
+
+namespace {
+
+#define GSC_TRY(expr)                                                     \
+  do {                                                                    \
+    hipError_t e_ = (expr);                                               \
+    if (e_ != hipSuccess) throw_hip(ctx, e_, #expr, __LINE__);            \
+  } while (0)
+
+[[noreturn]] void throw_hip(gsc_ctx* ctx, hipError_t e, const char* what, int line) {
+  char buf[512];
+  snprintf(buf, sizeof(buf), "HIP error %d (%s) at runtime.hip:%d: %s", (int)e,
+           hipGetErrorString(e), line, what);
+  ctx->err = buf;
+  ctx->sticky = true;
+  throw Fail{GSC_E_DEVICE};
+}
+
+[[noreturn]] void invalid(gsc_ctx* ctx, const std::string& msg) {
+  ctx->err = msg;
+  throw Fail{GSC_E_INVALID_ARG};
+}
+
+[[noreturn]] void oom(gsc_ctx* ctx, const char* what, size_t bytes) {
+  char buf[256];
+  snprintf(buf, sizeof(buf), "allocation of %zu bytes for %s failed", bytes, what);
+  ctx->err = buf;
+  throw Fail{GSC_E_OUT_OF_MEMORY};
+}
+
+void need(gsc_ctx* ctx, DevBuf& b, const Alloc& a, size_t bytes, const char* what) {
+  if (!b.ensure(a, bytes)) oom(ctx, what, bytes);
+}
+
+template <typename F>
+gsc_status guarded(gsc_ctx* ctx, F&& f) {
+  if (!ctx) return GSC_E_INVALID_ARG;
+  if (ctx->sticky) return GSC_E_DEVICE;
+  try {
+    ctx->err.clear();
+    GSC_TRY(hipSetDevice(ctx->device));
+    return f();
+  } catch (const Fail& fl) {
+    return fl.st;
+  } catch (const std::bad_alloc&) {
+    ctx->err = "host allocation failed";
+    return GSC_E_OUT_OF_MEMORY;
+  } catch (...) {
+    ctx->err = "unexpected exception";
+    return GSC_E_DEVICE;
+  }
+}
+
+// Copies host bytes to device through the pinned ring, on the context stream.
+void upload(gsc_ctx* ctx, void* dst, const void* src, size_t bytes) {
+  if (bytes == 0) return;
+  if (bytes > ctx->pinned_cap) {
+    // Rare: very large tables go through a synchronous copy.
+    GSC_TRY(hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, ctx->stream));
+    GSC_TRY(hipStreamSynchronize(ctx->stream));
+    return;
+  }
+  size_t off = (ctx->pinned_head + 255) & ~size_t(255);
+  if (off + bytes > ctx->pinned_cap) {
+    if (ctx->upload_pending) GSC_TRY(hipEventSynchronize(ctx->upload_ev));
+    off = 0;
+  }
+  std::memcpy(ctx->pinned + off, src, bytes);
+  GSC_TRY(hipMemcpyAsync(dst, ctx->pinned + off, bytes, hipMemcpyHostToDevice, ctx->stream));
+  GSC_TRY(hipEventRecord(ctx->upload_ev, ctx->stream));
+  ctx->upload_pending = true;
+  ctx->pinned_head = off + bytes;
+}
+
+uint64_t read_u64(gsc_ctx* ctx, const uint64_t* dev) {
+  GSC_TRY(hipMemcpyAsync(ctx->host_u64, dev, sizeof(uint64_t), hipMemcpyDeviceToHost, ctx->stream));
+  GSC_TRY(hipStreamSynchronize(ctx->stream));
+  return ctx->host_u64[0];
+}
+
+const char* const kProfNames[] = {"project", "depth_sort", "bin_count", "bin_scan", "bin_place",
+                                  "splat_forward", "trace", "loss_composite", "splat_backward",
+                                  "project_backward", "adam", "gather_rect"};
+constexpr int kProfCount = 12;
+enum { P_PROJECT, P_SORT, P_COUNT, P_SCAN, P_PLACE, P_FWD, P_TRACE, P_LOSS, P_BWD, P_PBWD, P_ADAM,
+       P_GATHER };
+
+hipEvent_t pool_event(gsc_ctx* ctx) {
+  if (!ctx->ev_pool.empty()) {
+    hipEvent_t e = ctx->ev_pool.back();
+    ctx->ev_pool.pop_back();
+    return e;
+  }
+  hipEvent_t e;
+  GSC_TRY(hipEventCreate(&e));
+  return e;
+}
+
+// Records HIP events around one launch on its own stream when profiling is on.
+struct ProfScope {
+  gsc_ctx* ctx;
+  hipStream_t st;
+  int id;
+  hipEvent_t a = nullptr;
+  ProfScope(gsc_ctx* c, int i, hipStream_t s) : ctx(c), st(s), id(i) {
+    if (ctx->prof_on) {
+      a = pool_event(ctx);
+      GSC_TRY(hipEventRecord(a, st));
+    }
+  }
+  ~ProfScope() {
+    if (!a) return;
+    hipEvent_t b = nullptr;
+    if (!ctx->ev_pool.empty()) { b = ctx->ev_pool.back(); ctx->ev_pool.pop_back(); }
+    else if (hipEventCreate(&b) != hipSuccess) b = nullptr;
+    if (b && hipEventRecord(b, st) == hipSuccess) ctx->prof_pending.push_back({id, a, b});
+    else { ctx->ev_pool.push_back(a); if (b) ctx->ev_pool.push_back(b); }
+  }
+};
+
+void prof_resolve(gsc_ctx* ctx) {
+  for (auto& p : ctx->prof_pending) {
+    GSC_TRY(hipEventSynchronize(p.b));
+    float ms = 0.0f;
+    GSC_TRY(hipEventElapsedTime(&ms, p.a, p.b));
+    ctx->prof_ms[p.id] += (double)ms;
+    ctx->prof_n[p.id] += 1;
+    ctx->ev_pool.push_back(p.a);
+    ctx->ev_pool.push_back(p.b);
+  }
+  ctx->prof_pending.clear();
+}
+
+DevCam to_dev(const gsc_camera& c) {
+  DevCam d;
+  std::memcpy(d.R, c.R, sizeof(d.R));
+  std::memcpy(d.t, c.t, sizeof(d.t));
+  d.fx = c.fx; d.fy = c.fy; d.cx = c.cx; d.cy = c.cy;
+  d.full_w = c.full_w; d.full_h = c.full_h;
+  d.x0 = c.x0; d.y0 = c.y0; d.w = c.w; d.h = c.h;
+  d.znear = c.znear;
+  return d;
+}
+
+void check_camera(gsc_ctx* ctx, const gsc_camera* c) {
+  if (!c) invalid(ctx, "camera is NULL");
+  if (c->w < 1 || c->h < 1 || c->w > 16384 || c->h > 16384) invalid(ctx, "camera window size out of range");
+  if (c->full_w < 1 || c->full_h < 1 || c->full_w > 65535 || c->full_h > 65535) invalid(ctx, "full frame size out of range");
+  if (c->x0 < 0 || c->y0 < 0 || c->x0 + c->w > c->full_w || c->y0 + c->h > c->full_h)
+    invalid(ctx, "camera window outside the full frame");
+  if (!(c->fx > 0.0f) || !(c->fy > 0.0f) || !std::isfinite(c->cx) || !std::isfinite(c->cy))
+    invalid(ctx, "camera intrinsics invalid");
+  for (float r : c->R) if (!std::isfinite(r)) invalid(ctx, "camera rotation not finite");
+  for (float t : c->t) if (!std::isfinite(t)) invalid(ctx, "camera translation not finite");
+  if (!(c->znear > 0.0f)) invalid(ctx, "znear must be positive");
+}
+
+void check_levels(gsc_ctx* ctx, const gsc_gaussians* lv, int K) {
+  if (K < 1 || K > 8) invalid(ctx, "num_levels must be in [1, 8]");
+  if (!lv) invalid(ctx, "levels is NULL");
+  for (int l = 0; l < K; ++l) {
+    if (lv[l].n < 0 || lv[l].n >= (int64_t(1) << 31)) invalid(ctx, "level size out of range");
+    if (lv[l].n > 0 && (!lv[l].pos || !lv[l].rot || !lv[l].log_scale || !lv[l].rgb || !lv[l].opacity_logit))
+      invalid(ctx, "level parameter pointer is NULL");
+  }
+}
+
+// One request of a batch: a camera and K levels.
+struct ReqSpec {
+  gsc_camera cam;
+  std::vector<gsc_gaussians> levels;
+};
+
+// Builds (or rebuilds) a binning object's tables for a list of requests and uploads them.
+void plan_batch(gsc_ctx* ctx, gsc_binning* b, const std::vector<ReqSpec>& reqs) {
+  b->segs.clear();
+  b->cams.clear();
+  b->seg_gstart.clear();
+  b->seg_tstart.clear();
+  int64_t g = 0, tiles = 0, pix = 0;
+  for (size_t r = 0; r < reqs.size(); ++r) {
+    const gsc_camera& c = reqs[r].cam;
+    b->cams.push_back(to_dev(c));
+    const int TX = (c.w + kTile - 1) / kTile, TY = (c.h + kTile - 1) / kTile;
+    for (size_t l = 0; l < reqs[r].levels.size(); ++l) {
+      const gsc_gaussians& lv = reqs[r].levels[l];
+      Seg s{};
+      s.pos = lv.pos; s.rot = lv.rot; s.ls = lv.log_scale; s.rgb = lv.rgb; s.logit = lv.opacity_logit;
+      s.n = lv.n;
+      s.g_off = g;
+      s.tile_base = tiles;
+      s.pix_off = pix;
+      s.cam = (int32_t)r;
+      s.TX = TX; s.TY = TY;
+      s.level = (int32_t)l;
+      s.request = (int32_t)r;
+      s.n_chunks = (int32_t)((lv.n + kChunk - 1) / kChunk);
+      b->segs.push_back(s);
+      b->seg_gstart.push_back(g);
+      b->seg_tstart.push_back(tiles);
+      g += lv.n;
+      tiles += (int64_t)TX * TY;
+      pix += (int64_t)c.w * c.h;
+    }
+  }
+  b->S = (int)b->segs.size();
+  b->R = (int)reqs.size();
+  b->G = g;
+  b->n_tiles = tiles;
+  b->pixels = pix;
+  std::vector<int64_t> seg_n(b->S), seg_off(b->S);
+  for (int s = 0; s < b->S; ++s) { seg_n[s] = b->segs[s].n; seg_off[s] = b->segs[s].g_off; }
+  b->n_sort_blocks = sort_count_blocks(seg_n.data(), b->S);
+  auto al = [](size_t x) { return (x + 255) & ~size_t(255); };
+  size_t off = al(sizeof(Seg) * b->S);
+  b->off_cams = off;
+  off = al(off + sizeof(DevCam) * b->R);
+  b->off_gstart = off;
+  off = al(off + sizeof(int64_t) * b->S);
+  b->off_tstart = off;
+  off = al(off + sizeof(int64_t) * b->S);
+  b->off_sort = off;
+  off = al(off + sort_table_bytes(b->n_sort_blocks, b->S));
+  b->off_work = off;
+  off = al(off + bin_work_bytes(b->S));
+  std::vector<char> host(off, 0);
+  std::memcpy(host.data(), b->segs.data(), sizeof(Seg) * b->S);
+  std::memcpy(host.data() + b->off_cams, b->cams.data(), sizeof(DevCam) * b->R);
+  std::memcpy(host.data() + b->off_gstart, b->seg_gstart.data(), sizeof(int64_t) * b->S);
+  std::memcpy(host.data() + b->off_tstart, b->seg_tstart.data(), sizeof(int64_t) * b->S);
+  sort_fill_table(host.data() + b->off_sort, seg_n.data(), seg_off.data(), b->S);
+  b->bin_waves = bin_fill_work(host.data() + b->off_work, b->segs.data(), b->S, &b->chunk_tiles);
+  need(ctx, b->tables, b->alloc, off, "descriptor tables");
+  upload(ctx, b->tables.p, host.data(), off);
+  b->forward_done = false;
+}
+
+// Projection, depth sort and binning of a planned batch.  capacity_hint 0: exact sizing with one
+// read-back of the instance count.
+gsc_status run_project_bin(gsc_ctx* ctx, gsc_binning* b, uint64_t capacity_hint) {
+  const Alloc& a = b->alloc;
+  const int64_t G = b->G;
+  const int64_t Gp = std::max<int64_t>(G, 1);
+  need(ctx, b->rec, a, sizeof(SplatRec) * Gp, "projected records");
+  need(ctx, b->depth_key, a, 4 * Gp, "depth keys");
+  need(ctx, b->rect, a, 8 * Gp, "tile rects");
+  need(ctx, b->tiles, a, 4 * Gp, "tiles touched");
+  need(ctx, b->ids, a, 4 * Gp, "ids");
+  need(ctx, b->keys_tmp, a, 4 * Gp, "sort keys");
+  need(ctx, b->ids_tmp, a, 4 * Gp, "sort values");
+  need(ctx, b->hist, a, 4 * 256 * (size_t)std::max(b->n_sort_blocks, 1), "sort histograms");
+  need(ctx, b->rect_sorted, a, 8 * Gp, "sorted rects");
+  need(ctx, b->counts, a, 4 * (size_t)std::max<int64_t>(b->chunk_tiles, 1), "chunk counts");
+  need(ctx, b->tile_total, a, 4 * (size_t)std::max<int64_t>(b->n_tiles, 1), "tile totals");
+  need(ctx, b->partial, a, 8 * bin_scan_partials(b->n_tiles), "scan partials");
+  need(ctx, b->tile_start, a, 8 * (size_t)std::max<int64_t>(b->n_tiles, 1), "tile starts");
+  need(ctx, b->ranges, a, 16 * (size_t)std::max<int64_t>(b->n_tiles, 1), "tile ranges");
+  need(ctx, b->scalars, a, 64, "scalars");
+  hipStream_t st = ctx->stream;
+  GSC_TRY(hipMemsetAsync(b->scalars.p, 0, 64, st));
+  { ProfScope ps_(ctx, P_PROJECT, st);
+  GSC_TRY(launch_project(st, b->d_segs(), b->d_gstart(), b->S, b->d_cams(), G, b->rec.as<SplatRec>(),
+                         b->depth_key.as<uint32_t>(), b->rect.as<uint64_t>(), b->tiles.as<uint32_t>(),
+                         b->ids.as<uint32_t>()));
+  }
+  // The sort consumes a copy of the depth keys (the originals serve the key view); the odd
+  // passes of the sort use rect_sorted as key scratch before the gather fills it.
+  GSC_TRY(hipMemcpyAsync(b->keys_tmp.p, b->depth_key.p, 4 * G, hipMemcpyDeviceToDevice, st));
+  { ProfScope ps_(ctx, P_SORT, st);
+  GSC_TRY(launch_segmented_sort(st, b->d_sort(), b->n_sort_blocks, b->S, b->keys_tmp.as<uint32_t>(),
+                                b->ids.as<uint32_t>(), b->rect_sorted.as<uint32_t>(),
+                                b->ids_tmp.as<uint32_t>(), b->hist.as<uint32_t>()));
+  }
+  { ProfScope ps_(ctx, P_GATHER, st);
+  GSC_TRY(launch_gather_rect(st, b->d_gstart(), b->S, G, b->ids.as<uint32_t>(), b->rect.as<uint64_t>(),
+                             b->rect_sorted.as<uint64_t>()));
+  }
+  { ProfScope ps_(ctx, P_COUNT, st);
+  GSC_TRY(launch_bin_count(st, b->d_work(), b->S, b->bin_waves, b->ids.as<uint32_t>(),
+                           b->rect_sorted.as<uint64_t>(), b->counts.as<uint32_t>()));
+  }
+  { ProfScope ps_(ctx, P_SCAN, st);
+  GSC_TRY(launch_bin_scan(st, b->d_work(), b->S, b->d_tstart(), b->n_tiles, b->counts.as<uint32_t>(),
+                          b->tile_total.as<uint32_t>(), b->partial.as<uint64_t>(),
+                          b->tile_start.as<uint64_t>(), b->ranges.as<uint64_t>(), b->d_ninst()));
+  }
+  uint64_t cap = capacity_hint;
+  uint64_t n_inst = 0;
+  if (cap == 0) {
+    n_inst = read_u64(ctx, b->d_ninst());
+    cap = n_inst;
+  }
+  need(ctx, b->values, a, 4 * (size_t)std::max<uint64_t>(cap, 1), "instance values");
+  b->capacity = cap;
+  { ProfScope ps_(ctx, P_PLACE, st);
+  GSC_TRY(launch_bin_place(st, b->d_work(), b->S, b->bin_waves, b->ids.as<uint32_t>(),
+                           b->rect_sorted.as<uint64_t>(), b->counts.as<uint32_t>(),
+                           b->tile_start.as<uint64_t>(), b->d_ninst(), cap, b->values.as<uint32_t>()));
+  }
+  if (capacity_hint != 0) n_inst = read_u64(ctx, b->d_ninst());
+  b->n_instances = n_inst;
+  ctx->acc_instances += n_inst;
+  ctx->acc_frames += 1;
+  if (n_inst > cap) {
+    ctx->required = n_inst;
+    char buf[160];
+    snprintf(buf, sizeof(buf), "instance capacity %llu exceeded: %llu needed",
+             (unsigned long long)cap, (unsigned long long)n_inst);
+    ctx->err = buf;
+    return GSC_E_CAPACITY;
+  }
+  return GSC_OK;
+}
+
+void run_forward(gsc_ctx* ctx, gsc_binning* b, float* images, float* final_T, int32_t* last_id) {
+  need(ctx, b->n_contrib, b->alloc, 4 * (size_t)std::max<int64_t>(b->pixels, 1), "n_contrib");
+  { ProfScope ps_(ctx, P_FWD, ctx->stream);
+  GSC_TRY(launch_splat_forward(ctx->stream, b->d_segs(), b->d_tstart(), b->S, b->d_cams(), b->n_tiles,
+                               b->ranges.as<uint64_t>(), b->values.as<uint32_t>(),
+                               b->rec.as<SplatRec>(), images, final_T, last_id,
+                               b->n_contrib.as<uint32_t>()));
+  }
+  b->forward_done = true;
+}
+
+void run_backward(gsc_ctx* ctx, gsc_binning* b, const float* final_T, const float* dL,
+                  float* grads14) {
+  need(ctx, b->grad2d, b->alloc, 4 * 9 * (size_t)std::max<int64_t>(b->G, 1), "2D gradients");
+  GSC_TRY(hipMemsetAsync(b->grad2d.p, 0, 4 * 9 * (size_t)b->G, ctx->stream));
+  { ProfScope ps_(ctx, P_BWD, ctx->stream);
+  GSC_TRY(launch_splat_backward(ctx->stream, b->d_segs(), b->d_tstart(), b->S, b->d_cams(), b->n_tiles,
+                                b->ranges.as<uint64_t>(), b->values.as<uint32_t>(),
+                                b->rec.as<SplatRec>(), final_T, b->n_contrib.as<uint32_t>(), dL,
+                                b->grad2d.as<float>(), b->G, ctx->deterministic));
+  }
+  { ProfScope ps_(ctx, P_PBWD, ctx->stream);
+  GSC_TRY(launch_project_backward(ctx->stream, b->d_segs(), b->d_gstart(), b->S, b->d_cams(), b->G,
+                                  b->grad2d.as<float>(), grads14));
+  }
+}
+
+
+float max_alpha(const float* tf, int P) {
+  float m = 0.0f;
+  for (int i = 0; i < P; ++i) m = std::fmax(m, tf[4 * i + 3]);
+  return m;
+}
+
+void check_volume_host(gsc_ctx* ctx, const float* tf, int P, const float* lights, int nl) {
+  if (P < 2 || P > kMaxTf) invalid(ctx, "tf_points must be in [2, 64]");
+  if (nl < 1 || nl > kMaxLights) invalid(ctx, "n_lights must be in [1, 8]");
+  if (!tf || !lights) invalid(ctx, "tf_rgba / lights is NULL");
+  for (int i = 0; i < 4 * P; ++i) if (!std::isfinite(tf[i])) invalid(ctx, "transfer function not finite");
+  if (!(max_alpha(tf, P) > 0.0f)) invalid(ctx, "transfer function opacity is zero everywhere (no majorant)");
+  for (int i = 0; i < 6 * nl; ++i) if (!std::isfinite(lights[i])) invalid(ctx, "lights not finite");
+}
+
+TraceDesc make_trace_desc(const float* density, int nx, int ny, int nz, float dmax, const float* tf,
+                          int P, const float* lights, int nl, const gsc_camera& cam,
+                          const gsc_trace_params& tp) {
+  TraceDesc d;
+  std::memset(&d, 0, sizeof(d));
+  d.density = density;
+  d.nx = nx; d.ny = ny; d.nz = nz;
+  d.dmax = dmax;
+  d.majorant = dmax * max_alpha(tf, P);
+  d.P = P;
+  d.n_lights = nl;
+  std::memcpy(d.tf, tf, sizeof(float) * 4 * P);
+  std::memcpy(d.lights, lights, sizeof(float) * 6 * nl);
+  d.cam = to_dev(cam);
+  d.seed = tp.seed;
+  d.frame = tp.frame;
+  d.spp = tp.spp;
+  d.max_bounces = tp.max_bounces;
+  d.K = tp.num_levels;
+  d.C = tp.C;
+  d.C_inf = tp.C_inf;
+  d.eps = tp.eps;
+  return d;
+}
+
+void check_trace_params(gsc_ctx* ctx, const gsc_trace_params* tp) {
+  if (!tp) invalid(ctx, "trace params NULL");
+  if (tp->spp < 1) invalid(ctx, "spp must be >= 1");
+  if (tp->max_bounces < 1) invalid(ctx, "max_bounces must be >= 1");
+  if (tp->num_levels < 1 || tp->num_levels > 8) invalid(ctx, "num_levels must be in [1, 8]");
+  if (!tp->C_inf && !std::isfinite(tp->C)) invalid(ctx, "C must be finite unless C_inf is set");
+  if (!std::isfinite(tp->eps) || tp->eps < 0.0f) invalid(ctx, "eps must be finite and >= 0");
+}
+
+void adam_group(gsc_ctx* ctx, float* p, float* m, float* v, const float* g, int64_t count, double lr,
+                double b1, double b2, double eps, double wd, int64_t step, const float* guard) {
+  const float s1 = (float)(lr / (1.0 - std::pow(b1, (double)step)));
+  const float s2 = (float)(1.0 / std::sqrt(1.0 - std::pow(b2, (double)step)));
+  const float wdf = (float)(1.0 - lr * wd);
+  { ProfScope ps_(ctx, P_ADAM, ctx->stream);
+  GSC_TRY(launch_adam(ctx->stream, p, m, v, g, count, (float)b1, (float)b2, (float)(1.0 - b1),
+                      (float)(1.0 - b2), s1, s2, wdf, (float)eps, guard));
+  }
+}
+
+double elapsed(hipEvent_t a, hipEvent_t b) {
+  float ms = 0.0f;
+  if (hipEventElapsedTime(&ms, a, b) != hipSuccess) return 0.0;
+  return (double)ms;
+}
+
+// The frame pipeline over a batch of (distinct) scenes.
+gsc_status render_batch(gsc_ctx* ctx, gsc_scene* const* scenes, const gsc_frame_request* reqs,
+                        float* const* images, int n, gsc_frame_stats* stats) {
+  if (n < 1) invalid(ctx, "batch is empty");
+  if (!scenes || !reqs || !images) invalid(ctx, "NULL argument");
+  for (int i = 0; i < n; ++i) {
+    if (!scenes[i]) invalid(ctx, "scene is NULL");
+    if (!images[i]) invalid(ctx, "image is NULL");
+    for (int j = 0; j < i; ++j) if (scenes[j] == scenes[i]) invalid(ctx, "scenes of a batch must be distinct");
+    check_camera(ctx, &reqs[i].cam);
+    check_trace_params(ctx, &reqs[i].trace);
+    if ((int)reqs[i].trace.num_levels != scenes[i]->K) invalid(ctx, "trace.num_levels must equal the scene's K");
+    if (reqs[i].trace.spp != 1) invalid(ctx, "frames trace 1 sample per pixel");
+    if (reqs[i].loss != 0 && reqs[i].loss != 1) invalid(ctx, "loss must be 0 (L2) or 1 (HDR)");
+    if (reqs[i].viewport_frames < 1) invalid(ctx, "viewport_frames must be >= 1");
+  }
+  hipStream_t st = ctx->stream;
+  const bool timing = stats != nullptr;
+  if (timing) GSC_TRY(hipEventRecord(ctx->tev[0], st));
+  // ---- plan -----------------------------------------------------------------------------------
+  if (!ctx->frame_bin) {
+    ctx->frame_bin = new gsc_binning();
+    ctx->frame_bin->alloc = ctx->alloc;
+  }
+  gsc_binning* b = ctx->frame_bin;
+  std::vector<ReqSpec> specs(n);
+  std::vector<int64_t> pix_base(n), rec_base(n);
+  int64_t pix = 0, rpix = 0;
+  for (int i = 0; i < n; ++i) {
+    specs[i].cam = reqs[i].cam;
+    gsc_scene* sc = scenes[i];
+    for (int l = 0; l < sc->K; ++l) {
+      gsc_gaussians lv;
+      float* p = sc->params[l];
+      const int64_t nn = sc->n[l];
+      lv.pos = p; lv.rot = p + 3 * nn; lv.log_scale = p + 7 * nn; lv.rgb = p + 10 * nn;
+      lv.opacity_logit = p + 13 * nn; lv.n = nn;
+      specs[i].levels.push_back(lv);
+    }
+    pix_base[i] = pix;
+    rec_base[i] = rpix;
+    pix += (int64_t)sc->K * reqs[i].cam.w * reqs[i].cam.h;
+    rpix += (int64_t)reqs[i].cam.w * reqs[i].cam.h;
+  }
+  plan_batch(ctx, b, specs);
+  const Alloc& a = ctx->alloc;
+  need(ctx, ctx->images, a, 12 * (size_t)pix, "cache images");
+  need(ctx, ctx->targets, a, 12 * (size_t)pix, "targets");
+  need(ctx, ctx->dL, a, 12 * (size_t)pix, "dL/dimages");
+  need(ctx, ctx->final_T, a, 4 * (size_t)pix, "final T");
+  need(ctx, ctx->last_id, a, 4 * (size_t)pix, "last id");
+  need(ctx, ctx->records, a, sizeof(gsc_path_record) * (size_t)rpix, "records");
+  int max_partials = 1;
+  for (int i = 0; i < n; ++i) max_partials = std::max(max_partials, loss_num_partials((int64_t)reqs[i].cam.w * reqs[i].cam.h));
+  need(ctx, ctx->partials, a, 8 * (size_t)max_partials * n, "loss partials");
+  need(ctx, ctx->losses, a, 4 * (size_t)n, "losses");
+  need(ctx, ctx->grads14, a, 4 * 14 * (size_t)std::max<int64_t>(b->G, 1), "parameter gradients");
+  need(ctx, ctx->vertices, a, 8, "vertex counter");
+  // ---- trace on the side stream (independent of the cache) --------------------------------------
+  std::vector<TraceDesc> td(n);
+  std::vector<int64_t> tstart(n);
+  for (int i = 0; i < n; ++i) {
+    gsc_scene* sc = scenes[i];
+    td[i] = make_trace_desc(sc->density, sc->nx, sc->ny, sc->nz, sc->dmax, sc->tf.data(),
+                            (int)sc->tf.size() / 4, sc->lights.data(), (int)sc->lights.size() / 6,
+                            reqs[i].cam, reqs[i].trace);
+    td[i].pix_off = rec_base[i];
+    td[i].targets = ctx->targets.as<float>() + 3 * pix_base[i];
+    td[i].records = (char*)ctx->records.p + sizeof(gsc_path_record) * rec_base[i];
+    tstart[i] = rec_base[i];
+  }
+  const size_t tbytes = sizeof(TraceDesc) * n + sizeof(int64_t) * n;
+  need(ctx, ctx->trace_tab, a, tbytes, "trace descriptors");
+  std::vector<char> th(tbytes);
+  std::memcpy(th.data(), td.data(), sizeof(TraceDesc) * n);
+  std::memcpy(th.data() + sizeof(TraceDesc) * n, tstart.data(), sizeof(int64_t) * n);
+  upload(ctx, ctx->trace_tab.p, th.data(), tbytes);
+  GSC_TRY(hipMemsetAsync(ctx->vertices.p, 0, 8, st));
+  GSC_TRY(hipEventRecord(ctx->ev_fork, st));
+  GSC_TRY(hipStreamWaitEvent(ctx->side, ctx->ev_fork, 0));
+  if (timing) GSC_TRY(hipEventRecord(ctx->tev[6], ctx->side));
+  { ProfScope ps_(ctx, P_TRACE, ctx->side);
+  GSC_TRY(launch_trace(ctx->side, ctx->trace_tab.as<TraceDesc>(),
+                       (const int64_t*)((char*)ctx->trace_tab.p + sizeof(TraceDesc) * n), n, rpix,
+                       ctx->vertices.as<unsigned long long>()));
+  }
+  if (timing) GSC_TRY(hipEventRecord(ctx->tev[7], ctx->side));
+  GSC_TRY(hipEventRecord(ctx->ev_join, ctx->side));
+  // ---- splat the cache images ---------------------------------------------------------------------
+  gsc_status s = run_project_bin(ctx, b, 0);
+  if (s != GSC_OK) {
+    GSC_TRY(hipStreamWaitEvent(st, ctx->ev_join, 0));
+    return s;
+  }
+  if (timing) GSC_TRY(hipEventRecord(ctx->tev[1], st));
+  run_forward(ctx, b, ctx->images.as<float>(), ctx->final_T.as<float>(), ctx->last_id.as<int32_t>());
+  if (timing) GSC_TRY(hipEventRecord(ctx->tev[2], st));
+  GSC_TRY(hipStreamWaitEvent(st, ctx->ev_join, 0));
+  // ---- loss, composite ----------------------------------------------------------------------------
+  for (int i = 0; i < n; ++i) {
+    const int w = reqs[i].cam.w, h = reqs[i].cam.h;
+  { ProfScope ps_(ctx, P_LOSS, st);
+  GSC_TRY(launch_loss_composite(st, ctx->images.as<float>() + 3 * pix_base[i],
+                                  ctx->targets.as<float>() + 3 * pix_base[i],
+                                  (char*)ctx->records.p + sizeof(gsc_path_record) * rec_base[i],
+                                  scenes[i]->K, w, h, reqs[i].loss,
+                                  ctx->dL.as<float>() + 3 * pix_base[i],
+                                  ctx->partials.as<double>() + (size_t)max_partials * i,
+                                  ctx->losses.as<float>() + i, images[i]));
+  }
+  }
+  if (timing) GSC_TRY(hipEventRecord(ctx->tev[3], st));
+  // ---- backward + AdamW ---------------------------------------------------------------------------
+  bool any_train = false;
+  for (int i = 0; i < n; ++i) any_train = any_train || reqs[i].train;
+  if (any_train) {
+    run_backward(ctx, b, ctx->final_T.as<float>(), ctx->dL.as<float>(), ctx->grads14.as<float>());
+    if (timing) GSC_TRY(hipEventRecord(ctx->tev[4], st));
+    int si = 0;
+    for (int i = 0; i < n; ++i) {
+      gsc_scene* sc = scenes[i];
+      const double eta = 1.0 / (1.0 + std::log((double)reqs[i].viewport_frames));
+      for (int l = 0; l < sc->K; ++l, ++si) {
+        if (!reqs[i].train) continue;
+        const Seg& sg = b->segs[si];
+        const int64_t nn = sc->n[l];
+        if (nn == 0) continue;
+        const int64_t step = sc->step[l] + 1;
+        float* g = ctx->grads14.as<float>() + 14 * sg.g_off;
+        const int64_t off[6] = {0, 3 * nn, 7 * nn, 10 * nn, 13 * nn, 14 * nn};
+        for (int grp = 0; grp < 5; ++grp) {
+          adam_group(ctx, sc->params[l] + off[grp], sc->m[l] + off[grp], sc->v[l] + off[grp],
+                     g + off[grp], off[grp + 1] - off[grp], (double)reqs[i].lr[grp] * eta,
+                     reqs[i].beta1, reqs[i].beta2, reqs[i].eps, reqs[i].weight_decay, step,
+                     ctx->losses.as<float>() + i);
+        }
+        sc->step[l] = step;
+      }
+    }
+  } else if (timing) {
+    GSC_TRY(hipEventRecord(ctx->tev[4], st));
+  }
+  if (timing) {
+    GSC_TRY(hipEventRecord(ctx->tev[5], st));
+    std::vector<float> losses(n);
+    GSC_TRY(hipMemcpyAsync(losses.data(), ctx->losses.p, 4 * n, hipMemcpyDeviceToHost, st));
+    GSC_TRY(hipMemcpyAsync(ctx->host_u64 + 1, ctx->vertices.p, 8, hipMemcpyDeviceToHost, st));
+    GSC_TRY(hipStreamSynchronize(st));
+    for (int i = 0; i < n; ++i) {
+      gsc_frame_stats& fs = stats[i];
+      std::memset(&fs, 0, sizeof(fs));
+      fs.ms_project_bin = elapsed(ctx->tev[0], ctx->tev[1]);
+      fs.ms_forward = elapsed(ctx->tev[1], ctx->tev[2]);
+      fs.ms_trace = elapsed(ctx->tev[6], ctx->tev[7]);
+      fs.ms_loss = elapsed(ctx->tev[2], ctx->tev[3]);
+      fs.ms_backward = any_train ? elapsed(ctx->tev[3], ctx->tev[4]) : 0.0;
+      fs.ms_adam = any_train ? elapsed(ctx->tev[4], ctx->tev[5]) : 0.0;
+      fs.ms_total = elapsed(ctx->tev[0], ctx->tev[5]);
+      int64_t gi = 0;
+      for (int l = 0; l < scenes[i]->K; ++l) gi += scenes[i]->n[l];
+      fs.gaussians = (uint64_t)gi;
+      fs.instances = b->n_instances;
+      fs.tiles = (uint64_t)b->n_tiles;
+      fs.pixels = (uint64_t)reqs[i].cam.w * reqs[i].cam.h;
+      fs.paths = fs.pixels;
+      fs.path_vertices = ctx->host_u64[1];
+      fs.loss = (double)losses[i];
+      fs.adam_skipped = (reqs[i].train && !std::isfinite(losses[i])) ? 1 : 0;
+    }
+  }
+  return GSC_OK;
+}
+
+}  // namespace
+
+// =============================================================================================
+// C ABI
+// =============================================================================================
+extern "C" {
+
+gsc_status gsc_ctx_create(int device, void* hip_stream, const gsc_allocator* alloc, gsc_ctx** out) {
+  if (!out) return GSC_E_INVALID_ARG;
+  *out = nullptr;
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || count < 1) return GSC_E_DEVICE;
+  if (device < 0 || device >= count) return GSC_E_INVALID_ARG;
+  if (alloc && (!alloc->alloc || !alloc->release)) return GSC_E_INVALID_ARG;
+  gsc_ctx* c = new (std::nothrow) gsc_ctx();
+  if (!c) return GSC_E_OUT_OF_MEMORY;
+  c->device = device;
+  c->stream = (hipStream_t)hip_stream;
+  if (alloc) { c->alloc.hook = *alloc; c->alloc.has = true; }
+  bool ok = hipSetDevice(device) == hipSuccess;
+  ok = ok && hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking) == hipSuccess;
+  ok = ok && hipEventCreateWithFlags(&c->upload_ev, hipEventDisableTiming) == hipSuccess;
+  ok = ok && hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) == hipSuccess;
+  ok = ok && hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) == hipSuccess;
+  for (int i = 0; i < 8 && ok; ++i) ok = hipEventCreate(&c->tev[i]) == hipSuccess;
+  c->pinned_cap = size_t(4) << 20;
+  ok = ok && hipHostMalloc((void**)&c->pinned, c->pinned_cap, hipHostMallocDefault) == hipSuccess;
+  ok = ok && hipHostMalloc((void**)&c->host_u64, 64, hipHostMallocDefault) == hipSuccess;
+  if (!ok) {
+    gsc_ctx_destroy(c);
+    return GSC_E_DEVICE;
+  }
+  *out = c;
+  return GSC_OK;
+}
+
+void gsc_ctx_destroy(gsc_ctx* c) {
+  if (!c) return;
+  (void)hipSetDevice(c->device);
+  if (c->stream) (void)hipStreamSynchronize(c->stream);
+  if (c->side) (void)hipStreamSynchronize(c->side);
+  if (c->frame_bin) { c->frame_bin->free_all(); delete c->frame_bin; }
+  DevBuf* all[] = {&c->targets, &c->records, &c->dL, &c->partials, &c->losses, &c->grads14,
+                   &c->images, &c->final_T, &c->last_id, &c->trace_tab, &c->vertices,
+                   &c->composite_tmp};
+  for (DevBuf* b : all) b->release(c->alloc);
+  if (c->pinned) (void)hipHostFree(c->pinned);
+  if (c->host_u64) (void)hipHostFree(c->host_u64);
+  if (c->upload_ev) (void)hipEventDestroy(c->upload_ev);
+  if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
+  if (c->ev_join) (void)hipEventDestroy(c->ev_join);
+  for (hipEvent_t e : c->tev) if (e) (void)hipEventDestroy(e);
+  for (auto& p : c->prof_pending) { (void)hipEventDestroy(p.a); (void)hipEventDestroy(p.b); }
+  for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
+  if (c->side) (void)hipStreamDestroy(c->side);
+  delete c;
+}
+
+const char* gsc_ctx_last_error(const gsc_ctx* ctx) { return ctx ? ctx->err.c_str() : "NULL context"; }
+
+gsc_status gsc_ctx_set_stream(gsc_ctx* ctx, void* hip_stream) {
+  if (!ctx) return GSC_E_INVALID_ARG;
+  ctx->stream = (hipStream_t)hip_stream;
+  ctx->upload_pending = false;
+  return guarded(ctx, [&]() -> gsc_status {
+    // Make sure no staged upload on the previous stream is still reading the ring.
+    GSC_TRY(hipDeviceSynchronize());
+    return GSC_OK;
+  });
+}
+
+gsc_status gsc_ctx_set_deterministic(gsc_ctx* ctx, int32_t on) {
+  if (!ctx) return GSC_E_INVALID_ARG;
+  if (on) { ctx->err = "deterministic backward reduction is not available"; return GSC_E_UNSUPPORTED; }
+  ctx->deterministic = 0;
+  return GSC_OK;
+}
+
+uint64_t gsc_ctx_required_capacity(const gsc_ctx* ctx) { return ctx ? ctx->required : 0; }
+
+gsc_status gsc_ctx_trim(gsc_ctx* ctx) {
+  return guarded(ctx, [&]() -> gsc_status {
+    GSC_TRY(hipStreamSynchronize(ctx->stream));
+    if (ctx->frame_bin) { ctx->frame_bin->free_all(); delete ctx->frame_bin; ctx->frame_bin = nullptr; }
+    DevBuf* all[] = {&ctx->targets, &ctx->records, &ctx->dL, &ctx->partials, &ctx->losses,
+                     &ctx->grads14, &ctx->images, &ctx->final_T, &ctx->last_id, &ctx->trace_tab,
+                     &ctx->vertices, &ctx->composite_tmp};
+    for (DevBuf* b : all) b->release(ctx->alloc);
+    return GSC_OK;
+  });
+}
+
+gsc_status gsc_trace_targets(gsc_ctx* ctx, const gsc_volume* vol, const gsc_camera* cam,
+                             const gsc_trace_params* params, float* targets,
+                             gsc_path_record* records, gsc_frame_stats* stats) {
+  return guarded(ctx, [&]() -> gsc_status {
+    if (!vol || !vol->density) invalid(ctx, "volume or density is NULL");
+    if (vol->nx < 1 || vol->ny < 1 || vol->nz < 1) invalid(ctx, "volume dimensions must be >= 1");
+    if (!(vol->density_max > 0.0f) || !std::isfinite(vol->density_max)) invalid(ctx, "density_max must be positive");
+    check_volume_host(ctx, vol->tf_rgba, vol->tf_points, vol->lights, vol->n_lights);
+    check_camera(ctx, cam);
+    check_trace_params(ctx, params);
+    if (!targets) invalid(ctx, "targets is NULL");
+    if (records && params->spp != 1) invalid(ctx, "records require spp == 1");
+    TraceDesc d = make_trace_desc(vol->density, vol->nx, vol->ny, vol->nz, vol->density_max,
+                                  vol->tf_rgba, vol->tf_points, vol->lights, vol->n_lights, *cam, *params);
+    d.pix_off = 0;
+    d.targets = targets;
+    d.records = records;
+    const size_t bytes = sizeof(TraceDesc) + sizeof(int64_t);
+    need(ctx, ctx->trace_tab, ctx->alloc, bytes, "trace descriptor");
+    need(ctx, ctx->vertices, ctx->alloc, 8, "vertex counter");
+    std::vector<char> h(bytes, 0);
+    std::memcpy(h.data(), &d, sizeof(TraceDesc));
+    upload(ctx, ctx->trace_tab.p, h.data(), bytes);
+    hipStream_t st = ctx->stream;
+    GSC_TRY(hipMemsetAsync(ctx->vertices.p, 0, 8, st));
+    if (stats) GSC_TRY(hipEventRecord(ctx->tev[6], st));
+    const int64_t P = (int64_t)cam->w * cam->h;
+  { ProfScope ps_(ctx, P_TRACE, st);
+  GSC_TRY(launch_trace(st, ctx->trace_tab.as<TraceDesc>(),
+                         (const int64_t*)((char*)ctx->trace_tab.p + sizeof(TraceDesc)), 1, P,
+                         ctx->vertices.as<unsigned long long>()));
+  }
+    if (stats) {
+      GSC_TRY(hipEventRecord(ctx->tev[7], st));
+      GSC_TRY(hipMemcpyAsync(ctx->host_u64 + 1, ctx->vertices.p, 8, hipMemcpyDeviceToHost, st));
+      GSC_TRY(hipStreamSynchronize(st));
+      std::memset(stats, 0, sizeof(*stats));
+      stats->ms_trace = elapsed(ctx->tev[6], ctx->tev[7]);
+      stats->paths = (uint64_t)P * params->spp;
+      stats->pixels = (uint64_t)P;
+      stats->path_vertices = ctx->host_u64[1];
+    }
+    return GSC_OK;
+  });
+}
+
+gsc_status gsc_project_bin(gsc_ctx* ctx, const gsc_gaussians* levels, int32_t num_levels,
+                           const gsc_camera* cam, uint64_t capacity_hint, gsc_binning** out) {
+  return guarded(ctx, [&]() -> gsc_status {
+    if (!out) invalid(ctx, "out is NULL");
+    *out = nullptr;
+    check_levels(ctx, levels, num_levels);
+    check_camera(ctx, cam);
+    gsc_binning* b = new gsc_binning();
+    b->alloc = ctx->alloc;
+    std::vector<ReqSpec> specs(1);
+    specs[0].cam = *cam;
+    specs[0].levels.assign(levels, levels + num_levels);
+    b->K = num_levels;
+    b->TX = (cam->w + kTile - 1) / kTile;
+    b->TY = (cam->h + kTile - 1) / kTile;
+    gsc_status s;
+    try {
+      plan_batch(ctx, b, specs);
+      s = run_project_bin(ctx, b, capacity_hint);
+    } catch (...) {
+      b->free_all();
+      delete b;
+      throw;
+    }
+    if (s != GSC_OK) {
+      (void)hipStreamSynchronize(ctx->stream);
+      b->free_all();
+      delete b;
+      return s;
+    }
+    *out = b;
+    return GSC_OK;
+  });
+}
+
+gsc_status gsc_binning_view(gsc_ctx* ctx, const gsc_binning* bin, gsc_binning_info* out) {
+  return guarded(ctx, [&]() -> gsc_status {
+    if (!bin || !out) invalid(ctx, "NULL argument");
+    gsc_binning* b = const_cast<gsc_binning*>(bin);
+    need(ctx, b->view_window, b->alloc, 16 * (size_t)std::max<int64_t>(b->G, 1), "window view");
+    need(ctx, b->view_screen, b->alloc, 24 * (size_t)std::max<int64_t>(b->G, 1), "screen view");
+    GSC_TRY(launch_view(ctx->stream, b->G, b->rec.as<SplatRec>(), b->tiles.as<uint32_t>(),
+                        b->view_window.as<int32_t>(), b->view_screen.as<float>()));
+    GSC_TRY(hipStreamSynchronize(ctx->stream));
+    std::memset(out, 0, sizeof(*out));
+    out->n_instances = b->n_instances;
+    out->n_tiles = (uint64_t)b->n_tiles;
+    out->num_levels = b->S;
+    out->tiles_x = b->TX;
+    out->tiles_y = b->TY;
+    for (int s = 0; s < b->S && s < 8; ++s) out->gauss_offset[s] = b->segs[s].g_off;
+    out->gauss_offset[std::min(b->S, 8)] = b->G;
+    out->values = b->values.as<uint32_t>();
+    out->ranges = b->ranges.as<uint64_t>();
+    out->window = b->view_window.as<int32_t>();
+    out->tiles_touched = b->tiles.as<uint32_t>();
+    out->depth_key = b->depth_key.as<uint32_t>();
+    out->screen = b->view_screen.as<float>();
+    return GSC_OK;
+  });
+}
+
+gsc_status gsc_binning_keys(gsc_ctx* ctx, const gsc_binning* bin, uint64_t* keys) {
+  return guarded(ctx, [&]() -> gsc_status {
+    if (!bin) invalid(ctx, "NULL binning");
+    const gsc_binning* b = bin;
+    if (b->n_instances == 0) return GSC_OK;
+    if (!keys) invalid(ctx, "keys is NULL");
+    GSC_TRY(launch_binning_keys(ctx->stream, b->d_tstart(), b->S, b->d_gstart(), b->n_tiles,
+                                b->tile_start.as<uint64_t>(), b->d_ninst(), b->n_instances,
+                                b->values.as<uint32_t>(), b->depth_key.as<uint32_t>(), keys));
+    return GSC_OK;
+  });
+}
+
+void gsc_binning_release(gsc_ctx* ctx, gsc_binning* bin) {
+  if (!bin) return;
+  if (ctx) {
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+  }
+  bin->free_all();
+  delete bin;
+}
+
+gsc_status gsc_splat_forward(gsc_ctx* ctx, gsc_binning* bin, float* images, float* final_T,
+                             int32_t* last_id) {
+  return guarded(ctx, [&]() -> gsc_status {
+    if (!bin || !images || !final_T || !last_id) invalid(ctx, "NULL argument");
+    run_forward(ctx, bin, images, final_T, last_id);
+    return GSC_OK;
+  });
+}
+
+gsc_status gsc_splat_backward(gsc_ctx* ctx, const gsc_binning* bin, const gsc_gaussians* levels,
+                              int32_t num_levels, const gsc_camera* cam, const float* final_T,
+                              const int32_t* last_id, const float* dL_dimages,
+                              const gsc_grads* grads) {
+  return guarded(ctx, [&]() -> gsc_status {
+    if (!bin || !final_T || !last_id || !dL_dimages || !grads) invalid(ctx, "NULL argument");
+    gsc_binning* b = const_cast<gsc_binning*>(bin);
+    if (!b->forward_done) invalid(ctx, "gsc_splat_forward has not run on this binning");
+    check_levels(ctx, levels, num_levels);
+    check_camera(ctx, cam);
+    if (num_levels != b->S) invalid(ctx, "num_levels differs from the binning's");
+    for (int l = 0; l < num_levels; ++l) {
+      const Seg& sg = b->segs[l];
+      if (levels[l].n != sg.n || levels[l].pos != sg.pos || levels[l].rot != sg.rot ||
+          levels[l].log_scale != sg.ls || levels[l].rgb != sg.rgb ||
+          levels[l].opacity_logit != sg.logit)
+        invalid(ctx, "levels differ from those given to gsc_project_bin");
+      if (levels[l].n > 0 && (!grads[l].pos || !grads[l].rot || !grads[l].log_scale ||
+                              !grads[l].rgb || !grads[l].opacity_logit))
+        invalid(ctx, "gradient pointer is NULL");
+    }
+    need(ctx, ctx->grads14, ctx->alloc, 4 * 14 * (size_t)std::max<int64_t>(b->G, 1), "parameter gradients");
+    run_backward(ctx, b, final_T, dL_dimages, ctx->grads14.as<float>());
+    for (int l = 0; l < num_levels; ++l) {
+      const int64_t nn = levels[l].n;
+      if (nn == 0) continue;
+      const float* g = ctx->grads14.as<float>() + 14 * b->segs[l].g_off;
+      GSC_TRY(hipMemcpyAsync(grads[l].pos, g, 12 * nn, hipMemcpyDeviceToDevice, ctx->stream));
+      GSC_TRY(hipMemcpyAsync(grads[l].rot, g + 3 * nn, 16 * nn, hipMemcpyDeviceToDevice, ctx->stream));
+      GSC_TRY(hipMemcpyAsync(grads[l].log_scale, g + 7 * nn, 12 * nn, hipMemcpyDeviceToDevice, ctx->stream));
+      GSC_TRY(hipMemcpyAsync(grads[l].rgb, g + 10 * nn, 12 * nn, hipMemcpyDeviceToDevice, ctx->stream));
+      GSC_TRY(hipMemcpyAsync(grads[l].opacity_logit, g + 13 * nn, 4 * nn, hipMemcpyDeviceToDevice, ctx->stream));
+    }
+    return GSC_OK;
+  });
+}
+
+gsc_status gsc_loss_composite(gsc_ctx* ctx, const float* images, const float* targets,
+                              const gsc_path_record* records, int32_t num_levels, int32_t w,
+                              int32_t h, int32_t loss, float* dL_dimages, float* loss_out,
+                              float* composite) {
+  return guarded(ctx, [&]() -> gsc_status {
+    if (!images || !targets || !dL_dimages || !loss_out) invalid(ctx, "NULL argument");
+    if (num_levels < 1 || num_levels > 8) invalid(ctx, "num_levels must be in [1, 8]");
+    if (w < 1 || h < 1 || w > 16384 || h > 16384) invalid(ctx, "image size out of range");
+    if (loss != 0 && loss != 1) invalid(ctx, "loss must be 0 or 1");
+    if ((records == nullptr) != (composite == nullptr)) invalid(ctx, "records and composite go together");
+    const int np = loss_num_partials((int64_t)w * h);
+    need(ctx, ctx->partials, ctx->alloc, 8 * (size_t)np, "loss partials");
+    GSC_TRY(launch_loss_composite(ctx->stream, images, targets, records, num_levels, w, h, loss,
+                                  dL_dimages, ctx->partials.as<double>(), loss_out, composite));
+    return GSC_OK;
+  });
+}
+
+gsc_status gsc_adam_step(gsc_ctx* ctx, float* param, float* m, float* v, const float* grad,
+                         int64_t count, const gsc_adam_hparams* hp) {
+  return guarded(ctx, [&]() -> gsc_status {
+    if (!hp) invalid(ctx, "hparams NULL");
+    if (count < 0) invalid(ctx, "count must be >= 0");
+    if (count > 0 && (!param || !m || !v || !grad)) invalid(ctx, "NULL argument");
+    if (hp->step < 1) invalid(ctx, "step must be >= 1");
+    if (!(hp->beta1 >= 0.0f && hp->beta1 < 1.0f) || !(hp->beta2 >= 0.0f && hp->beta2 < 1.0f))
+      invalid(ctx, "betas must be in [0, 1)");
+    if (!std::isfinite(hp->lr) || !std::isfinite(hp->eps) || !std::isfinite(hp->weight_decay))
+      invalid(ctx, "hyper-parameters must be finite");
+    adam_group(ctx, param, m, v, grad, count, hp->lr, hp->beta1, hp->beta2, hp->eps,
+               hp->weight_decay, hp->step, nullptr);
+    return GSC_OK;
+  });
+}
+
+gsc_status gsc_scene_create(gsc_ctx* ctx, const gsc_volume* vol, const gsc_gaussians* init_levels,
+                            int32_t K, gsc_scene** out) {
+  return guarded(ctx, [&]() -> gsc_status {
+    if (!out) invalid(ctx, "out is NULL");
+    *out = nullptr;
+    if (!vol || !vol->density) invalid(ctx, "volume or density is NULL");
+    if (vol->nx < 1 || vol->ny < 1 || vol->nz < 1) invalid(ctx, "volume dimensions must be >= 1");
+    if (!(vol->density_max > 0.0f)) invalid(ctx, "density_max must be positive");
+    check_volume_host(ctx, vol->tf_rgba, vol->tf_points, vol->lights, vol->n_lights);
+    check_levels(ctx, init_levels, K);
+    gsc_scene* sc = new gsc_scene();
+    sc->alloc = ctx->alloc;
+    auto cleanup = [&]() {
+      for (float* p : sc->params) sc->alloc.put(p);
+      for (float* p : sc->m) sc->alloc.put(p);
+      for (float* p : sc->v) sc->alloc.put(p);
+      sc->alloc.put(sc->density);
+      delete sc;
+    };
+    try {
+      sc->K = K;
+      sc->nx = vol->nx; sc->ny = vol->ny; sc->nz = vol->nz;
+      sc->dmax = vol->density_max;
+      sc->tf.assign(vol->tf_rgba, vol->tf_rgba + 4 * vol->tf_points);
+      sc->lights.assign(vol->lights, vol->lights + 6 * vol->n_lights);
+      const size_t vb = 4 * (size_t)vol->nx * vol->ny * vol->nz;
+      sc->density = (float*)sc->alloc.get(vb);
+      if (!sc->density) oom(ctx, "scene volume", vb);
+      GSC_TRY(hipMemcpyAsync(sc->density, vol->density, vb, hipMemcpyDeviceToDevice, ctx->stream));
+      for (int l = 0; l < K; ++l) {
+        const int64_t nn = init_levels[l].n;
+        const size_t bytes = 4 * 14 * (size_t)std::max<int64_t>(nn, 1);
+        float* p = (float*)sc->alloc.get(bytes);
+        float* m = (float*)sc->alloc.get(bytes);
+        float* v = (float*)sc->alloc.get(bytes);
+        sc->params.push_back(p); sc->m.push_back(m); sc->v.push_back(v);
+        if (!p || !m || !v) oom(ctx, "scene parameters", bytes);
+        sc->n.push_back(nn);
+        sc->step.push_back(0);
+        if (nn > 0) {
+          const gsc_gaussians& g = init_levels[l];
+          GSC_TRY(hipMemcpyAsync(p, g.pos, 12 * nn, hipMemcpyDeviceToDevice, ctx->stream));
+          GSC_TRY(hipMemcpyAsync(p + 3 * nn, g.rot, 16 * nn, hipMemcpyDeviceToDevice, ctx->stream));
+          GSC_TRY(hipMemcpyAsync(p + 7 * nn, g.log_scale, 12 * nn, hipMemcpyDeviceToDevice, ctx->stream));
+          GSC_TRY(hipMemcpyAsync(p + 10 * nn, g.rgb, 12 * nn, hipMemcpyDeviceToDevice, ctx->stream));
+          GSC_TRY(hipMemcpyAsync(p + 13 * nn, g.opacity_logit, 4 * nn, hipMemcpyDeviceToDevice, ctx->stream));
+        }
+        GSC_TRY(hipMemsetAsync(m, 0, bytes, ctx->stream));
+        GSC_TRY(hipMemsetAsync(v, 0, bytes, ctx->stream));
+      }
+    } catch (...) {
+      cleanup();
+      throw;
+    }
+    *out = sc;
+    return GSC_OK;
+  });
+}
+
+void gsc_scene_destroy(gsc_ctx* ctx, gsc_scene* sc) {
+  if (!sc) return;
+  if (ctx) {
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+  }
+  for (float* p : sc->params) sc->alloc.put(p);
+  for (float* p : sc->m) sc->alloc.put(p);
+  for (float* p : sc->v) sc->alloc.put(p);
+  sc->alloc.put(sc->density);
+  delete sc;
+}
+
+gsc_status gsc_scene_set_optics(gsc_ctx* ctx, gsc_scene* sc, const float* tf_rgba, int32_t tf_points,
+                                const float* lights, int32_t n_lights) {
+  return guarded(ctx, [&]() -> gsc_status {
+    if (!sc) invalid(ctx, "scene is NULL");
+    check_volume_host(ctx, tf_rgba, tf_points, lights, n_lights);
+    sc->tf.assign(tf_rgba, tf_rgba + 4 * tf_points);
+    sc->lights.assign(lights, lights + 6 * n_lights);
+    return GSC_OK;
+  });
+}
+
+gsc_status gsc_scene_level(const gsc_scene* sc, int32_t l, gsc_gaussians* out) {
+  if (!sc || !out || l < 0 || l >= sc->K) return GSC_E_INVALID_ARG;
+  float* p = sc->params[l];
+  const int64_t nn = sc->n[l];
+  out->pos = p; out->rot = p + 3 * nn; out->log_scale = p + 7 * nn; out->rgb = p + 10 * nn;
+  out->opacity_logit = p + 13 * nn; out->n = nn;
+  return GSC_OK;
+}
+
+gsc_status gsc_scene_state(const gsc_scene* sc, int32_t l, float** params, float** m, float** v,
+                           int64_t* n, int64_t* step) {
+  if (!sc || l < 0 || l >= sc->K || !params || !m || !v || !n || !step) return GSC_E_INVALID_ARG;
+  *params = sc->params[l];
+  *m = sc->m[l];
+  *v = sc->v[l];
+  *n = sc->n[l];
+  *step = sc->step[l];
+  return GSC_OK;
+}
+
+gsc_status gsc_scene_copy_state(gsc_ctx* ctx, gsc_scene* dst, const gsc_scene* src) {
+  return guarded(ctx, [&]() -> gsc_status {
+    if (!dst || !src) invalid(ctx, "NULL scene");
+    if (dst->K != src->K) invalid(ctx, "level counts differ");
+    for (int l = 0; l < src->K; ++l) if (dst->n[l] != src->n[l]) invalid(ctx, "level sizes differ");
+    for (int l = 0; l < src->K; ++l) {
+      const size_t bytes = 4 * 14 * (size_t)src->n[l];
+      if (bytes == 0) continue;
+      GSC_TRY(hipMemcpyAsync(dst->params[l], src->params[l], bytes, hipMemcpyDeviceToDevice, ctx->stream));
+      GSC_TRY(hipMemcpyAsync(dst->m[l], src->m[l], bytes, hipMemcpyDeviceToDevice, ctx->stream));
+      GSC_TRY(hipMemcpyAsync(dst->v[l], src->v[l], bytes, hipMemcpyDeviceToDevice, ctx->stream));
+      dst->step[l] = src->step[l];
+    }
+    return GSC_OK;
+  });
+}
+
+size_t gsc_scene_footprint_bytes(const gsc_scene* sc) {
+  if (!sc) return 0;
+  size_t b = 4 * (size_t)sc->nx * sc->ny * sc->nz;
+  for (int l = 0; l < sc->K; ++l) b += 3 * 14 * 4 * (size_t)sc->n[l];
+  return b;
+}
+
+size_t gsc_frame_footprint_bytes(const gsc_scene* sc, int32_t w, int32_t h, uint64_t instance_estimate) {
+  if (!sc || w < 1 || h < 1) return 0;
+  int64_t G = 0;
+  for (int l = 0; l < sc->K; ++l) G += sc->n[l];
+  const size_t P = (size_t)w * h;
+  const size_t K = (size_t)sc->K;
+  const size_t tiles = K * (size_t)((w + 15) / 16) * ((h + 15) / 16);
+  size_t b = 0;
+  b += (size_t)G * (48 + 4 + 8 + 4 + 4 * 4 + 8 + 9 * 4 + 14 * 4);   // per-Gaussian buffers
+  b += 4 * (size_t)instance_estimate;                              // instance ids
+  b += tiles * (8 + 16 + 4) + 4 * tiles * (size_t)((G / (int64_t)K + kChunk - 1) / kChunk);
+  b += P * K * (12 * 3 + 4 + 4 + 4) + P * (20 + 12);              // images, targets, dL, T, ids
+  return b;
+}
+
+gsc_status gsc_render_frame(gsc_ctx* ctx, gsc_scene* scene, const gsc_frame_request* req,
+                            float* image, gsc_frame_stats* stats) {
+  return guarded(ctx, [&]() -> gsc_status {
+    gsc_scene* const scenes[1] = {scene};
+    float* const images[1] = {image};
+    if (!req) invalid(ctx, "request is NULL");
+    return render_batch(ctx, scenes, req, images, 1, stats);
+  });
+}
+
+gsc_status gsc_render_frames(gsc_ctx* ctx, gsc_scene* const* scenes, const gsc_frame_request* reqs,
+                             float* const* images, int32_t n, gsc_frame_stats* stats) {
+  return guarded(ctx, [&]() -> gsc_status { return render_batch(ctx, scenes, reqs, images, n, stats); });
+}
+
+gsc_status gsc_ctx_profile(gsc_ctx* ctx, int32_t on) {
+  return guarded(ctx, [&]() -> gsc_status {
+    prof_resolve(ctx);
+    ctx->prof_on = on != 0;
+    if (on) {
+      for (int i = 0; i < 16; ++i) { ctx->prof_ms[i] = 0.0; ctx->prof_n[i] = 0; }
+      ctx->acc_instances = 0;
+      ctx->acc_frames = 0;
+    }
+    return GSC_OK;
+  });
+}
+
+gsc_status gsc_ctx_profile_read(gsc_ctx* ctx, int32_t index, char* name, size_t name_len,
+                                double* total_ms, int64_t* launches) {
+  return guarded(ctx, [&]() -> gsc_status {
+    if (index < 0 || index >= kProfCount || !name || name_len < 2 || !total_ms || !launches)
+      invalid(ctx, "bad profile query");
+    prof_resolve(ctx);
+    std::snprintf(name, name_len, "%s", kProfNames[index]);
+    *total_ms = ctx->prof_ms[index];
+    *launches = ctx->prof_n[index];
+    return GSC_OK;
+  });
+}
+
+gsc_status gsc_ctx_counters(gsc_ctx* ctx, uint64_t* instances, uint64_t* binnings) {
+  if (!ctx || !instances || !binnings) return GSC_E_INVALID_ARG;
+  *instances = ctx->acc_instances;
+  *binnings = ctx->acc_frames;
+  return GSC_OK;
+}
+
+gsc_status gsc_copy(gsc_ctx* ctx, void* dst, const void* src, size_t bytes) {
+  return guarded(ctx, [&]() -> gsc_status {
+    if (bytes == 0) return GSC_OK;
+    if (!dst || !src) invalid(ctx, "NULL pointer");
+    GSC_TRY(hipMemcpyAsync(dst, src, bytes, hipMemcpyDefault, ctx->stream));
+    return GSC_OK;
+  });
+}
+
+gsc_status gsc_ctx_synchronize(gsc_ctx* ctx) {
+  return guarded(ctx, [&]() -> gsc_status {
+    GSC_TRY(hipStreamSynchronize(ctx->stream));
+    return GSC_OK;
+  });
+}
+
+size_t gsc_abi_struct_size(int32_t which) {
+  switch (which) {
+    case 0: return sizeof(gsc_camera);
+    case 1: return sizeof(gsc_gaussians);
+    case 2: return sizeof(gsc_grads);
+    case 3: return sizeof(gsc_volume);
+    case 4: return sizeof(gsc_trace_params);
+    case 5: return sizeof(gsc_path_record);
+    case 6: return sizeof(gsc_frame_stats);
+    case 7: return sizeof(gsc_binning_info);
+    case 8: return sizeof(gsc_adam_hparams);
+    case 9: return sizeof(gsc_frame_request);
+    case 10: return sizeof(gsc_allocator);
+    default: return 0;
+  }
+}
+
+}  // extern "C"

@@ -1,0 +1,181 @@
+"""GPU parity of the splat path through the C ABI: projection and binning bit-exact against the
+oracle (per-Gaussian windows and tile counts, 64-bit keys, ids, per-tile ranges), the forward
+within 1e-5 relative (non-boundary pixels, last contributor exact), the adjoint within 1e-4
+relative against the fp64 oracle gradient, and the autograd wrapper."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from oracle import backward as obwd
+from tests.gpu_common import forward_close, grads_close, to_np, u32, u64
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gsc():
+    import paper_2507_19718_amd as m
+    return m
+
+
+@pytest.fixture(scope="module")
+def gctx(gsc):
+    return gsc.Context(0)
+
+
+def run_bin(gsc, gctx, levels_np, cam):
+    levels = [gsc.level_to_device(g) for g in levels_np]
+    b = gsc.gsc_project_bin(gctx, levels, cam)
+    view = gsc.gsc_binning_view(gctx, b)
+    keys = gsc.gsc_binning_keys(gctx, b, view["n_instances"])
+    return levels, b, view, keys
+
+
+def check_binning(view, keys, levels_np, cam):
+    projs = [oracle.project(g, cam) for g in levels_np]
+    ob = oracle.bin_levels(projs, cam)
+    off = view["gauss_offset"]
+    for l, pr in enumerate(projs):
+        sl = slice(off[l], off[l + 1])
+        assert np.array_equal(to_np(view["tiles_touched"][sl]).astype(np.uint32), pr["tiles"]), l
+        assert np.array_equal(to_np(view["window"][sl]), pr["window"]), l
+        live = pr["tiles"] > 0
+        assert np.array_equal(u32(view["depth_key"][sl])[live], pr["depth"].view(np.uint32)[live])
+        scr = to_np(view["screen"][sl])
+        assert np.array_equal(scr[live].view(np.uint32), pr["screen"][live].view(np.uint32)), l
+    assert view["n_instances"] == ob["keys"].size
+    assert np.array_equal(u64(keys), ob["keys"])
+    assert np.array_equal(u32(view["values"]), ob["values"])
+    assert np.array_equal(u64(view["ranges"]), ob["ranges"])
+    return projs
+
+
+def test_binning_bit_exact_tiny(gsc, gctx):
+    wl = synth.workload("tiny")
+    cam = wl.camera()
+    levels_np = wl.gaussians()
+    _, _, view, keys = run_bin(gsc, gctx, levels_np, cam)
+    check_binning(view, keys, levels_np, cam)
+
+
+def test_binning_bit_exact_multilevel_crop_ragged(gsc, gctx):
+    cam = synth.orbit_camera(300, 200, azimuth_deg=75.0).crop(37, 21, 229, 157)   # ragged tiles
+    levels_np = [synth.random_gaussians(n, 17, l) for l, n in enumerate((5000, 2500, 1, 0))]
+    _, _, view, keys = run_bin(gsc, gctx, levels_np, cam)
+    check_binning(view, keys, levels_np, cam)
+
+
+def test_binning_empty_frame(gsc, gctx):
+    # All Gaussians behind the camera: no instance, every range (0, 0).
+    cam = synth.orbit_camera(64, 64, azimuth_deg=0.0)
+    g = synth.random_gaussians(300, 3)
+    g.pos[:] = g.pos * 0.01 + np.array([0.5, 0.5 + 0.62, 0.5 + 1.7], np.float32)
+    _, _, view, keys = run_bin(gsc, gctx, [g], cam)
+    check_binning(view, keys, [g], cam)
+
+
+def test_binning_bit_exact_one_orbit1k_level(gsc, gctx):
+    wl = synth.workload("orbit1k")
+    cam = wl.camera()
+    g = synth.random_gaussians(200_000, wl.seed, 0)
+    _, _, view, keys = run_bin(gsc, gctx, [g], cam)
+    assert view["n_instances"] > 10_000_000
+    check_binning(view, keys, [g], cam)
+
+
+def forward_levels(gsc, gctx, levels, cam, K):
+    b = gsc.gsc_project_bin(gctx, levels, cam)
+    img = torch.empty((K, cam.h, cam.w, 3), device="cuda")
+    T = torch.empty((K, cam.h, cam.w), device="cuda")
+    last = torch.empty((K, cam.h, cam.w), dtype=torch.int32, device="cuda")
+    gsc.gsc_splat_forward(gctx, b, img, T, last)
+    return b, img, T, last
+
+
+@pytest.mark.parametrize("case", ["tiny", "multilevel"])
+def test_forward_parity(gsc, gctx, case):
+    if case == "tiny":
+        wl = synth.workload("tiny")
+        cam = wl.camera()
+        levels_np = wl.gaussians()
+    else:
+        cam = synth.orbit_camera(240, 180, azimuth_deg=40.0).crop(11, 7, 200, 150)
+        levels_np = [synth.random_gaussians(n, 23, l) for l, n in enumerate((8000, 4000, 2000))]
+    levels = [gsc.level_to_device(g) for g in levels_np]
+    K = len(levels)
+    _, img, T, last = forward_levels(gsc, gctx, levels, cam, K)
+    n_boundary = 0
+    for l, g in enumerate(levels_np):
+        pr = oracle.project(g, cam)
+        fw = oracle.forward(pr, g.rgb, cam)
+        ok = ~fw["boundary"]
+        n_boundary += int(fw["boundary"].sum())
+        good, info = forward_close(to_np(img[l]), fw["image"], ok)
+        assert good, ("image", l, info)
+        good, info = forward_close(to_np(T[l]), fw["final_T"], ok)
+        assert good, ("final_T", l, info)
+        assert np.array_equal(to_np(last[l])[ok], fw["last_id"][ok])
+    assert n_boundary <= 1e-3 * K * cam.w * cam.h + 4
+
+
+def grad_case_backward(gsc, gctx, cam, g, rng):
+    lv = gsc.level_to_device(g)
+    b, img, T, last = forward_levels(gsc, gctx, [lv], cam, 1)
+    pr = oracle.project(g, cam)
+    fw = oracle.forward(pr, g.rgb, cam, lists=True)
+    keep = ~fw["boundary"]
+    G = (rng.normal(size=(cam.h, cam.w, 3)) * keep[..., None]).astype(np.float32)
+    grads = [{k: torch.empty_like(lv[k]) for k in gsc.PARAM_NAMES}]
+    gsc.gsc_splat_backward(gctx, b, [lv], cam, T, last,
+                           torch.from_numpy(G[None]).cuda().contiguous(), grads)
+    ref = obwd.backward(g, cam, fw, G.astype(np.float64))
+    return grads[0], ref
+
+
+@pytest.mark.parametrize("case", ["crop32_64", "tiny"])
+def test_backward_parity(gsc, gctx, case):
+    rng = np.random.default_rng(3)
+    if case == "crop32_64":
+        cam = synth.orbit_camera(1920, 1080, azimuth_deg=30.0).crop(944, 524, 32, 32)
+        g = synth.frustum_gaussians(cam, 64, seed=31)
+    else:
+        wl = synth.workload("tiny")
+        cam = wl.camera()
+        g = synth.random_gaussians(4096, 5, log_scale_mean=math.log(0.03), log_scale_std=0.2)
+    got, ref = grad_case_backward(gsc, gctx, cam, g, rng)
+    for k in gsc.PARAM_NAMES:
+        good, info = grads_close(to_np(got[k]).reshape(ref[k].shape), ref[k])
+        assert good, (k, info)
+
+
+def test_autograd_function_matches_direct_backward(gsc, gctx):
+    cam = synth.orbit_camera(1920, 1080, azimuth_deg=30.0).crop(900, 500, 96, 64)
+    levels_np = [synth.frustum_gaussians(cam, 300, seed=41, index=l) for l in range(2)]
+    levels = [gsc.level_to_device(g) for g in levels_np]
+    leaf = [{k: v.clone().requires_grad_(True) for k, v in lv.items()} for lv in levels]
+    images, T, last = gsc.splat(gctx, cam, leaf)
+    w = torch.randn_like(images)
+    (images * w).sum().backward()
+    b, img2, T2, last2 = forward_levels(gsc, gctx, levels, cam, 2)
+    assert torch.equal(images.detach(), img2) and torch.equal(T, T2) and torch.equal(last, last2)
+    grads = [{k: torch.empty_like(lv[k]) for k in gsc.PARAM_NAMES} for lv in levels]
+    gsc.gsc_splat_backward(gctx, b, levels, cam, T2, last2, w.contiguous(), grads)
+    for l in range(2):
+        for k in gsc.PARAM_NAMES:
+            good, info = grads_close(to_np(leaf[l][k].grad), to_np(grads[l][k]), tol=1e-5)
+            assert good, (l, k, info)
+
+
+def test_invalid_arguments_rejected(gsc, gctx):
+    cam = synth.orbit_camera(64, 64, 0.0)
+    g = gsc.level_to_device(synth.random_gaussians(10, 1))
+    bad = cam.crop(0, 0, 65, 64)
+    with pytest.raises(gsc.GscError) as e:
+        gsc.gsc_project_bin(gctx, [g], bad)
+    assert e.value.status == 1
+    with pytest.raises(gsc.GscError):
+        gsc.gsc_project_bin(gctx, [g] * 9, cam)

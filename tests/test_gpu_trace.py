@@ -1,0 +1,105 @@
+"""GPU parity of the tracer through the C ABI.
+
+Both sides draw from the same Philox streams with the same operation order, so the paths are
+expected to be bit-identical (the diagnostic); the parity bar is statistical: per pixel and
+channel at 1024 spp, |z| > 3 for at most 0.5% of the entries and |mean z| <= 3."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import synth
+from tests.gpu_common import to_np
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gsc():
+    import paper_2507_19718_amd as m
+    return m
+
+
+@pytest.fixture(scope="module")
+def gctx(gsc):
+    return gsc.Context(0)
+
+
+def gpu_trace(gsc, gctx, vol, cam, seed, frame, spp, B, K, C, records=True):
+    gv = gsc.Volume.from_synth(vol)
+    tg = torch.empty((K, cam.h, cam.w, 3), device="cuda")
+    rec = torch.empty((cam.h, cam.w, 5), dtype=torch.int32, device="cuda") if records else None
+    stats = gsc.gsc_trace_targets(gctx, gv, cam, gsc.trace_params(seed, frame, spp, B, K, C), tg,
+                                  rec, stats=True)
+    return tg, rec, stats
+
+
+@pytest.mark.parametrize("C", [0.5, math.inf, 0.0])
+def test_trace_bit_identical_tiny(gsc, gctx, C):
+    wl = synth.workload("tiny")
+    vol = wl.volume()
+    cam = wl.camera()
+    tg, rec, stats = gpu_trace(gsc, gctx, vol, cam, wl.seed, 3, 1, 3, 3, C)
+    ora = oracle.trace(vol, cam, wl.seed, 3, 1, 3, 3, C=C)
+    t = to_np(tg)
+    same = np.all(t == ora["targets"], axis=(0, 3))
+    r = to_np(rec).view(np.uint32)
+    same_rec = np.all(r[..., :3].view(np.float32) == ora["L"], axis=-1) & \
+        (r[..., 3].view(np.float32) == ora["beta"]) & \
+        ((r[..., 4] & 0xFFFF) == ora["n"]) & ((r[..., 4] >> 16) == ora["kind"])
+    assert same.mean() >= 0.999, same.mean()
+    assert same_rec.mean() >= 0.999, same_rec.mean()
+    assert stats["path_vertices"] == ora["path_vertices"] or same.mean() < 1.0
+
+
+def test_trace_crop_reproduces_full_frame_pixels(gsc, gctx):
+    wl = synth.workload("tiny")
+    vol = wl.volume()
+    cam = wl.camera()
+    full, _, _ = gpu_trace(gsc, gctx, vol, cam, 5, 0, 1, 3, 2, 0.5)
+    crop = cam.crop(17, 33, 61, 45)
+    part, _, _ = gpu_trace(gsc, gctx, vol, crop, 5, 0, 1, 3, 2, 0.5)
+    assert torch.equal(full[:, 33:33 + 45, 17:17 + 61], part)
+
+
+def test_trace_3sigma_1024spp_fbm_crop(gsc, gctx):
+    wl = synth.workload("orbit1k", volume_res=64)
+    vol = wl.volume()
+    cam = wl.camera().crop(496, 496, 24, 24)
+    spp = 1024
+    tg, _, _ = gpu_trace(gsc, gctx, vol, cam, 77, 0, spp, 3, 3, 0.5, records=False)
+    ora = oracle.trace(vol, cam, 77, 0, spp, 3, 3, C=0.5, records=False, second_moment=True)
+    mu_g = to_np(tg).astype(np.float64)
+    mu_o = ora["targets"].astype(np.float64)
+    var = np.maximum(ora["targets_sq"].astype(np.float64) - mu_o * mu_o, 0.0)
+    zero = var == 0
+    assert np.array_equal(mu_g[zero], mu_o[zero])
+    z = (mu_g - mu_o)[~zero] / np.sqrt(2 * var[~zero] / spp)
+    assert np.mean(np.abs(z) > 3) <= 0.005
+    assert abs(np.mean(z)) <= 3
+    # Diagnostic: the fraction of bit-identical per-pixel means.
+    assert np.mean(mu_g == mu_o) > 0.99
+
+
+def test_trace_targets_one_level_per_pixel_and_records(gsc, gctx):
+    wl = synth.workload("tiny")
+    vol = wl.volume()
+    cam = wl.camera()
+    tg, rec, _ = gpu_trace(gsc, gctx, vol, cam, 9, 1, 1, 4, 4, 0.5)
+    t = to_np(tg)
+    assert ((t != 0).any(-1).sum(0) <= 1).all()
+    r = to_np(rec).view(np.uint32)
+    n = r[..., 4] & 0xFFFF
+    assert n.max() <= 4
+    beta = r[..., 3].view(np.float32)
+    assert (beta > 0).all() and (beta <= 1).all()
+
+
+def test_trace_rejects_records_with_spp(gsc, gctx):
+    wl = synth.workload("tiny")
+    vol = wl.volume()
+    cam = wl.camera()
+    with pytest.raises(gsc.GscError):
+        gpu_trace(gsc, gctx, vol, cam, 1, 0, 4, 3, 1, 0.5, records=True)
