@@ -115,6 +115,51 @@ def cpu_baseline(wl, vol, levels, crop=64):
     }
 
 
+SERVE_SCENES = ((128, 100_000), (256, 300_000), (512, 600_000), (512, 1_000_000))
+
+
+def serving(duration_s: float, rate_hz: float = 240.0, slots: int = 2):
+    """Served vs plain on the same Poisson request log: 4 resident scenes (128^3, 256^3, 512^3,
+    512^3 fBm; 3 levels of 100k / 300k / 600k / 1M Gaussians), 32 viewers at 640x360 /
+    1280x720 / 1920x1080 on random orbits, 1 spp trace + train step + composite per request."""
+    import torch
+    import synth
+    import paper_2507_19718_amd as gsc
+    from paper_2507_19718_amd import serve
+    ctx = gsc.Context(0)
+
+    def scenes():
+        out = []
+        for i, (res, n) in enumerate(SERVE_SCENES):
+            wl = synth.workload("orbit1k", volume_res=res, levels=[n] * 3, seed=0x47534305 + 10 + i)
+            vol = wl.volume()
+            sc = gsc.Scene(ctx, gsc.Volume.from_synth(vol), [gsc.level_to_device(g) for g in wl.gaussians()])
+            out.append(serve.SceneSpec(sc, wl.K, wl.max_bounces, 1, wl.lr, wl.weight_decay, wl.C))
+        return out
+
+    log_ = synth.poisson_requests(rate_hz, duration_s, 32, 4, 0x47534305)
+    cam = lambda e: synth.orbit_camera(e["width"], e["height"], e["azimuth"], e["elevation"], e["radius"])
+    t = time.time()
+    specs = scenes()
+    log(f"serving: {len(log_)} requests over {duration_s} s; scenes ready in {time.time() - t:.1f} s")
+    free, total = torch.cuda.mem_get_info()
+    budget = int(0.8 * free)
+    plain = serve.run_plain(ctx, specs, serve.make_requests(log_, cam))
+    log(f"plain: {plain}")
+    specs2 = scenes()
+    # Instance estimate for admission: the 1080p / 1M level binning reaches ~1e9 instances.
+    est = lambda r: int(360.0 * r.cam.w * r.cam.h * specs2[r.scene].K)
+    b = serve.ContinuousBatcher(specs2, slots=slots, hbm_budget=budget, instance_estimate=est)
+    served = b.run(serve.make_requests(log_, cam))
+    log(f"served: {served}")
+    sizes = [len(x) for x in b.batches]
+    return {"requests": len(log_), "rate_hz": rate_hz, "duration_s": duration_s,
+            "plain": {k: round(v, 3) for k, v in plain.items()},
+            "served": {k: round(v, 3) for k, v in served.items()},
+            "served_batches": len(sizes), "mean_batch": round(float(sum(sizes)) / max(len(sizes), 1), 2),
+            "slots": slots, "hbm_budget_GB": round(budget / 1e9, 1)}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -122,6 +167,10 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--workload", default="fhd")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="only run a plain 1 GiB device copy 5 times (calibrates HBM counters)")
+    ap.add_argument("--serve-seconds", type=float, default=0.0,
+                    help="also replay a Poisson log of this length, served vs plain")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (the GSCache hot path is single-GPU here); "
@@ -131,6 +180,17 @@ def main():
     import numpy as np
     import torch
     import paper_2507_19718_amd as gsc
+
+    if args.copy_probe:
+        n = 1 << 28                                      # 1 GiB of fp32
+        src = torch.ones(n, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(5):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_probe_bytes_read": 4 * n, "copy_probe_bytes_written": 4 * n,
+                          "launches": 5}), flush=True)
+        return
 
     wl, vol, levels = build_inputs(args.workload)
     cam = wl.camera()
@@ -204,6 +264,13 @@ def main():
         cpu = cpu_baseline(wl, vol, levels)
         log(f"cpu baseline {time.time() - t:.1f} s")
 
+    serve_res = None
+    if args.serve_seconds > 0:
+        del scene
+        ctx.trim()
+        torch.cuda.empty_cache()
+        serve_res = serving(args.serve_seconds)
+
     out = {
         "metric": METRIC,
         "value": round(fps, 3),
@@ -230,6 +297,8 @@ def main():
                      "paths_per_s": round(c["paths"] * fps, 1)},
         "stage_ms_one_frame": {k: round(v, 3) for k, v in stats.items() if k.startswith("ms_")},
     }
+    if serve_res is not None:
+        out["serving"] = serve_res
     print(json.dumps(out), flush=True)
 
 

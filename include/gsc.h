@@ -34,8 +34,8 @@
  *   - Threading: a context is used by one host thread at a time; several contexts may share a
  *     device (one per concurrently running stream).
  *   - Determinism: every output is deterministic except the float-atomic sums of
- *     gsc_splat_backward (order of accumulation); gsc_ctx_set_deterministic(ctx, 1) replaces
- *     them by a fixed-order reduction.
+ *     gsc_splat_backward (order of accumulation across tiles); a fixed-order mode is not
+ *     provided (gsc_ctx_set_deterministic(ctx, 1) returns GSC_E_UNSUPPORTED).
  */
 #ifndef GSC_H_
 #define GSC_H_
@@ -165,9 +165,10 @@ typedef struct {
   const float* screen;     /* [sum n][6] u, v, conic A, B, C, opacity                        */
 } gsc_binning_info;
 
-/* HOST.  AdamW hyper-parameters of one parameter group; lr already includes the Eq. 5 factor. */
+/* HOST.  AdamW hyper-parameters of one parameter group; lr already includes the Eq. 5 factor.
+ * Doubles: the step factors are formed in double on the host before rounding to fp32. */
 typedef struct {
-  float lr, beta1, beta2, eps, weight_decay;
+  double lr, beta1, beta2, eps, weight_decay;
   int64_t step;            /* >= 1: the bias-correction step                                */
 } gsc_adam_hparams;
 
@@ -178,8 +179,8 @@ typedef struct {
   int32_t loss;            /* 0 = L2, 1 = HDR (Eq. 4)                                      */
   int32_t train;           /* 0: render only (no backward, no optimiser step)              */
   uint32_t viewport_frames;/* t >= 1 of Eq. 5                                               */
-  float lr[5];             /* pos, rot, log_scale, rgb, opacity_logit (before Eq. 5)       */
-  float beta1, beta2, eps, weight_decay;
+  double lr[5];            /* pos, rot, log_scale, rgb, opacity_logit (before Eq. 5)       */
+  double beta1, beta2, eps, weight_decay;
 } gsc_frame_request;
 
 /* ---- context ------------------------------------------------------------------------- */

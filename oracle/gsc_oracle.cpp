@@ -671,12 +671,20 @@ void ora_forward(const float* screen, const float* depth, const int32_t* window,
     return ka != kb ? ka < kb : a < b;
   });
   const float ALPHA_MIN = 1.0f / 255.0f;
+  // Boundary flags: the GPU evaluates power, (1 - alpha) and T in the same fp32 operation order,
+  // so its decisions can differ from these only through the exponential (a hardware exp within
+  // EPS_EXP relative of a correctly rounded one for the arguments alpha >= 1/255 allows).  A
+  // pixel is flagged when a decision lies within that uncertainty of its threshold: alpha vs
+  // 1/255, o exp(power) vs the 0.99 clamp, and T (1 - alpha) vs 1e-4, whose relative
+  // uncertainty accumulates EPS_EXP alpha / (1 - alpha) per blended pair.
+  const double EPS_EXP = 5e-7;
   int64_t tests = 0, contrib = 0;
 #pragma omp parallel for schedule(dynamic, 4) reduction(+ : tests, contrib)
   for (int64_t p = 0; p < (int64_t)W * H; ++p) {
     int i = x0 + (int)(p % W), j = y0 + (int)(p / W);
     float T = 1.0f, C[3] = {0.f, 0.f, 0.f};
     int last = -1, nb = 0, bnd = 0;
+    double terr = 0.0;
     int64_t wr = list_off ? list_off[p] : 0;
     for (size_t k = 0; k < live.size(); ++k) {
       int64_t g = live[k];
@@ -686,19 +694,20 @@ void ora_forward(const float* screen, const float* depth, const int32_t* window,
       const float* s = screen + 6 * g;
       float dx = s[0] - (float)i, dy = s[1] - (float)j;
       float power = -0.5f * ((s[2] * dx) * dx + (s[4] * dy) * dy) - (s[3] * dx) * dy;
-      if (std::fabs(power) <= 1e-6f) bnd = 1;
       if (power > 0.0f) continue;
       float e = std::exp(power);
       float oe = s[5] * e;
-      if (std::fabs(oe - 0.99f) <= 2e-6f) bnd = 1;
+      if (std::fabs((double)oe - 0.99) <= EPS_EXP * oe) bnd = 1;
       float alpha = std::fmin(0.99f, oe);
-      if (std::fabs(alpha - ALPHA_MIN) <= 2e-6f * ALPHA_MIN + 1e-9f) bnd = 1;
+      if (std::fabs((double)alpha - (double)ALPHA_MIN) <= EPS_EXP * alpha) bnd = 1;
       if (alpha < ALPHA_MIN) continue;
       float Tn = T * (1.0f - alpha);
-      if (std::fabs(Tn - 1e-4f) <= 1e-4f * 1e-3f) bnd = 1;
+      double da = (oe > 0.99f) ? 0.0 : EPS_EXP * alpha / (1.0 - alpha);
+      if (std::fabs((double)Tn - 1e-4) <= 1e-4 * (terr + da + 1e-7)) bnd = 1;
       if (Tn < 1e-4f) break;
       for (int c = 0; c < 3; ++c) C[c] = C[c] + rgb[3 * g + c] * (alpha * T);
       T = Tn;
+      terr += da;
       last = (int)g;
       ++contrib;
       if (list_off) list_ids[wr++] = (int32_t)g;

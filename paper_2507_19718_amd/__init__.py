@@ -59,6 +59,40 @@ def _f32_cuda(t: torch.Tensor, name: str) -> torch.Tensor:
 # ----------------------------------------------------------------------------------------------
 # Context (with torch's caching allocator as the device-memory hook)
 # ----------------------------------------------------------------------------------------------
+# The allocator hook's C thunks live at module level for the life of the process: library
+# objects (scenes, binnings, context workspaces) may release memory through them during
+# garbage collection, after the Python object that configured them is gone.
+_ALLOC_USERS: Dict[int, tuple] = {}
+
+
+def _torch_alloc(nbytes, user):
+    dev, st = _ALLOC_USERS[int(user or 0)]
+    try:
+        return torch.cuda.caching_allocator_alloc(int(nbytes), dev, st)
+    except Exception:
+        return None
+
+
+def _torch_release(ptr, user):
+    torch.cuda.caching_allocator_delete(int(ptr))
+
+
+_ALLOC_FN = _abi.gsc_allocator._fields_[0][1](_torch_alloc)
+_RELEASE_FN = _abi.gsc_allocator._fields_[1][1](_torch_release)
+
+
+def _destroy_ctx(lib_, h):
+    lib_.gsc_ctx_destroy(h)
+
+
+def _destroy_scene(ctx, h):
+    ctx._lib.gsc_scene_destroy(ctx.handle, h)
+
+
+def _release_binning(ctx, h):
+    ctx._lib.gsc_binning_release(ctx.handle, h)
+
+
 class Context:
     """A library context on one device enqueuing on one stream (default: torch's current)."""
 
@@ -70,20 +104,9 @@ class Context:
         self._alloc = None
         alloc_p = None
         if torch_allocator:
-            dev = device
-            st = self.stream
-
-            def _a(nbytes, user):
-                try:
-                    return torch.cuda.caching_allocator_alloc(int(nbytes), dev, st)
-                except Exception:
-                    return None
-
-            def _r(ptr, user):
-                torch.cuda.caching_allocator_delete(int(ptr))
-
-            self._cb = (_abi.gsc_allocator._fields_[0][1](_a), _abi.gsc_allocator._fields_[1][1](_r))
-            self._alloc = _abi.gsc_allocator(self._cb[0], self._cb[1], None)
+            key = len(_ALLOC_USERS) + 1
+            _ALLOC_USERS[key] = (device, self.stream)
+            self._alloc = _abi.gsc_allocator(_ALLOC_FN, _RELEASE_FN, ctypes.c_void_p(key))
             alloc_p = ctypes.byref(self._alloc)
         h = ctypes.c_void_p()
         st = self._lib.gsc_ctx_create(device, ctypes.c_void_p(self.stream.cuda_stream), alloc_p,
@@ -91,7 +114,10 @@ class Context:
         if st != GSC_OK:
             raise GscError(st, "gsc_ctx_create failed")
         self.handle = h
-        self._finalizer = weakref.finalize(self, self._lib.gsc_ctx_destroy, h)
+        # Objects that belong to this context hold it (through their finalizers) until they are
+        # released; nothing is released at interpreter exit.
+        self._finalizer = weakref.finalize(self, _destroy_ctx, self._lib, h)
+        self._finalizer.atexit = False
 
     def check(self, status: int):
         if status != GSC_OK:
@@ -227,7 +253,8 @@ class Binning:
         self.handle = handle
         self.K = K
         self.cam = cam
-        self._finalizer = weakref.finalize(self, ctx._lib.gsc_binning_release, ctx.handle, handle)
+        self._finalizer = weakref.finalize(self, _release_binning, ctx, handle)
+        self._finalizer.atexit = False
 
     def release(self):
         self._finalizer()
@@ -373,7 +400,8 @@ class Scene:
         ctx.check(ctx._lib.gsc_scene_create(ctx.handle, ctypes.byref(vs), arr, len(levels),
                                             ctypes.byref(h)))
         self.handle = h
-        self._finalizer = weakref.finalize(self, ctx._lib.gsc_scene_destroy, ctx.handle, h)
+        self._finalizer = weakref.finalize(self, _destroy_scene, ctx, h)
+        self._finalizer.atexit = False
 
     def destroy(self):
         self._finalizer()

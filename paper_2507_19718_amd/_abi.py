@@ -72,15 +72,15 @@ class gsc_binning_info(Structure):
 
 
 class gsc_adam_hparams(Structure):
-    _fields_ = [("lr", c_float), ("beta1", c_float), ("beta2", c_float), ("eps", c_float),
-                ("weight_decay", c_float), ("step", c_int64)]
+    _fields_ = [("lr", c_double), ("beta1", c_double), ("beta2", c_double), ("eps", c_double),
+                ("weight_decay", c_double), ("step", c_int64)]
 
 
 class gsc_frame_request(Structure):
     _fields_ = [("cam", gsc_camera), ("trace", gsc_trace_params), ("loss", c_int32),
-                ("train", c_int32), ("viewport_frames", c_uint32), ("lr", c_float * 5),
-                ("beta1", c_float), ("beta2", c_float), ("eps", c_float),
-                ("weight_decay", c_float)]
+                ("train", c_int32), ("viewport_frames", c_uint32), ("lr", c_double * 5),
+                ("beta1", c_double), ("beta2", c_double), ("eps", c_double),
+                ("weight_decay", c_double)]
 
 
 STRUCTS = [gsc_camera, gsc_gaussians, gsc_grads, gsc_volume, gsc_trace_params, gsc_path_record,

@@ -60,7 +60,7 @@ struct TraceDesc {
   float C;
   int32_t C_inf;
   float eps;
-  int64_t pix_off;      // first pixel of this request in the launch
+  int64_t pix_off;      // first launch index of this request (a multiple of the block size)
   float* targets;       // [K][h][w][3]
   void* records;        // [h][w] x 20 B or NULL
 };
@@ -121,8 +121,9 @@ hipError_t launch_splat_backward(hipStream_t st, const Seg* segs, const int64_t*
                                  const uint32_t* n_contrib, const float* dL_dimages,
                                  float* grad2d, int64_t G, int deterministic);
 
+int64_t trace_align(int64_t pixels);
 hipError_t launch_trace(hipStream_t st, const TraceDesc* descs, const int64_t* req_pstart, int R,
-                        int64_t total_pixels, unsigned long long* path_vertices);
+                        int64_t total_launch, unsigned long long* path_vertices);
 
 int loss_num_partials(int64_t pixels);
 hipError_t launch_loss_composite(hipStream_t st, const float* images, const float* targets,

@@ -6,10 +6,11 @@
 // histogram is computed from the Gaussians' tile rectangles, so no key or per-instance
 // temporary is ever written: every instance costs one 4-byte id store.
 //
-//   count  : one wavefront per (segment, chunk of kChunk depth-ordered Gaussians, tile row,
-//            block of 64 tile columns).  Lanes own tile columns.  The wave tests 64 Gaussians
-//            at a time against its row (ballot), then walks the hits in depth order; each lane
-//            counts the hits that cover its column.
+//   count  : one workgroup per (segment, chunk of kChunk depth-ordered Gaussians, 4 tile rows,
+//            block of 64 tile columns); the chunk is staged in LDS, each wavefront owns a row
+//            and its lanes own tile columns.  The wave tests 64 Gaussians at a time against its
+//            row (ballot), then walks the hits in depth order; each lane counts the hits that
+//            cover its column.
 //   scan   : per tile, an exclusive scan over chunks; then a scan over all tiles gives each
 //            tile's [start, end) and the instance total.
 //   place  : the count walk again; each lane appends ids to its column's list at its cursor,
@@ -20,8 +21,8 @@ namespace gsc {
 
 namespace {
 
-struct BinWork {          // per segment, for the wave -> work item map
-  int64_t wave_start;     // first wave of this segment
+struct BinWork {          // per segment, for the workgroup -> work item map
+  int64_t wave_start;     // first workgroup of this segment
   int64_t g_off;
   int64_t n;
   int64_t tile_base;
@@ -41,10 +42,15 @@ __global__ void __launch_bounds__(256) gather_rect_kernel(const int64_t* __restr
   rect_sorted[i] = rect[seg_gstart[s] + sorted_ids[i]];
 }
 
+// One workgroup per (segment, chunk, group of 4 tile rows, block of 64 tile columns); wave w
+// owns row 4 g + w.  The chunk's depth-ordered rects (and ids when placing) are staged in LDS
+// once and scanned by all four waves.
+constexpr int kRowsPerGroup = 4;
+
 template <bool kPlace>
 __global__ void __launch_bounds__(256) bin_walk_kernel(const BinWork* __restrict__ work,
-                                                       const int64_t* __restrict__ wave_start, int S,
-                                                       int64_t total_waves,
+                                                       const int64_t* __restrict__ block_start, int S,
+                                                       int64_t total_blocks,
                                                        const uint32_t* __restrict__ sorted_ids,
                                                        const uint64_t* __restrict__ rect_sorted,
                                                        uint32_t* __restrict__ counts,
@@ -52,19 +58,32 @@ __global__ void __launch_bounds__(256) bin_walk_kernel(const BinWork* __restrict
                                                        const uint64_t* __restrict__ n_instances,
                                                        uint64_t capacity,
                                                        uint32_t* __restrict__ values) {
-  const int64_t wv = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-  if (wv >= total_waves) return;
+  __shared__ uint64_t sh_rect[kChunk];
+  __shared__ uint32_t sh_id[kPlace ? kChunk : 1];
+  const int64_t blk = blockIdx.x;
+  if (blk >= total_blocks) return;
   if (kPlace && *n_instances > capacity) return;
   const int lane = __lane_id();
-  const int s = find_segment(wave_start, S, wv);
+  const int wave = threadIdx.x >> 6;
+  const int s = find_segment(block_start, S, blk);
   const BinWork W = work[s];
-  int64_t l = wv - W.wave_start;
+  int64_t l = blk - W.wave_start;
   const int cb = (int)(l % W.CB);
   l /= W.CB;
-  const int ty = (int)(l % W.TY);
-  const int c = (int)(l / W.TY);
+  const int RG = (W.TY + kRowsPerGroup - 1) / kRowsPerGroup;
+  const int rg = (int)(l % RG);
+  const int c = (int)(l / RG);
   const int64_t g0 = (int64_t)c * kChunk;
   const int cnt_g = (int)((W.n - g0) < kChunk ? (W.n - g0) : kChunk);
+  const uint64_t* rs = rect_sorted + W.g_off + g0;
+  const uint32_t* ids = sorted_ids + W.g_off + g0;
+  for (int k = threadIdx.x; k < cnt_g; k += 256) {
+    sh_rect[k] = rs[k];
+    if (kPlace) sh_id[k] = ids[k];
+  }
+  __syncthreads();
+  const int ty = rg * kRowsPerGroup + wave;
+  if (ty >= W.TY) return;
   const int cbs = cb * 64, cbe = cbs + 63;
   const int col = cbs + lane;
   const bool col_ok = col < W.TX;
@@ -73,16 +92,10 @@ __global__ void __launch_bounds__(256) bin_walk_kernel(const BinWork* __restrict
   uint32_t count = 0u;
   uint64_t cursor = 0ull;
   if (kPlace && col_ok) cursor = tile_start[W.tile_base + (int64_t)ty * W.TX + col] + counts[cidx];
-  const uint64_t* rs = rect_sorted + W.g_off + g0;
-  const uint32_t* ids = sorted_ids + W.g_off + g0;
   for (int j = 0; j < cnt_g; j += 64) {
     const int k = j + lane;
     uint64_t r = 0x0000000100000001ull;
-    uint32_t id = 0u;
-    if (k < cnt_g) {
-      r = rs[k];
-      if (kPlace) id = ids[k];
-    }
+    if (k < cnt_g) r = sh_rect[k];
     const uint32_t xr = (uint32_t)r;
     const int tx0 = (int)(xr & 0xffffu), tx1 = (int)(xr >> 16);
     const int ty0 = (int)((r >> 32) & 0xffffu), ty1 = (int)(r >> 48);
@@ -95,8 +108,7 @@ __global__ void __launch_bounds__(256) bin_walk_kernel(const BinWork* __restrict
       const int hx0 = (int)(hx & 0xffffu), hx1 = (int)(hx >> 16);
       if (col >= hx0 && col <= hx1) {
         if (kPlace) {
-          const uint32_t hid = (uint32_t)__builtin_amdgcn_readlane((int)id, b);
-          values[cursor] = hid;
+          values[cursor] = sh_id[j + b];
           ++cursor;
         } else {
           ++count;
@@ -273,7 +285,7 @@ int64_t bin_fill_work(void* host, const Seg* segs, int S, int64_t* total_chunk_t
     W[s].CB = (g.TX + 63) / 64;
     W[s].n_chunks = (int32_t)((g.n + kChunk - 1) / kChunk);
     ws[s] = waves;
-    waves += (int64_t)W[s].n_chunks * g.TY * W[s].CB;
+    waves += (int64_t)W[s].n_chunks * ((g.TY + kRowsPerGroup - 1) / kRowsPerGroup) * W[s].CB;
     ct += (int64_t)W[s].n_chunks * g.TX * g.TY;
   }
   *total_chunk_tiles = ct;
@@ -295,7 +307,7 @@ hipError_t launch_bin_count(hipStream_t st, const void* work_dev, int S, int64_t
   if (total_waves == 0) return hipSuccess;
   const BinWork* W = (const BinWork*)work_dev;
   const int64_t* ws = (const int64_t*)(W + S);
-  hipLaunchKernelGGL(bin_walk_kernel<false>, dim3(nblk(total_waves, 4)), dim3(256), 0, st, W, ws, S,
+  hipLaunchKernelGGL(bin_walk_kernel<false>, dim3((unsigned)total_waves), dim3(256), 0, st, W, ws, S,
                      total_waves, sorted_ids, rect_sorted, counts, nullptr, nullptr, 0ull, nullptr);
   return hipGetLastError();
 }
@@ -327,7 +339,7 @@ hipError_t launch_bin_place(hipStream_t st, const void* work_dev, int S, int64_t
   if (total_waves == 0) return hipSuccess;
   const BinWork* W = (const BinWork*)work_dev;
   const int64_t* ws = (const int64_t*)(W + S);
-  hipLaunchKernelGGL(bin_walk_kernel<true>, dim3(nblk(total_waves, 4)), dim3(256), 0, st, W, ws, S,
+  hipLaunchKernelGGL(bin_walk_kernel<true>, dim3((unsigned)total_waves), dim3(256), 0, st, W, ws, S,
                      total_waves, sorted_ids, rect_sorted, counts, tile_start, n_instances,
                      capacity, values);
   return hipGetLastError();

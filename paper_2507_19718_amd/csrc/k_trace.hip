@@ -17,6 +17,7 @@ namespace gsc {
 namespace {
 
 constexpr uint32_t kMaxSteps = 1u << 20;   // per free-flight / shadow segment (never reached)
+constexpr int kTraceBlock = 256;
 
 struct Vol {
   const float* d;
@@ -110,7 +111,8 @@ struct PathResult {
   uint32_t n, kind;
 };
 
-__device__ PathResult trace_path(const TraceDesc& D, const Vol& V, int px, int py, uint32_t sample) {
+__device__ PathResult trace_path(const TraceDesc& D, const Vol& V, const float* lights, int px,
+                                 int py, uint32_t sample) {
   PathResult res{0.0f, 0.0f, 0.0f, 1.0f, 0u, 0u};
   const DevCam& cam = D.cam;
   PathStream rng(D.seed, (uint32_t)py * (uint32_t)cam.full_w + (uint32_t)px, sample, D.frame);
@@ -156,7 +158,7 @@ __device__ PathResult trace_path(const TraceDesc& D, const Vol& V, int px, int p
     raw0 = raw0 * ar; raw1 = raw1 * ag; raw2 = raw2 * ab;
     tr0 = tr0 * ar; tr1 = tr1 * ag; tr2 = tr2 * ab;
     for (int l = 0; l < D.n_lights; ++l) {
-      const float* lp = D.lights + 6 * l;
+      const float* lp = lights + 6 * l;
       const float dl0 = lp[0] - x, dl1 = lp[1] - y, dl2 = lp[2] - z;
       const float dist2 = (dl0 * dl0 + dl1 * dl1) + dl2 * dl2;
       const float dist = sqrtf(dist2);
@@ -211,59 +213,68 @@ __device__ PathResult trace_path(const TraceDesc& D, const Vol& V, int px, int p
   return res;
 }
 
-__global__ void __launch_bounds__(256) trace_kernel(const TraceDesc* __restrict__ descs,
-                                                    const int64_t* __restrict__ req_pstart, int R,
-                                                    int64_t total, unsigned long long* path_vertices) {
-  const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (p >= total) return;
-  const int r = find_segment(req_pstart, R, p);
+// Each request's pixels start at a multiple of kTraceBlock in the launch index space, so a
+// workgroup never straddles two requests: the request index is workgroup-uniform (scalar
+// descriptor loads) and the transfer function and lights are staged once in LDS.
+__global__ void __launch_bounds__(kTraceBlock) trace_kernel(const TraceDesc* __restrict__ descs,
+                                                            const int64_t* __restrict__ req_pstart,
+                                                            int R, unsigned long long* path_vertices) {
+  __shared__ float s_tf[kMaxTf * 4];
+  __shared__ float s_lights[kMaxLights * 6];
+  const int64_t block0 = (int64_t)blockIdx.x * kTraceBlock;
+  const int r = find_segment(req_pstart, R, block0);
   const TraceDesc& D = descs[r];
-  const Vol V{D.density, D.nx, D.ny, D.nz, D.dmax, D.tf, D.P};
-  const int64_t lp = p - D.pix_off;
+  for (int i = threadIdx.x; i < 4 * D.P; i += kTraceBlock) s_tf[i] = D.tf[i];
+  for (int i = threadIdx.x; i < 6 * D.n_lights; i += kTraceBlock) s_lights[i] = D.lights[i];
+  __syncthreads();
   const int W = D.cam.w, H = D.cam.h;
-  const int lx = (int)(lp % W), ly = (int)(lp / W);
-  const int px = D.cam.x0 + lx, py = D.cam.y0 + ly;
   const int64_t plane = (int64_t)W * H;
-  const uint32_t K = D.K;
+  const int64_t lp = block0 + threadIdx.x - D.pix_off;
   uint64_t verts = 0;
-  if (D.spp == 1u) {
-    const PathResult pr = trace_path(D, V, px, py, 0u);
-    verts = pr.n;
-    const uint32_t lvl = pr.n ? (min(pr.n, K) - 1u) : 0xFFFFFFFFu;
-    for (uint32_t l = 0; l < K; ++l) {
-      float* o = D.targets + 3 * (l * plane + lp);
-      const bool mine = (l == lvl);
-      o[0] = mine ? pr.L0 : 0.0f;
-      o[1] = mine ? pr.L1 : 0.0f;
-      o[2] = mine ? pr.L2 : 0.0f;
-    }
-    if (D.records) {
-      uint32_t* rec = (uint32_t*)D.records + 5 * lp;
-      rec[0] = __float_as_uint(pr.L0);
-      rec[1] = __float_as_uint(pr.L1);
-      rec[2] = __float_as_uint(pr.L2);
-      rec[3] = __float_as_uint(pr.beta);
-      rec[4] = pr.n | (pr.kind << 16);
-    }
-  } else {
-    for (uint32_t l = 0; l < K; ++l) {
-      float* o = D.targets + 3 * (l * plane + lp);
-      o[0] = 0.0f; o[1] = 0.0f; o[2] = 0.0f;
-    }
-    for (uint32_t smp = 0; smp < D.spp; ++smp) {
-      const PathResult pr = trace_path(D, V, px, py, smp);
-      verts += pr.n;
-      if (pr.n) {
-        float* o = D.targets + 3 * ((min(pr.n, K) - 1u) * plane + lp);
-        o[0] = o[0] + pr.L0;
-        o[1] = o[1] + pr.L1;
-        o[2] = o[2] + pr.L2;
+  if (lp < plane) {
+    const Vol V{D.density, D.nx, D.ny, D.nz, D.dmax, s_tf, D.P};
+    const int lx = (int)(lp % W), ly = (int)(lp / W);
+    const int px = D.cam.x0 + lx, py = D.cam.y0 + ly;
+    const uint32_t K = D.K;
+    if (D.spp == 1u) {
+      const PathResult pr = trace_path(D, V, s_lights, px, py, 0u);
+      verts = pr.n;
+      const uint32_t lvl = pr.n ? (min(pr.n, K) - 1u) : 0xFFFFFFFFu;
+      for (uint32_t l = 0; l < K; ++l) {
+        float* o = D.targets + 3 * (l * plane + lp);
+        const bool mine = (l == lvl);
+        o[0] = mine ? pr.L0 : 0.0f;
+        o[1] = mine ? pr.L1 : 0.0f;
+        o[2] = mine ? pr.L2 : 0.0f;
       }
-    }
-    const float fs = (float)D.spp;
-    for (uint32_t l = 0; l < K; ++l) {
-      float* o = D.targets + 3 * (l * plane + lp);
-      o[0] = o[0] / fs; o[1] = o[1] / fs; o[2] = o[2] / fs;
+      if (D.records) {
+        uint32_t* rec = (uint32_t*)D.records + 5 * lp;
+        rec[0] = __float_as_uint(pr.L0);
+        rec[1] = __float_as_uint(pr.L1);
+        rec[2] = __float_as_uint(pr.L2);
+        rec[3] = __float_as_uint(pr.beta);
+        rec[4] = pr.n | (pr.kind << 16);
+      }
+    } else {
+      for (uint32_t l = 0; l < K; ++l) {
+        float* o = D.targets + 3 * (l * plane + lp);
+        o[0] = 0.0f; o[1] = 0.0f; o[2] = 0.0f;
+      }
+      for (uint32_t smp = 0; smp < D.spp; ++smp) {
+        const PathResult pr = trace_path(D, V, s_lights, px, py, smp);
+        verts += pr.n;
+        if (pr.n) {
+          float* o = D.targets + 3 * ((min(pr.n, K) - 1u) * plane + lp);
+          o[0] = o[0] + pr.L0;
+          o[1] = o[1] + pr.L1;
+          o[2] = o[2] + pr.L2;
+        }
+      }
+      const float fs = (float)D.spp;
+      for (uint32_t l = 0; l < K; ++l) {
+        float* o = D.targets + 3 * (l * plane + lp);
+        o[0] = o[0] / fs; o[1] = o[1] / fs; o[2] = o[2] / fs;
+      }
     }
   }
   if (path_vertices) {
@@ -271,17 +282,21 @@ __global__ void __launch_bounds__(256) trace_kernel(const TraceDesc* __restrict_
     unsigned long long v = verts;
 #pragma unroll
     for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
-    if (__lane_id() == 0) atomicAdd(path_vertices, v);
+    if (__lane_id() == 0 && v) atomicAdd(path_vertices, v);
   }
 }
 
 }  // namespace
 
+int64_t trace_align(int64_t pixels) { return (pixels + kTraceBlock - 1) / kTraceBlock * kTraceBlock; }
+
+// total_launch: the sum over requests of trace_align(w h); each request's pix_off and
+// req_pstart entry are its aligned start in that space.
 hipError_t launch_trace(hipStream_t st, const TraceDesc* descs, const int64_t* req_pstart, int R,
-                        int64_t total_pixels, unsigned long long* path_vertices) {
-  if (total_pixels == 0) return hipSuccess;
-  hipLaunchKernelGGL(trace_kernel, dim3((unsigned)((total_pixels + 255) / 256)), dim3(256), 0, st,
-                     descs, req_pstart, R, total_pixels, path_vertices);
+                        int64_t total_launch, unsigned long long* path_vertices) {
+  if (total_launch == 0) return hipSuccess;
+  hipLaunchKernelGGL(trace_kernel, dim3((unsigned)(total_launch / kTraceBlock)), dim3(kTraceBlock), 0,
+                     st, descs, req_pstart, R, path_vertices);
   return hipGetLastError();
 }
 

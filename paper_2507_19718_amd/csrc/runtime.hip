@@ -615,15 +615,17 @@ gsc_status render_batch(gsc_ctx* ctx, gsc_scene* const* scenes, const gsc_frame_
   // ---- trace on the side stream (independent of the cache) --------------------------------------
   std::vector<TraceDesc> td(n);
   std::vector<int64_t> tstart(n);
+  int64_t tlaunch = 0;
   for (int i = 0; i < n; ++i) {
     gsc_scene* sc = scenes[i];
     td[i] = make_trace_desc(sc->density, sc->nx, sc->ny, sc->nz, sc->dmax, sc->tf.data(),
                             (int)sc->tf.size() / 4, sc->lights.data(), (int)sc->lights.size() / 6,
                             reqs[i].cam, reqs[i].trace);
-    td[i].pix_off = rec_base[i];
+    td[i].pix_off = tlaunch;
     td[i].targets = ctx->targets.as<float>() + 3 * pix_base[i];
     td[i].records = (char*)ctx->records.p + sizeof(gsc_path_record) * rec_base[i];
-    tstart[i] = rec_base[i];
+    tstart[i] = tlaunch;
+    tlaunch += trace_align((int64_t)reqs[i].cam.w * reqs[i].cam.h);
   }
   const size_t tbytes = sizeof(TraceDesc) * n + sizeof(int64_t) * n;
   need(ctx, ctx->trace_tab, a, tbytes, "trace descriptors");
@@ -637,7 +639,7 @@ gsc_status render_batch(gsc_ctx* ctx, gsc_scene* const* scenes, const gsc_frame_
   if (timing) GSC_TRY(hipEventRecord(ctx->tev[6], ctx->side));
   { ProfScope ps_(ctx, P_TRACE, ctx->side);
   GSC_TRY(launch_trace(ctx->side, ctx->trace_tab.as<TraceDesc>(),
-                       (const int64_t*)((char*)ctx->trace_tab.p + sizeof(TraceDesc) * n), n, rpix,
+                       (const int64_t*)((char*)ctx->trace_tab.p + sizeof(TraceDesc) * n), n, tlaunch,
                        ctx->vertices.as<unsigned long long>()));
   }
   if (timing) GSC_TRY(hipEventRecord(ctx->tev[7], ctx->side));
@@ -848,8 +850,8 @@ gsc_status gsc_trace_targets(gsc_ctx* ctx, const gsc_volume* vol, const gsc_came
     const int64_t P = (int64_t)cam->w * cam->h;
   { ProfScope ps_(ctx, P_TRACE, st);
   GSC_TRY(launch_trace(st, ctx->trace_tab.as<TraceDesc>(),
-                         (const int64_t*)((char*)ctx->trace_tab.p + sizeof(TraceDesc)), 1, P,
-                         ctx->vertices.as<unsigned long long>()));
+                         (const int64_t*)((char*)ctx->trace_tab.p + sizeof(TraceDesc)), 1,
+                         trace_align(P), ctx->vertices.as<unsigned long long>()));
   }
     if (stats) {
       GSC_TRY(hipEventRecord(ctx->tev[7], st));
@@ -1021,7 +1023,7 @@ gsc_status gsc_adam_step(gsc_ctx* ctx, float* param, float* m, float* v, const f
     if (count < 0) invalid(ctx, "count must be >= 0");
     if (count > 0 && (!param || !m || !v || !grad)) invalid(ctx, "NULL argument");
     if (hp->step < 1) invalid(ctx, "step must be >= 1");
-    if (!(hp->beta1 >= 0.0f && hp->beta1 < 1.0f) || !(hp->beta2 >= 0.0f && hp->beta2 < 1.0f))
+    if (!(hp->beta1 >= 0.0 && hp->beta1 < 1.0) || !(hp->beta2 >= 0.0 && hp->beta2 < 1.0))
       invalid(ctx, "betas must be in [0, 1)");
     if (!std::isfinite(hp->lr) || !std::isfinite(hp->eps) || !std::isfinite(hp->weight_decay))
       invalid(ctx, "hyper-parameters must be finite");

@@ -106,18 +106,48 @@ class ContinuousBatcher:
     def __init__(self, scenes: Sequence[SceneSpec], slots: int = 2, hbm_budget: Optional[int] = None,
                  instance_estimate: Callable[[Request], int] = lambda r: 0,
                  max_batch: int = 8,
-                 before_launch: Optional[Callable[[List[Request]], None]] = None):
+                 before_launch: Optional[Callable[[int, List[Request]], None]] = None,
+                 executor: Optional[Callable[[int, List[Request]], None]] = None,
+                 footprint: Optional[Callable[[Request], int]] = None,
+                 after_batch: Optional[Callable[[int, List[Request], List[torch.Tensor]], None]] = None):
+        """executor(slot, batch) runs a batch to completion (default: gsc_render_frames on the
+        slot's context, then a stream synchronise); footprint(r) gives a request's transient
+        bytes (default: gsc_frame_footprint_bytes of its scene).  before_launch(slot, batch)
+        runs on the scheduler thread before a batch starts; after_batch(slot, batch, images)
+        after the default executor finished it (for snapshots in tests)."""
         self.scenes = scenes
-        self.slots = [Context(0, torch.cuda.Stream()) for _ in range(slots)]
+        self.n_slots = slots
         self.budget = hbm_budget
         self.estimate = instance_estimate
         self.max_batch = max_batch
         self.before_launch = before_launch
-        self.images: Dict[tuple, List[torch.Tensor]] = {}
+        self.after_batch = after_batch
+        self._footprint = footprint
+        self.executor = executor if executor is not None else self._gpu_executor
+        self.slots = [Context(0, torch.cuda.Stream()) for _ in range(slots)] if executor is None else []
+        self.images: Dict[tuple, torch.Tensor] = {}
+        self.batches: List[List[int]] = []
 
     def footprint(self, r: Request) -> int:
+        if self._footprint is not None:
+            return self._footprint(r)
         sc = self.scenes[r.scene].scene
         return sc.frame_footprint_bytes(r.cam.w, r.cam.h, self.estimate(r))
+
+    def _gpu_executor(self, slot: int, batch: List[Request]):
+        ctx = self.slots[slot]
+        images = []
+        for k, r in enumerate(batch):
+            key = (slot, k, r.cam.h, r.cam.w)
+            if key not in self.images:
+                self.images[key] = torch.empty((r.cam.h, r.cam.w, 3), device="cuda")
+            images.append(self.images[key])
+        with torch.cuda.stream(ctx.stream):
+            gsc_render_frames(ctx, [self.scenes[r.scene].scene for r in batch],
+                              [_req_struct(self.scenes[r.scene], r) for r in batch], images)
+            ctx.synchronize()
+            if self.after_batch:
+                self.after_batch(slot, batch, images)
 
     def run(self, reqs: Sequence[Request], realtime: bool = True) -> dict:
         pending = collections.deque()                 # arrived, not started (arrival order)
@@ -125,18 +155,14 @@ class ContinuousBatcher:
         busy_scenes = set()
         in_use = 0
         lock = threading.Condition()
-        free_slots = list(range(len(self.slots)))
+        free_slots = list(range(self.n_slots))
         done_batches = collections.deque()
         errors = []
         t0 = time.perf_counter()
 
-        def worker(slot: int, batch: List[Request], images: List[torch.Tensor]):
-            ctx = self.slots[slot]
+        def worker(slot: int, batch: List[Request]):
             try:
-                with torch.cuda.stream(ctx.stream):
-                    gsc_render_frames(ctx, [self.scenes[r.scene].scene for r in batch],
-                                      [_req_struct(self.scenes[r.scene], r) for r in batch], images)
-                    ctx.synchronize()
+                self.executor(slot, batch)
             except Exception as e:  # surfaced after the run
                 errors.append(e)
             t = time.perf_counter() - t0
@@ -187,15 +213,10 @@ class ContinuousBatcher:
                             busy_scenes.add(r.scene)
                             in_use += self.footprint(r)
                             r.t_start = now
-                        images = []
-                        for k, r in enumerate(batch):
-                            key = (slot, k, r.cam.h, r.cam.w)
-                            if key not in self.images:
-                                self.images[key] = torch.empty((r.cam.h, r.cam.w, 3), device="cuda")
-                            images.append(self.images[key])
+                        self.batches.append([r.idx for r in batch])
                         if self.before_launch:
-                            self.before_launch(batch)
-                        th = threading.Thread(target=worker, args=(slot, batch, images), daemon=True)
+                            self.before_launch(slot, batch)
+                        th = threading.Thread(target=worker, args=(slot, batch), daemon=True)
                         th.start()
                         threads.append(th)
                         launched = True

@@ -166,7 +166,8 @@ def test_autograd_function_matches_direct_backward(gsc, gctx):
     gsc.gsc_splat_backward(gctx, b, levels, cam, T2, last2, w.contiguous(), grads)
     for l in range(2):
         for k in gsc.PARAM_NAMES:
-            good, info = grads_close(to_np(leaf[l][k].grad), to_np(grads[l][k]), tol=1e-5)
+            # Both are the GPU's fp32 gradient; they differ only in float-atomic order.
+            good, info = grads_close(to_np(leaf[l][k].grad), to_np(grads[l][k]), tol=1e-4)
             assert good, (l, k, info)
 
 
