@@ -292,6 +292,8 @@ def main():
         "cpu_baseline": cpu,
         "kernels": kernels,
         "counters": {"instances_per_frame": int(per_frame_inst), "gaussians": int(c["gaussians"]),
+                     "gaussian_pixel_evals_per_frame": int(cnt["evaluations"] / args.steps),
+                     "gaussian_pixel_evals_per_s": round(cnt["evaluations"] / elapsed, 1),
                      "paths_per_frame": int(c["paths"]),
                      "path_vertices_per_frame": int(stats["path_vertices"]),
                      "paths_per_s": round(c["paths"] * fps, 1)},

@@ -203,8 +203,11 @@ gsc_status gsc_ctx_profile(gsc_ctx* ctx, int32_t on);
  * GSC_E_INVALID_ARG past the last index. */
 gsc_status gsc_ctx_profile_read(gsc_ctx* ctx, int32_t index, char* name, size_t name_len,
                                 double* total_ms, int64_t* launches);
-/* Instances binned and binnings run since profiling was last turned on (HOST). */
-gsc_status gsc_ctx_counters(gsc_ctx* ctx, uint64_t* instances, uint64_t* binnings);
+/* Since profiling was last turned on (HOST): instances binned, binnings run, and Gaussian-pixel
+ * evaluations of the splat forward (per pixel, the tile-list entries it examined before it
+ * finished, summed over pixels).  Synchronises. */
+gsc_status gsc_ctx_counters(gsc_ctx* ctx, uint64_t* instances, uint64_t* binnings,
+                            uint64_t* evaluations);
 /* Frees the context's cached workspace (binning buffers, frame scratch). */
 gsc_status gsc_ctx_trim(gsc_ctx* ctx);
 

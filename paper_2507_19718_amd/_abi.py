@@ -100,7 +100,7 @@ _SIGNATURES = {
     "gsc_ctx_profile": (c_int32, [c_void_p, c_int32]),
     "gsc_ctx_profile_read": (c_int32, [c_void_p, c_int32, ctypes.c_char_p, c_size_t, P(c_double),
                                        P(c_int64)]),
-    "gsc_ctx_counters": (c_int32, [c_void_p, P(c_uint64), P(c_uint64)]),
+    "gsc_ctx_counters": (c_int32, [c_void_p, P(c_uint64), P(c_uint64), P(c_uint64)]),
     "gsc_trace_targets": (c_int32, [c_void_p, P(gsc_volume), P(gsc_camera), P(gsc_trace_params),
                                     c_void_p, c_void_p, P(gsc_frame_stats)]),
     "gsc_project_bin": (c_int32, [c_void_p, P(gsc_gaussians), c_int32, P(gsc_camera), c_uint64,

@@ -81,6 +81,7 @@ hipError_t launch_project_backward(hipStream_t st, const Seg* segs, const int64_
 hipError_t launch_fill_u32(hipStream_t st, uint32_t* p, uint32_t value, int64_t count);
 
 size_t sort_table_bytes(int n_blocks, int S);
+size_t sort_hist_words(int n_blocks, int S);
 int sort_count_blocks(const int64_t* seg_n, int S);
 void sort_fill_table(void* host, const int64_t* seg_n, const int64_t* seg_off, int S);
 hipError_t launch_segmented_sort(hipStream_t st, const void* table_dev, int n_blocks, int S,
@@ -114,7 +115,8 @@ hipError_t launch_view(hipStream_t st, int64_t G, const SplatRec* rec, const uin
 hipError_t launch_splat_forward(hipStream_t st, const Seg* segs, const int64_t* seg_tstart, int S,
                                 const DevCam* cams, int64_t n_tiles, const uint64_t* ranges,
                                 const uint32_t* values, const SplatRec* rec, float* images,
-                                float* final_T, int32_t* last_id, uint32_t* n_contrib);
+                                float* final_T, int32_t* last_id, uint32_t* n_contrib,
+                                unsigned long long* evals);
 hipError_t launch_splat_backward(hipStream_t st, const Seg* segs, const int64_t* seg_tstart, int S,
                                  const DevCam* cams, int64_t n_tiles, const uint64_t* ranges,
                                  const uint32_t* values, const SplatRec* rec, const float* final_T,

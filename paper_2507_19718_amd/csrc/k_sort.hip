@@ -4,10 +4,10 @@
 // are the four low digits of the (tile << 32 | depth) instance key, sorted once per Gaussian
 // instead of once per instance; the tile digit is applied by the binning placement pass.
 //
-// Per pass: (1) per-block digit histograms, (2) per-segment digit-major exclusive scan over
-// blocks, (3) stable scatter: items are taken in index order, 256 per round, and ranked within
-// a 64-wide wavefront by eight ballots (lanes with equal digits), then across the block's four
-// wavefronts in LDS.
+// Per pass: (1) per-block digit histograms, (2) per (segment, digit) exclusive scans over the
+// segment's blocks and a per-segment scan of the digit totals, (3) stable scatter: items are
+// taken in index order, 256 per round, and ranked within a 64-wide wavefront by eight ballots
+// (lanes with equal digits), then across the block's four wavefronts in LDS.
 #include "gsc_dev.h"
 
 namespace gsc {
@@ -27,7 +27,8 @@ struct SortBlock {
 
 __global__ void __launch_bounds__(kSortThreads) sort_hist_kernel(const SortBlock* __restrict__ blocks,
                                                                  const uint32_t* __restrict__ keys,
-                                                                 int shift, uint32_t* __restrict__ hist) {
+                                                                 int shift, uint32_t* __restrict__ hist,
+                                                                 int n_blocks) {
   __shared__ uint32_t cnt[256];
   const SortBlock B = blocks[blockIdx.x];
   cnt[threadIdx.x] = 0u;
@@ -37,39 +38,58 @@ __global__ void __launch_bounds__(kSortThreads) sort_hist_kernel(const SortBlock
     if (k < B.count) atomicAdd(&cnt[(keys[B.start + k] >> shift) & 0xffu], 1u);
   }
   __syncthreads();
-  hist[(int64_t)blockIdx.x * 256 + threadIdx.x] = cnt[threadIdx.x];
+  hist[(int64_t)threadIdx.x * n_blocks + blockIdx.x] = cnt[threadIdx.x];
 }
 
-// One workgroup per segment; thread d owns digit d.
-__global__ void __launch_bounds__(256) sort_scan_kernel(const int32_t* __restrict__ seg_first_block,
-                                                        uint32_t* __restrict__ hist) {
-  __shared__ uint32_t tot[256];
-  const int s = blockIdx.x;
+// One workgroup per (segment, digit): exclusive scan of the digit's per-block counts over the
+// segment's blocks (in place, digit-local offsets) and the digit total.
+__global__ void __launch_bounds__(256) sort_scan_digit_kernel(const int32_t* __restrict__ seg_first_block,
+                                                              uint32_t* __restrict__ hist, int n_blocks,
+                                                              uint32_t* __restrict__ dtot) {
+  __shared__ uint32_t tmp[256];
+  const int s = blockIdx.x >> 8, d = blockIdx.x & 255;
   const int b0 = seg_first_block[s], b1 = seg_first_block[s + 1];
-  const int d = threadIdx.x;
-  uint32_t t = 0u;
-  for (int b = b0; b < b1; ++b) t += hist[(int64_t)b * 256 + d];
-  tot[d] = t;
+  uint32_t* h = hist + (int64_t)d * n_blocks;
+  uint32_t carry = 0u;
+  for (int base = b0; base < b1; base += 256) {
+    const int b = base + (int)threadIdx.x;
+    const uint32_t v = (b < b1) ? h[b] : 0u;
+    tmp[threadIdx.x] = v;
+    __syncthreads();
+    for (int off = 1; off < 256; off <<= 1) {
+      const uint32_t a = (threadIdx.x >= (unsigned)off) ? tmp[threadIdx.x - off] : 0u;
+      __syncthreads();
+      tmp[threadIdx.x] += a;
+      __syncthreads();
+    }
+    if (b < b1) h[b] = carry + tmp[threadIdx.x] - v;
+    carry += tmp[255];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) dtot[s * 256 + d] = carry;
+}
+
+// One workgroup per segment: exclusive scan of the 256 digit totals -> digit bases.
+__global__ void __launch_bounds__(256) sort_scan_base_kernel(uint32_t* __restrict__ dtot) {
+  __shared__ uint32_t tmp[256];
+  const int s = blockIdx.x, d = threadIdx.x;
+  const uint32_t v = dtot[s * 256 + d];
+  tmp[d] = v;
   __syncthreads();
-  // Exclusive scan over the 256 digit totals (Hillis-Steele in LDS).
   for (int off = 1; off < 256; off <<= 1) {
-    const uint32_t v = (d >= off) ? tot[d - off] : 0u;
+    const uint32_t a = (d >= off) ? tmp[d - off] : 0u;
     __syncthreads();
-    tot[d] += v;
+    tmp[d] += a;
     __syncthreads();
   }
-  uint32_t run = tot[d] - t;
-  for (int b = b0; b < b1; ++b) {
-    const uint32_t v = hist[(int64_t)b * 256 + d];
-    hist[(int64_t)b * 256 + d] = run;
-    run += v;
-  }
+  dtot[s * 256 + d] = tmp[d] - v;
 }
 
 __global__ void __launch_bounds__(kSortThreads) sort_scatter_kernel(
     const SortBlock* __restrict__ blocks, const uint32_t* __restrict__ keys_in,
-    const uint32_t* __restrict__ vals_in, int shift, const uint32_t* __restrict__ hist,
-    uint32_t* __restrict__ keys_out, uint32_t* __restrict__ vals_out) {
+    const uint32_t* __restrict__ vals_in, int shift, const uint32_t* __restrict__ hist, int n_blocks,
+    const uint32_t* __restrict__ dbase, uint32_t* __restrict__ keys_out,
+    uint32_t* __restrict__ vals_out) {
   __shared__ uint32_t run[256];
   __shared__ uint32_t wcnt[4][256];
   const SortBlock B = blocks[blockIdx.x];
@@ -77,7 +97,7 @@ __global__ void __launch_bounds__(kSortThreads) sort_scatter_kernel(
   const int wave = tid >> 6;
   const int lane = __lane_id();
   const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
-  run[tid] = hist[(int64_t)blockIdx.x * 256 + tid];
+  run[tid] = hist[(int64_t)tid * n_blocks + blockIdx.x] + dbase[B.seg * 256 + tid];
   for (int w = 0; w < 4; ++w) wcnt[w][tid] = 0u;
   __syncthreads();
   for (int r = 0; r < kSortRounds; ++r) {
@@ -116,14 +136,12 @@ __global__ void __launch_bounds__(kSortThreads) sort_scatter_kernel(
 }  // namespace
 
 // Host side of the sort: the block table is built from the segment sizes.
-struct SortPlan {
-  int n_blocks = 0;
-  int S = 0;
-};
-
 size_t sort_table_bytes(int n_blocks, int S) {
   return sizeof(SortBlock) * (size_t)n_blocks + sizeof(int32_t) * (size_t)(S + 1);
 }
+
+// Histogram scratch in 32-bit words: [256][n_blocks] counts plus [S][256] digit totals.
+size_t sort_hist_words(int n_blocks, int S) { return 256 * (size_t)n_blocks + 256 * (size_t)S; }
 
 int sort_count_blocks(const int64_t* seg_n, int S) {
   int nb = 0;
@@ -160,11 +178,14 @@ hipError_t launch_segmented_sort(hipStream_t st, const void* table_dev, int n_bl
   uint32_t* kout = keys_tmp; uint32_t* vout = vals_tmp;
   for (int pass = 0; pass < 4; ++pass) {
     const int shift = 8 * pass;
+    uint32_t* dtot = hist + 256 * (size_t)n_blocks;
     hipLaunchKernelGGL(sort_hist_kernel, dim3(n_blocks), dim3(kSortThreads), 0, st, blocks, kin,
-                       shift, hist);
-    hipLaunchKernelGGL(sort_scan_kernel, dim3(S), dim3(256), 0, st, first, hist);
+                       shift, hist, n_blocks);
+    hipLaunchKernelGGL(sort_scan_digit_kernel, dim3(S * 256), dim3(256), 0, st, first, hist,
+                       n_blocks, dtot);
+    hipLaunchKernelGGL(sort_scan_base_kernel, dim3(S), dim3(256), 0, st, dtot);
     hipLaunchKernelGGL(sort_scatter_kernel, dim3(n_blocks), dim3(kSortThreads), 0, st, blocks,
-                       kin, vin, shift, hist, kout, vout);
+                       kin, vin, shift, hist, n_blocks, dtot, kout, vout);
     uint32_t* t;
     t = kin; kin = kout; kout = t;
     t = vin; vin = vout; vout = t;

@@ -145,6 +145,7 @@ struct gsc_ctx {
   double prof_ms[16] = {};
   int64_t prof_n[16] = {};
   uint64_t acc_instances = 0, acc_frames = 0;
+  DevBuf d_evals;                  // device counter of Gaussian-pixel evaluations (forward)
 };
 
 namespace {
@@ -396,7 +397,7 @@ gsc_status run_project_bin(gsc_ctx* ctx, gsc_binning* b, uint64_t capacity_hint)
   need(ctx, b->ids, a, 4 * Gp, "ids");
   need(ctx, b->keys_tmp, a, 4 * Gp, "sort keys");
   need(ctx, b->ids_tmp, a, 4 * Gp, "sort values");
-  need(ctx, b->hist, a, 4 * 256 * (size_t)std::max(b->n_sort_blocks, 1), "sort histograms");
+  need(ctx, b->hist, a, 4 * sort_hist_words(std::max(b->n_sort_blocks, 1), b->S), "sort histograms");
   need(ctx, b->rect_sorted, a, 8 * Gp, "sorted rects");
   need(ctx, b->counts, a, 4 * (size_t)std::max<int64_t>(b->chunk_tiles, 1), "chunk counts");
   need(ctx, b->tile_total, a, 4 * (size_t)std::max<int64_t>(b->n_tiles, 1), "tile totals");
@@ -462,11 +463,15 @@ gsc_status run_project_bin(gsc_ctx* ctx, gsc_binning* b, uint64_t capacity_hint)
 
 void run_forward(gsc_ctx* ctx, gsc_binning* b, float* images, float* final_T, int32_t* last_id) {
   need(ctx, b->n_contrib, b->alloc, 4 * (size_t)std::max<int64_t>(b->pixels, 1), "n_contrib");
+  if (!ctx->d_evals.p) {
+    need(ctx, ctx->d_evals, ctx->alloc, 8, "evaluation counter");
+    GSC_TRY(hipMemsetAsync(ctx->d_evals.p, 0, 8, ctx->stream));
+  }
   { ProfScope ps_(ctx, P_FWD, ctx->stream);
   GSC_TRY(launch_splat_forward(ctx->stream, b->d_segs(), b->d_tstart(), b->S, b->d_cams(), b->n_tiles,
                                b->ranges.as<uint64_t>(), b->values.as<uint32_t>(),
                                b->rec.as<SplatRec>(), images, final_T, last_id,
-                               b->n_contrib.as<uint32_t>()));
+                               b->n_contrib.as<uint32_t>(), ctx->d_evals.as<unsigned long long>()));
   }
   b->forward_done = true;
 }
@@ -773,7 +778,7 @@ void gsc_ctx_destroy(gsc_ctx* c) {
   if (c->frame_bin) { c->frame_bin->free_all(); delete c->frame_bin; }
   DevBuf* all[] = {&c->targets, &c->records, &c->dL, &c->partials, &c->losses, &c->grads14,
                    &c->images, &c->final_T, &c->last_id, &c->trace_tab, &c->vertices,
-                   &c->composite_tmp};
+                   &c->composite_tmp, &c->d_evals};
   for (DevBuf* b : all) b->release(c->alloc);
   if (c->pinned) (void)hipHostFree(c->pinned);
   if (c->host_u64) (void)hipHostFree(c->host_u64);
@@ -1198,6 +1203,8 @@ gsc_status gsc_ctx_profile(gsc_ctx* ctx, int32_t on) {
       for (int i = 0; i < 16; ++i) { ctx->prof_ms[i] = 0.0; ctx->prof_n[i] = 0; }
       ctx->acc_instances = 0;
       ctx->acc_frames = 0;
+      need(ctx, ctx->d_evals, ctx->alloc, 8, "evaluation counter");
+      GSC_TRY(hipMemsetAsync(ctx->d_evals.p, 0, 8, ctx->stream));
     }
     return GSC_OK;
   });
@@ -1216,11 +1223,15 @@ gsc_status gsc_ctx_profile_read(gsc_ctx* ctx, int32_t index, char* name, size_t 
   });
 }
 
-gsc_status gsc_ctx_counters(gsc_ctx* ctx, uint64_t* instances, uint64_t* binnings) {
-  if (!ctx || !instances || !binnings) return GSC_E_INVALID_ARG;
-  *instances = ctx->acc_instances;
-  *binnings = ctx->acc_frames;
-  return GSC_OK;
+gsc_status gsc_ctx_counters(gsc_ctx* ctx, uint64_t* instances, uint64_t* binnings,
+                            uint64_t* evaluations) {
+  return guarded(ctx, [&]() -> gsc_status {
+    if (!instances || !binnings || !evaluations) invalid(ctx, "NULL argument");
+    *instances = ctx->acc_instances;
+    *binnings = ctx->acc_frames;
+    *evaluations = ctx->d_evals.p ? read_u64(ctx, ctx->d_evals.as<uint64_t>()) : 0;
+    return GSC_OK;
+  });
 }
 
 gsc_status gsc_copy(gsc_ctx* ctx, void* dst, const void* src, size_t bytes) {
