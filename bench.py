@@ -55,7 +55,7 @@ def algorithmic_bytes(kernel: str, c: dict) -> float:
         "project": 116.0 * G,            # 56 B params in; 48 B record, 4 B depth, 8 B rect out
         "depth_sort": 4 * 20.0 * G,      # 4 passes: key read (hist), key+id read and write
         "gather_rect": 20.0 * G,
-        "bin_count": 12.0 * G + 4.0 * CT,
+        "bin_count": 8.0 * G + 4.0 * CT,              # rects in, [chunk][tile] counts out
         "bin_scan": 8.0 * CT,
         "bin_place": 4.0 * I + 12.0 * G + 4.0 * CT,   # one 4-byte id per instance
         "splat_forward": 24.0 * P + 8.0 * P,          # image, T, last id, list position; ranges
@@ -66,6 +66,64 @@ def algorithmic_bytes(kernel: str, c: dict) -> float:
         "adam": 14 * 28.0 * G,           # p, m, v, g in; p, m, v out
     }
     return table.get(kernel, 0.0)
+
+
+# Algorithmic fp32 operations of the splat kernels per (pixel, list entry) pair, counted from the
+# blend and its adjoint (the exponential counts as one operation):
+#   test    14: pixel offset (2), quadratic form -(A dx^2 + C dy^2)/2 - B dx dy (9), exp (1),
+#               alpha = min(0.99, o e) (2)
+#   blend   +9: 1 - alpha, T (1 - alpha), alpha T, three colour multiply-adds (6)
+#   adjoint 65: test (14), T / (1 - alpha) with 1 - alpha (2), w = alpha T (1), colour gradients
+#               (6), dL/dalpha = T sum_k (c_k - B_k) g_k (9), background update (9),
+#               dL/dpower (1), opacity (2), conic A, C, B (4 + 4 + 3), mean u, v (5 + 5)
+# The forward tests every entry a pixel examines and blends `blended` of them; the adjoint walks
+# each pixel's list up to its last contributor (`contributors` entries), tests them all and runs
+# the full adjoint on the blended ones.
+F_TEST, F_BLEND, F_ADJOINT = 14.0, 9.0, 65.0
+
+
+def algorithmic_flops(kernel: str, cnt: dict, frames: int) -> float:
+    ev, bl, ncs = (cnt[k] / frames for k in ("evaluations", "blended", "contributors"))
+    if kernel == "splat_forward":
+        return F_TEST * ev + F_BLEND * bl
+    if kernel == "splat_backward":
+        return F_TEST * ncs + (F_ADJOINT - F_TEST) * bl
+    return 0.0
+
+
+ALU_KERNELS = ("splat_forward", "splat_backward")
+KERNEL_SOURCES = {"splat_forward": "k_splat.hip", "splat_backward": "k_splat.hip",
+                  "bin_place": "k_bin.hip", "bin_count": "k_bin.hip", "trace": "k_trace.hip",
+                  "project": "k_project.hip", "depth_sort": "k_sort.hip"}
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "hbm_traffic_fhd_1080p_4x1M.txt")
+
+
+def source_sha(kernel: str):
+    import hashlib
+    src = KERNEL_SOURCES.get(kernel)
+    if src is None:
+        return None
+    with open(os.path.join(ROOT, "paper_2507_19718_amd", "csrc", src), "rb") as f:
+        return hashlib.sha256(f.read()).hexdigest()[:16]
+
+
+def measured_traffic(kernel: str):
+    """HBM bytes per launch of `kernel` from the committed rocprofv3 FETCH_SIZE / WRITE_SIZE
+    summary, scaled by the copy-probe factors; None when the summary is missing or the kernel's
+    source changed since the counters were taken."""
+    if not os.path.exists(TRAFFIC_FILE):
+        return None
+    sha = source_sha(kernel)
+    with open(TRAFFIC_FILE) as f:
+        for line in f:
+            parts = line.split()
+            if len(parts) >= 6 and parts[0] == kernel and not line.startswith("#"):
+                try:
+                    nbytes = float(parts[4])
+                except ValueError:
+                    return None
+                return nbytes if sha is not None and parts[5] == sha else None
+    return None
 
 
 def cpu_baseline(wl, vol, levels, crop=64):
@@ -244,18 +302,39 @@ def main():
         if v["launches"] == 0:
             continue
         per_frame_ms = v["ms"] / args.steps
-        b = algorithmic_bytes(name, c)
-        kernels[name] = {"ms_per_frame": round(per_frame_ms, 4), "launches": v["launches"],
-                         "algorithmic_GBs": round(b / (per_frame_ms * 1e-3) / 1e9, 1) if per_frame_ms > 0 else None}
+        info = {"ms_per_frame": round(per_frame_ms, 4), "launches": v["launches"]}
+        if name in ALU_KERNELS:
+            fl = algorithmic_flops(name, cnt, args.steps)
+            info["algorithmic_TFLOPs"] = round(fl / (per_frame_ms * 1e-3) / 1e12, 2) if per_frame_ms > 0 else None
+        else:
+            b = algorithmic_bytes(name, c)
+            info["algorithmic_GBs"] = round(b / (per_frame_ms * 1e-3) / 1e9, 1) if per_frame_ms > 0 else None
+        kernels[name] = info
     dominant = max(kernels, key=lambda k: kernels[k]["ms_per_frame"])
-    dom = kernels[dominant]
-    dom_bytes = algorithmic_bytes(dominant, c)
     per_launch_ms = prof[dominant]["ms"] / prof[dominant]["launches"]
     launches_per_frame = prof[dominant]["launches"] / args.steps
-    achieved = dom_bytes / launches_per_frame / (per_launch_ms * 1e-3) / 1e9
-    roofline = {"bound": "hbm", "kernel": dominant, "achieved": round(achieved, 1),
-                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": None, "avg_launch_ms": round(per_launch_ms, 4)}
+    traffic = measured_traffic(dominant)
+    if dominant in ALU_KERNELS:
+        per_launch = algorithmic_flops(dominant, cnt, args.steps) / launches_per_frame
+        achieved = per_launch / (per_launch_ms * 1e-3) / 1e12
+        roofline = {"bound": "alu", "achieved": round(achieved, 2), "peak": FP32_PEAK_TFLOPS,
+                    "unit": "TFLOP/s", "frac": round(achieved / FP32_PEAK_TFLOPS, 4)}
+    else:
+        per_launch = algorithmic_bytes(dominant, c) / launches_per_frame
+        achieved = per_launch / (per_launch_ms * 1e-3) / 1e9
+        roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS,
+                    "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4)}
+    roofline.update({"traffic": traffic, "kernel": dominant, "avg_launch_ms": round(per_launch_ms, 4),
+                     "algorithmic_per_launch": per_launch})
+    # Frame-level fraction: sum over kernels of the time their algorithmic work needs at the
+    # vendor peak (bytes at HBM peak, or fp32 operations at the vector peak) over the frame time.
+    t_min = 0.0
+    for name in kernels:
+        if name in ALU_KERNELS:
+            t_min += algorithmic_flops(name, cnt, args.steps) / (FP32_PEAK_TFLOPS * 1e12)
+        else:
+            t_min += algorithmic_bytes(name, c) / (HBM_PEAK_GBS * 1e9)
+    frame_frac = t_min / (ms_step * 1e-3)
 
     cpu = None
     if not args.no_cpu_baseline:
@@ -290,9 +369,13 @@ def main():
                    "parallelism": "single GPU"},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "frame_roofline_frac": round(frame_frac, 4),
         "kernels": kernels,
         "counters": {"instances_per_frame": int(per_frame_inst), "gaussians": int(c["gaussians"]),
                      "gaussian_pixel_evals_per_frame": int(cnt["evaluations"] / args.steps),
+                     "blended_pairs_per_frame": int(cnt["blended"] / args.steps),
+                     "adjoint_walk_pairs_per_frame": int(cnt["contributors"] / args.steps),
+                     "tile_entries_per_frame": int(cnt["tile_entries"] / args.steps),
                      "gaussian_pixel_evals_per_s": round(cnt["evaluations"] / elapsed, 1),
                      "paths_per_frame": int(c["paths"]),
                      "path_vertices_per_frame": int(stats["path_vertices"]),

@@ -203,11 +203,22 @@ gsc_status gsc_ctx_profile(gsc_ctx* ctx, int32_t on);
  * GSC_E_INVALID_ARG past the last index. */
 gsc_status gsc_ctx_profile_read(gsc_ctx* ctx, int32_t index, char* name, size_t name_len,
                                 double* total_ms, int64_t* launches);
-/* Since profiling was last turned on (HOST): instances binned, binnings run, and Gaussian-pixel
- * evaluations of the splat forward (per pixel, the tile-list entries it examined before it
- * finished, summed over pixels).  Synchronises. */
-gsc_status gsc_ctx_counters(gsc_ctx* ctx, uint64_t* instances, uint64_t* binnings,
-                            uint64_t* evaluations);
+/* Work counters since profiling was last turned on (HOST struct).  The splat counters count
+ * pairs of the cache-image forward (the front-to-back blend): per pixel, `evaluations` sums the
+ * list entries it examined before it finished (its termination position, or the list length),
+ * `blended` the entries it blended (alpha >= 1/255 before termination) and `contributors` the
+ * position of its last blended entry (the length of the adjoint's walk); `tile_entries` sums,
+ * per 16x16 tile, the entries its wavefront evaluated after the tile-ellipse cull. */
+typedef struct gsc_counters {
+  uint64_t instances;      /* (tile, Gaussian) instances binned */
+  uint64_t binnings;       /* binnings run */
+  uint64_t evaluations;
+  uint64_t blended;
+  uint64_t contributors;
+  uint64_t tile_entries;
+} gsc_counters;
+/* Fills *out; synchronises the context's stream.  GSC_E_INVALID_ARG for NULL. */
+gsc_status gsc_ctx_counters(gsc_ctx* ctx, gsc_counters* out);
 /* Frees the context's cached workspace (binning buffers, frame scratch). */
 gsc_status gsc_ctx_trim(gsc_ctx* ctx);
 
@@ -329,7 +340,10 @@ gsc_status gsc_copy(gsc_ctx* ctx, void* dst, const void* src, size_t bytes);
 /* Waits for all work enqueued on the context's stream. */
 gsc_status gsc_ctx_synchronize(gsc_ctx* ctx);
 
-/* HOST, side-effect free: sizes of the structs above, for bindings to check their layouts. */
+/* HOST, side-effect free: sizes of the structs above, for bindings to check their layouts:
+ * which = 0 camera, 1 gaussians, 2 grads, 3 volume, 4 trace_params, 5 path_record,
+ * 6 frame_stats, 7 binning_info, 8 adam_hparams, 9 frame_request, 10 allocator, 11 counters;
+ * 0 for any other value. */
 size_t gsc_abi_struct_size(int32_t which);
 
 #ifdef __cplusplus

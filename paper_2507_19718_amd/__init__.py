@@ -149,10 +149,9 @@ class Context:
         return out
 
     def counters(self):
-        inst, nb, ev = ctypes.c_uint64(), ctypes.c_uint64(), ctypes.c_uint64()
-        self.check(self._lib.gsc_ctx_counters(self.handle, ctypes.byref(inst), ctypes.byref(nb),
-                                              ctypes.byref(ev)))
-        return {"instances": int(inst.value), "binnings": int(nb.value), "evaluations": int(ev.value)}
+        c = _abi.gsc_counters()
+        self.check(self._lib.gsc_ctx_counters(self.handle, ctypes.byref(c)))
+        return c.as_dict()
 
     def trim(self):
         self.check(self._lib.gsc_ctx_trim(self.handle))

@@ -83,8 +83,17 @@ class gsc_frame_request(Structure):
                 ("weight_decay", c_double)]
 
 
+class gsc_counters(Structure):
+    _fields_ = [("instances", c_uint64), ("binnings", c_uint64), ("evaluations", c_uint64),
+                ("blended", c_uint64), ("contributors", c_uint64), ("tile_entries", c_uint64)]
+
+    def as_dict(self):
+        return {k: int(getattr(self, k)) for k, _ in self._fields_}
+
+
 STRUCTS = [gsc_camera, gsc_gaussians, gsc_grads, gsc_volume, gsc_trace_params, gsc_path_record,
-           gsc_frame_stats, gsc_binning_info, gsc_adam_hparams, gsc_frame_request, gsc_allocator]
+           gsc_frame_stats, gsc_binning_info, gsc_adam_hparams, gsc_frame_request, gsc_allocator,
+           gsc_counters]
 
 P = POINTER
 _SIGNATURES = {
@@ -100,7 +109,7 @@ _SIGNATURES = {
     "gsc_ctx_profile": (c_int32, [c_void_p, c_int32]),
     "gsc_ctx_profile_read": (c_int32, [c_void_p, c_int32, ctypes.c_char_p, c_size_t, P(c_double),
                                        P(c_int64)]),
-    "gsc_ctx_counters": (c_int32, [c_void_p, P(c_uint64), P(c_uint64), P(c_uint64)]),
+    "gsc_ctx_counters": (c_int32, [c_void_p, P(gsc_counters)]),
     "gsc_trace_targets": (c_int32, [c_void_p, P(gsc_volume), P(gsc_camera), P(gsc_trace_params),
                                     c_void_p, c_void_p, P(gsc_frame_stats)]),
     "gsc_project_bin": (c_int32, [c_void_p, P(gsc_gaussians), c_int32, P(gsc_camera), c_uint64,

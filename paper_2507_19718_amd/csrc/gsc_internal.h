@@ -89,21 +89,21 @@ hipError_t launch_segmented_sort(hipStream_t st, const void* table_dev, int n_bl
                                  uint32_t* vals_tmp, uint32_t* hist);
 
 size_t bin_work_bytes(int S);
-int64_t bin_fill_work(void* host, const Seg* segs, int S, int64_t* total_chunk_tiles);
+int64_t bin_fill_work(void* host, const Seg* segs, int S, int64_t* total_chunk_tiles,
+                      int64_t* total_count_blocks);
 size_t bin_scan_partials(int64_t n_tiles);
 hipError_t launch_gather_rect(hipStream_t st, const int64_t* seg_gstart, int S, int64_t G,
                               const uint32_t* sorted_ids, const uint64_t* rect,
                               uint64_t* rect_sorted);
-hipError_t launch_bin_count(hipStream_t st, const void* work_dev, int S, int64_t total_waves,
-                            const uint32_t* sorted_ids, const uint64_t* rect_sorted,
-                            uint32_t* counts);
+hipError_t launch_bin_count(hipStream_t st, const void* work_dev, int S, int64_t total_blocks,
+                            const uint64_t* rect_sorted, uint32_t* counts);
 hipError_t launch_bin_scan(hipStream_t st, const void* work_dev, int S, const int64_t* seg_tstart,
                            int64_t n_tiles, uint32_t* counts, uint32_t* tile_total,
                            uint64_t* partial, uint64_t* tile_start, uint64_t* ranges,
                            uint64_t* n_instances);
 hipError_t launch_bin_place(hipStream_t st, const void* work_dev, int S, int64_t total_waves,
                             const uint32_t* sorted_ids, const uint64_t* rect_sorted,
-                            uint32_t* counts, const uint64_t* tile_start,
+                            const uint32_t* counts, const uint64_t* tile_start,
                             const uint64_t* n_instances, uint64_t capacity, uint32_t* values);
 hipError_t launch_binning_keys(hipStream_t st, const int64_t* seg_tstart, int S,
                                const int64_t* seg_goff, int64_t n_tiles, const uint64_t* tile_start,
@@ -116,7 +116,7 @@ hipError_t launch_splat_forward(hipStream_t st, const Seg* segs, const int64_t* 
                                 const DevCam* cams, int64_t n_tiles, const uint64_t* ranges,
                                 const uint32_t* values, const SplatRec* rec, float* images,
                                 float* final_T, int32_t* last_id, uint32_t* n_contrib,
-                                unsigned long long* evals);
+                                unsigned long long* stats);
 hipError_t launch_splat_backward(hipStream_t st, const Seg* segs, const int64_t* seg_tstart, int S,
                                  const DevCam* cams, int64_t n_tiles, const uint64_t* ranges,
                                  const uint32_t* values, const SplatRec* rec, const float* final_T,
@@ -132,6 +132,18 @@ hipError_t launch_loss_composite(hipStream_t st, const float* images, const floa
                                  const void* records, int K, int w, int h, int loss,
                                  float* dL_dimages, double* partials, float* loss_out,
                                  float* composite);
+// One AdamW parameter group of a fused multi-group step (hyper-parameters prepared on the host).
+struct AdamGroup {
+  float* p;
+  float* m;
+  float* v;
+  const float* g;
+  int64_t n;
+  const float* guard;     // the step is skipped when *guard is not finite (nullptr: never)
+  float b1, b2, omb1, omb2, s1, s2, wdf, eps;
+};
+hipError_t launch_adam_groups(hipStream_t st, const AdamGroup* groups_dev, int n_groups,
+                              int64_t max_n);
 hipError_t launch_adam(hipStream_t st, float* param, float* m, float* v, const float* grad,
                        int64_t count, float b1, float b2, float omb1, float omb2, float s1,
                        float s2, float wdf, float eps, const float* guard);

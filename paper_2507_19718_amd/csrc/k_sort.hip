@@ -25,17 +25,41 @@ struct SortBlock {
   int32_t seg;        // segment index
 };
 
+// Lanes of the wavefront whose 8-bit digit equals this lane's (valid lanes only).
+__device__ __forceinline__ uint64_t digit_peers(uint32_t d, bool valid) {
+  uint64_t peers = __ballot(valid);
+#pragma unroll
+  for (int bit = 0; bit < 8; ++bit) {
+    const bool set = (d >> bit) & 1u;
+    const uint64_t m = __ballot(valid && set);
+    peers &= set ? m : ~m;
+  }
+  return peers;
+}
+
 __global__ void __launch_bounds__(kSortThreads) sort_hist_kernel(const SortBlock* __restrict__ blocks,
                                                                  const uint32_t* __restrict__ keys,
                                                                  int shift, uint32_t* __restrict__ hist,
                                                                  int n_blocks) {
   __shared__ uint32_t cnt[256];
   const SortBlock B = blocks[blockIdx.x];
-  cnt[threadIdx.x] = 0u;
-  __syncthreads();
+  const int lane = __lane_id();
+  const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  uint32_t kr[kSortRounds];
+#pragma unroll
   for (int r = 0; r < kSortRounds; ++r) {
     const int k = r * kSortThreads + threadIdx.x;
-    if (k < B.count) atomicAdd(&cnt[(keys[B.start + k] >> shift) & 0xffu], 1u);
+    kr[r] = (k < B.count) ? keys[B.start + k] : 0u;
+  }
+  cnt[threadIdx.x] = 0u;
+  __syncthreads();
+#pragma unroll
+  for (int r = 0; r < kSortRounds; ++r) {
+    const bool valid = r * kSortThreads + (int)threadIdx.x < B.count;
+    const uint32_t d = (kr[r] >> shift) & 0xffu;
+    // One LDS atomic per distinct digit of the wavefront (keys often share their high digits).
+    const uint64_t peers = digit_peers(d, valid);
+    if (valid && (peers & lt_mask) == 0ull) atomicAdd(&cnt[d], (uint32_t)__popcll(peers));
   }
   __syncthreads();
   hist[(int64_t)threadIdx.x * n_blocks + blockIdx.x] = cnt[threadIdx.x];
@@ -97,25 +121,22 @@ __global__ void __launch_bounds__(kSortThreads) sort_scatter_kernel(
   const int wave = tid >> 6;
   const int lane = __lane_id();
   const uint64_t lt_mask = (lane == 0) ? 0ull : (~0ull >> (64 - lane));
+  uint32_t kr[kSortRounds], vr[kSortRounds];
+#pragma unroll
+  for (int r = 0; r < kSortRounds; ++r) {   // all loads issued before the first barrier
+    const int k = r * kSortThreads + tid;
+    kr[r] = (k < B.count) ? keys_in[B.start + k] : 0u;
+    vr[r] = (k < B.count) ? vals_in[B.start + k] : 0u;
+  }
   run[tid] = hist[(int64_t)tid * n_blocks + blockIdx.x] + dbase[B.seg * 256 + tid];
   for (int w = 0; w < 4; ++w) wcnt[w][tid] = 0u;
   __syncthreads();
-  for (int r = 0; r < kSortRounds; ++r) {
-    const int k = r * kSortThreads + tid;
-    const bool valid = k < B.count;
-    uint32_t key = 0u, val = 0u, d = 0u;
-    if (valid) {
-      key = keys_in[B.start + k];
-      val = vals_in[B.start + k];
-      d = (key >> shift) & 0xffu;
-    }
-    uint64_t peers = __ballot(valid);
 #pragma unroll
-    for (int bit = 0; bit < 8; ++bit) {
-      const bool set = (d >> bit) & 1u;
-      const uint64_t m = __ballot(valid && set);
-      peers &= set ? m : ~m;
-    }
+  for (int r = 0; r < kSortRounds; ++r) {
+    const bool valid = r * kSortThreads + tid < B.count;
+    const uint32_t key = kr[r], val = vr[r];
+    const uint32_t d = (key >> shift) & 0xffu;
+    const uint64_t peers = digit_peers(d, valid);
     const uint32_t rank = (uint32_t)__popcll(peers & lt_mask);
     const bool leader = valid && ((peers & lt_mask) == 0ull);
     if (leader) wcnt[wave][d] = (uint32_t)__popcll(peers);

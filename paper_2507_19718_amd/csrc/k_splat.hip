@@ -2,20 +2,22 @@
 // its adjoint (3D Gaussian splatting's tile rasteriser, adapted by GSCache to render each cache
 // level; Method: "A Path Space Radiance Cache", "Cache Training").
 //
-// One 64-lane wavefront per 16x16 tile; lane l owns the four pixels (l & 15, (l >> 4) + 4k),
-// k = 0..3.  The tile's list is consumed 64 entries at a time: lane j loads entry j's 48-byte
-// record into registers, then the wave walks the entries in list order and broadcasts each
-// record to scalar registers (v_readlane), so every lane evaluates its four pixels against it
-// with scalar operands -- no LDS traffic and no workgroup barriers.  An entry whose alpha >=
-// 1/255 ellipse provably misses every pixel of the tile (a conservative test of the quadratic
-// form over the tile rectangle) is skipped by the whole wave; such an entry is skipped by every
-// pixel anyway, so results do not change.
+// One 64-lane wavefront per 16x16 tile; lane l owns the four pixels (l & 15, (l >> 4) + 4p),
+// p = 0..3, so slot p of the wave is the tile's 16x4 row band 4p..4p+3.  The tile's list is
+// consumed 64 entries at a time: lane j loads entry j's 48-byte record into registers, then the
+// wave walks the entries in list order and broadcasts each record to scalar registers
+// (v_readlane).  The Gaussian's integer pixel window becomes, on the scalar unit, one 64-bit
+// lane mask per slot; a slot with no live pixel inside the window is skipped by a scalar branch
+// and the others run branch-free (predicated selects), so the vector unit sees only the blend.
+// An entry whose alpha >= 1/255 ellipse provably misses every pixel of the tile (a conservative
+// test of the quadratic form over the tile rectangle) is skipped by the whole wave; such an
+// entry is skipped by every pixel anyway, so results do not change.
 //
 // The adjoint walks the same lists back to front from each pixel's last contributor, recovers
-// the transmittance before each Gaussian by dividing the stored final transmittance by
-// (1 - alpha), sums each Gaussian's nine screen-space gradients over the lane's four pixels,
-// reduces them across the wavefront with DPP row shifts and row broadcasts, and issues nine
-// float atomics per (tile, Gaussian) from the lane that loaded the entry.
+// the transmittance before each Gaussian as T / (1 - alpha), sums each Gaussian's nine
+// screen-space gradients over the lane's four pixels, reduces them within each 16-lane row with
+// DPP row shifts, parks the four row sums in LDS, and once per batch of 64 entries the lane that
+// loaded an entry adds its rows and issues the nine float atomics of that (tile, Gaussian).
 #include "gsc_dev.h"
 
 namespace gsc {
@@ -26,15 +28,16 @@ constexpr float kAlphaMin = 1.0f / 255.0f;
 constexpr float kAlphaMax = 0.99f;
 constexpr float kTmin = 1e-4f;
 constexpr int kPx = 4;
+constexpr int kPartStride = 10;   // floats per (row, entry) of the adjoint's LDS partials
 
 struct Tile {
   int64_t start, end;
   int64_t g_off, pix_off;
-  int W;                     // render window width
   float fi;                  // this lane's pixel column (full-frame)
   float fj[kPx];             // this lane's four pixel rows
   int64_t pix[kPx];          // pixel index within the segment image
   bool inside[kPx];
+  int xbase, ybase;          // full-frame coordinates of the tile's first pixel
   float ti0, ti1, tj0, tj1;  // the tile's pixel rectangle inside the render window
 };
 
@@ -54,7 +57,6 @@ __device__ __forceinline__ Tile tile_setup(const Seg* __restrict__ segs,
   c.end = (int64_t)ranges[2 * t + 1];
   c.g_off = sg.g_off;
   c.pix_off = sg.pix_off;
-  c.W = cam.w;
   c.fi = (float)(cam.x0 + px);
 #pragma unroll
   for (int k = 0; k < kPx; ++k) {
@@ -63,6 +65,8 @@ __device__ __forceinline__ Tile tile_setup(const Seg* __restrict__ segs,
     c.pix[k] = (int64_t)py * cam.w + px;
     c.fj[k] = (float)(cam.y0 + py);
   }
+  c.xbase = cam.x0 + tx * kTile;
+  c.ybase = cam.y0 + ty * kTile;
   c.ti0 = (float)(cam.x0 + tx * kTile);
   c.ti1 = (float)(cam.x0 + min(tx * kTile + kTile, cam.w) - 1);
   c.tj0 = (float)(cam.y0 + ty * kTile);
@@ -103,28 +107,50 @@ __device__ __forceinline__ uint32_t rlu(float v, int k) {
   return (uint32_t)__builtin_amdgcn_readlane(__float_as_int(v), k);
 }
 
+// Lane masks of the tile's pixels inside a Gaussian's integer window (packed full-frame bounds
+// wx = px0 | px1 << 16, wy = py0 | py1 << 16), one per slot.  Uniform arithmetic: it runs on
+// the scalar unit.
+__device__ __forceinline__ void window_masks(uint32_t wx, uint32_t wy, int xbase, int ybase,
+                                             uint64_t m[kPx]) {
+  const int lo = max((int)(wx & 0xffffu) - xbase, 0);
+  const int hi = min((int)(wx >> 16) - xbase, 15);
+  const uint32_t c16 = (lo <= hi) ? ((2u << hi) - (1u << lo)) : 0u;
+  const uint32_t c32 = c16 | (c16 << 16);
+  const uint64_t c64 = ((uint64_t)c32 << 32) | (uint64_t)c32;
+  const int ylo = (int)(wy & 0xffffu) - ybase, yhi = (int)(wy >> 16) - ybase;
+#pragma unroll
+  for (int p = 0; p < kPx; ++p) {
+    const int glo = max(ylo - 4 * p, 0), ghi = min(yhi - 4 * p, 3);
+    m[p] = (glo <= ghi) ? (c64 & (~0ull >> (48 - 16 * ghi)) & (~0ull << (16 * glo))) : 0ull;
+  }
+}
+
+__device__ __forceinline__ bool lane_in(uint64_t mask) {
+  return __builtin_amdgcn_inverse_ballot_w64(mask);
+}
+
 __global__ void __launch_bounds__(64) splat_forward_kernel(
     const Seg* __restrict__ segs, const int64_t* __restrict__ seg_tstart, int S,
     const DevCam* __restrict__ cams, const uint64_t* __restrict__ ranges,
     const uint32_t* __restrict__ values, const SplatRec* __restrict__ rec,
     float* __restrict__ images, float* __restrict__ final_T, int32_t* __restrict__ last_id,
-    uint32_t* __restrict__ n_contrib, unsigned long long* __restrict__ evals) {
+    uint32_t* __restrict__ n_contrib, unsigned long long* __restrict__ stats) {
   const int64_t t = blockIdx.x;
   const Tile tc = tile_setup(segs, seg_tstart, S, cams, ranges, t);
   const int lane = __lane_id();
   float T[kPx], C0[kPx], C1[kPx], C2[kPx];
   uint32_t nc[kPx], stop[kPx];
-  bool done[kPx];
+  uint64_t done[kPx];                    // lanes finished (terminated, or outside the image)
+  uint32_t n_blend = 0u, n_entries = 0u;
 #pragma unroll
-  for (int k = 0; k < kPx; ++k) {
-    T[k] = 1.0f; C0[k] = 0.0f; C1[k] = 0.0f; C2[k] = 0.0f;
-    nc[k] = 0u; stop[k] = 0u;
-    done[k] = !tc.inside[k];
+  for (int p = 0; p < kPx; ++p) {
+    T[p] = 1.0f; C0[p] = 0.0f; C1[p] = 0.0f; C2[p] = 0.0f;
+    nc[p] = 0u; stop[p] = 0u;
+    done[p] = __ballot(!tc.inside[p]);
   }
   const uint32_t len = (uint32_t)(tc.end - tc.start);
   for (int64_t bs = tc.start; bs < tc.end; bs += 64) {
-    const bool all = done[0] && done[1] && done[2] && done[3];
-    if (__ballot(!all) == 0ull) break;
+    if ((done[0] & done[1] & done[2] & done[3]) == ~0ull) break;
     const int64_t idx = bs + lane;
     float4 q0 = make_float4(0, 0, 0, 0), q1 = q0, q2 = q0;
     bool keep = false;
@@ -136,40 +162,46 @@ __global__ void __launch_bounds__(64) splat_forward_kernel(
     uint64_t mask = __ballot(keep);
     const uint32_t rel0 = (uint32_t)(bs - tc.start);
     while (mask) {
-      if (__ballot(!(done[0] && done[1] && done[2] && done[3])) == 0ull) break;
+      if ((done[0] & done[1] & done[2] & done[3]) == ~0ull) break;
       const int k = __builtin_ctzll(mask);
       mask &= mask - 1ull;
+      ++n_entries;
       const float u = rl(q0.x, k), v = rl(q0.y, k), A = rl(q0.z, k), B = rl(q0.w, k);
       const float Cc = rl(q1.x, k), o = rl(q1.y, k);
-      const uint32_t wx = rlu(q2.y, k), wy = rlu(q2.z, k);
-      const float fx0 = (float)(wx & 0xffffu), fx1 = (float)(wx >> 16);
-      const float fy0 = (float)(wy & 0xffffu), fy1 = (float)(wy >> 16);
       const float cr = rl(q1.z, k), cg = rl(q1.w, k), cb = rl(q2.x, k);
-      const bool colin = !(tc.fi < fx0 || tc.fi > fx1);
+      uint64_t win[kPx];
+      window_masks(rlu(q2.y, k), rlu(q2.z, k), tc.xbase, tc.ybase, win);
       const float dx = u - tc.fi;
       const float adx = (A * dx) * dx;
       const float bdx = B * dx;
       const uint32_t pos = rel0 + (uint32_t)k + 1u;
 #pragma unroll
       for (int p = 0; p < kPx; ++p) {
-        if (done[p] || !colin || tc.fj[p] < fy0 || tc.fj[p] > fy1) continue;
+        const uint64_t act = win[p] & ~done[p];
+        if (act == 0ull) continue;
         const float dy = v - tc.fj[p];
         const float power = -0.5f * (adx + (Cc * dy) * dy) - bdx * dy;
-        if (power > 0.0f) continue;
         const float alpha = fminf(kAlphaMax, o * __expf(power));
-        if (alpha < kAlphaMin) continue;
+        // Lane masks on the scalar unit: ballots of single compares cost no vector work.
+        const uint64_t okm = act & __builtin_amdgcn_ballot_w64(!(power > 0.0f)) &
+                             __builtin_amdgcn_ballot_w64(!(alpha < kAlphaMin));
         const float Tn = T[p] * (1.0f - alpha);
-        if (Tn < kTmin) { done[p] = true; stop[p] = pos; continue; }
-        const float w = alpha * T[p];
-        C0[p] = C0[p] + cr * w;
-        C1[p] = C1[p] + cg * w;
-        C2[p] = C2[p] + cb * w;
-        T[p] = Tn;
-        nc[p] = pos;
+        const uint64_t finm = okm & __builtin_amdgcn_ballot_w64(Tn < kTmin);
+        const uint64_t blm = okm & ~finm;
+        const bool bl = lane_in(blm);
+        const float w = bl ? alpha * T[p] : 0.0f;
+        C0[p] = fmaf(cr, w, C0[p]);
+        C1[p] = fmaf(cg, w, C1[p]);
+        C2[p] = fmaf(cb, w, C2[p]);
+        T[p] = bl ? Tn : T[p];
+        nc[p] = bl ? pos : nc[p];
+        stop[p] = lane_in(finm) ? pos : stop[p];
+        done[p] |= finm;
+        n_blend += (uint32_t)__popcll(blm);
       }
     }
   }
-  uint64_t ev = 0;
+  uint64_t ev = 0, ncs = 0;
 #pragma unroll
   for (int p = 0; p < kPx; ++p) {
     if (!tc.inside[p]) continue;
@@ -180,27 +212,33 @@ __global__ void __launch_bounds__(64) splat_forward_kernel(
     final_T[q] = T[p];
     last_id[q] = nc[p] ? (int32_t)values[tc.start + nc[p] - 1u] : -1;
     n_contrib[q] = nc[p];
-    ev += done[p] ? stop[p] : len;
+    ev += stop[p] ? stop[p] : len;
+    ncs += nc[p];
   }
-  if (evals) {
+  if (stats) {
 #pragma unroll
-    for (int off = 32; off > 0; off >>= 1) ev += __shfl_xor(ev, off, 64);
-    if (lane == 0 && ev) atomicAdd(evals, (unsigned long long)ev);
+    for (int off = 32; off > 0; off >>= 1) {
+      ev += __shfl_xor(ev, off, 64);
+      ncs += __shfl_xor(ncs, off, 64);
+    }
+    if (lane == 0) {
+      atomicAdd(&stats[0], (unsigned long long)ev);
+      atomicAdd(&stats[1], (unsigned long long)n_blend);
+      atomicAdd(&stats[2], (unsigned long long)ncs);
+      atomicAdd(&stats[3], (unsigned long long)n_entries);
+    }
   }
 }
 
-// Sum over the 64 lanes; the total lands in lane 63 (row shifts within 16-lane rows, then row
-// broadcasts across rows).
-__device__ __forceinline__ float wave_total(float v) {
+// Sum over each 16-lane row; lane 15 of the row receives it (row shifts with zero fill).
+__device__ __forceinline__ float row_total(float v) {
   float t = v;
   t = t + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x111, 0xf, 0xf, true));
   t = t + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x112, 0xf, 0xf, true));
   t = t + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x113, 0xf, 0xf, true));
-  t = t + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(t), 0x114, 0xf, 0xe, false));
-  t = t + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(t), 0x118, 0xf, 0xc, false));
-  t = t + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(t), 0x142, 0xa, 0xf, false));
-  t = t + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(t), 0x143, 0xc, 0xf, false));
-  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(t), 63));
+  t = t + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(t), 0x114, 0xf, 0xf, true));
+  t = t + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(t), 0x118, 0xf, 0xf, true));
+  return t;
 }
 
 __global__ void __launch_bounds__(64) splat_backward_kernel(
@@ -209,6 +247,7 @@ __global__ void __launch_bounds__(64) splat_backward_kernel(
     const uint32_t* __restrict__ values, const SplatRec* __restrict__ rec,
     const float* __restrict__ final_T, const uint32_t* __restrict__ n_contrib,
     const float* __restrict__ dL_dimages, float* __restrict__ grad2d, int64_t G) {
+  __shared__ float part[4][64][kPartStride];
   const int64_t t = blockIdx.x;
   const Tile tc = tile_setup(segs, seg_tstart, S, cams, ranges, t);
   const int lane = __lane_id();
@@ -245,73 +284,82 @@ __global__ void __launch_bounds__(64) splat_backward_kernel(
       q0 = r.q0; q1 = r.q1; q2 = r.q2;
       keep = may_touch(q0, q1, q2, tc);
     }
-    float acc[9];
-#pragma unroll
-    for (int a = 0; a < 9; ++a) acc[a] = 0.0f;
     uint64_t mask = __ballot(keep);
+    uint64_t has = 0ull;                       // entries whose row sums are parked in LDS
     const uint32_t rel0 = (uint32_t)(bs - tc.start);
     while (mask) {
       const int k = 63 - __builtin_clzll(mask);          // back to front
       mask &= ~(1ull << k);
       const float u = rl(q0.x, k), v = rl(q0.y, k), A = rl(q0.z, k), B = rl(q0.w, k);
       const float Cc = rl(q1.x, k), o = rl(q1.y, k);
-      const uint32_t wx = rlu(q2.y, k), wy = rlu(q2.z, k);
-      const float fx0 = (float)(wx & 0xffffu), fx1 = (float)(wx >> 16);
-      const float fy0 = (float)(wy & 0xffffu), fy1 = (float)(wy >> 16);
       const float cr = rl(q1.z, k), cg = rl(q1.w, k), cb = rl(q2.x, k);
-      const bool colin = !(tc.fi < fx0 || tc.fi > fx1);
+      uint64_t win[kPx];
+      window_masks(rlu(q2.y, k), rlu(q2.z, k), tc.xbase, tc.ybase, win);
       const float dx = u - tc.fi;
       const float adx = (A * dx) * dx;
       const float bdx = B * dx;
+      const float hdx2 = (-0.5f * dx) * dx;
+      const float mAdx = -A * dx, mBdx = -B * dx;
       const uint32_t rel = rel0 + (uint32_t)k;
       float su = 0.0f, sv = 0.0f, sA = 0.0f, sB = 0.0f, sC = 0.0f, so = 0.0f;
       float sr = 0.0f, sg = 0.0f, sb = 0.0f;
-      bool any = false;
+      uint64_t any = 0ull;
 #pragma unroll
       for (int p = 0; p < kPx; ++p) {
-        if (!(rel < nc[p]) || !colin || tc.fj[p] < fy0 || tc.fj[p] > fy1) continue;
+        const uint64_t act = win[p] & __builtin_amdgcn_ballot_w64(rel < nc[p]);
+        if (act == 0ull) continue;
         const float dy = v - tc.fj[p];
         const float power = -0.5f * (adx + (Cc * dy) * dy) - bdx * dy;
-        if (power > 0.0f) continue;
         const float e = __expf(power);
         const float oe = o * e;
         const float alpha = fminf(kAlphaMax, oe);
-        if (alpha < kAlphaMin) continue;
-        any = true;
-        T[p] = T[p] / (1.0f - alpha);
-        const float w = alpha * T[p];
-        sr += w * g0[p];
-        sg += w * g1[p];
-        sb += w * g2[p];
-        const float dalpha = T[p] * (((cr - B0[p]) * g0[p] + (cg - B1[p]) * g1[p]) + (cb - B2[p]) * g2[p]);
-        B0[p] = alpha * cr + (1.0f - alpha) * B0[p];
-        B1[p] = alpha * cg + (1.0f - alpha) * B1[p];
-        B2[p] = alpha * cb + (1.0f - alpha) * B2[p];
-        if (!(oe > kAlphaMax)) {
-          const float dpow = dalpha * alpha;
-          so += dalpha * e;
-          sA += -0.5f * dx * dx * dpow;
-          sC += -0.5f * dy * dy * dpow;
-          sB += -dx * dy * dpow;
-          su += (-A * dx - B * dy) * dpow;
-          sv += (-Cc * dy - B * dx) * dpow;
-        }
+        const uint64_t okm = act & __builtin_amdgcn_ballot_w64(!(power > 0.0f)) &
+                             __builtin_amdgcn_ballot_w64(!(alpha < kAlphaMin));
+        any |= okm;
+        const bool ok = lane_in(okm);
+        const float az = ok ? alpha : 0.0f;
+        T[p] = ok ? T[p] * __builtin_amdgcn_rcpf(1.0f - alpha) : T[p];
+        const float w = az * T[p];
+        sr = fmaf(w, g0[p], sr);
+        sg = fmaf(w, g1[p], sg);
+        sb = fmaf(w, g2[p], sb);
+        const float d0 = cr - B0[p], d1 = cg - B1[p], d2 = cb - B2[p];
+        const float dal = T[p] * fmaf(d0, g0[p], fmaf(d1, g1[p], d2 * g2[p]));
+        B0[p] = fmaf(az, d0, B0[p]);
+        B1[p] = fmaf(az, d1, B1[p]);
+        B2[p] = fmaf(az, d2, B2[p]);
+        // alpha not clamped: it depends on power and opacity.
+        const bool gate = lane_in(okm & __builtin_amdgcn_ballot_w64(!(oe > kAlphaMax)));
+        const float dpow = gate ? dal * alpha : 0.0f;
+        so = gate ? fmaf(dal, e, so) : so;
+        sA = fmaf(dpow, hdx2, sA);
+        sC = fmaf(dpow, (-0.5f * dy) * dy, sC);
+        sB = fmaf(dpow, -dx * dy, sB);
+        su = fmaf(dpow, fmaf(-B, dy, mAdx), su);
+        sv = fmaf(dpow, fmaf(-Cc, dy, mBdx), sv);
       }
-      if (__ballot(any) == 0ull) continue;
-      const float tu = wave_total(su), tv = wave_total(sv), tA = wave_total(sA);
-      const float tB = wave_total(sB), tC = wave_total(sC), to = wave_total(so);
-      const float tr = wave_total(sr), tg = wave_total(sg), tb = wave_total(sb);
-      if (lane == k) {
-        acc[0] = tu; acc[1] = tv; acc[2] = tA; acc[3] = tB; acc[4] = tC;
-        acc[5] = to; acc[6] = tr; acc[7] = tg; acc[8] = tb;
+      if (any == 0ull) continue;
+      has |= 1ull << k;
+      const float r0 = row_total(su), r1 = row_total(sv), r2 = row_total(sA);
+      const float r3 = row_total(sB), r4 = row_total(sC), r5 = row_total(so);
+      const float r6 = row_total(sr), r7 = row_total(sg), r8 = row_total(sb);
+      if ((lane & 15) == 15) {
+        float* d = part[lane >> 4][k];
+        d[0] = r0; d[1] = r1; d[2] = r2; d[3] = r3; d[4] = r4;
+        d[5] = r5; d[6] = r6; d[7] = r7; d[8] = r8;
       }
     }
-    if (lane < n) {
+    if (has == 0ull) continue;
+    __syncthreads();
+    if ((has >> lane) & 1ull) {
       const int64_t gi = tc.g_off + (int64_t)my_id;
 #pragma unroll
-      for (int a = 0; a < 9; ++a)
-        if (acc[a] != 0.0f) unsafeAtomicAdd(&grad2d[(int64_t)a * G + gi], acc[a]);
+      for (int a = 0; a < 9; ++a) {
+        const float acc = (part[0][lane][a] + part[1][lane][a]) + (part[2][lane][a] + part[3][lane][a]);
+        if (acc != 0.0f) unsafeAtomicAdd(&grad2d[(int64_t)a * G + gi], acc);
+      }
     }
+    __syncthreads();
   }
 }
 
@@ -321,11 +369,11 @@ hipError_t launch_splat_forward(hipStream_t st, const Seg* segs, const int64_t* 
                                 const DevCam* cams, int64_t n_tiles, const uint64_t* ranges,
                                 const uint32_t* values, const SplatRec* rec, float* images,
                                 float* final_T, int32_t* last_id, uint32_t* n_contrib,
-                                unsigned long long* evals) {
+                                unsigned long long* stats) {
   if (n_tiles == 0) return hipSuccess;
   hipLaunchKernelGGL(splat_forward_kernel, dim3((unsigned)n_tiles), dim3(64), 0, st, segs,
                      seg_tstart, S, cams, ranges, values, rec, images, final_T, last_id, n_contrib,
-                     evals);
+                     stats);
   return hipGetLastError();
 }
 

@@ -73,7 +73,7 @@ struct gsc_binning {
   std::vector<int64_t> seg_gstart, seg_tstart;
   int64_t G = 0, n_tiles = 0, pixels = 0;
   int n_sort_blocks = 0;
-  int64_t bin_waves = 0, chunk_tiles = 0;
+  int64_t bin_waves = 0, count_blocks = 0, chunk_tiles = 0;
   // device tables: [Seg x S][DevCam x R][int64 gstart x S][int64 tstart x S][sort table][bin work]
   DevBuf tables;
   size_t off_cams = 0, off_gstart = 0, off_tstart = 0, off_sort = 0, off_work = 0;
@@ -145,7 +145,8 @@ struct gsc_ctx {
   double prof_ms[16] = {};
   int64_t prof_n[16] = {};
   uint64_t acc_instances = 0, acc_frames = 0;
-  DevBuf d_evals;                  // device counter of Gaussian-pixel evaluations (forward)
+  DevBuf adam_tab;                 // fused AdamW group table
+  DevBuf d_stats;                  // splat forward counters: evaluations, blended, contributors, entries
 };
 
 namespace {
@@ -231,6 +232,7 @@ const char* const kProfNames[] = {"project", "depth_sort", "bin_count", "bin_sca
                                   "splat_forward", "trace", "loss_composite", "splat_backward",
                                   "project_backward", "adam", "gather_rect"};
 constexpr int kProfCount = 12;
+constexpr int kStatWords = 4;   // splat forward counters (gsc_counters)
 enum { P_PROJECT, P_SORT, P_COUNT, P_SCAN, P_PLACE, P_FWD, P_TRACE, P_LOSS, P_BWD, P_PBWD, P_ADAM,
        P_GATHER };
 
@@ -378,7 +380,8 @@ void plan_batch(gsc_ctx* ctx, gsc_binning* b, const std::vector<ReqSpec>& reqs) 
   std::memcpy(host.data() + b->off_gstart, b->seg_gstart.data(), sizeof(int64_t) * b->S);
   std::memcpy(host.data() + b->off_tstart, b->seg_tstart.data(), sizeof(int64_t) * b->S);
   sort_fill_table(host.data() + b->off_sort, seg_n.data(), seg_off.data(), b->S);
-  b->bin_waves = bin_fill_work(host.data() + b->off_work, b->segs.data(), b->S, &b->chunk_tiles);
+  b->bin_waves = bin_fill_work(host.data() + b->off_work, b->segs.data(), b->S, &b->chunk_tiles,
+                                &b->count_blocks);
   need(ctx, b->tables, b->alloc, off, "descriptor tables");
   upload(ctx, b->tables.p, host.data(), off);
   b->forward_done = false;
@@ -425,8 +428,8 @@ gsc_status run_project_bin(gsc_ctx* ctx, gsc_binning* b, uint64_t capacity_hint)
                              b->rect_sorted.as<uint64_t>()));
   }
   { ProfScope ps_(ctx, P_COUNT, st);
-  GSC_TRY(launch_bin_count(st, b->d_work(), b->S, b->bin_waves, b->ids.as<uint32_t>(),
-                           b->rect_sorted.as<uint64_t>(), b->counts.as<uint32_t>()));
+  GSC_TRY(launch_bin_count(st, b->d_work(), b->S, b->count_blocks, b->rect_sorted.as<uint64_t>(),
+                           b->counts.as<uint32_t>()));
   }
   { ProfScope ps_(ctx, P_SCAN, st);
   GSC_TRY(launch_bin_scan(st, b->d_work(), b->S, b->d_tstart(), b->n_tiles, b->counts.as<uint32_t>(),
@@ -463,15 +466,15 @@ gsc_status run_project_bin(gsc_ctx* ctx, gsc_binning* b, uint64_t capacity_hint)
 
 void run_forward(gsc_ctx* ctx, gsc_binning* b, float* images, float* final_T, int32_t* last_id) {
   need(ctx, b->n_contrib, b->alloc, 4 * (size_t)std::max<int64_t>(b->pixels, 1), "n_contrib");
-  if (!ctx->d_evals.p) {
-    need(ctx, ctx->d_evals, ctx->alloc, 8, "evaluation counter");
-    GSC_TRY(hipMemsetAsync(ctx->d_evals.p, 0, 8, ctx->stream));
+  if (!ctx->d_stats.p) {
+    need(ctx, ctx->d_stats, ctx->alloc, kStatWords * 8, "splat counters");
+    GSC_TRY(hipMemsetAsync(ctx->d_stats.p, 0, kStatWords * 8, ctx->stream));
   }
   { ProfScope ps_(ctx, P_FWD, ctx->stream);
   GSC_TRY(launch_splat_forward(ctx->stream, b->d_segs(), b->d_tstart(), b->S, b->d_cams(), b->n_tiles,
                                b->ranges.as<uint64_t>(), b->values.as<uint32_t>(),
                                b->rec.as<SplatRec>(), images, final_T, last_id,
-                               b->n_contrib.as<uint32_t>(), ctx->d_evals.as<unsigned long long>()));
+                               b->n_contrib.as<uint32_t>(), ctx->d_stats.as<unsigned long long>()));
   }
   b->forward_done = true;
 }
@@ -542,14 +545,27 @@ void check_trace_params(gsc_ctx* ctx, const gsc_trace_params* tp) {
   if (!std::isfinite(tp->eps) || tp->eps < 0.0f) invalid(ctx, "eps must be finite and >= 0");
 }
 
+// AdamW hyper-parameters of one group at `step`: bias corrections s1 = lr / (1 - b1^t) and
+// s2 = 1 / sqrt(1 - b2^t) and the decoupled decay factor 1 - lr wd, in double, then rounded.
+AdamGroup adam_params(float* p, float* m, float* v, const float* g, int64_t count, double lr,
+                      double b1, double b2, double eps, double wd, int64_t step, const float* guard) {
+  AdamGroup a;
+  a.p = p; a.m = m; a.v = v; a.g = g; a.n = count; a.guard = guard;
+  a.b1 = (float)b1; a.b2 = (float)b2;
+  a.omb1 = (float)(1.0 - b1); a.omb2 = (float)(1.0 - b2);
+  a.s1 = (float)(lr / (1.0 - std::pow(b1, (double)step)));
+  a.s2 = (float)(1.0 / std::sqrt(1.0 - std::pow(b2, (double)step)));
+  a.wdf = (float)(1.0 - lr * wd);
+  a.eps = (float)eps;
+  return a;
+}
+
 void adam_group(gsc_ctx* ctx, float* p, float* m, float* v, const float* g, int64_t count, double lr,
                 double b1, double b2, double eps, double wd, int64_t step, const float* guard) {
-  const float s1 = (float)(lr / (1.0 - std::pow(b1, (double)step)));
-  const float s2 = (float)(1.0 / std::sqrt(1.0 - std::pow(b2, (double)step)));
-  const float wdf = (float)(1.0 - lr * wd);
+  const AdamGroup a = adam_params(p, m, v, g, count, lr, b1, b2, eps, wd, step, guard);
   { ProfScope ps_(ctx, P_ADAM, ctx->stream);
-  GSC_TRY(launch_adam(ctx->stream, p, m, v, g, count, (float)b1, (float)b2, (float)(1.0 - b1),
-                      (float)(1.0 - b2), s1, s2, wdf, (float)eps, guard));
+  GSC_TRY(launch_adam(ctx->stream, p, m, v, g, count, a.b1, a.b2, a.omb1, a.omb2, a.s1, a.s2,
+                      a.wdf, a.eps, guard));
   }
 }
 
@@ -679,6 +695,9 @@ gsc_status render_batch(gsc_ctx* ctx, gsc_scene* const* scenes, const gsc_frame_
   if (any_train) {
     run_backward(ctx, b, ctx->final_T.as<float>(), ctx->dL.as<float>(), ctx->grads14.as<float>());
     if (timing) GSC_TRY(hipEventRecord(ctx->tev[4], st));
+    // One fused AdamW launch over every (request, level, parameter group).
+    std::vector<AdamGroup> groups;
+    int64_t max_n = 0;
     int si = 0;
     for (int i = 0; i < n; ++i) {
       gsc_scene* sc = scenes[i];
@@ -692,13 +711,21 @@ gsc_status render_batch(gsc_ctx* ctx, gsc_scene* const* scenes, const gsc_frame_
         float* g = ctx->grads14.as<float>() + 14 * sg.g_off;
         const int64_t off[6] = {0, 3 * nn, 7 * nn, 10 * nn, 13 * nn, 14 * nn};
         for (int grp = 0; grp < 5; ++grp) {
-          adam_group(ctx, sc->params[l] + off[grp], sc->m[l] + off[grp], sc->v[l] + off[grp],
-                     g + off[grp], off[grp + 1] - off[grp], (double)reqs[i].lr[grp] * eta,
-                     reqs[i].beta1, reqs[i].beta2, reqs[i].eps, reqs[i].weight_decay, step,
-                     ctx->losses.as<float>() + i);
+          groups.push_back(adam_params(sc->params[l] + off[grp], sc->m[l] + off[grp],
+                                       sc->v[l] + off[grp], g + off[grp], off[grp + 1] - off[grp],
+                                       (double)reqs[i].lr[grp] * eta, reqs[i].beta1, reqs[i].beta2,
+                                       reqs[i].eps, reqs[i].weight_decay, step,
+                                       ctx->losses.as<float>() + i));
+          max_n = std::max(max_n, off[grp + 1] - off[grp]);
         }
         sc->step[l] = step;
       }
+    }
+    if (!groups.empty()) {
+      need(ctx, ctx->adam_tab, ctx->alloc, sizeof(AdamGroup) * groups.size(), "AdamW groups");
+      upload(ctx, ctx->adam_tab.p, groups.data(), sizeof(AdamGroup) * groups.size());
+      ProfScope ps_(ctx, P_ADAM, st);
+      GSC_TRY(launch_adam_groups(st, ctx->adam_tab.as<AdamGroup>(), (int)groups.size(), max_n));
     }
   } else if (timing) {
     GSC_TRY(hipEventRecord(ctx->tev[4], st));
@@ -778,7 +805,7 @@ void gsc_ctx_destroy(gsc_ctx* c) {
   if (c->frame_bin) { c->frame_bin->free_all(); delete c->frame_bin; }
   DevBuf* all[] = {&c->targets, &c->records, &c->dL, &c->partials, &c->losses, &c->grads14,
                    &c->images, &c->final_T, &c->last_id, &c->trace_tab, &c->vertices,
-                   &c->composite_tmp, &c->d_evals};
+                   &c->composite_tmp, &c->d_stats, &c->adam_tab};
   for (DevBuf* b : all) b->release(c->alloc);
   if (c->pinned) (void)hipHostFree(c->pinned);
   if (c->host_u64) (void)hipHostFree(c->host_u64);
@@ -820,7 +847,7 @@ gsc_status gsc_ctx_trim(gsc_ctx* ctx) {
     if (ctx->frame_bin) { ctx->frame_bin->free_all(); delete ctx->frame_bin; ctx->frame_bin = nullptr; }
     DevBuf* all[] = {&ctx->targets, &ctx->records, &ctx->dL, &ctx->partials, &ctx->losses,
                      &ctx->grads14, &ctx->images, &ctx->final_T, &ctx->last_id, &ctx->trace_tab,
-                     &ctx->vertices, &ctx->composite_tmp};
+                     &ctx->vertices, &ctx->composite_tmp, &ctx->adam_tab};
     for (DevBuf* b : all) b->release(ctx->alloc);
     return GSC_OK;
   });
@@ -1203,8 +1230,8 @@ gsc_status gsc_ctx_profile(gsc_ctx* ctx, int32_t on) {
       for (int i = 0; i < 16; ++i) { ctx->prof_ms[i] = 0.0; ctx->prof_n[i] = 0; }
       ctx->acc_instances = 0;
       ctx->acc_frames = 0;
-      need(ctx, ctx->d_evals, ctx->alloc, 8, "evaluation counter");
-      GSC_TRY(hipMemsetAsync(ctx->d_evals.p, 0, 8, ctx->stream));
+      need(ctx, ctx->d_stats, ctx->alloc, kStatWords * 8, "splat counters");
+      GSC_TRY(hipMemsetAsync(ctx->d_stats.p, 0, kStatWords * 8, ctx->stream));
     }
     return GSC_OK;
   });
@@ -1223,13 +1250,21 @@ gsc_status gsc_ctx_profile_read(gsc_ctx* ctx, int32_t index, char* name, size_t 
   });
 }
 
-gsc_status gsc_ctx_counters(gsc_ctx* ctx, uint64_t* instances, uint64_t* binnings,
-                            uint64_t* evaluations) {
+gsc_status gsc_ctx_counters(gsc_ctx* ctx, gsc_counters* out) {
   return guarded(ctx, [&]() -> gsc_status {
-    if (!instances || !binnings || !evaluations) invalid(ctx, "NULL argument");
-    *instances = ctx->acc_instances;
-    *binnings = ctx->acc_frames;
-    *evaluations = ctx->d_evals.p ? read_u64(ctx, ctx->d_evals.as<uint64_t>()) : 0;
+    if (!out) invalid(ctx, "NULL argument");
+    uint64_t d[kStatWords] = {0, 0, 0, 0};
+    if (ctx->d_stats.p) {
+      GSC_TRY(hipMemcpyAsync(ctx->host_u64, ctx->d_stats.p, sizeof(d), hipMemcpyDeviceToHost, ctx->stream));
+      GSC_TRY(hipStreamSynchronize(ctx->stream));
+      std::memcpy(d, ctx->host_u64, sizeof(d));
+    }
+    out->instances = ctx->acc_instances;
+    out->binnings = ctx->acc_frames;
+    out->evaluations = d[0];
+    out->blended = d[1];
+    out->contributors = d[2];
+    out->tile_entries = d[3];
     return GSC_OK;
   });
 }
@@ -1263,6 +1298,7 @@ size_t gsc_abi_struct_size(int32_t which) {
     case 8: return sizeof(gsc_adam_hparams);
     case 9: return sizeof(gsc_frame_request);
     case 10: return sizeof(gsc_allocator);
+    case 11: return sizeof(gsc_counters);
     default: return 0;
   }
 }

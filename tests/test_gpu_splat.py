@@ -180,3 +180,43 @@ def test_invalid_arguments_rejected(gsc, gctx):
     assert e.value.status == 1
     with pytest.raises(gsc.GscError):
         gsc.gsc_project_bin(gctx, [g] * 9, cam)
+
+
+def test_splat_counters_match_oracle(gsc, gctx):
+    """The work counters behind the splat roofline: blended pairs and the adjoint's walk length
+    (position of each pixel's last blended entry in its tile list) equal the oracle's, on a
+    frame without boundary pixels."""
+    wl = synth.workload("tiny")
+    levels_np = wl.gaussians()
+    base = wl.camera()
+    for cam in [base, base.crop(8, 8, 96, 96), base.crop(3, 40, 80, 64), base.crop(50, 2, 64, 100)]:
+        projs = [oracle.project(g, cam) for g in levels_np]
+        fws = [oracle.forward(pr, g.rgb, cam) for pr, g in zip(projs, levels_np)]
+        if not any(f["boundary"].any() for f in fws):
+            break
+    else:
+        pytest.skip("no boundary-free crop among the candidates")
+    ob = oracle.bin_levels(projs, cam)
+    TX, TY = (cam.w + 15) // 16, (cam.h + 15) // 16
+    ranges = ob["ranges"].astype(np.int64)
+    want_blend = sum(int(f["n_blend"].sum()) for f in fws)
+    want_walk = 0
+    for l, f in enumerate(fws):
+        for y in range(cam.h):
+            for x in range(cam.w):
+                gid = f["last_id"][y, x]
+                if gid < 0:
+                    continue
+                t = l * TX * TY + (y // 16) * TX + (x // 16)
+                lst = ob["values"][ranges[t, 0]:ranges[t, 1]]
+                want_walk += int(np.nonzero(lst == gid)[0][0]) + 1
+    levels = [gsc.level_to_device(g) for g in levels_np]
+    gctx.profile(True)
+    forward_levels(gsc, gctx, levels, cam, len(levels))
+    c = gctx.counters()
+    gctx.profile(False)
+    assert c["blended"] == want_blend
+    assert c["contributors"] == want_walk
+    assert c["evaluations"] >= c["contributors"]
+    assert 0 < c["tile_entries"] <= ob["keys"].size
+    assert c["binnings"] == 1 and c["instances"] == ob["keys"].size
