@@ -295,8 +295,11 @@ gsc_status gsc_adam_step(gsc_ctx* ctx, float* param, float* m, float* v, const f
                          int64_t count, const gsc_adam_hparams* hp);
 
 /* ---- scenes and frames ------------------------------------------------------------------ */
-/* A scene keeps resident on the device: a copy of the volume grid, its TF and lights, and
- * K levels of parameters with their Adam moments and step counter (copied from init_levels). */
+/* A scene keeps resident on the device: its volume grid in a cell-corner layout (for every
+ * trilinear cell the eight clamped corner values, 32 bytes, (nx+1)(ny+1)(nz+1) cells, so a
+ * tracer lookup reads one aligned 32-byte block; built from vol->density, which the caller may
+ * free once the call's stream work is done), its TF and lights, and K levels of parameters with
+ * their Adam moments and step counter (copied from init_levels). */
 gsc_status gsc_scene_create(gsc_ctx* ctx, const gsc_volume* vol, const gsc_gaussians* init_levels,
                             int32_t K, gsc_scene** out);
 void gsc_scene_destroy(gsc_ctx* ctx, gsc_scene* scene);
@@ -312,7 +315,8 @@ gsc_status gsc_scene_state(const gsc_scene* scene, int32_t l, float** params, fl
                            int64_t* n, int64_t* step);
 /* Copies parameters, moments and step counters from src to dst (same level sizes). */
 gsc_status gsc_scene_copy_state(gsc_ctx* ctx, gsc_scene* dst, const gsc_scene* src);
-/* Resident bytes: grid + 3 x 14 fp32 per Gaussian (parameters and two moments). */
+/* Resident bytes: the cell-corner grid (32 (nx+1)(ny+1)(nz+1)) + 3 x 14 fp32 per Gaussian
+ * (parameters and two moments). */
 size_t gsc_scene_footprint_bytes(const gsc_scene* scene);
 /* Transient bytes one frame of w x h needs, for an instance estimate. */
 size_t gsc_frame_footprint_bytes(const gsc_scene* scene, int32_t w, int32_t h,

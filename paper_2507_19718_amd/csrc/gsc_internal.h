@@ -48,7 +48,8 @@ struct Seg {
 
 // Per request of a trace launch.
 struct TraceDesc {
-  const float* density;
+  const float* density;   // [nz][ny][nx], used when cells is NULL
+  const float4* cells;    // cell-corner layout (see launch_build_cells) or NULL
   int32_t nx, ny, nz;
   float dmax, majorant;
   int32_t P, n_lights;
@@ -72,6 +73,11 @@ struct alignas(16) SplatRec {
 };
 
 // ---- launchers (all enqueue on `st`) ---------------------------------------------------------
+// Cell-corner layout of a density grid: for every trilinear cell (x0, y0, z0) in [-1, n-1]^3 the
+// eight clamped corner values, 32 bytes, so one lookup reads one aligned 32-byte block.
+size_t cells_bytes(int nx, int ny, int nz);
+hipError_t launch_build_cells(hipStream_t st, const float* density, int nx, int ny, int nz,
+                              float4* cells);
 hipError_t launch_project(hipStream_t st, const Seg* segs, const int64_t* seg_gstart, int S,
                           const DevCam* cams, int64_t G, SplatRec* rec, uint32_t* depth_key,
                           uint64_t* rect, uint32_t* tiles, uint32_t* ids);

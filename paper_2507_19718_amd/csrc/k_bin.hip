@@ -12,11 +12,10 @@
 //            atomics), then the band is summed down its columns and along its rows.
 //   scan   : per tile, an exclusive scan over chunks; then a scan over all tiles gives each
 //            tile's [start, end) and the instance total.
-//   place  : one workgroup per (segment, chunk, 4 tile rows, block of 64 tile columns); the
-//            chunk is staged in LDS, each wavefront owns a row and its lanes own tile columns.
-//            The wave tests 64 Gaussians at a time against its row (ballot), then walks the hits
-//            in depth order; each lane appends the ids covering its column at its cursor, so
-//            within a tile ids come out in (depth, id) order.
+//   place  : one workgroup per (segment, chunk, 16x16-tile region), one 16x4 block of tiles
+//            per wavefront and one tile per lane; the wave walks the chunk's rectangles in depth
+//            order and every covered lane appends the id to its tile's run, so within a tile
+//            ids come out in (depth, id) order (details at the kernel).
 #include "gsc_dev.h"
 
 namespace gsc {
@@ -30,7 +29,7 @@ struct BinWork {          // per segment, for the workgroup -> work item maps
   int64_t n;
   int64_t tile_base;
   int64_t ct_off;         // offset of this segment's [chunk][tile] counts
-  int32_t TX, TY, CB;     // tiles, column blocks of 64
+  int32_t TX, TY;         // tiles
   int32_t n_chunks;
   int32_t band_rows;      // tile rows per counting workgroup
   int32_t n_bands;
@@ -119,12 +118,63 @@ __global__ void __launch_bounds__(256) bin_count_kernel(const BinWork* __restric
   for (int k = threadIdx.x; k < words; k += 256) out[k] = (uint32_t)D[k];
 }
 
-// One workgroup per (segment, chunk, group of 4 tile rows, block of 64 tile columns); wave w
-// owns row 4 g + w.  The chunk's depth-ordered rects and ids are staged in LDS once and scanned
-// by all four waves.  Each lane writes its tile's run for the chunk: ids before the first
-// 16-byte boundary one by one, then four at a time from registers (one 16-byte store per four
-// instances), the remainder at the end.
-constexpr int kRowsPerGroup = 4;
+// Placement.  One workgroup per (segment, group of kPlaceChunks consecutive chunks, 16x16-tile
+// region); wavefront w owns the region's 16x4 block of tiles in rows 4w..4w+3, lane t the
+// block's tile (t & 15, t >> 4).  Chunk by chunk, the depth-ordered rectangles and ids are
+// staged in LDS; each wave scans them 64 at a time and compacts, in order, the Gaussians whose
+// rectangle overlaps its block into a small LDS queue; whenever 64 are queued it places them as
+// a batch, lanes now holding Gaussians: for every tile of the batch's bounding box, the lanes
+// whose rectangle covers it (a ballot) write their ids to consecutive positions of the tile's
+// run (rank = number of covering lanes below), one coalesced store per tile, and the tile's
+// cursor (kept in VGPR lane t) advances by their count.  A tile's runs for consecutive chunks
+// are adjacent in the output, so the cursors and the queue carry over from one chunk of the
+// group to the next.  Within a tile ids come out in (depth, id) order, and every store writes a
+// contiguous stretch of the run.
+constexpr int kRegion = 16;      // tiles per region side
+constexpr int kQueue = 128;      // compaction queue entries per wave (a ring)
+constexpr int kPlaceChunks = 1;  // chunks per placement workgroup
+
+__device__ __forceinline__ uint32_t lane_rank(uint64_t m) {
+  return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+}
+
+// Places n <= 64 queued Gaussians (lane i holds entry i) into the runs of the wave's tiles.
+__device__ __forceinline__ void place_batch(uint32_t* __restrict__ values, uint64_t& cur, int lane,
+                                            int n, uint64_t r, uint32_t id, int bx0, int by0,
+                                            int bx1, int by1) {
+  const bool live = lane < n;
+  const uint32_t xr = (uint32_t)r, yr = (uint32_t)(r >> 32);
+  const int tx0 = (int)(xr & 0xffffu), tx1 = (int)(xr >> 16);
+  const int ty0 = (int)(yr & 0xffffu), ty1 = (int)(yr >> 16);
+  // Bounding box of the batch inside the block (wave-uniform).
+  int x0 = live ? max(tx0, bx0) : 0x7fff, x1 = live ? min(tx1, bx1) : -1;
+  int y0 = live ? max(ty0, by0) : 0x7fff, y1 = live ? min(ty1, by1) : -1;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    x0 = min(x0, __shfl_xor(x0, off, 64));
+    x1 = max(x1, __shfl_xor(x1, off, 64));
+    y0 = min(y0, __shfl_xor(y0, off, 64));
+    y1 = max(y1, __shfl_xor(y1, off, 64));
+  }
+  x0 = __builtin_amdgcn_readfirstlane(x0);
+  x1 = __builtin_amdgcn_readfirstlane(x1);
+  y0 = __builtin_amdgcn_readfirstlane(y0);
+  y1 = __builtin_amdgcn_readfirstlane(y1);
+  for (int ty = y0; ty <= y1; ++ty) {
+    const bool rowin = live && ty0 <= ty && ty <= ty1;
+    for (int tx = x0; tx <= x1; ++tx) {
+      const bool cov = rowin && tx0 <= tx && tx <= tx1;
+      const uint64_t m = __ballot(cov);
+      if (m == 0ull) continue;
+      const int t = (tx - bx0) + 16 * (ty - by0);
+      const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)cur, t);
+      const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(cur >> 32), t);
+      const uint64_t base = ((uint64_t)hi << 32) | lo;
+      if (cov) values[base + lane_rank(m)] = id;
+      if (lane == t) cur = base + (uint64_t)__popcll(m);
+    }
+  }
+}
 
 __global__ void __launch_bounds__(256) bin_place_kernel(const BinWork* __restrict__ work,
                                                         const int64_t* __restrict__ block_start,
@@ -138,6 +188,8 @@ __global__ void __launch_bounds__(256) bin_place_kernel(const BinWork* __restric
                                                         uint32_t* __restrict__ values) {
   __shared__ uint64_t sh_rect[kChunk];
   __shared__ uint32_t sh_id[kChunk];
+  __shared__ uint64_t q_rect[4][kQueue];
+  __shared__ uint32_t q_id[4][kQueue];
   const int64_t blk = blockIdx.x;
   if (blk >= total_blocks) return;
   if (*n_instances > capacity) return;
@@ -145,73 +197,81 @@ __global__ void __launch_bounds__(256) bin_place_kernel(const BinWork* __restric
   const int wave = threadIdx.x >> 6;
   const int s = find_segment(block_start, S, blk);
   const BinWork W = work[s];
-  int64_t l = blk - W.wave_start;
-  const int cb = (int)(l % W.CB);
-  l /= W.CB;
-  const int RG = (W.TY + kRowsPerGroup - 1) / kRowsPerGroup;
-  const int rg = (int)(l % RG);
-  const int c = (int)(l / RG);
-  const int64_t g0 = (int64_t)c * kChunk;
-  const int cnt_g = (int)((W.n - g0) < kChunk ? (W.n - g0) : kChunk);
-  const uint64_t* rs = rect_sorted + W.g_off + g0;
-  const uint32_t* ids = sorted_ids + W.g_off + g0;
-  for (int k = threadIdx.x; k < cnt_g; k += 256) {
-    sh_rect[k] = rs[k];
-    sh_id[k] = ids[k];
+  // Chunk group fastest: consecutive workgroups (which the dispatcher spreads over the XCDs
+  // round-robin) take different depth slices of the same region, so every XCD gets a share of
+  // the heavily covered central regions.
+  const int64_t l = blk - W.wave_start;
+  const int RX = (W.TX + kRegion - 1) / kRegion;
+  const int NG = (W.n_chunks + kPlaceChunks - 1) / kPlaceChunks;
+  const int cg = (int)(l % NG);
+  const int region = (int)(l / NG);
+  const int rx = region % RX, ry = region / RX;
+  const int c0 = cg * kPlaceChunks;
+  const int c1 = min(c0 + kPlaceChunks, W.n_chunks);
+  const int bx0 = rx * kRegion, by0 = ry * kRegion + 4 * wave;
+  const bool wave_live = by0 < W.TY;
+  const int bx1 = min(bx0 + kRegion, W.TX) - 1, by1 = min(by0 + 4, W.TY) - 1;
+  // Lane t's tile cursor: where the tile's run continues (first, chunk c0's run).
+  uint64_t cur = 0ull;
+  {
+    const int col = bx0 + (lane & 15), row = by0 + (lane >> 4);
+    if (wave_live && col <= bx1 && row <= by1)
+      cur = tile_start[W.tile_base + (int64_t)row * W.TX + col] +
+            counts[W.ct_off + (int64_t)c0 * ((int64_t)W.TX * W.TY) + (int64_t)row * W.TX + col];
   }
-  __syncthreads();
-  const int ty = rg * kRowsPerGroup + wave;
-  if (ty >= W.TY) return;
-  const int cbs = cb * 64, cbe = cbs + 63;
-  const int col = cbs + lane;
-  const bool col_ok = col < W.TX;
-  const int64_t T = (int64_t)W.TX * W.TY;
-  uint64_t cursor = 0ull;
-  if (col_ok)
-    cursor = tile_start[W.tile_base + (int64_t)ty * W.TX + col] +
-             counts[W.ct_off + (int64_t)c * T + (int64_t)ty * W.TX + col];
-  const uint64_t head_end = (cursor + 3ull) & ~3ull;   // first 16-byte boundary of the run
-  uint32_t q0 = 0u, q1 = 0u, q2 = 0u, q3 = 0u;          // ids of [cursor & ~3, cursor)
-  for (int j = 0; j < cnt_g; j += 64) {
-    const int k = j + lane;
-    uint64_t r = 0x0000000100000001ull;
-    uint32_t my_id = 0u;
-    if (k < cnt_g) {
-      r = sh_rect[k];
-      my_id = sh_id[k];
+  uint64_t* qr = q_rect[wave];
+  uint32_t* qi = q_id[wave];
+  int head = 0, tail = 0;                 // queue: entries [head, tail), modulo kQueue
+  for (int c = c0; c < c1; ++c) {
+    const int64_t g0 = (int64_t)c * kChunk;
+    const int cnt_g = (int)((W.n - g0) < kChunk ? (W.n - g0) : kChunk);
+    const uint64_t* rs = rect_sorted + W.g_off + g0;
+    const uint32_t* ids = sorted_ids + W.g_off + g0;
+    __syncthreads();                       // the previous chunk is consumed
+    for (int k = threadIdx.x; k < cnt_g; k += 256) {
+      sh_rect[k] = rs[k];
+      sh_id[k] = ids[k];
     }
-    const uint32_t xr = (uint32_t)r;
-    const int tx0 = (int)(xr & 0xffffu), tx1 = (int)(xr >> 16);
-    const int ty0 = (int)((r >> 32) & 0xffffu), ty1 = (int)(r >> 48);
-    const bool hit = (ty0 <= ty) && (ty <= ty1) && (tx0 <= cbe) && (tx1 >= cbs) && (tx0 <= tx1);
-    uint64_t mask = __ballot(hit);
-    while (mask) {
-      const int b = __builtin_ctzll(mask);
-      mask &= mask - 1ull;
-      const uint32_t hx = (uint32_t)__builtin_amdgcn_readlane((int)xr, b);
-      const uint32_t id = (uint32_t)__builtin_amdgcn_readlane((int)my_id, b);
-      const int hx0 = (int)(hx & 0xffffu), hx1 = (int)(hx >> 16);
-      if (col >= hx0 && col <= hx1) {
-        if (cursor < head_end) {
-          values[cursor] = id;
-        } else {
-          const uint32_t slot = (uint32_t)cursor & 3u;
-          q0 = slot == 0u ? id : q0;
-          q1 = slot == 1u ? id : q1;
-          q2 = slot == 2u ? id : q2;
-          q3 = slot == 3u ? id : q3;
-          if (slot == 3u) *(uint4*)(values + (cursor - 3ull)) = make_uint4(q0, q1, q2, q3);
-        }
-        ++cursor;
+    __syncthreads();
+    if (!wave_live) continue;
+    for (int j = 0; j < cnt_g; j += 64) {
+      const int k = j + lane;
+      uint64_t r = 0x0000000100000001ull;   // empty rectangle
+      uint32_t id = 0u;
+      if (k < cnt_g) {
+        r = sh_rect[k];
+        id = sh_id[k];
+      }
+      const uint32_t xr = (uint32_t)r, yr = (uint32_t)(r >> 32);
+      const int tx0 = (int)(xr & 0xffffu), tx1 = (int)(xr >> 16);
+      const int ty0 = (int)(yr & 0xffffu), ty1 = (int)(yr >> 16);
+      const bool hit = (tx0 <= tx1) && (tx0 <= bx1) && (tx1 >= bx0) && (ty0 <= by1) && (ty1 >= by0);
+      const uint64_t m = __ballot(hit);
+      if (hit) {
+        const int slot = (tail + (int)lane_rank(m)) & (kQueue - 1);
+        qr[slot] = r;
+        qi[slot] = id;
+      }
+      tail += __popcll(m);
+      while (tail - head >= 64) {
+        __builtin_amdgcn_wave_barrier();
+        const uint64_t qrr = qr[(head + lane) & (kQueue - 1)];
+        const uint32_t qid = qi[(head + lane) & (kQueue - 1)];
+        head += 64;
+        place_batch(values, cur, lane, 64, qrr, qid, bx0, by0, bx1, by1);
       }
     }
   }
-  if (cursor > head_end) {   // then cursor & ~3 >= head_end: flush the partial group
-    const uint64_t base = cursor & ~3ull;
-    const uint32_t n = (uint32_t)cursor & 3u;
-    if (n > 0u) values[base] = q0;
-    if (n > 1u) values[base + 1] = q1;
-    if (n > 2u) values[base + 2] = q2;
+  if (wave_live && tail > head) {          // the last, partial batch
+    const int n = tail - head;
+    __builtin_amdgcn_wave_barrier();
+    uint64_t qrr = 0x0000000100000001ull;
+    uint32_t qid = 0u;
+    if (lane < n) {
+      qrr = qr[(head + lane) & (kQueue - 1)];
+      qid = qi[(head + lane) & (kQueue - 1)];
+    }
+    place_batch(values, cur, lane, n, qrr, qid, bx0, by0, bx1, by1);
   }
 }
 
@@ -382,13 +442,13 @@ int64_t bin_fill_work(void* host, const Seg* segs, int S, int64_t* total_chunk_t
     W[s].ct_off = ct;
     W[s].TX = g.TX;
     W[s].TY = g.TY;
-    W[s].CB = (g.TX + 63) / 64;
     W[s].n_chunks = (int32_t)((g.n + kChunk - 1) / kChunk);
     W[s].band_rows = std::max(1, std::min(g.TY, kDiffWords / std::max(g.TX, 1)));
     W[s].n_bands = (g.TY + W[s].band_rows - 1) / W[s].band_rows;
     ws[s] = waves;
     cs[s] = cblk;
-    waves += (int64_t)W[s].n_chunks * ((g.TY + kRowsPerGroup - 1) / kRowsPerGroup) * W[s].CB;
+    waves += (int64_t)((W[s].n_chunks + kPlaceChunks - 1) / kPlaceChunks) *
+             ((g.TY + kRegion - 1) / kRegion) * ((g.TX + kRegion - 1) / kRegion);
     cblk += (int64_t)W[s].n_chunks * W[s].n_bands;
     ct += (int64_t)W[s].n_chunks * g.TX * g.TY;
   }

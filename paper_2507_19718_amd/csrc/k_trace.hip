@@ -21,6 +21,7 @@ constexpr int kTraceBlock = 256;
 
 struct Vol {
   const float* d;
+  const float4* cells;     // cell-corner layout, or NULL for the plain grid
   int nx, ny, nz;
   float dmax;
   const float* tf;
@@ -29,23 +30,40 @@ struct Vol {
 
 __device__ __forceinline__ float lerpf_(float a, float b, float f) { return a + f * (b - a); }
 
+// Trilinear, cell-centred, clamp-to-edge density at a point of the unit cube.  The eight taps
+// come either from the cell-corner copy (one 32-byte block per lookup) or from the plain grid;
+// both give the same values and the interpolation is the same.
 __device__ __forceinline__ float density(const Vol& V, float px, float py, float pz) {
   const float gx = px * (float)V.nx - 0.5f, gy = py * (float)V.ny - 0.5f, gz = pz * (float)V.nz - 0.5f;
   const float ix = floorf(gx), iy = floorf(gy), iz = floorf(gz);
   const float fx = gx - ix, fy = gy - iy, fz = gz - iz;
   const int x0i = (int)ix, y0i = (int)iy, z0i = (int)iz;
-  const int x0 = min(max(x0i, 0), V.nx - 1), x1 = min(max(x0i + 1, 0), V.nx - 1);
-  const int y0 = min(max(y0i, 0), V.ny - 1), y1 = min(max(y0i + 1, 0), V.ny - 1);
-  const int z0 = min(max(z0i, 0), V.nz - 1), z1 = min(max(z0i + 1, 0), V.nz - 1);
-  const int64_t sy = V.nx, sz = (int64_t)V.nx * V.ny;
-  const float* p00 = V.d + z0 * sz + y0 * sy;
-  const float* p10 = V.d + z0 * sz + y1 * sy;
-  const float* p01 = V.d + z1 * sz + y0 * sy;
-  const float* p11 = V.d + z1 * sz + y1 * sy;
-  const float c00 = lerpf_(p00[x0], p00[x1], fx);
-  const float c10 = lerpf_(p10[x0], p10[x1], fx);
-  const float c01 = lerpf_(p01[x0], p01[x1], fx);
-  const float c11 = lerpf_(p11[x0], p11[x1], fx);
+  float c00, c10, c01, c11;
+  if (V.cells) {
+    // Inside the cube x0i, y0i, z0i lie in [-1, n - 1]; clamp anyway so a lookup never leaves
+    // the array.
+    const int cx = min(max(x0i, -1), V.nx - 1) + 1, cy = min(max(y0i, -1), V.ny - 1) + 1;
+    const int cz = min(max(z0i, -1), V.nz - 1) + 1;
+    const int64_t ci = ((int64_t)cz * (V.ny + 1) + cy) * (V.nx + 1) + cx;
+    const float4 a = V.cells[2 * ci], b = V.cells[2 * ci + 1];
+    c00 = lerpf_(a.x, a.y, fx);
+    c10 = lerpf_(a.z, a.w, fx);
+    c01 = lerpf_(b.x, b.y, fx);
+    c11 = lerpf_(b.z, b.w, fx);
+  } else {
+    const int x0 = min(max(x0i, 0), V.nx - 1), x1 = min(max(x0i + 1, 0), V.nx - 1);
+    const int y0 = min(max(y0i, 0), V.ny - 1), y1 = min(max(y0i + 1, 0), V.ny - 1);
+    const int z0 = min(max(z0i, 0), V.nz - 1), z1 = min(max(z0i + 1, 0), V.nz - 1);
+    const int64_t sy = V.nx, sz = (int64_t)V.nx * V.ny;
+    const float* p00 = V.d + z0 * sz + y0 * sy;
+    const float* p10 = V.d + z0 * sz + y1 * sy;
+    const float* p01 = V.d + z1 * sz + y0 * sy;
+    const float* p11 = V.d + z1 * sz + y1 * sy;
+    c00 = lerpf_(p00[x0], p00[x1], fx);
+    c10 = lerpf_(p10[x0], p10[x1], fx);
+    c01 = lerpf_(p01[x0], p01[x1], fx);
+    c11 = lerpf_(p11[x0], p11[x1], fx);
+  }
   const float c0 = lerpf_(c00, c10, fy), c1 = lerpf_(c01, c11, fy);
   return lerpf_(c0, c1, fz);
 }
@@ -232,7 +250,7 @@ __global__ void __launch_bounds__(kTraceBlock) trace_kernel(const TraceDesc* __r
   const int64_t lp = block0 + threadIdx.x - D.pix_off;
   uint64_t verts = 0;
   if (lp < plane) {
-    const Vol V{D.density, D.nx, D.ny, D.nz, D.dmax, s_tf, D.P};
+    const Vol V{D.density, D.cells, D.nx, D.ny, D.nz, D.dmax, s_tf, D.P};
     const int lx = (int)(lp % W), ly = (int)(lp / W);
     const int px = D.cam.x0 + lx, py = D.cam.y0 + ly;
     const uint32_t K = D.K;
@@ -286,6 +304,28 @@ __global__ void __launch_bounds__(kTraceBlock) trace_kernel(const TraceDesc* __r
   }
 }
 
+// One thread per cell (x0, y0, z0) in [-1, n-1]^3: the clamped corners in the order
+// (x0,y0,z0) (x1,y0,z0) (x0,y1,z0) (x1,y1,z0) (x0,y0,z1) (x1,y0,z1) (x0,y1,z1) (x1,y1,z1).
+__global__ void __launch_bounds__(256) build_cells_kernel(const float* __restrict__ d, int nx, int ny,
+                                                          int nz, float4* __restrict__ cells) {
+  const int64_t n = (int64_t)(nx + 1) * (ny + 1) * (nz + 1);
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int cx = (int)(i % (nx + 1)) - 1;
+  const int cy = (int)((i / (nx + 1)) % (ny + 1)) - 1;
+  const int cz = (int)(i / ((int64_t)(nx + 1) * (ny + 1))) - 1;
+  const int x0 = max(cx, 0), x1 = min(cx + 1, nx - 1);
+  const int y0 = max(cy, 0), y1 = min(cy + 1, ny - 1);
+  const int z0 = max(cz, 0), z1 = min(cz + 1, nz - 1);
+  const int64_t sy = nx, sz = (int64_t)nx * ny;
+  const float* p00 = d + z0 * sz + y0 * sy;
+  const float* p10 = d + z0 * sz + y1 * sy;
+  const float* p01 = d + z1 * sz + y0 * sy;
+  const float* p11 = d + z1 * sz + y1 * sy;
+  cells[2 * i] = make_float4(p00[x0], p00[x1], p10[x0], p10[x1]);
+  cells[2 * i + 1] = make_float4(p01[x0], p01[x1], p11[x0], p11[x1]);
+}
+
 }  // namespace
 
 int64_t trace_align(int64_t pixels) { return (pixels + kTraceBlock - 1) / kTraceBlock * kTraceBlock; }
@@ -297,6 +337,18 @@ hipError_t launch_trace(hipStream_t st, const TraceDesc* descs, const int64_t* r
   if (total_launch == 0) return hipSuccess;
   hipLaunchKernelGGL(trace_kernel, dim3((unsigned)(total_launch / kTraceBlock)), dim3(kTraceBlock), 0,
                      st, descs, req_pstart, R, path_vertices);
+  return hipGetLastError();
+}
+
+size_t cells_bytes(int nx, int ny, int nz) {
+  return 32 * (size_t)(nx + 1) * (size_t)(ny + 1) * (size_t)(nz + 1);
+}
+
+hipError_t launch_build_cells(hipStream_t st, const float* density, int nx, int ny, int nz,
+                              float4* cells) {
+  const int64_t n = (int64_t)(nx + 1) * (ny + 1) * (nz + 1);
+  hipLaunchKernelGGL(build_cells_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, density,
+                     nx, ny, nz, cells);
   return hipGetLastError();
 }
 

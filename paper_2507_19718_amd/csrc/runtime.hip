@@ -110,7 +110,7 @@ struct gsc_scene {
   std::vector<float*> params;      // per level: [pos 3n][rot 4n][ls 3n][rgb 3n][logit n]
   std::vector<float*> m, v;
   std::vector<int64_t> step;       // Adam steps taken per level
-  float* density = nullptr;
+  float4* cells = nullptr;         // density in the cell-corner layout (32 B per trilinear cell)
   int32_t nx = 0, ny = 0, nz = 0;
   float dmax = 1.0f;
   std::vector<float> tf, lights;
@@ -511,12 +511,14 @@ void check_volume_host(gsc_ctx* ctx, const float* tf, int P, const float* lights
   for (int i = 0; i < 6 * nl; ++i) if (!std::isfinite(lights[i])) invalid(ctx, "lights not finite");
 }
 
-TraceDesc make_trace_desc(const float* density, int nx, int ny, int nz, float dmax, const float* tf,
+TraceDesc make_trace_desc(const float* density, const float4* cells, int nx, int ny, int nz, float dmax,
+                          const float* tf,
                           int P, const float* lights, int nl, const gsc_camera& cam,
                           const gsc_trace_params& tp) {
   TraceDesc d;
   std::memset(&d, 0, sizeof(d));
   d.density = density;
+  d.cells = cells;
   d.nx = nx; d.ny = ny; d.nz = nz;
   d.dmax = dmax;
   d.majorant = dmax * max_alpha(tf, P);
@@ -639,7 +641,7 @@ gsc_status render_batch(gsc_ctx* ctx, gsc_scene* const* scenes, const gsc_frame_
   int64_t tlaunch = 0;
   for (int i = 0; i < n; ++i) {
     gsc_scene* sc = scenes[i];
-    td[i] = make_trace_desc(sc->density, sc->nx, sc->ny, sc->nz, sc->dmax, sc->tf.data(),
+    td[i] = make_trace_desc(nullptr, sc->cells, sc->nx, sc->ny, sc->nz, sc->dmax, sc->tf.data(),
                             (int)sc->tf.size() / 4, sc->lights.data(), (int)sc->lights.size() / 6,
                             reqs[i].cam, reqs[i].trace);
     td[i].pix_off = tlaunch;
@@ -865,7 +867,7 @@ gsc_status gsc_trace_targets(gsc_ctx* ctx, const gsc_volume* vol, const gsc_came
     check_trace_params(ctx, params);
     if (!targets) invalid(ctx, "targets is NULL");
     if (records && params->spp != 1) invalid(ctx, "records require spp == 1");
-    TraceDesc d = make_trace_desc(vol->density, vol->nx, vol->ny, vol->nz, vol->density_max,
+    TraceDesc d = make_trace_desc(vol->density, nullptr, vol->nx, vol->ny, vol->nz, vol->density_max,
                                   vol->tf_rgba, vol->tf_points, vol->lights, vol->n_lights, *cam, *params);
     d.pix_off = 0;
     d.targets = targets;
@@ -1081,7 +1083,7 @@ gsc_status gsc_scene_create(gsc_ctx* ctx, const gsc_volume* vol, const gsc_gauss
       for (float* p : sc->params) sc->alloc.put(p);
       for (float* p : sc->m) sc->alloc.put(p);
       for (float* p : sc->v) sc->alloc.put(p);
-      sc->alloc.put(sc->density);
+      sc->alloc.put(sc->cells);
       delete sc;
     };
     try {
@@ -1090,10 +1092,10 @@ gsc_status gsc_scene_create(gsc_ctx* ctx, const gsc_volume* vol, const gsc_gauss
       sc->dmax = vol->density_max;
       sc->tf.assign(vol->tf_rgba, vol->tf_rgba + 4 * vol->tf_points);
       sc->lights.assign(vol->lights, vol->lights + 6 * vol->n_lights);
-      const size_t vb = 4 * (size_t)vol->nx * vol->ny * vol->nz;
-      sc->density = (float*)sc->alloc.get(vb);
-      if (!sc->density) oom(ctx, "scene volume", vb);
-      GSC_TRY(hipMemcpyAsync(sc->density, vol->density, vb, hipMemcpyDeviceToDevice, ctx->stream));
+      const size_t vb = cells_bytes(vol->nx, vol->ny, vol->nz);
+      sc->cells = (float4*)sc->alloc.get(vb);
+      if (!sc->cells) oom(ctx, "scene volume", vb);
+      GSC_TRY(launch_build_cells(ctx->stream, vol->density, vol->nx, vol->ny, vol->nz, sc->cells));
       for (int l = 0; l < K; ++l) {
         const int64_t nn = init_levels[l].n;
         const size_t bytes = 4 * 14 * (size_t)std::max<int64_t>(nn, 1);
@@ -1133,7 +1135,7 @@ void gsc_scene_destroy(gsc_ctx* ctx, gsc_scene* sc) {
   for (float* p : sc->params) sc->alloc.put(p);
   for (float* p : sc->m) sc->alloc.put(p);
   for (float* p : sc->v) sc->alloc.put(p);
-  sc->alloc.put(sc->density);
+  sc->alloc.put(sc->cells);
   delete sc;
 }
 
@@ -1187,7 +1189,7 @@ gsc_status gsc_scene_copy_state(gsc_ctx* ctx, gsc_scene* dst, const gsc_scene* s
 
 size_t gsc_scene_footprint_bytes(const gsc_scene* sc) {
   if (!sc) return 0;
-  size_t b = 4 * (size_t)sc->nx * sc->ny * sc->nz;
+  size_t b = cells_bytes(sc->nx, sc->ny, sc->nz);
   for (int l = 0; l < sc->K; ++l) b += 3 * 14 * 4 * (size_t)sc->n[l];
   return b;
 }
