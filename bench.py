@@ -12,8 +12,14 @@ lights, 1920x1080, static camera (orbit radius 1.8, azimuth 30, elevation 20, fo
 cache levels x 1M Gaussians (means U[0,1]^3, log-scales N(-3, 0.3), random rotations, RGB
 U[0,1], opacity U[0.1, 0.9]), B = 4, C = 0.5, paper learning rates, weight decay 1e-2.
 
+Also replays a Poisson request log (4 resident scenes, 32 viewers, 240 requests/s) through the
+plain serial loop and the continuous batcher and reports frames/s and p50/p99 latency of both.
+
 Prints one JSON line (rank 0).  Kernel times come from HIP events the library records on each
-kernel's own stream during the timed region (gsc_ctx_profile).
+kernel's own stream during the timed region (gsc_ctx_profile); `roofline` is the dominant
+kernel's algorithmic work per launch over its average launch time against the MI355X peak, with
+the HBM traffic measured by rocprofv3 (committed summary) when the kernel source still matches;
+`cpu_baseline` is the CPU oracle on a bounded sample of the same frame.
 """
 from __future__ import annotations
 
@@ -126,7 +132,7 @@ def measured_traffic(kernel: str):
     return None
 
 
-def cpu_baseline(wl, vol, levels, crop=64):
+def cpu_baseline(wl, vol, levels, crop=256):
     """The oracle, as it stands, on a bounded sample of the same frame: a crop x crop centre
     window at the full Gaussian count; per-pixel stages are extrapolated to the full frame."""
     import numpy as np
@@ -227,8 +233,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy 5 times (calibrates HBM counters)")
-    ap.add_argument("--serve-seconds", type=float, default=0.0,
-                    help="also replay a Poisson log of this length, served vs plain")
+    ap.add_argument("--serve-seconds", type=float, default=8.0,
+                    help="length of the Poisson request log replayed served vs plain (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (the GSCache hot path is single-GPU here); "

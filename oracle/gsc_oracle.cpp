@@ -827,3 +827,67 @@ void ora_forward_f64(const double* pos, const double* rot, const double* ls, con
   }
 }
 }  // extern "C"
+
+// ------------------------------------------------------------------------------------------
+// Cache initialisation points (Method: "Cache Initialization"): random rays are tracked through
+// the volume by delta tracking until their first real interaction, whose position and albedo
+// are recorded; a ray that leaves the volume is replaced by a fresh one.  Point i, attempt a
+// draws from the Philox stream with counter (i, a, 0x494E4954, block): p = (u0, u1, u2) uniform
+// in the cube, direction w from (u3, u4) uniform on the sphere (as the phase function), the ray
+// starts at p - 2 w (outside the cube, through p), then free flight as in the tracer.
+// ------------------------------------------------------------------------------------------
+extern "C" {
+
+int ora_init_points(const float* density, int nx, int ny, int nz, float dmax, const float* tf,
+                    int P, int64_t n, uint64_t seed, int max_attempts, float* pos, float* albedo,
+                    int32_t* attempts) {
+  OVolume V{density, nx, ny, nz, dmax, tf, P, 0.0f};
+  float amax = 0.0f;
+  for (int i = 0; i < P; ++i) amax = std::fmax(amax, tf[4 * i + 3]);
+  V.majorant = dmax * amax;
+  const float sb = V.majorant;
+  int failed = 0;
+#pragma omp parallel for schedule(dynamic, 256) reduction(| : failed)
+  for (int64_t i = 0; i < n; ++i) {
+    bool found = false;
+    int a = 0;
+    for (; a < max_attempts && !found; ++a) {
+      PathRng rng(seed, (uint32_t)i, (uint32_t)a, 0x494E4954u);
+      float p[3];
+      for (int k = 0; k < 3; ++k) p[k] = rng.uniform();
+      float u3 = rng.uniform(), u4 = rng.uniform();
+      float z = 1.0f - 2.0f * u3;
+      float r = std::sqrt(std::fmax(0.0f, 1.0f - z * z));
+      float phi = (float)(2.0 * 3.14159265358979323846) * u4;
+      float sp, cp;
+      ora_sincosf_impl(phi, &sp, &cp);
+      float w[3] = {r * cp, r * sp, z};
+      float o[3];
+      for (int k = 0; k < 3; ++k) o[k] = p[k] - 2.0f * w[k];
+      float t0, t1;
+      if (!ora_box(o, w, &t0, &t1)) continue;
+      float t = t0;
+      for (uint32_t step = 0; step < MAX_STEPS; ++step) {
+        float u = rng.uniform();
+        t = t - ora_logf_impl(1.0f - u) / sb;
+        if (t >= t1) break;
+        float x[3];
+        for (int k = 0; k < 3; ++k) x[k] = o[k] + t * w[k];
+        float u2 = rng.uniform();
+        if (u2 < ora_sigma_t(V, x[0], x[1], x[2]) / sb) {
+          float d = ora_density(V, x[0], x[1], x[2]);
+          float rgba[4];
+          ora_tf(V, d, rgba);
+          for (int k = 0; k < 3; ++k) { pos[3 * i + k] = x[k]; albedo[3 * i + k] = rgba[k]; }
+          found = true;
+          break;
+        }
+      }
+    }
+    attempts[i] = a;
+    if (!found) failed = 1;
+  }
+  return failed;
+}
+
+}  // extern "C"
