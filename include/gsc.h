@@ -90,6 +90,16 @@ typedef struct {
   int64_t n;
 } gsc_gaussians;
 
+/* Writable parameter arrays of one level (cache initialisation output).  DEVICE, overwritten. */
+typedef struct {
+  float* pos;
+  float* rot;
+  float* log_scale;
+  float* rgb;
+  float* opacity_logit;
+  int64_t n;
+} gsc_level_buffers;
+
 /* Parameter gradients of one level, same shapes as gsc_gaussians.  DEVICE, overwritten. */
 typedef struct {
   float* pos;
@@ -294,6 +304,30 @@ gsc_status gsc_loss_composite(gsc_ctx* ctx, const float* images, const float* ta
 gsc_status gsc_adam_step(gsc_ctx* ctx, float* param, float* m, float* v, const float* grad,
                          int64_t count, const gsc_adam_hparams* hp);
 
+/* ---- cache initialisation (Method: "Cache Initialization", Eq. 2) ------------------------ */
+/* n points of first interaction of random rays with the volume (delta tracking against the
+ * majorant; a ray that leaves the cube is replaced by a new one, up to 4096 per point), with
+ * the transfer function's colour at the point as albedo.  Point i's attempt a draws from the
+ * Philox4x32-10 stream keyed by seed with counter (i, a, 0x494E4954, block): a point p uniform
+ * in the cube, a direction w uniform on the sphere, the ray starting at p - 2 w.  vol: density
+ * DEVICE, TF HOST (lights unused).  pos, albedo: DEVICE [n][3] fp32, caller-owned.
+ * GSC_E_INVALID_ARG for bad arguments or if some point found no interaction (a volume that is
+ * transparent under its TF); then pos/albedo are partially written. */
+gsc_status gsc_init_points(gsc_ctx* ctx, const gsc_volume* vol, int64_t n, uint64_t seed,
+                           float* pos, float* albedo);
+/* For each of n points (DEVICE [n][3], in the unit cube) the mean Euclidean distance to its 3
+ * nearest other points (uniform grid, rings searched outward until exact).  mean3: DEVICE [n].
+ * n >= 4. */
+gsc_status gsc_knn_mean3(gsc_ctx* ctx, const float* pos, int64_t n, float* mean3);
+/* K cache levels from one sampling pass: n points as gsc_init_points; level l takes the first
+ * n >> l of them (the points are i.i.d., so a prefix is a uniform sub-sample, sum_l n / 2^l in
+ * total), isotropic scale s_i = min(mu + 2 sigma, m_i) / 2 (Eq. 2; m_i the mean 3-NN distance
+ * within the level, mu and sigma its mean and population standard deviation), identity
+ * rotation, log-scale log(s_i) on all axes, the albedo as colour, opacity 0.1 (logit).
+ * levels[l].n must equal n >> l, and n >> (K - 1) >= 4.  Arrays DEVICE, caller-owned. */
+gsc_status gsc_cache_init(gsc_ctx* ctx, const gsc_volume* vol, int64_t n, int32_t K, uint64_t seed,
+                          const gsc_level_buffers* levels);
+
 /* ---- scenes and frames ------------------------------------------------------------------ */
 /* A scene keeps resident on the device: its volume grid in a cell-corner layout (for every
  * trilinear cell the eight clamped corner values, 32 bytes, (nx+1)(ny+1)(nz+1) cells, so a
@@ -346,7 +380,8 @@ gsc_status gsc_ctx_synchronize(gsc_ctx* ctx);
 
 /* HOST, side-effect free: sizes of the structs above, for bindings to check their layouts:
  * which = 0 camera, 1 gaussians, 2 grads, 3 volume, 4 trace_params, 5 path_record,
- * 6 frame_stats, 7 binning_info, 8 adam_hparams, 9 frame_request, 10 allocator, 11 counters;
+ * 6 frame_stats, 7 binning_info, 8 adam_hparams, 9 frame_request, 10 allocator, 11 counters,
+ * 12 level_buffers;
  * 0 for any other value. */
 size_t gsc_abi_struct_size(int32_t which);
 

@@ -245,6 +245,47 @@ def gsc_trace_targets(ctx: Context, vol: Volume, cam, params: gsc_trace_params,
     return st.as_dict() if st is not None else None
 
 
+# ----------------------------------------------------------------------------------------------
+# Cache initialisation (Method: "Cache Initialization", Eq. 2)
+# ----------------------------------------------------------------------------------------------
+def gsc_init_points(ctx: Context, vol: Volume, n: int, seed: int):
+    """n first-interaction points of random rays and their albedo: (pos, albedo), [n][3] each."""
+    pos = torch.empty((n, 3), dtype=torch.float32, device="cuda")
+    albedo = torch.empty((n, 3), dtype=torch.float32, device="cuda")
+    vs = vol.struct()
+    ctx.check(ctx._lib.gsc_init_points(ctx.handle, ctypes.byref(vs), n, seed, _ptr(pos), _ptr(albedo)))
+    return pos, albedo
+
+
+def gsc_knn_mean3(ctx: Context, pos: torch.Tensor) -> torch.Tensor:
+    """Mean distance of every point ([n][3] float32, CUDA) to its 3 nearest other points."""
+    _f32_cuda(pos, "pos")
+    n = pos.shape[0]
+    out = torch.empty(n, dtype=torch.float32, device="cuda")
+    ctx.check(ctx._lib.gsc_knn_mean3(ctx.handle, _ptr(pos), n, _ptr(out)))
+    return out
+
+
+def gsc_cache_init(ctx: Context, vol: Volume, n: int, K: int, seed: int) -> List[Dict[str, torch.Tensor]]:
+    """K initial cache levels (level l has n >> l Gaussians), as dicts of CUDA tensors with the
+    parameter names (pos, rot, log_scale, rgb, opacity_logit)."""
+    levels = []
+    bufs = (_abi.gsc_level_buffers * K)()
+    for l in range(K):
+        nl = n >> l
+        lv = {"pos": torch.empty((nl, 3), dtype=torch.float32, device="cuda"),
+              "rot": torch.empty((nl, 4), dtype=torch.float32, device="cuda"),
+              "log_scale": torch.empty((nl, 3), dtype=torch.float32, device="cuda"),
+              "rgb": torch.empty((nl, 3), dtype=torch.float32, device="cuda"),
+              "opacity_logit": torch.empty((nl,), dtype=torch.float32, device="cuda")}
+        levels.append(lv)
+        bufs[l] = _abi.gsc_level_buffers(_ptr(lv["pos"]), _ptr(lv["rot"]), _ptr(lv["log_scale"]),
+                                         _ptr(lv["rgb"]), _ptr(lv["opacity_logit"]), nl)
+    vs = vol.struct()
+    ctx.check(ctx._lib.gsc_cache_init(ctx.handle, ctypes.byref(vs), n, K, seed, bufs))
+    return levels
+
+
 class Binning:
     """Owns a gsc_binning*; released on garbage collection (after the stream drains)."""
 

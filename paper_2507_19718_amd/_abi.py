@@ -83,6 +83,11 @@ class gsc_frame_request(Structure):
                 ("weight_decay", c_double)]
 
 
+class gsc_level_buffers(Structure):
+    _fields_ = [("pos", c_void_p), ("rot", c_void_p), ("log_scale", c_void_p), ("rgb", c_void_p),
+                ("opacity_logit", c_void_p), ("n", c_int64)]
+
+
 class gsc_counters(Structure):
     _fields_ = [("instances", c_uint64), ("binnings", c_uint64), ("evaluations", c_uint64),
                 ("blended", c_uint64), ("contributors", c_uint64), ("tile_entries", c_uint64)]
@@ -93,7 +98,7 @@ class gsc_counters(Structure):
 
 STRUCTS = [gsc_camera, gsc_gaussians, gsc_grads, gsc_volume, gsc_trace_params, gsc_path_record,
            gsc_frame_stats, gsc_binning_info, gsc_adam_hparams, gsc_frame_request, gsc_allocator,
-           gsc_counters]
+           gsc_counters, gsc_level_buffers]
 
 P = POINTER
 _SIGNATURES = {
@@ -110,6 +115,10 @@ _SIGNATURES = {
     "gsc_ctx_profile_read": (c_int32, [c_void_p, c_int32, ctypes.c_char_p, c_size_t, P(c_double),
                                        P(c_int64)]),
     "gsc_ctx_counters": (c_int32, [c_void_p, P(gsc_counters)]),
+    "gsc_init_points": (c_int32, [c_void_p, P(gsc_volume), c_int64, c_uint64, c_void_p, c_void_p]),
+    "gsc_knn_mean3": (c_int32, [c_void_p, c_void_p, c_int64, c_void_p]),
+    "gsc_cache_init": (c_int32, [c_void_p, P(gsc_volume), c_int64, c_int32, c_uint64,
+                                 P(gsc_level_buffers)]),
     "gsc_trace_targets": (c_int32, [c_void_p, P(gsc_volume), P(gsc_camera), P(gsc_trace_params),
                                     c_void_p, c_void_p, P(gsc_frame_stats)]),
     "gsc_project_bin": (c_int32, [c_void_p, P(gsc_gaussians), c_int32, P(gsc_camera), c_uint64,

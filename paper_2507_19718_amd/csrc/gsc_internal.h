@@ -78,6 +78,23 @@ struct alignas(16) SplatRec {
 size_t cells_bytes(int nx, int ny, int nz);
 hipError_t launch_build_cells(hipStream_t st, const float* density, int nx, int ny, int nz,
                               float4* cells);
+// Cache initialisation (k_trace.hip: points; k_init.hip: neighbours, Eq. 2, levels).
+hipError_t launch_init_points(hipStream_t st, const TraceDesc* desc, int64_t n, int max_attempts,
+                              float* pos, float* albedo, int32_t* tries);
+int init_grid_side(int64_t n);
+hipError_t launch_grid_keys(hipStream_t st, const float* pos, int64_t n, int G, uint32_t* key,
+                            uint32_t* id);
+hipError_t launch_cell_ranges(hipStream_t st, const uint32_t* key, const uint32_t* id, const float* pos,
+                              int64_t n, uint32_t* start, uint32_t* end, float4* spos);
+hipError_t launch_knn3(hipStream_t st, const float4* spos, const uint32_t* id, int64_t n, int G,
+                       const uint32_t* start, const uint32_t* end, float* mean3);
+int init_moment_blocks();
+size_t init_partial_doubles();
+hipError_t launch_count_failed(hipStream_t st, const int32_t* tries, int64_t n,
+                               unsigned long long* out);
+hipError_t launch_init_level(hipStream_t st, const float* mean3, int64_t n, const float* pos,
+                             const float* albedo, float opacity_logit, double* partial, float* gpos,
+                             float* grot, float* gls, float* grgb, float* glogit);
 hipError_t launch_project(hipStream_t st, const Seg* segs, const int64_t* seg_gstart, int S,
                           const DevCam* cams, int64_t G, SplatRec* rec, uint32_t* depth_key,
                           uint64_t* rect, uint32_t* tiles, uint32_t* ids);

@@ -304,6 +304,62 @@ __global__ void __launch_bounds__(kTraceBlock) trace_kernel(const TraceDesc* __r
   }
 }
 
+// Cache initialisation points (Method: "Cache Initialization"): one lane per point; random rays
+// are tracked through the volume by delta tracking until their first real interaction, whose
+// position and albedo (the transfer function's colour at that density) are recorded; a ray that
+// leaves the volume is replaced by a fresh one.  Attempt a of point i draws from the Philox
+// stream with counter (i, a, 0x494E4954, block): a point p uniform in the cube (3 draws), a
+// direction w uniform on the sphere (2 draws, as the phase function), the ray starts at
+// p - 2 w, outside the cube, and passes through p.  tries[i] = attempts used, 0 if none found.
+__global__ void __launch_bounds__(kTraceBlock) init_points_kernel(const TraceDesc* __restrict__ D,
+                                                                  int64_t n, int max_attempts,
+                                                                  float* __restrict__ pos,
+                                                                  float* __restrict__ albedo,
+                                                                  int32_t* __restrict__ tries) {
+  __shared__ float s_tf[kMaxTf * 4];
+  for (int k = threadIdx.x; k < 4 * D->P; k += kTraceBlock) s_tf[k] = D->tf[k];
+  __syncthreads();
+  const int64_t i = (int64_t)blockIdx.x * kTraceBlock + threadIdx.x;
+  if (i >= n) return;
+  const Vol V{D->density, D->cells, D->nx, D->ny, D->nz, D->dmax, s_tf, D->P};
+  const float sb = D->majorant;
+  int32_t used = 0;
+  for (int a = 0; a < max_attempts; ++a) {
+    PathStream rng(D->seed, (uint32_t)i, (uint32_t)a, 0x494E4954u);
+    const float p0 = rng.uniform(), p1 = rng.uniform(), p2 = rng.uniform();
+    const float u3 = rng.uniform(), u4 = rng.uniform();
+    const float cz = 1.0f - 2.0f * u3;
+    const float r = sqrtf(fmaxf(0.0f, 1.0f - cz * cz));
+    float sp, cp;
+    gsincos(kTwoPi * u4, &sp, &cp);
+    const float wx = r * cp, wy = r * sp, wz = cz;
+    const float ox = p0 - 2.0f * wx, oy = p1 - 2.0f * wy, oz = p2 - 2.0f * wz;
+    float t0, t1;
+    if (!box(ox, oy, oz, wx, wy, wz, &t0, &t1)) continue;
+    float t = t0;
+    bool hit = false;
+    for (uint32_t step = 0; step < kMaxSteps; ++step) {
+      const float u = rng.uniform();
+      t = t - glog(1.0f - u) / sb;
+      if (t >= t1) break;
+      const float x = ox + t * wx, y = oy + t * wy, z = oz + t * wz;
+      const float u2 = rng.uniform();
+      float dd;
+      const float st = sigma_t(V, x, y, z, &dd);
+      if (u2 < st / sb) {
+        float ar, ag, ab, aa;
+        transfer(V, dd, &ar, &ag, &ab, &aa);
+        pos[3 * i + 0] = x; pos[3 * i + 1] = y; pos[3 * i + 2] = z;
+        albedo[3 * i + 0] = ar; albedo[3 * i + 1] = ag; albedo[3 * i + 2] = ab;
+        hit = true;
+        break;
+      }
+    }
+    if (hit) { used = a + 1; break; }
+  }
+  tries[i] = used;
+}
+
 // One thread per cell (x0, y0, z0) in [-1, n-1]^3: the clamped corners in the order
 // (x0,y0,z0) (x1,y0,z0) (x0,y1,z0) (x1,y1,z0) (x0,y0,z1) (x1,y0,z1) (x0,y1,z1) (x1,y1,z1).
 __global__ void __launch_bounds__(256) build_cells_kernel(const float* __restrict__ d, int nx, int ny,
@@ -349,6 +405,14 @@ hipError_t launch_build_cells(hipStream_t st, const float* density, int nx, int 
   const int64_t n = (int64_t)(nx + 1) * (ny + 1) * (nz + 1);
   hipLaunchKernelGGL(build_cells_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, density,
                      nx, ny, nz, cells);
+  return hipGetLastError();
+}
+
+hipError_t launch_init_points(hipStream_t st, const TraceDesc* desc, int64_t n, int max_attempts,
+                              float* pos, float* albedo, int32_t* tries) {
+  if (n == 0) return hipSuccess;
+  hipLaunchKernelGGL(init_points_kernel, dim3((unsigned)((n + kTraceBlock - 1) / kTraceBlock)),
+                     dim3(kTraceBlock), 0, st, desc, n, max_attempts, pos, albedo, tries);
   return hipGetLastError();
 }
 

@@ -136,6 +136,9 @@ struct gsc_ctx {
   gsc_binning* frame_bin = nullptr;
   DevBuf targets, records, dL, partials, losses, grads14, images, final_T, last_id, trace_tab,
       vertices, composite_tmp;
+  // cache initialisation workspace
+  DevBuf ini_tries, ini_key, ini_id, ini_key_tmp, ini_id_tmp, ini_hist, ini_sort_tab, ini_start,
+      ini_end, ini_spos, ini_partial, ini_pos, ini_alb, ini_mean3, ini_count;
   uint64_t* host_u64 = nullptr;    // pinned scalars for readback
   // per-kernel event timing (gsc_ctx_profile)
   bool prof_on = false;
@@ -807,7 +810,10 @@ void gsc_ctx_destroy(gsc_ctx* c) {
   if (c->frame_bin) { c->frame_bin->free_all(); delete c->frame_bin; }
   DevBuf* all[] = {&c->targets, &c->records, &c->dL, &c->partials, &c->losses, &c->grads14,
                    &c->images, &c->final_T, &c->last_id, &c->trace_tab, &c->vertices,
-                   &c->composite_tmp, &c->d_stats, &c->adam_tab};
+                   &c->composite_tmp, &c->d_stats, &c->adam_tab, &c->ini_tries, &c->ini_key,
+                   &c->ini_id, &c->ini_key_tmp, &c->ini_id_tmp, &c->ini_hist, &c->ini_sort_tab,
+                   &c->ini_start, &c->ini_end, &c->ini_spos, &c->ini_partial, &c->ini_pos,
+                   &c->ini_alb, &c->ini_mean3, &c->ini_count};
   for (DevBuf* b : all) b->release(c->alloc);
   if (c->pinned) (void)hipHostFree(c->pinned);
   if (c->host_u64) (void)hipHostFree(c->host_u64);
@@ -849,7 +855,11 @@ gsc_status gsc_ctx_trim(gsc_ctx* ctx) {
     if (ctx->frame_bin) { ctx->frame_bin->free_all(); delete ctx->frame_bin; ctx->frame_bin = nullptr; }
     DevBuf* all[] = {&ctx->targets, &ctx->records, &ctx->dL, &ctx->partials, &ctx->losses,
                      &ctx->grads14, &ctx->images, &ctx->final_T, &ctx->last_id, &ctx->trace_tab,
-                     &ctx->vertices, &ctx->composite_tmp, &ctx->adam_tab};
+                     &ctx->vertices, &ctx->composite_tmp, &ctx->adam_tab, &ctx->ini_tries,
+                     &ctx->ini_key, &ctx->ini_id, &ctx->ini_key_tmp, &ctx->ini_id_tmp,
+                     &ctx->ini_hist, &ctx->ini_sort_tab, &ctx->ini_start, &ctx->ini_end,
+                     &ctx->ini_spos, &ctx->ini_partial, &ctx->ini_pos, &ctx->ini_alb,
+                     &ctx->ini_mean3, &ctx->ini_count};
     for (DevBuf* b : all) b->release(ctx->alloc);
     return GSC_OK;
   });
@@ -1224,6 +1234,142 @@ gsc_status gsc_render_frames(gsc_ctx* ctx, gsc_scene* const* scenes, const gsc_f
   return guarded(ctx, [&]() -> gsc_status { return render_batch(ctx, scenes, reqs, images, n, stats); });
 }
 
+}  // extern "C"
+
+namespace {
+
+// ---- cache initialisation (Method: "Cache Initialization", Eq. 2) ------------------------------
+constexpr int kInitMaxAttempts = 4096;
+
+void check_init_volume(gsc_ctx* ctx, const gsc_volume* vol) {
+  if (!vol || !vol->density) invalid(ctx, "volume or density is NULL");
+  if (vol->nx < 1 || vol->ny < 1 || vol->nz < 1) invalid(ctx, "volume dimensions must be >= 1");
+  if (!(vol->density_max > 0.0f) || !std::isfinite(vol->density_max)) invalid(ctx, "density_max must be positive");
+  if (vol->tf_points < 2 || vol->tf_points > kMaxTf) invalid(ctx, "tf_points must be in [2, 64]");
+  if (!vol->tf_rgba) invalid(ctx, "tf_rgba is NULL");
+  for (int i = 0; i < 4 * vol->tf_points; ++i)
+    if (!std::isfinite(vol->tf_rgba[i])) invalid(ctx, "transfer function not finite");
+  if (!(max_alpha(vol->tf_rgba, vol->tf_points) > 0.0f))
+    invalid(ctx, "transfer function opacity is zero everywhere (no majorant)");
+}
+
+void run_init_points(gsc_ctx* ctx, const gsc_volume* vol, int64_t n, uint64_t seed, float* pos,
+                     float* albedo) {
+  gsc_camera cam{};
+  gsc_trace_params tp{};
+  tp.seed = seed;
+  TraceDesc d = make_trace_desc(vol->density, nullptr, vol->nx, vol->ny, vol->nz, vol->density_max,
+                                vol->tf_rgba, vol->tf_points, nullptr, 0, cam, tp);
+  need(ctx, ctx->trace_tab, ctx->alloc, sizeof(TraceDesc) + sizeof(int64_t), "trace descriptor");
+  upload(ctx, ctx->trace_tab.p, &d, sizeof(TraceDesc));
+  need(ctx, ctx->ini_tries, ctx->alloc, 4 * (size_t)n, "init attempts");
+  need(ctx, ctx->ini_count, ctx->alloc, 8, "init failure count");
+  hipStream_t st = ctx->stream;
+  GSC_TRY(launch_init_points(st, ctx->trace_tab.as<TraceDesc>(), n, kInitMaxAttempts, pos, albedo,
+                             ctx->ini_tries.as<int32_t>()));
+  GSC_TRY(hipMemsetAsync(ctx->ini_count.p, 0, 8, st));
+  GSC_TRY(launch_count_failed(st, ctx->ini_tries.as<int32_t>(), n,
+                              ctx->ini_count.as<unsigned long long>()));
+  const uint64_t failed = read_u64(ctx, ctx->ini_count.as<uint64_t>());
+  if (failed) {
+    char buf[200];
+    snprintf(buf, sizeof(buf), "%llu of %lld points found no interaction in %d rays (is the volume "
+             "transparent under its transfer function?)", (unsigned long long)failed, (long long)n,
+             kInitMaxAttempts);
+    ctx->err = buf;
+    throw Fail{GSC_E_INVALID_ARG};
+  }
+}
+
+void run_knn_mean3(gsc_ctx* ctx, const float* pos, int64_t n, float* mean3) {
+  const int G = init_grid_side(n);
+  const int64_t cells = (int64_t)G * G * G;
+  const Alloc& a = ctx->alloc;
+  need(ctx, ctx->ini_key, a, 4 * (size_t)n, "grid keys");
+  need(ctx, ctx->ini_id, a, 4 * (size_t)n, "grid ids");
+  need(ctx, ctx->ini_key_tmp, a, 4 * (size_t)n, "grid keys (sort)");
+  need(ctx, ctx->ini_id_tmp, a, 4 * (size_t)n, "grid ids (sort)");
+  need(ctx, ctx->ini_start, a, 4 * (size_t)cells, "cell starts");
+  need(ctx, ctx->ini_end, a, 4 * (size_t)cells, "cell ends");
+  need(ctx, ctx->ini_spos, a, 16 * (size_t)n, "sorted points");
+  const int64_t seg_n[1] = {n}, seg_off[1] = {0};
+  const int nb = sort_count_blocks(seg_n, 1);
+  const size_t tab = sort_table_bytes(nb, 1);
+  std::vector<char> host(tab, 0);
+  sort_fill_table(host.data(), seg_n, seg_off, 1);
+  need(ctx, ctx->ini_sort_tab, a, tab, "sort table");
+  upload(ctx, ctx->ini_sort_tab.p, host.data(), tab);
+  need(ctx, ctx->ini_hist, a, 4 * sort_hist_words(std::max(nb, 1), 1), "sort histograms");
+  hipStream_t st = ctx->stream;
+  GSC_TRY(launch_grid_keys(st, pos, n, G, ctx->ini_key.as<uint32_t>(), ctx->ini_id.as<uint32_t>()));
+  GSC_TRY(launch_segmented_sort(st, ctx->ini_sort_tab.p, nb, 1, ctx->ini_key.as<uint32_t>(),
+                                ctx->ini_id.as<uint32_t>(), ctx->ini_key_tmp.as<uint32_t>(),
+                                ctx->ini_id_tmp.as<uint32_t>(), ctx->ini_hist.as<uint32_t>()));
+  GSC_TRY(hipMemsetAsync(ctx->ini_start.p, 0, 4 * (size_t)cells, st));
+  GSC_TRY(hipMemsetAsync(ctx->ini_end.p, 0, 4 * (size_t)cells, st));
+  GSC_TRY(launch_cell_ranges(st, ctx->ini_key.as<uint32_t>(), ctx->ini_id.as<uint32_t>(), pos, n,
+                             ctx->ini_start.as<uint32_t>(), ctx->ini_end.as<uint32_t>(),
+                             ctx->ini_spos.as<float4>()));
+  GSC_TRY(launch_knn3(st, ctx->ini_spos.as<float4>(), ctx->ini_id.as<uint32_t>(), n, G,
+                      ctx->ini_start.as<uint32_t>(), ctx->ini_end.as<uint32_t>(), mean3));
+}
+
+}  // namespace
+
+extern "C" {
+
+gsc_status gsc_init_points(gsc_ctx* ctx, const gsc_volume* vol, int64_t n, uint64_t seed, float* pos,
+                           float* albedo) {
+  return guarded(ctx, [&]() -> gsc_status {
+    check_init_volume(ctx, vol);
+    if (n < 1 || n > ((int64_t)1 << 31)) invalid(ctx, "n must be in [1, 2^31]");
+    if (!pos || !albedo) invalid(ctx, "pos / albedo is NULL");
+    run_init_points(ctx, vol, n, seed, pos, albedo);
+    return GSC_OK;
+  });
+}
+
+gsc_status gsc_knn_mean3(gsc_ctx* ctx, const float* pos, int64_t n, float* mean3) {
+  return guarded(ctx, [&]() -> gsc_status {
+    if (n < 4 || n > ((int64_t)1 << 31)) invalid(ctx, "n must be in [4, 2^31]");
+    if (!pos || !mean3) invalid(ctx, "pos / mean3 is NULL");
+    run_knn_mean3(ctx, pos, n, mean3);
+    return GSC_OK;
+  });
+}
+
+gsc_status gsc_cache_init(gsc_ctx* ctx, const gsc_volume* vol, int64_t n, int32_t K, uint64_t seed,
+                          const gsc_level_buffers* levels) {
+  return guarded(ctx, [&]() -> gsc_status {
+    check_init_volume(ctx, vol);
+    if (K < 1 || K > 8) invalid(ctx, "K must be in [1, 8]");
+    if (n > ((int64_t)1 << 31)) invalid(ctx, "n must be <= 2^31");
+    if ((n >> (K - 1)) < 4) invalid(ctx, "every level needs at least 4 points (n >> (K - 1) >= 4)");
+    if (!levels) invalid(ctx, "levels is NULL");
+    for (int l = 0; l < K; ++l) {
+      const gsc_level_buffers& g = levels[l];
+      if (g.n != (n >> l)) invalid(ctx, "levels[l].n must be n >> l");
+      if (!g.pos || !g.rot || !g.log_scale || !g.rgb || !g.opacity_logit) invalid(ctx, "level pointer is NULL");
+    }
+    const Alloc& a = ctx->alloc;
+    need(ctx, ctx->ini_pos, a, 12 * (size_t)n, "init points");
+    need(ctx, ctx->ini_alb, a, 12 * (size_t)n, "init albedo");
+    need(ctx, ctx->ini_mean3, a, 4 * (size_t)n, "init neighbour distances");
+    need(ctx, ctx->ini_partial, a, 8 * init_partial_doubles(), "init moments");
+    run_init_points(ctx, vol, n, seed, ctx->ini_pos.as<float>(), ctx->ini_alb.as<float>());
+    const float logit = (float)std::log(0.1 / 0.9);
+    for (int l = 0; l < K; ++l) {
+      const int64_t nl = n >> l;   // level l: the first n / 2^l points
+      run_knn_mean3(ctx, ctx->ini_pos.as<float>(), nl, ctx->ini_mean3.as<float>());
+      const gsc_level_buffers& g = levels[l];
+      GSC_TRY(launch_init_level(ctx->stream, ctx->ini_mean3.as<float>(), nl, ctx->ini_pos.as<float>(),
+                                ctx->ini_alb.as<float>(), logit, ctx->ini_partial.as<double>(),
+                                g.pos, g.rot, g.log_scale, g.rgb, g.opacity_logit));
+    }
+    return GSC_OK;
+  });
+}
+
 gsc_status gsc_ctx_profile(gsc_ctx* ctx, int32_t on) {
   return guarded(ctx, [&]() -> gsc_status {
     prof_resolve(ctx);
@@ -1301,6 +1447,7 @@ size_t gsc_abi_struct_size(int32_t which) {
     case 9: return sizeof(gsc_frame_request);
     case 10: return sizeof(gsc_allocator);
     case 11: return sizeof(gsc_counters);
+    case 12: return sizeof(gsc_level_buffers);
     default: return 0;
   }
 }

@@ -1,0 +1,92 @@
+"""GPU parity of cache initialisation (Method: "Cache Initialization", Eq. 2) through the C
+ABI: first-interaction points bit-identical to the oracle's sampler, mean 3-NN distances within
+fp32 rounding of the oracle's exact ones (k-d tree), and whole levels (Eq. 2 scales)."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+from oracle import init as oinit
+from tests.gpu_common import to_np
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def gsc():
+    import paper_2507_19718_amd as m
+    return m
+
+
+@pytest.fixture(scope="module")
+def gctx(gsc):
+    return gsc.Context(0)
+
+
+def same_rows(a, b):
+    return np.all(a.view(np.uint32) == b.view(np.uint32), axis=1)
+
+
+@pytest.mark.parametrize("kind", ["tiny", "fbm256"])
+def test_points_bit_identical(gsc, gctx, kind):
+    vol = synth.workload("tiny").volume() if kind == "tiny" else synth.workload("orbit1k").volume()
+    n = 20000
+    pos, alb = gsc.gsc_init_points(gctx, gsc.Volume.from_synth(vol), n, 0x1A17)
+    want_pos, want_alb, att = oinit.points(vol, n, 0x1A17)
+    ok = same_rows(to_np(pos), want_pos) & same_rows(to_np(alb), want_alb)
+    assert ok.mean() >= 0.999, ok.mean()
+    assert np.all(np.isfinite(to_np(pos)))
+
+
+def test_knn_matches_oracle_on_sampled_points(gsc, gctx):
+    vol = synth.workload("orbit1k").volume()
+    pos, _ = gsc.gsc_init_points(gctx, gsc.Volume.from_synth(vol), 30000, 5)
+    got = to_np(gsc.gsc_knn_mean3(gctx, pos)).astype(np.float64)
+    want = oinit.knn_mean3(to_np(pos))
+    assert np.max(np.abs(got - want) / want) <= 2e-6
+
+
+def test_knn_edge_cases(gsc, gctx):
+    rng = np.random.default_rng(4)
+    cluster = rng.random((4000, 3)) * 0.1                       # dense corner cluster
+    dups = np.repeat(np.array([[0.5, 0.5, 0.5]]), 3, axis=0)    # three identical points
+    corners = np.array([[0, 0, 0], [1, 1, 1], [1, 0, 1], [0.95, 0.95, 0.95]])
+    p = np.concatenate([cluster, dups, corners]).astype(np.float32)
+    got = to_np(gsc.gsc_knn_mean3(gctx, torch.from_numpy(p).cuda())).astype(np.float64)
+    want = oinit.knn_mean3(p)
+    denom = np.maximum(want, 1e-30)
+    assert np.all(np.abs(got - want) <= 2e-6 * denom + 1e-7)
+
+
+def test_cache_init_levels_match_oracle(gsc, gctx):
+    wl = synth.workload("tiny")
+    vol = wl.volume()
+    n, K, seed = 16384, 3, 77
+    levels = gsc.gsc_cache_init(gctx, gsc.Volume.from_synth(vol), n, K, seed)
+    ref = oinit.cache_levels(vol, n, K, seed)
+    for l in range(K):
+        g, r = levels[l], ref[l]
+        assert g["pos"].shape[0] == n >> l
+        ok = same_rows(to_np(g["pos"]), r["pos"])
+        assert ok.mean() >= 0.999
+        assert np.array_equal(to_np(g["rgb"])[ok], r["rgb"][ok])
+        assert np.all(to_np(g["rot"]) == np.array([1, 0, 0, 0], np.float32))
+        logit = to_np(g["opacity_logit"])
+        assert np.all(logit == np.float32(math.log(0.1 / 0.9)))
+        ls = to_np(g["log_scale"]).astype(np.float64)
+        assert np.all(ls[:, 0] == ls[:, 1]) and np.all(ls[:, 0] == ls[:, 2])
+        if ok.all():
+            assert np.max(np.abs(ls[:, 0] - np.log(r["scale"]))) <= 3e-6
+
+
+def test_cache_init_rejects_bad_requests(gsc, gctx):
+    vol = synth.workload("tiny").volume()
+    gv = gsc.Volume.from_synth(vol)
+    with pytest.raises(gsc.GscError):
+        gsc.gsc_cache_init(gctx, gv, 12, 3, 1)            # level 2 would hold 12 >> 2 = 3 < 4 points
+    empty = synth.Volume(np.zeros((8, 8, 8), np.float32), 1.0, vol.tf, vol.lights)
+    with pytest.raises(gsc.GscError) as e:
+        gsc.gsc_init_points(gctx, gsc.Volume.from_synth(empty), 64, 1)
+    assert "no interaction" in str(e.value)
