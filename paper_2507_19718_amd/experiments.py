@@ -1,0 +1,177 @@
+"""Experiment harness on the hot-path calls: synthetic stand-ins for the paper's studies of the
+sampling coefficient C and of cold-start training (Evaluation), and of the hyper-parameter
+ablation (supplement: regularisation and covariance learning rate).
+
+Everything runs through the library's entry points: `gsc_cache_init` for volume-shaped initial
+caches, `gsc_render_frame` for cached frames (trace + splat + train + composite), and
+`gsc_trace_targets` for the references (no early termination, many samples per pixel).
+
+    python -m paper_2507_19718_amd.experiments [--workload orbit1k] [--what C,cold,ablation]
+
+prints one JSON object per study.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import time
+from typing import Dict, List, Sequence
+
+import torch
+
+from . import (Context, Scene, Volume, frame_request, gsc_cache_init, gsc_render_frame,
+               gsc_trace_targets, trace_params)
+
+
+def reference_radiance(ctx: Context, vol: Volume, cam, K: int, B: int, seed: int, spp: int = 1024,
+                       chunk: int = 64) -> torch.Tensor:
+    """Unbiased pixel radiance [h][w][3]: the per-length targets summed over lengths, traced
+    without early termination (C = inf) and averaged over spp samples."""
+    tg = torch.empty((K, cam.h, cam.w, 3), device="cuda")
+    acc = torch.zeros((cam.h, cam.w, 3), device="cuda", dtype=torch.float64)
+    done = 0
+    while done < spp:
+        n = min(chunk, spp - done)
+        # A distinct frame index per chunk gives independent Philox streams.
+        gsc_trace_targets(ctx, vol, cam, trace_params(seed, 1_000_000 + done, n, B, K, C=math.inf), tg)
+        acc += tg.sum(0).double() * n
+        done += n
+    return (acc / spp).float()
+
+
+def path_traced(ctx: Context, vol: Volume, cam, K: int, B: int, seed: int, frame: int) -> torch.Tensor:
+    """One 1-spp path-traced image (next-event estimation, no cache): the uncached baseline."""
+    tg = torch.empty((K, cam.h, cam.w, 3), device="cuda")
+    gsc_trace_targets(ctx, vol, cam, trace_params(seed, frame, 1, B, K, C=math.inf), tg)
+    return tg.sum(0)
+
+
+def mse(a: torch.Tensor, ref: torch.Tensor) -> float:
+    return float(((a.double() - ref.double()) ** 2).mean())
+
+
+def fresh_scene(ctx: Context, vol: Volume, init_levels: Sequence[Dict[str, torch.Tensor]]) -> Scene:
+    return Scene(ctx, vol, [{k: v.clone() for k, v in lv.items()} for lv in init_levels])
+
+
+def run_frames(ctx, scene, cams, wl, C: float, lr, weight_decay: float, seed: int, frame0: int = 0,
+               viewport_frames=None, keep: Sequence[int] = ()) -> Dict:
+    """Cached frames over the camera list; returns the kept composites and ms per frame."""
+    img = torch.empty((cams[0].h, cams[0].w, 3), device="cuda")
+    kept = {}
+    torch.cuda.synchronize()
+    t = time.perf_counter()
+    for i, cam in enumerate(cams):
+        vf = viewport_frames[i] if viewport_frames is not None else i + 1
+        req = frame_request(cam, seed, frame0 + i, wl.K, wl.max_bounces, loss=wl.loss, lr=lr,
+                            weight_decay=weight_decay, C=C, viewport_frames=vf)
+        gsc_render_frame(ctx, scene, req, img)
+        if i in keep:
+            kept[i] = img.clone()
+    torch.cuda.synchronize()
+    return {"images": kept, "ms_per_frame": (time.perf_counter() - t) * 1e3 / len(cams)}
+
+
+def study_C(ctx, wl, vol, gv, init_levels, ref, cam, Cs=(0.0, 0.25, 0.5, 1.0, math.inf),
+            warm: int = 32, measure: int = 32) -> Dict:
+    """Bias / variance / MSE of the composite against the reference, and ms per frame, per C
+    (static camera, `warm` training frames, then `measure` frames)."""
+    out = []
+    for C in Cs:
+        scene = fresh_scene(ctx, gv, init_levels)
+        n = warm + measure
+        r = run_frames(ctx, scene, [cam] * n, wl, C, wl.lr, wl.weight_decay, wl.seed,
+                       keep=range(warm, n))
+        imgs = torch.stack([r["images"][i] for i in range(warm, n)]).double()
+        mean = imgs.mean(0)
+        bias2 = float(((mean - ref.double()) ** 2).mean())
+        var = float(imgs.var(0, unbiased=True).mean())
+        out.append({"C": "inf" if math.isinf(C) else C, "bias2": bias2, "variance": var,
+                    "mse": float(((imgs - ref.double()) ** 2).mean()),
+                    "ms_per_frame": round(r["ms_per_frame"], 3)})
+        scene.destroy()
+    pt = torch.stack([path_traced(ctx, gv, cam, wl.K, wl.max_bounces, wl.seed, 50_000 + f)
+                      for f in range(measure)]).double()
+    base = {"bias2": float(((pt.mean(0) - ref.double()) ** 2).mean()),
+            "variance": float(pt.var(0, unbiased=True).mean()),
+            "mse": float(((pt - ref.double()) ** 2).mean())}
+    return {"study": "C", "static_frames": warm + measure, "measured": measure, "cached": out,
+            "path_traced_1spp": base}
+
+
+def study_cold_start(ctx, wl, vol, gv, init_levels, ref, cam, frames: int = 64,
+                     marks=(1, 2, 4, 8, 16, 32, 64)) -> Dict:
+    """Composite MSE after 1, 2, 4, ... frames of training from the initial cache, next to the
+    MSE of uncached 1-spp path tracing; the first frame whose cached MSE beats it."""
+    scene = fresh_scene(ctx, gv, init_levels)
+    keep = [m - 1 for m in marks if m <= frames]
+    r = run_frames(ctx, scene, [cam] * frames, wl, wl.C, wl.lr, wl.weight_decay, wl.seed,
+                   keep=range(frames))
+    curve = {m: mse(r["images"][m - 1], ref) for m in marks if m <= frames}
+    pt = [mse(path_traced(ctx, gv, cam, wl.K, wl.max_bounces, wl.seed, 60_000 + f), ref) for f in range(8)]
+    base = sum(pt) / len(pt)
+    first = next((i + 1 for i in range(frames) if mse(r["images"][i], ref) < base), None)
+    scene.destroy()
+    return {"study": "cold_start", "mse_after_frames": curve, "path_traced_1spp_mse": base,
+            "first_frame_below_path_traced": first}
+
+
+def study_ablation(ctx, wl, vol, gv, init_levels, ref_still, still_cam, orbit: int = 256,
+                   still: int = 256, marks=(1, 16, 64, 256)) -> Dict:
+    """An orbit of `orbit` frames (one turn), then `still` frames at the still camera (the
+    viewport counter restarts); composite MSE at the still camera after `marks` still frames,
+    for: ours (AdamW, scale lr 0), -REG (Adam: no weight decay), -CO (scale lr 0.0125),
+    -CO-REG."""
+    import synth
+    lr0 = list(wl.lr)
+    variants = {"ours": (lr0, wl.weight_decay), "-REG": (lr0, 0.0),
+                "-CO": (lr0[:2] + [0.0125] + lr0[3:], wl.weight_decay),
+                "-CO,-REG": (lr0[:2] + [0.0125] + lr0[3:], 0.0)}
+    cams = [synth.orbit_camera(still_cam.w, still_cam.h, 30.0 + 360.0 * i / orbit) for i in range(orbit)]
+    cams += [still_cam] * still
+    vfs = list(range(1, orbit + 1)) + list(range(1, still + 1))
+    out = {}
+    for name, (lr, wd) in variants.items():
+        scene = fresh_scene(ctx, gv, init_levels)
+        keep = [orbit + m - 1 for m in marks if m <= still]
+        r = run_frames(ctx, scene, cams, wl, wl.C, lr, wd, wl.seed, viewport_frames=vfs, keep=keep)
+        out[name] = {m: mse(r["images"][orbit + m - 1], ref_still) for m in marks if m <= still}
+        scene.destroy()
+    return {"study": "ablation", "orbit_frames": orbit, "still_frames": still, "mse_at_still_frames": out}
+
+
+def main():
+    import synth
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--workload", default="orbit1k")
+    ap.add_argument("--what", default="C,cold,ablation")
+    ap.add_argument("--init-points", type=int, default=300_000)
+    ap.add_argument("--ref-spp", type=int, default=1024)
+    ap.add_argument("--orbit", type=int, default=256)
+    ap.add_argument("--still", type=int, default=256)
+    args = ap.parse_args()
+    wl = synth.workload(args.workload)
+    vol = wl.volume()
+    ctx = Context(0)
+    gv = Volume.from_synth(vol)
+    cam = wl.camera()
+    t = time.perf_counter()
+    init_levels = gsc_cache_init(ctx, gv, args.init_points, wl.K, wl.seed)
+    torch.cuda.synchronize()
+    init_ms = (time.perf_counter() - t) * 1e3
+    ref = reference_radiance(ctx, gv, cam, wl.K, wl.max_bounces, wl.seed, spp=args.ref_spp)
+    head = {"workload": wl.name, "width": cam.w, "height": cam.h, "levels": wl.K,
+            "init_points": args.init_points, "init_ms": round(init_ms, 2), "ref_spp": args.ref_spp}
+    what = set(args.what.split(","))
+    if "C" in what:
+        print(json.dumps({**head, **study_C(ctx, wl, vol, gv, init_levels, ref, cam)}), flush=True)
+    if "cold" in what:
+        print(json.dumps({**head, **study_cold_start(ctx, wl, vol, gv, init_levels, ref, cam)}), flush=True)
+    if "ablation" in what:
+        print(json.dumps({**head, **study_ablation(ctx, wl, vol, gv, init_levels, ref, cam,
+                                                   orbit=args.orbit, still=args.still)}), flush=True)
+
+
+if __name__ == "__main__":
+    main()

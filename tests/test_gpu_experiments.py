@@ -1,0 +1,55 @@
+"""The experiment harness runs end to end on the tiny workload through the library calls, its
+reference converges, and its metrics are finite."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def env():
+    import paper_2507_19718_amd as gsc
+    from paper_2507_19718_amd import experiments as ex
+    wl = synth.workload("tiny")
+    vol = wl.volume()
+    ctx = gsc.Context(0)
+    gv = gsc.Volume.from_synth(vol)
+    init = gsc.gsc_cache_init(ctx, gv, 8192, wl.K, wl.seed)
+    return dict(gsc=gsc, ex=ex, wl=wl, vol=vol, ctx=ctx, gv=gv, init=init, cam=wl.camera())
+
+
+def test_reference_converges(env):
+    ex, e = env["ex"], env
+    a = ex.reference_radiance(e["ctx"], e["gv"], e["cam"], e["wl"].K, e["wl"].max_bounces, 1, spp=256)
+    b = ex.reference_radiance(e["ctx"], e["gv"], e["cam"], e["wl"].K, e["wl"].max_bounces, 2, spp=256)
+    rel = float((a - b).norm() / (0.5 * (a + b)).norm())
+    assert rel < 0.2, rel
+    # 4x the samples halves the difference (Monte Carlo rate), up to noise.
+    c = ex.reference_radiance(e["ctx"], e["gv"], e["cam"], e["wl"].K, e["wl"].max_bounces, 3, spp=1024)
+    d = ex.reference_radiance(e["ctx"], e["gv"], e["cam"], e["wl"].K, e["wl"].max_bounces, 4, spp=1024)
+    rel4 = float((c - d).norm() / (0.5 * (c + d)).norm())
+    assert 0.3 < rel4 / rel < 0.75, (rel, rel4)
+
+
+def test_studies_run(env):
+    ex, e = env["ex"], env
+    ref = ex.reference_radiance(e["ctx"], e["gv"], e["cam"], e["wl"].K, e["wl"].max_bounces, 5, spp=128)
+    r = ex.study_C(e["ctx"], e["wl"], e["vol"], e["gv"], e["init"], ref, e["cam"], Cs=(0.5, math.inf),
+                   warm=2, measure=4)
+    assert len(r["cached"]) == 2
+    for row in r["cached"]:
+        assert all(math.isfinite(row[k]) for k in ("bias2", "variance", "mse"))
+        assert row["mse"] >= row["bias2"] * 0.5
+    c = ex.study_cold_start(e["ctx"], e["wl"], e["vol"], e["gv"], e["init"], ref, e["cam"], frames=8,
+                            marks=(1, 4, 8))
+    assert set(c["mse_after_frames"]) == {1, 4, 8}
+    a = ex.study_ablation(e["ctx"], e["wl"], e["vol"], e["gv"], e["init"], ref, e["cam"], orbit=6,
+                          still=4, marks=(1, 4))
+    assert set(a["mse_at_still_frames"]) == {"ours", "-REG", "-CO", "-CO,-REG"}
+    for v in a["mse_at_still_frames"].values():
+        assert all(math.isfinite(x) for x in v.values())
