@@ -139,12 +139,17 @@ hipError_t launch_splat_forward(hipStream_t st, const Seg* segs, const int64_t* 
                                 const DevCam* cams, int64_t n_tiles, const uint64_t* ranges,
                                 const uint32_t* values, const SplatRec* rec, float* images,
                                 float* final_T, int32_t* last_id, uint32_t* n_contrib,
-                                unsigned long long* stats);
+                                unsigned long long* stats, const uint32_t* order,
+                                uint32_t* tile_work);
+// Keys ordering tiles by decreasing work (work NULL: list length from ranges).
+hipError_t launch_tile_order_keys(hipStream_t st, const uint64_t* ranges, const uint32_t* work,
+                                  int64_t n_tiles, uint32_t* key, uint32_t* val);
 hipError_t launch_splat_backward(hipStream_t st, const Seg* segs, const int64_t* seg_tstart, int S,
                                  const DevCam* cams, int64_t n_tiles, const uint64_t* ranges,
                                  const uint32_t* values, const SplatRec* rec, const float* final_T,
                                  const uint32_t* n_contrib, const float* dL_dimages,
-                                 float* grad2d, int64_t G, int deterministic);
+                                 float* grad2d, int64_t G, int deterministic,
+                                 const uint32_t* order);
 
 int64_t trace_align(int64_t pixels);
 hipError_t launch_trace(hipStream_t st, const TraceDesc* descs, const int64_t* req_pstart, int R,

@@ -134,8 +134,9 @@ __global__ void __launch_bounds__(64) splat_forward_kernel(
     const DevCam* __restrict__ cams, const uint64_t* __restrict__ ranges,
     const uint32_t* __restrict__ values, const SplatRec* __restrict__ rec,
     float* __restrict__ images, float* __restrict__ final_T, int32_t* __restrict__ last_id,
-    uint32_t* __restrict__ n_contrib, unsigned long long* __restrict__ stats) {
-  const int64_t t = blockIdx.x;
+    uint32_t* __restrict__ n_contrib, unsigned long long* __restrict__ stats,
+    const uint32_t* __restrict__ order, uint32_t* __restrict__ tile_work) {
+  const int64_t t = order ? (int64_t)order[blockIdx.x] : (int64_t)blockIdx.x;
   const Tile tc = tile_setup(segs, seg_tstart, S, cams, ranges, t);
   const int lane = __lane_id();
   float T[kPx], C0[kPx], C1[kPx], C2[kPx];
@@ -201,6 +202,7 @@ __global__ void __launch_bounds__(64) splat_forward_kernel(
       }
     }
   }
+  if (tile_work && lane == 0) tile_work[t] = n_entries;
   uint64_t ev = 0, ncs = 0;
 #pragma unroll
   for (int p = 0; p < kPx; ++p) {
@@ -246,18 +248,21 @@ __global__ void __launch_bounds__(64) splat_backward_kernel(
     const DevCam* __restrict__ cams, const uint64_t* __restrict__ ranges,
     const uint32_t* __restrict__ values, const SplatRec* __restrict__ rec,
     const float* __restrict__ final_T, const uint32_t* __restrict__ n_contrib,
-    const float* __restrict__ dL_dimages, float* __restrict__ grad2d, int64_t G) {
+    const float* __restrict__ dL_dimages, float* __restrict__ grad2d, int64_t G,
+    const uint32_t* __restrict__ order) {
   __shared__ float part[4][64][kPartStride];
-  const int64_t t = blockIdx.x;
+  const int64_t t = order ? (int64_t)order[blockIdx.x] : (int64_t)blockIdx.x;
   const Tile tc = tile_setup(segs, seg_tstart, S, cams, ranges, t);
   const int lane = __lane_id();
-  float T[kPx], g0[kPx], g1[kPx], g2[kPx], B0[kPx], B1[kPx], B2[kPx];
+  // BG: the colour blended behind the current Gaussian (from the entries already walked), dotted
+  // with the pixel's image gradient g; it is all the adjoint needs of that colour.
+  float T[kPx], g0[kPx], g1[kPx], g2[kPx], BG[kPx];
   uint32_t nc[kPx];
   uint32_t mx = 0u;
 #pragma unroll
   for (int p = 0; p < kPx; ++p) {
     T[p] = 1.0f; g0[p] = 0.0f; g1[p] = 0.0f; g2[p] = 0.0f;
-    B0[p] = 0.0f; B1[p] = 0.0f; B2[p] = 0.0f;
+    BG[p] = 0.0f;
     nc[p] = 0u;
     if (tc.inside[p]) {
       const int64_t q = tc.pix_off + tc.pix[p];
@@ -300,6 +305,7 @@ __global__ void __launch_bounds__(64) splat_backward_kernel(
       const float bdx = B * dx;
       const float hdx2 = (-0.5f * dx) * dx;
       const float mAdx = -A * dx, mBdx = -B * dx;
+      const float inv_o = __builtin_amdgcn_rcpf(o);
       const uint32_t rel = rel0 + (uint32_t)k;
       float su = 0.0f, sv = 0.0f, sA = 0.0f, sB = 0.0f, sC = 0.0f, so = 0.0f;
       float sr = 0.0f, sg = 0.0f, sb = 0.0f;
@@ -323,15 +329,15 @@ __global__ void __launch_bounds__(64) splat_backward_kernel(
         sr = fmaf(w, g0[p], sr);
         sg = fmaf(w, g1[p], sg);
         sb = fmaf(w, g2[p], sb);
-        const float d0 = cr - B0[p], d1 = cg - B1[p], d2 = cb - B2[p];
-        const float dal = T[p] * fmaf(d0, g0[p], fmaf(d1, g1[p], d2 * g2[p]));
-        B0[p] = fmaf(az, d0, B0[p]);
-        B1[p] = fmaf(az, d1, B1[p]);
-        B2[p] = fmaf(az, d2, B2[p]);
-        // alpha not clamped: it depends on power and opacity.
-        const bool gate = lane_in(okm & __builtin_amdgcn_ballot_w64(!(oe > kAlphaMax)));
-        const float dpow = gate ? dal * alpha : 0.0f;
-        so = gate ? fmaf(dal, e, so) : so;
+        // dL/dalpha = T (c - background) . g; the background moves towards c by alpha.
+        const float cgp = fmaf(cr, g0[p], fmaf(cg, g1[p], cb * g2[p]));
+        const float dd = cgp - BG[p];
+        const float dal = T[p] * dd;
+        BG[p] = fmaf(az, dd, BG[p]);
+        // alpha not clamped: it depends on power and opacity (dL/do = dL/dpower / o).
+        const bool unclamped = lane_in(__builtin_amdgcn_ballot_w64(!(oe > kAlphaMax)));
+        const float dpow = unclamped ? dal * az : 0.0f;
+        so = fmaf(dpow, inv_o, so);
         sA = fmaf(dpow, hdx2, sA);
         sC = fmaf(dpow, (-0.5f * dy) * dy, sC);
         sB = fmaf(dpow, -dx * dy, sB);
@@ -363,17 +369,31 @@ __global__ void __launch_bounds__(64) splat_backward_kernel(
   }
 }
 
+// Sort keys for scheduling tiles heaviest first: the bitwise complement of a work estimate (the
+// list length, or the entries the forward processed), with the tile index as value.
+__global__ void __launch_bounds__(256) tile_order_keys_kernel(const uint64_t* __restrict__ ranges,
+                                                              const uint32_t* __restrict__ work,
+                                                              int64_t n_tiles, uint32_t* __restrict__ key,
+                                                              uint32_t* __restrict__ val) {
+  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (t >= n_tiles) return;
+  const uint64_t w = work ? (uint64_t)work[t] : ranges[2 * t + 1] - ranges[2 * t];
+  key[t] = ~(uint32_t)(w > 0xffffffffull ? 0xffffffffull : w);
+  val[t] = (uint32_t)t;
+}
+
 }  // namespace
 
 hipError_t launch_splat_forward(hipStream_t st, const Seg* segs, const int64_t* seg_tstart, int S,
                                 const DevCam* cams, int64_t n_tiles, const uint64_t* ranges,
                                 const uint32_t* values, const SplatRec* rec, float* images,
                                 float* final_T, int32_t* last_id, uint32_t* n_contrib,
-                                unsigned long long* stats) {
+                                unsigned long long* stats, const uint32_t* order,
+                                uint32_t* tile_work) {
   if (n_tiles == 0) return hipSuccess;
   hipLaunchKernelGGL(splat_forward_kernel, dim3((unsigned)n_tiles), dim3(64), 0, st, segs,
                      seg_tstart, S, cams, ranges, values, rec, images, final_T, last_id, n_contrib,
-                     stats);
+                     stats, order, tile_work);
   return hipGetLastError();
 }
 
@@ -381,12 +401,21 @@ hipError_t launch_splat_backward(hipStream_t st, const Seg* segs, const int64_t*
                                  const DevCam* cams, int64_t n_tiles, const uint64_t* ranges,
                                  const uint32_t* values, const SplatRec* rec, const float* final_T,
                                  const uint32_t* n_contrib, const float* dL_dimages,
-                                 float* grad2d, int64_t G, int deterministic) {
+                                 float* grad2d, int64_t G, int deterministic,
+                                 const uint32_t* order) {
   (void)deterministic;
   if (n_tiles == 0) return hipSuccess;
   hipLaunchKernelGGL(splat_backward_kernel, dim3((unsigned)n_tiles), dim3(64), 0, st, segs,
                      seg_tstart, S, cams, ranges, values, rec, final_T, n_contrib, dL_dimages,
-                     grad2d, G);
+                     grad2d, G, order);
+  return hipGetLastError();
+}
+
+hipError_t launch_tile_order_keys(hipStream_t st, const uint64_t* ranges, const uint32_t* work,
+                                  int64_t n_tiles, uint32_t* key, uint32_t* val) {
+  if (n_tiles == 0) return hipSuccess;
+  hipLaunchKernelGGL(tile_order_keys_kernel, dim3((unsigned)((n_tiles + 255) / 256)), dim3(256), 0, st,
+                     ranges, work, n_tiles, key, val);
   return hipGetLastError();
 }
 

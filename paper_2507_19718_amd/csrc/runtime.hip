@@ -79,6 +79,8 @@ struct gsc_binning {
   size_t off_cams = 0, off_gstart = 0, off_tstart = 0, off_sort = 0, off_work = 0;
   DevBuf rec, depth_key, rect, tiles, ids, keys_tmp, ids_tmp, hist, rect_sorted;
   DevBuf counts, tile_total, partial, tile_start, ranges, scalars, values, n_contrib, grad2d;
+  // heaviest-first tile schedules of the splat kernels
+  DevBuf ord_key, ord_val, ord_ktmp, ord_vtmp, ord_hist, ord_tab, tile_work;
   uint64_t n_instances = 0;
   uint64_t capacity = 0;
   bool forward_done = false;
@@ -98,7 +100,8 @@ struct gsc_binning {
   void free_all() {
     DevBuf* all[] = {&tables, &rec, &depth_key, &rect, &tiles, &ids, &keys_tmp, &ids_tmp, &hist,
                      &rect_sorted, &counts, &tile_total, &partial, &tile_start, &ranges, &scalars,
-                     &values, &n_contrib, &grad2d, &view_window, &view_screen};
+                     &values, &n_contrib, &grad2d, &view_window, &view_screen, &ord_key, &ord_val,
+                     &ord_ktmp, &ord_vtmp, &ord_hist, &ord_tab, &tile_work};
     for (DevBuf* b : all) b->release(alloc);
   }
 };
@@ -467,17 +470,47 @@ gsc_status run_project_bin(gsc_ctx* ctx, gsc_binning* b, uint64_t capacity_hint)
   return GSC_OK;
 }
 
+// Heaviest-first tile schedule for a splat launch: tiles sorted by decreasing work estimate
+// (work NULL: list length), ties in tile order.  Single-wave workgroups start in that order, so
+// the long tiles do not end up in the launch's tail.
+const uint32_t* tile_order(gsc_ctx* ctx, gsc_binning* b, const uint32_t* work) {
+  const int64_t n = b->n_tiles;
+  const Alloc& a = b->alloc;
+  need(ctx, b->ord_key, a, 4 * (size_t)n, "tile order keys");
+  need(ctx, b->ord_val, a, 4 * (size_t)n, "tile order");
+  need(ctx, b->ord_ktmp, a, 4 * (size_t)n, "tile order keys (sort)");
+  need(ctx, b->ord_vtmp, a, 4 * (size_t)n, "tile order (sort)");
+  const int64_t seg_n[1] = {n}, seg_off[1] = {0};
+  const int nb = sort_count_blocks(seg_n, 1);
+  const size_t tab = sort_table_bytes(nb, 1);
+  std::vector<char> host(tab, 0);
+  sort_fill_table(host.data(), seg_n, seg_off, 1);
+  need(ctx, b->ord_tab, a, tab, "tile order sort table");
+  upload(ctx, b->ord_tab.p, host.data(), tab);
+  need(ctx, b->ord_hist, a, 4 * sort_hist_words(std::max(nb, 1), 1), "tile order histograms");
+  hipStream_t st = ctx->stream;
+  GSC_TRY(launch_tile_order_keys(st, b->ranges.as<uint64_t>(), work, n, b->ord_key.as<uint32_t>(),
+                                 b->ord_val.as<uint32_t>()));
+  GSC_TRY(launch_segmented_sort(st, b->ord_tab.p, nb, 1, b->ord_key.as<uint32_t>(),
+                                b->ord_val.as<uint32_t>(), b->ord_ktmp.as<uint32_t>(),
+                                b->ord_vtmp.as<uint32_t>(), b->ord_hist.as<uint32_t>()));
+  return b->ord_val.as<uint32_t>();
+}
+
 void run_forward(gsc_ctx* ctx, gsc_binning* b, float* images, float* final_T, int32_t* last_id) {
   need(ctx, b->n_contrib, b->alloc, 4 * (size_t)std::max<int64_t>(b->pixels, 1), "n_contrib");
+  need(ctx, b->tile_work, b->alloc, 4 * (size_t)std::max<int64_t>(b->n_tiles, 1), "tile work");
   if (!ctx->d_stats.p) {
     need(ctx, ctx->d_stats, ctx->alloc, kStatWords * 8, "splat counters");
     GSC_TRY(hipMemsetAsync(ctx->d_stats.p, 0, kStatWords * 8, ctx->stream));
   }
+  const uint32_t* order = tile_order(ctx, b, nullptr);
   { ProfScope ps_(ctx, P_FWD, ctx->stream);
   GSC_TRY(launch_splat_forward(ctx->stream, b->d_segs(), b->d_tstart(), b->S, b->d_cams(), b->n_tiles,
                                b->ranges.as<uint64_t>(), b->values.as<uint32_t>(),
                                b->rec.as<SplatRec>(), images, final_T, last_id,
-                               b->n_contrib.as<uint32_t>(), ctx->d_stats.as<unsigned long long>()));
+                               b->n_contrib.as<uint32_t>(), ctx->d_stats.as<unsigned long long>(),
+                               order, b->tile_work.as<uint32_t>()));
   }
   b->forward_done = true;
 }
@@ -486,11 +519,12 @@ void run_backward(gsc_ctx* ctx, gsc_binning* b, const float* final_T, const floa
                   float* grads14) {
   need(ctx, b->grad2d, b->alloc, 4 * 9 * (size_t)std::max<int64_t>(b->G, 1), "2D gradients");
   GSC_TRY(hipMemsetAsync(b->grad2d.p, 0, 4 * 9 * (size_t)b->G, ctx->stream));
+  const uint32_t* order = tile_order(ctx, b, b->tile_work.as<uint32_t>());
   { ProfScope ps_(ctx, P_BWD, ctx->stream);
   GSC_TRY(launch_splat_backward(ctx->stream, b->d_segs(), b->d_tstart(), b->S, b->d_cams(), b->n_tiles,
                                 b->ranges.as<uint64_t>(), b->values.as<uint32_t>(),
                                 b->rec.as<SplatRec>(), final_T, b->n_contrib.as<uint32_t>(), dL,
-                                b->grad2d.as<float>(), b->G, ctx->deterministic));
+                                b->grad2d.as<float>(), b->G, ctx->deterministic, order));
   }
   { ProfScope ps_(ctx, P_PBWD, ctx->stream);
   GSC_TRY(launch_project_backward(ctx->stream, b->d_segs(), b->d_gstart(), b->S, b->d_cams(), b->G,
