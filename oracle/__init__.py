@@ -151,14 +151,20 @@ def _cam_args(cam):
 # ------------------------------------------------------------------------------------------
 # Tracer
 # ------------------------------------------------------------------------------------------
+STRATEGY_NEE, STRATEGY_UNIFORM = 0, 1
+
+
 def trace(vol, cam, seed: int, frame: int, spp: int, max_bounces: int, K: int, C: float = 0.5,
           eps: float = 0.0, records: bool = True, second_moment: bool = False,
-          kinds: bool = False):
+          kinds: bool = False, strategy: int = STRATEGY_NEE):
     """Per-path-length targets [K][h][w][3] (mean over spp), optional second moments and
-    per-pixel records (L[3], beta, n, kind) for spp == 1.  C = inf disables Algorithm 1."""
+    per-pixel records (L[3], beta, n, kind) for spp == 1.  C = inf disables Algorithm 1.
+    strategy: next-event estimation with MIS for area lights (0) or phase sampling only (1)."""
     d = _f32(vol.density)
     nz, ny, nx = d.shape
-    tf, lights = _f32(vol.tf), _f32(vol.lights)
+    tf, lights = _f32(vol.tf), _f32(vol.lights).reshape(-1, 6)
+    spheres = getattr(vol, "spheres", None)
+    spheres = _f32(np.zeros((0, 7)) if spheres is None else spheres).reshape(-1, 7)
     keep, cargs = _cam_args(cam)
     H, W = cam.h, cam.w
     targets = np.zeros((K, H, W, 3), dtype=np.float32)
@@ -168,7 +174,8 @@ def trace(vol, cam, seed: int, frame: int, spp: int, max_bounces: int, K: int, C
     kc = np.zeros((H, W, 4), dtype=np.uint32) if kinds else None
     c_inf = 1 if math.isinf(C) else 0
     lib().ora_trace(_p(d), nx, ny, nz, ctypes.c_float(vol.density_max), _p(tf), tf.shape[0],
-                    _p(lights), lights.shape[0], *cargs, ctypes.c_uint64(seed),
+                    _p(lights), lights.shape[0], _p(spheres), spheres.shape[0], int(strategy),
+                    *cargs, ctypes.c_uint64(seed),
                     ctypes.c_uint32(frame), ctypes.c_uint32(spp), ctypes.c_uint32(max_bounces),
                     ctypes.c_uint32(K), ctypes.c_float(0.0 if c_inf else C), ctypes.c_int(c_inf),
                     ctypes.c_float(eps), _p(targets), _p(tsq), _p(rec), _p(stats), _p(kc))

@@ -13,10 +13,12 @@
 //   * Philox4x32-10 counter-based generator (Salmon, Moraes, Dror, Shaw, SC'11).
 //   * Portable exp / log / sincos (Cody-Waite reduction + truncated series).
 //   * Trilinear density lookup and 1D RGBA transfer function [Evaluation: predefined 1D TF].
-//   * Delta-tracking volume path tracer with next-event estimation to point lights, ratio-
-//     tracked shadow rays, the early-termination heuristic (Algorithm 1) with the cascaded
-//     survival product beta (Eq. 3), and per-path-length training targets [Method: path-space
-//     radiance cache, path termination heuristics, cache sampling, cache training].
+//   * Delta-tracking volume path tracer with next-event estimation to point lights and to
+//     spherical area lights (cone sampling, combined with the phase-sampled continuation by
+//     MIS, power heuristic), or phase sampling only (the uniform baseline), ratio-tracked
+//     shadow rays, the early-termination heuristic (Algorithm 1) with the cascaded survival
+//     product beta (Eq. 3), and per-path-length training targets [Method: path-space radiance
+//     cache, path termination heuristics, cache sampling, cache training; Evaluation: lights].
 //   * Projection of 3D Gaussians to screen-space conics (the 3D Gaussian splatting
 //     rasteriser the paper builds on) [Method: a path space radiance cache].
 //   * Binning: every (tile, Gaussian) pair sorted by (tile, depth, id), per-tile ranges.
@@ -254,7 +256,80 @@ struct OCam {
 struct OTraceParams {
   uint64_t seed; uint32_t frame, spp, max_bounces, K;
   float C; int C_inf; float eps;
+  int strategy;   // STRAT_NEE or STRAT_UNIFORM
 };
+
+// Light-transport estimators (Method: path termination heuristics): next-event estimation at
+// every vertex combined with the phase-sampled continuation by multiple importance sampling,
+// or the uniform (phase-sampling only) path tracer that the evaluation uses as a baseline.
+enum { STRAT_NEE = 0, STRAT_UNIFORM = 1 };
+
+// ------------------------------------------------------------------------------------------
+// Spherical area lights (Evaluation: small spherical lights placed outside the volume).
+// Seven floats per light: centre xyz, radius, emitted radiance rgb (uniform over the surface
+// and over outgoing directions).  Every light lies outside the unit cube, so a point inside
+// the cube sees each light under a cone and a ray from it reaches a light only after leaving
+// the cube.
+// ------------------------------------------------------------------------------------------
+float odot(const float a[3], const float b[3]) { return (a[0] * b[0] + a[1] * b[1]) + a[2] * b[2]; }
+
+// 1 - cos(theta_max) of the cone a sphere of radius r subtends from squared distance d2,
+// written as sin^2 / (1 + cos) so that small cones keep their precision.
+float ora_cone_one_minus(float r, float d2) {
+  float s2 = (r * r) / d2;
+  return s2 / (1.0f + std::sqrt(1.0f - s2));
+}
+
+// Nearest intersection of the ray o + t w (|w| = 1, o outside the sphere) with sphere s:
+// the smaller root of t^2 - 2 t (w.(c-o)) + |c-o|^2 - r^2 = 0.  False when the ray misses
+// or the sphere is behind the origin.
+bool ora_sphere_hit(const float* s, const float o[3], const float w[3], float* t) {
+  float oc[3] = {s[0] - o[0], s[1] - o[1], s[2] - o[2]};
+  float b = odot(w, oc);
+  float c = odot(oc, oc) - s[3] * s[3];
+  float disc = b * b - c;
+  if (!(b > 0.0f) || !(disc >= 0.0f)) return false;
+  *t = b - std::sqrt(disc);
+  return true;
+}
+
+// Orthonormal basis (b1, b2) completing the unit vector a (Duff, Burgess, Christensen, Hill,
+// Kensler, Liani, Lyne: "Building an Orthonormal Basis, Revisited", JCGT 2017).
+void ora_onb(const float a[3], float b1[3], float b2[3]) {
+  float sg = std::copysign(1.0f, a[2]);
+  float k = -1.0f / (sg + a[2]);
+  float m = (a[0] * a[1]) * k;
+  b1[0] = 1.0f + ((sg * a[0]) * a[0]) * k;
+  b1[1] = sg * m;
+  b1[2] = -(sg * a[0]);
+  b2[0] = m;
+  b2[1] = sg + (a[1] * a[1]) * k;
+  b2[2] = -a[1];
+}
+
+// Radiance picked up by a ray (o, w) that has left the volume from vertex o: the emitted
+// radiance of the nearest sphere light it hits (none: false), weighted for MIS against light
+// sampling of that sphere from o.  Solid-angle pdfs: phase 1/(4 pi), light 1/(2 pi (1-cos)),
+// so with the power heuristic the phase sample's weight is om^2 / (om^2 + 4), om = 1 - cos.
+bool ora_escape_light(const float* sph, int ns, int strategy, const float o[3], const float w[3],
+                      float le[3]) {
+  int best = -1;
+  float tbest = std::numeric_limits<float>::infinity();
+  for (int s = 0; s < ns; ++s) {
+    float th;
+    if (ora_sphere_hit(sph + 7 * s, o, w, &th) && th < tbest) { tbest = th; best = s; }
+  }
+  if (best < 0) return false;
+  const float* sp = sph + 7 * best;
+  float wt = 1.0f;
+  if (strategy == STRAT_NEE) {
+    float oc[3] = {sp[0] - o[0], sp[1] - o[1], sp[2] - o[2]};
+    float om = ora_cone_one_minus(sp[3], odot(oc, oc));
+    wt = (om * om) / (om * om + 4.0f);
+  }
+  for (int c = 0; c < 3; ++c) le[c] = sp[4 + c] * wt;
+  return true;
+}
 
 enum { KIND_ESCAPE0 = 0, KIND_ESCAPE = 1, KIND_MAXDEPTH = 2, KIND_EARLY = 3 };
 const uint32_t MAX_STEPS = 1u << 20;   // per free-flight / shadow segment (never reached)
@@ -262,8 +337,8 @@ const uint32_t MAX_STEPS = 1u << 20;   // per free-flight / shadow segment (neve
 struct PathOut { float L[3]; float beta; int n; int kind; };
 
 // One path (Method: path termination heuristics, Algorithm 1, Eq. 3; cache training).
-PathOut ora_trace_path(const OVolume& V, const float* lights, int nl, const OCam& cam,
-                       const OTraceParams& tp, int px, int py, uint32_t sample) {
+PathOut ora_trace_path(const OVolume& V, const float* lights, int nl, const float* sph, int ns,
+                       const OCam& cam, const OTraceParams& tp, int px, int py, uint32_t sample) {
   PathOut out{{0.f, 0.f, 0.f}, 1.0f, 0, KIND_ESCAPE0};
   uint32_t pixel = (uint32_t)py * (uint32_t)cam.full_w + (uint32_t)px;
   PathRng rng(tp.seed, pixel, sample, tp.frame);
@@ -297,9 +372,15 @@ PathOut ora_trace_path(const OVolume& V, const float* lights, int nl, const OCam
       if (u2 < ora_sigma_t(V, x[0], x[1], x[2]) / sb) { collided = true; break; }
     }
     if (!collided) {
+      // The path leaves the volume; from a vertex (not the camera) it may hit an area light.
+      float le[3];
+      if (n >= 1 && ora_escape_light(sph, ns, tp.strategy, o, w, le))
+        for (int c = 0; c < 3; ++c) L[c] = L[c] + tr_out[c] * le[c];
       out.kind = (n == 0) ? KIND_ESCAPE0 : KIND_ESCAPE;
       break;
     }
+    // The continuation after the last allowed vertex collided again: the path stops there.
+    if ((uint32_t)n >= tp.max_bounces) { out.kind = KIND_MAXDEPTH; break; }
     // Real collision: vertex n.
     n += 1;
     float dd = ora_density(V, x[0], x[1], x[2]);
@@ -307,7 +388,7 @@ PathOut ora_trace_path(const OVolume& V, const float* lights, int nl, const OCam
     ora_tf(V, dd, rgba);
     for (int c = 0; c < 3; ++c) { raw[c] = raw[c] * rgba[c]; tr_out[c] = tr_out[c] * rgba[c]; }
     // Next-event estimation to every point light, ratio-tracked shadow transmittance.
-    for (int l = 0; l < nl; ++l) {
+    for (int l = 0; l < (tp.strategy == STRAT_NEE ? nl : 0); ++l) {
       const float* lp = lights + 6 * l;
       float dl[3] = {lp[0] - x[0], lp[1] - x[1], lp[2] - x[2]};
       float dist2 = (dl[0] * dl[0] + dl[1] * dl[1]) + dl[2] * dl[2];
@@ -328,9 +409,55 @@ PathOut ora_trace_path(const OVolume& V, const float* lights, int nl, const OCam
       float g = (T / dist2) * INV4PI;
       for (int c = 0; c < 3; ++c) L[c] = L[c] + tr_out[c] * (lp[3 + c] * g);
     }
-    if ((uint32_t)n >= tp.max_bounces) { out.kind = KIND_MAXDEPTH; break; }
+    // Next-event estimation to every sphere light: a direction uniform in the cone the sphere
+    // subtends, its hit point, the shadow ray blocked by any other light in front of it, else
+    // ratio-tracked through the volume.  Estimate phase * Le * T / p_light, times the MIS
+    // weight p_light^2 / (p_light^2 + p_phase^2): together T * Le * 2 om / (om^2 + 4).
+    for (int s = 0; s < (tp.strategy == STRAT_NEE ? ns : 0); ++s) {
+      const float* sp = sph + 7 * s;
+      float dl[3] = {sp[0] - x[0], sp[1] - x[1], sp[2] - x[2]};
+      float d2 = odot(dl, dl);
+      float d = std::sqrt(d2);
+      float ax[3] = {dl[0] / d, dl[1] / d, dl[2] / d};
+      float om = ora_cone_one_minus(sp[3], d2);
+      float ua = rng.uniform(), ub = rng.uniform();
+      float v = ua * om;                       // 1 - cos(theta), uniform in [0, om)
+      float ct = 1.0f - v;
+      float st = std::sqrt(std::fmax(0.0f, v * (2.0f - v)));
+      float sphi, cphi;
+      ora_sincosf_impl((float)(2.0 * 3.14159265358979323846) * ub, &sphi, &cphi);
+      float b1[3], b2[3];
+      ora_onb(ax, b1, b2);
+      float wl[3];
+      for (int i = 0; i < 3; ++i) wl[i] = ((st * cphi) * b1[i] + (st * sphi) * b2[i]) + ct * ax[i];
+      // Hit distance on the sampled sphere (grazing directions: the tangent point).
+      float bq = odot(wl, dl);
+      float th = bq - std::sqrt(std::fmax(0.0f, bq * bq - (d2 - sp[3] * sp[3])));
+      bool blocked = false;
+      for (int m = 0; m < ns; ++m) {
+        float tm;
+        if (m != s && ora_sphere_hit(sph + 7 * m, x, wl, &tm) && tm < th) blocked = true;
+      }
+      if (blocked) continue;
+      float b0, b1e;
+      float texit = ora_box(x, wl, &b0, &b1e) ? std::fmin(th, b1e) : 0.0f;
+      float T = 1.0f, ts = 0.0f;
+      for (uint32_t step = 0; step < MAX_STEPS; ++step) {
+        float u = rng.uniform();
+        ts = ts - ora_logf_impl(1.0f - u) / sb;
+        if (ts >= texit) break;
+        float y0 = x[0] + ts * wl[0], y1 = x[1] + ts * wl[1], y2 = x[2] + ts * wl[2];
+        T = T * (1.0f - ora_sigma_t(V, y0, y1, y2) / sb);
+      }
+      float g = T * ((2.0f * om) / (om * om + 4.0f));
+      for (int c = 0; c < 3; ++c) L[c] = L[c] + tr_out[c] * (sp[4 + c] * g);
+    }
+    // After the last allowed vertex only a continuation that leaves the volume and reaches an
+    // area light can still contribute; without area lights the path ends here.
+    const bool last = (uint32_t)n >= tp.max_bounces;
+    if (last && ns == 0) { out.kind = KIND_MAXDEPTH; break; }
     // Algorithm 1: early termination into the cache, cumulative throughput reading.
-    if (!tp.C_inf) {
+    if (!last && !tp.C_inf) {
       float lum = (0.2126f * raw[0] + 0.7152f * raw[1]) + 0.0722f * raw[2];
       float Tr = std::fmin(std::fmax(tp.C * lum, 0.0f), 1.0f);
       if (Tr < 0.9f) {
@@ -350,7 +477,13 @@ PathOut ora_trace_path(const OVolume& V, const float* lights, int nl, const OCam
     w[0] = r * cp; w[1] = r * sp; w[2] = z;
     for (int i = 0; i < 3; ++i) o[i] = x[i];
     float bb0, bb1;
-    if (!ora_box(o, w, &bb0, &bb1)) { out.kind = KIND_ESCAPE; break; }
+    if (!ora_box(o, w, &bb0, &bb1)) {
+      float le[3];
+      if (ora_escape_light(sph, ns, tp.strategy, o, w, le))
+        for (int c = 0; c < 3; ++c) L[c] = L[c] + tr_out[c] * le[c];
+      out.kind = KIND_ESCAPE;
+      break;
+    }
     t0 = 0.0f; t1 = bb1;
   }
   out.L[0] = L[0]; out.L[1] = L[1]; out.L[2] = L[2];
@@ -543,7 +676,8 @@ double ora_ratio_tracking_mean(const float* d, int nx, int ny, int nz, float dma
 // mean of squares; records (optional; sample 0) five words per pixel:
 // L[3] (f32), beta (f32), n | kind << 16 (u32); kind_counts (optional) [h][w][4] per-kind counts.
 int ora_trace(const float* density, int nx, int ny, int nz, float dmax, const float* tf, int P,
-              const float* lights, int nl, const float* R, const float* t, const float* intr,
+              const float* lights, int nl, const float* spheres, int ns, int strategy,
+              const float* R, const float* t, const float* intr,
               const int* win, float znear, uint64_t seed, uint32_t frame, uint32_t spp,
               uint32_t max_bounces, uint32_t K, float C, int C_inf, float eps, float* targets,
               float* targets_sq, uint32_t* records, uint32_t* path_stats, uint32_t* kind_counts) {
@@ -551,7 +685,7 @@ int ora_trace(const float* density, int nx, int ny, int nz, float dmax, const fl
   for (int i = 0; i < P; ++i) amax = std::fmax(amax, tf[4 * i + 3]);
   OVolume V{density, nx, ny, nz, dmax, tf, P, dmax * amax};
   OCam cam = make_cam(R, t, intr, win, znear);
-  OTraceParams tp{seed, frame, spp, max_bounces, K, C, C_inf, eps};
+  OTraceParams tp{seed, frame, spp, max_bounces, K, C, C_inf, eps, strategy};
   const int W = cam.w, H = cam.h;
   const size_t plane = (size_t)W * H;
   std::memset(targets, 0, sizeof(float) * 3 * plane * K);
@@ -565,7 +699,7 @@ int ora_trace(const float* density, int nx, int ny, int nz, float dmax, const fl
     std::vector<float> sum(3 * K, 0.f), sq(3 * K, 0.f);
     PathOut first{};
     for (uint32_t s = 0; s < spp; ++s) {
-      PathOut po = ora_trace_path(V, lights, nl, cam, tp, px, py, s);
+      PathOut po = ora_trace_path(V, lights, nl, spheres, ns, cam, tp, px, py, s);
       if (s == 0) first = po;
       total_len += (uint64_t)po.n;
       if (kind_counts) kind_counts[4 * p + po.kind] += 1u;

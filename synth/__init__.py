@@ -24,7 +24,7 @@ import numpy as np
 __all__ = [
     "Camera", "Volume", "Gaussians", "Workload",
     "rng", "orbit_camera", "crop_camera", "blob_volume", "fbm_volume", "slab_volume",
-    "transfer_function", "point_lights", "tiny_gaussians", "random_gaussians",
+    "transfer_function", "point_lights", "sphere_lights", "tiny_gaussians", "random_gaussians",
     "frustum_gaussians", "workload", "WORKLOADS", "poisson_requests",
 ]
 
@@ -107,11 +107,14 @@ def crop_camera(cam: Camera, x0: int, y0: int, w: int, h: int) -> Camera:
 @dataclasses.dataclass
 class Volume:
     """Density grid [nz][ny][nx] fp32 over the unit cube, an RGBA transfer function with
-    `P` control points at i/(P-1), and point lights (xyz, rgb intensity)."""
+    `P` control points at i/(P-1), point lights (xyz, rgb intensity) and spherical area
+    lights (centre xyz, radius, rgb radiance)."""
     density: np.ndarray    # (nz, ny, nx) float32
     density_max: float
     tf: np.ndarray         # (P, 4) float32
     lights: np.ndarray     # (L, 6) float32
+    spheres: np.ndarray = dataclasses.field(
+        default_factory=lambda: np.zeros((0, 7), dtype=np.float32))   # (S, 7) float32
 
     @property
     def shape(self) -> Tuple[int, int, int]:
@@ -224,6 +227,21 @@ def transfer_function(points: int, seed: int, index: int = 0) -> np.ndarray:
     a[0] = 0.0
     a /= a.max()
     return np.concatenate([rgb, a[:, None]], axis=1).astype(np.float32)
+
+
+def sphere_lights(n: int, radius: float = 0.25, radiance: float = 20.0,
+                  centre=(0.5, 0.5, 0.5), distance: float = 1.5) -> np.ndarray:
+    """Up to two spherical area lights (centre xyz, radius, rgb radiance) at the same fixed
+    directions as `point_lights`, `distance` from the centre: outside the unit cube for
+    radius < 0.6 at the default distance.  The second light is tinted."""
+    c = np.asarray(centre, dtype=np.float64)
+    dirs = [np.array([1.0, 1.5, -1.0]), np.array([-1.2, 0.8, 0.6])]
+    tints = [np.array([1.0, 1.0, 1.0]), np.array([0.6, 0.8, 1.0])]
+    out = []
+    for i in range(n):
+        d = dirs[i % 2] / np.linalg.norm(dirs[i % 2])
+        out.append(np.concatenate([c + distance * d, [radius], radiance * tints[i % 2]]))
+    return np.asarray(out, dtype=np.float32).reshape(-1, 7)
 
 
 def point_lights(n: int, centre=(0.5, 0.5, 0.5), intensity: float = 3.0,
