@@ -30,7 +30,8 @@
  *     per-pixel quantity is computed in full-frame coordinates, so a crop reproduces the full
  *     frame's pixels exactly.  Tiles are 16x16 pixels laid out from (x0, y0).
  *   - Limits: 1 <= w, h <= 16384; 1 <= K <= 8 levels per request; 0 <= n < 2^31 Gaussians per
- *     level; 2 <= tf_points <= 64; 1 <= n_lights <= 8; instance counts are 64-bit.
+ *     level; 2 <= tf_points <= 64; 0 <= n_lights, n_spheres <= 8 with at least one light;
+ *     instance counts are 64-bit.
  *   - Threading: a context is used by one host thread at a time; several contexts may share a
  *     device (one per concurrently running stream).
  *   - Determinism: every output is deterministic except the float-atomic sums of
@@ -113,8 +114,13 @@ typedef struct {
  * cell-centred, clamp-to-edge).  tf_rgba: HOST [tf_points][4], control point i at density
  * i/(tf_points-1) * density_max; sigma_t = d * A(d), albedo = RGB(d); the delta-tracking
  * majorant is density_max * max_i A_i (Evaluation: a predefined 1D transfer function per
- * dataset).  lights: HOST [n_lights][6] point lights (position xyz, radiant intensity rgb;
- * the paper lights its scenes with two small lights placed outside the volume). */
+ * dataset).  lights: HOST [n_lights][6] point lights (position xyz, radiant intensity rgb),
+ * NULL when n_lights is 0.  spheres: HOST [n_spheres][7] spherical area lights (centre xyz,
+ * radius > 0, emitted radiance rgb, uniform over the surface and outgoing directions), NULL
+ * when n_spheres is 0; each must lie entirely outside the unit cube (the paper lights its
+ * scenes with two small spherical lights placed outside the volume, Evaluation), otherwise
+ * GSC_E_INVALID_ARG.  Lights are not seen directly by camera rays (paths of length 0 carry no
+ * radiance to the cache). */
 typedef struct {
   const float* density;
   int32_t nx, ny, nz;
@@ -123,12 +129,33 @@ typedef struct {
   int32_t tf_points;
   const float* lights;
   int32_t n_lights;
+  const float* spheres;
+  int32_t n_spheres;
 } gsc_volume;
+
+/* Light-transport estimator of the tracer (Method: "Path Termination Heuristics"; the
+ * evaluation's uniform and next-event-estimation baselines). */
+enum {
+  /* Next-event estimation at every real collision: each point light directly; each sphere
+   * light by one direction uniform in the cone it subtends (solid-angle pdf
+   * 1 / (2 pi (1 - cos theta_max))), blocked if another sphere light is nearer along it, else
+   * ratio-tracked; combined with the phase-sampled continuation (pdf 1/(4 pi)) that leaves the
+   * volume and hits the light, by the power heuristic. */
+  GSC_STRATEGY_NEE = 0,
+  /* Phase sampling only: radiance is gathered only when a continuation leaves the volume and
+   * hits a sphere light (weight 1); point lights contribute nothing. */
+  GSC_STRATEGY_UNIFORM = 1
+};
 
 /* HOST.  Tracer parameters.  Random numbers: Philox4x32-10 with key (lo32(seed), hi32(seed))
  * and counter (y * full_w + x, sample, frame, j); draw k of a path is word k mod 4 of block
- * j = k / 4; u = (word >> 8) * 2^-24.  C: the termination coefficient of Algorithm 1
- * (C_inf != 0 disables the heuristic); eps: the epsilon of Algorithm 1 (0 by default). */
+ * j = k / 4; u = (word >> 8) * 2^-24.  Draw order at a real collision: the point lights'
+ * shadow rays, then per sphere light two draws for the cone direction and (unless blocked)
+ * its shadow ray, then Algorithm 1's draw, then two for the phase direction.  C: the
+ * termination coefficient of Algorithm 1 (C_inf != 0 disables the heuristic); eps: the epsilon
+ * of Algorithm 1 (0 by default).  With sphere lights, the B-th collision still samples a
+ * continuation (no Algorithm 1 there): if it leaves the volume it may hit a light, if it
+ * collides the path ends with n = B. */
 typedef struct {
   uint64_t seed;
   uint32_t frame;
@@ -138,6 +165,7 @@ typedef struct {
   float C;
   int32_t C_inf;
   float eps;
+  uint32_t strategy;       /* GSC_STRATEGY_NEE (0) or GSC_STRATEGY_UNIFORM (1)             */
 } gsc_trace_params;
 
 /* DEVICE, one per pixel (spp == 1 only): the path's accumulated NEE radiance L, the product
@@ -233,13 +261,15 @@ gsc_status gsc_ctx_counters(gsc_ctx* ctx, gsc_counters* out);
 gsc_status gsc_ctx_trim(gsc_ctx* ctx);
 
 /* ---- the hot path ----------------------------------------------------------------------- */
-/* Delta-tracking volume path tracer with next-event estimation to every point light
- * (ratio-tracked shadow transmittance, isotropic phase 1/(4 pi)), Algorithm 1 early
- * termination with the cumulative throughput reading and beta of Eq. 3, at most max_bounces
- * real collisions; one path per pixel of the camera window per sample (Method: "Path
- * Termination Heuristics", "Cache Sampling", "Cache Training").
+/* Delta-tracking volume path tracer with next-event estimation to every light (ratio-tracked
+ * shadow transmittance, isotropic phase 1/(4 pi); sphere lights combined with phase sampling
+ * by MIS) or phase sampling only (params->strategy), Algorithm 1 early termination with the
+ * cumulative throughput reading and beta of Eq. 3, at most max_bounces real collisions; one
+ * path per pixel of the camera window per sample (Method: "Path Termination Heuristics",
+ * "Cache Sampling", "Cache Training").
  * targets: [K][h][w][3], written completely: level min(n,K)-1 of pixel p receives the
- * path's accumulated NEE radiance, every other level 0; mean over spp.
+ * path's accumulated radiance (next-event estimates plus light hits on leaving the volume),
+ * every other level 0; mean over spp.
  * records: [h][w] gsc_path_record, or NULL; must be NULL when spp > 1.
  * stats: HOST or NULL; non-NULL synchronises the stream and fills ms_trace, paths and
  * path_vertices. */
@@ -337,9 +367,11 @@ gsc_status gsc_cache_init(gsc_ctx* ctx, const gsc_volume* vol, int64_t n, int32_
 gsc_status gsc_scene_create(gsc_ctx* ctx, const gsc_volume* vol, const gsc_gaussians* init_levels,
                             int32_t K, gsc_scene** out);
 void gsc_scene_destroy(gsc_ctx* ctx, gsc_scene* scene);
-/* Replaces the TF and lights (HOST arrays; a transfer-function edit or a light move). */
+/* Replaces the TF, point lights and sphere lights (HOST arrays as in gsc_volume; a
+ * transfer-function edit or a light move). */
 gsc_status gsc_scene_set_optics(gsc_ctx* ctx, gsc_scene* scene, const float* tf_rgba,
-                                int32_t tf_points, const float* lights, int32_t n_lights);
+                                int32_t tf_points, const float* lights, int32_t n_lights,
+                                const float* spheres, int32_t n_spheres);
 /* DEVICE pointers to the scene's current parameters of level l. */
 gsc_status gsc_scene_level(const gsc_scene* scene, int32_t l, gsc_gaussians* out);
 /* DEVICE pointers to level l's optimiser state: params, m and v are each [14 n] floats laid out

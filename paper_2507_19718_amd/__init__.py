@@ -202,30 +202,46 @@ def level_to_device(g, device="cuda") -> Dict[str, torch.Tensor]:
             for k in PARAM_NAMES}
 
 
-class Volume:
-    """Device-resident density plus host TF and lights."""
+def _host_rows(a, width: int) -> np.ndarray:
+    return np.ascontiguousarray(np.zeros((0, width)) if a is None else a,
+                                dtype=np.float32).reshape(-1, width)
 
-    def __init__(self, density: torch.Tensor, density_max: float, tf, lights):
+
+def _rows_ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p) if a.shape[0] else None
+
+
+class Volume:
+    """Device-resident density plus host TF, point lights [L][6] and sphere lights [S][7]."""
+
+    def __init__(self, density: torch.Tensor, density_max: float, tf, lights, spheres=None):
         self.density = _f32_cuda(density, "density")
         self.density_max = float(density_max)
         self.tf = np.ascontiguousarray(tf, dtype=np.float32)
-        self.lights = np.ascontiguousarray(lights, dtype=np.float32)
+        self.lights = _host_rows(lights, 6)
+        self.spheres = _host_rows(spheres, 7)
 
     @classmethod
     def from_synth(cls, vol, device="cuda"):
-        return cls(torch.from_numpy(vol.density).to(device), vol.density_max, vol.tf, vol.lights)
+        return cls(torch.from_numpy(vol.density).to(device), vol.density_max, vol.tf, vol.lights,
+                   getattr(vol, "spheres", None))
 
     def struct(self) -> gsc_volume:
         nz, ny, nx = self.density.shape
         return gsc_volume(_ptr(self.density), nx, ny, nz, self.density_max,
                           self.tf.ctypes.data_as(ctypes.c_void_p), self.tf.shape[0],
-                          self.lights.ctypes.data_as(ctypes.c_void_p), self.lights.shape[0])
+                          _rows_ptr(self.lights), self.lights.shape[0],
+                          _rows_ptr(self.spheres), self.spheres.shape[0])
+
+
+STRATEGY_NEE, STRATEGY_UNIFORM = 0, 1
 
 
 def trace_params(seed: int, frame: int, spp: int, max_bounces: int, K: int, C: float = 0.5,
-                 eps: float = 0.0) -> gsc_trace_params:
+                 eps: float = 0.0, strategy: int = STRATEGY_NEE) -> gsc_trace_params:
     inf = math.isinf(C)
-    return gsc_trace_params(seed, frame, spp, max_bounces, K, 0.0 if inf else C, 1 if inf else 0, eps)
+    return gsc_trace_params(seed, frame, spp, max_bounces, K, 0.0 if inf else C, 1 if inf else 0, eps,
+                            strategy)
 
 
 # ----------------------------------------------------------------------------------------------
@@ -447,12 +463,12 @@ class Scene:
     def destroy(self):
         self._finalizer()
 
-    def set_optics(self, tf, lights):
+    def set_optics(self, tf, lights, spheres=None):
         tf = np.ascontiguousarray(tf, dtype=np.float32)
-        lights = np.ascontiguousarray(lights, dtype=np.float32)
+        lights, spheres = _host_rows(lights, 6), _host_rows(spheres, 7)
         self.ctx.check(self.ctx._lib.gsc_scene_set_optics(
             self.ctx.handle, self.handle, tf.ctypes.data_as(ctypes.c_void_p), tf.shape[0],
-            lights.ctypes.data_as(ctypes.c_void_p), lights.shape[0]))
+            _rows_ptr(lights), lights.shape[0], _rows_ptr(spheres), spheres.shape[0]))
 
     def level(self, l: int) -> Dict[str, torch.Tensor]:
         """Copies of level l's current parameters."""
@@ -488,10 +504,11 @@ class Scene:
 def frame_request(cam, seed: int, frame: int, K: int, max_bounces: int, loss: int = 1,
                   train: bool = True, viewport_frames: int = 1,
                   lr=(1.16e-3, 1e-3, 0.0, 1.25e-2, 1.5e-1), beta1=0.9, beta2=0.999, eps=1e-8,
-                  weight_decay=0.0, C: float = 0.5) -> gsc_frame_request:
+                  weight_decay=0.0, C: float = 0.5,
+                  strategy: int = STRATEGY_NEE) -> gsc_frame_request:
     r = gsc_frame_request()
     r.cam = camera_struct(cam)
-    r.trace = trace_params(seed, frame, 1, max_bounces, K, C)
+    r.trace = trace_params(seed, frame, 1, max_bounces, K, C, strategy=strategy)
     r.loss = loss
     r.train = 1 if train else 0
     r.viewport_frames = viewport_frames

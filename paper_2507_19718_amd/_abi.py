@@ -40,13 +40,14 @@ class gsc_grads(Structure):
 class gsc_volume(Structure):
     _fields_ = [("density", c_void_p), ("nx", c_int32), ("ny", c_int32), ("nz", c_int32),
                 ("density_max", c_float), ("tf_rgba", c_void_p), ("tf_points", c_int32),
-                ("lights", c_void_p), ("n_lights", c_int32)]
+                ("lights", c_void_p), ("n_lights", c_int32), ("spheres", c_void_p),
+                ("n_spheres", c_int32)]
 
 
 class gsc_trace_params(Structure):
     _fields_ = [("seed", c_uint64), ("frame", c_uint32), ("spp", c_uint32),
                 ("max_bounces", c_uint32), ("num_levels", c_uint32), ("C", c_float),
-                ("C_inf", c_int32), ("eps", c_float)]
+                ("C_inf", c_int32), ("eps", c_float), ("strategy", c_uint32)]
 
 
 class gsc_path_record(Structure):
@@ -135,7 +136,8 @@ _SIGNATURES = {
                                 P(gsc_adam_hparams)]),
     "gsc_scene_create": (c_int32, [c_void_p, P(gsc_volume), P(gsc_gaussians), c_int32, P(c_void_p)]),
     "gsc_scene_destroy": (None, [c_void_p, c_void_p]),
-    "gsc_scene_set_optics": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, c_void_p, c_int32]),
+    "gsc_scene_set_optics": (c_int32, [c_void_p, c_void_p, c_void_p, c_int32, c_void_p, c_int32,
+                                       c_void_p, c_int32]),
     "gsc_scene_level": (c_int32, [c_void_p, c_int32, P(gsc_gaussians)]),
     "gsc_scene_state": (c_int32, [c_void_p, c_int32, P(c_void_p), P(c_void_p), P(c_void_p),
                                   P(c_int64), P(c_int64)]),

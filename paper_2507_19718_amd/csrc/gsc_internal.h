@@ -52,9 +52,11 @@ struct TraceDesc {
   const float4* cells;    // cell-corner layout (see launch_build_cells) or NULL
   int32_t nx, ny, nz;
   float dmax, majorant;
-  int32_t P, n_lights;
+  int32_t P, n_lights, n_spheres;
+  uint32_t strategy;      // GSC_STRATEGY_NEE or GSC_STRATEGY_UNIFORM
   float tf[kMaxTf * 4];
   float lights[kMaxLights * 6];
+  float spheres[kMaxLights * 7];   // centre xyz, radius, radiance rgb
   DevCam cam;
   uint64_t seed;
   uint32_t frame, spp, max_bounces, K;

@@ -2,7 +2,10 @@
 //
 // One lane per pixel of a request, one path per sample: delta tracking against the global
 // majorant (free flight), albedo-weighted real collisions, next-event estimation to every
-// point light with ratio-tracked shadow transmittance and the isotropic phase function,
+// point light and every spherical area light (cone sampling, combined with the phase-sampled
+// continuation that reaches the light by the power heuristic) with ratio-tracked shadow
+// transmittance and the isotropic phase function, or phase sampling alone (the uniform
+// baseline of the evaluation),
 // Algorithm 1's early termination (cumulative throughput reading: the throughput is divided
 // by the survival probability Tr and beta multiplied by it), uniform sphere directions.  The
 // NEE radiance accumulated along the path is written to the target of its length (Method:
@@ -129,8 +132,59 @@ struct PathResult {
   uint32_t n, kind;
 };
 
-__device__ PathResult trace_path(const TraceDesc& D, const Vol& V, const float* lights, int px,
-                                 int py, uint32_t sample) {
+// ---- spherical area lights (centre xyz, radius, radiance rgb), all outside the unit cube ----
+
+__device__ __forceinline__ float dot3(float ax, float ay, float az, float bx, float by, float bz) {
+  return (ax * bx + ay * by) + az * bz;
+}
+
+// 1 - cos(theta_max) of the cone a sphere of radius r subtends from squared distance d2, as
+// sin^2 / (1 + cos) so that small cones keep their precision.
+__device__ __forceinline__ float cone_one_minus(float r, float d2) {
+  const float s2 = (r * r) / d2;
+  return s2 / (1.0f + sqrtf(1.0f - s2));
+}
+
+// Nearer root of |o + t w - c|^2 = r^2 for an origin outside the sphere; false on a miss or a
+// sphere behind the origin.
+__device__ __forceinline__ bool sphere_hit(const float* sp, float ox, float oy, float oz, float wx,
+                                           float wy, float wz, float* t) {
+  const float cx = sp[0] - ox, cy = sp[1] - oy, cz = sp[2] - oz;
+  const float b = dot3(wx, wy, wz, cx, cy, cz);
+  const float c = dot3(cx, cy, cz, cx, cy, cz) - sp[3] * sp[3];
+  const float disc = b * b - c;
+  if (!(b > 0.0f) || !(disc >= 0.0f)) return false;
+  *t = b - sqrtf(disc);
+  return true;
+}
+
+// Radiance gathered by a continuation (o, w) that left the volume from a vertex: the nearest
+// sphere light's radiance, with the phase sample's power-heuristic weight om^2 / (om^2 + 4)
+// against cone sampling of that light (solid-angle pdfs 1/(4 pi) and 1/(2 pi om)) when next-
+// event estimation is on, weight 1 for phase sampling alone.
+__device__ __forceinline__ bool escape_light(const float* sph, int ns, uint32_t strategy, float ox,
+                                             float oy, float oz, float wx, float wy, float wz,
+                                             float* e0, float* e1, float* e2) {
+  int best = -1;
+  float tbest = __int_as_float(0x7f800000);
+  for (int s = 0; s < ns; ++s) {
+    float th;
+    if (sphere_hit(sph + 7 * s, ox, oy, oz, wx, wy, wz, &th) && th < tbest) { tbest = th; best = s; }
+  }
+  if (best < 0) return false;
+  const float* sp = sph + 7 * best;
+  float wt = 1.0f;
+  if (strategy == GSC_STRATEGY_NEE) {
+    const float cx = sp[0] - ox, cy = sp[1] - oy, cz = sp[2] - oz;
+    const float om = cone_one_minus(sp[3], dot3(cx, cy, cz, cx, cy, cz));
+    wt = (om * om) / (om * om + 4.0f);
+  }
+  *e0 = sp[4] * wt; *e1 = sp[5] * wt; *e2 = sp[6] * wt;
+  return true;
+}
+
+__device__ PathResult trace_path(const TraceDesc& D, const Vol& V, const float* lights,
+                                 const float* sph, int px, int py, uint32_t sample) {
   PathResult res{0.0f, 0.0f, 0.0f, 1.0f, 0u, 0u};
   const DevCam& cam = D.cam;
   PathStream rng(D.seed, (uint32_t)py * (uint32_t)cam.full_w + (uint32_t)px, sample, D.frame);
@@ -149,6 +203,10 @@ __device__ PathResult trace_path(const TraceDesc& D, const Vol& V, const float* 
   float t0, t1;
   if (!box(ox, oy, oz, wx, wy, wz, &t0, &t1)) return res;
   const float sb = D.majorant;
+  const int ns = D.n_spheres;
+  // Next-event estimation only with that strategy: point lights and sphere lights sampled.
+  const int nl = D.strategy == GSC_STRATEGY_NEE ? D.n_lights : 0;
+  const int ne = D.strategy == GSC_STRATEGY_NEE ? ns : 0;
   float tr0 = 1.0f, tr1 = 1.0f, tr2 = 1.0f;
   float raw0 = 1.0f, raw1 = 1.0f, raw2 = 1.0f;
   float beta = 1.0f;
@@ -169,13 +227,23 @@ __device__ PathResult trace_path(const TraceDesc& D, const Vol& V, const float* 
       const float st = sigma_t(V, x, y, z, &dd);
       if (u2 < st / sb) { collided = true; dcol = dd; break; }
     }
-    if (!collided) { kind = (n == 0u) ? GSC_KIND_ESCAPE0 : GSC_KIND_ESCAPE; break; }
+    if (!collided) {
+      // Leaving the volume; from a vertex (not the camera) the ray may reach an area light.
+      float e0, e1, e2;
+      if (n > 0u && escape_light(sph, ns, D.strategy, ox, oy, oz, wx, wy, wz, &e0, &e1, &e2)) {
+        L0 = L0 + tr0 * e0; L1 = L1 + tr1 * e1; L2 = L2 + tr2 * e2;
+      }
+      kind = (n == 0u) ? GSC_KIND_ESCAPE0 : GSC_KIND_ESCAPE;
+      break;
+    }
+    // The continuation sampled after the last allowed vertex collided again.
+    if (n >= D.max_bounces) { kind = GSC_KIND_MAXDEPTH; break; }
     n += 1u;
     float ar, ag, ab, aa;
     transfer(V, dcol, &ar, &ag, &ab, &aa);
     raw0 = raw0 * ar; raw1 = raw1 * ag; raw2 = raw2 * ab;
     tr0 = tr0 * ar; tr1 = tr1 * ag; tr2 = tr2 * ab;
-    for (int l = 0; l < D.n_lights; ++l) {
+    for (int l = 0; l < nl; ++l) {
       const float* lp = lights + 6 * l;
       const float dl0 = lp[0] - x, dl1 = lp[1] - y, dl2 = lp[2] - z;
       const float dist2 = (dl0 * dl0 + dl1 * dl1) + dl2 * dl2;
@@ -199,8 +267,62 @@ __device__ PathResult trace_path(const TraceDesc& D, const Vol& V, const float* 
       L1 = L1 + tr1 * (lp[4] * g);
       L2 = L2 + tr2 * (lp[5] * g);
     }
-    if (n >= D.max_bounces) { kind = GSC_KIND_MAXDEPTH; break; }
-    if (!D.C_inf) {
+    // Sphere lights: one direction uniform in the subtended cone (1 - cos theta = u_a om,
+    // phi = 2 pi u_b, around the axis by the Duff et al. 2017 orthonormal basis), its hit
+    // point, blocked if another sphere is nearer, else ratio-tracked.  phase * Le * T / p_light
+    // with the power-heuristic weight p_light^2 / (p_light^2 + p_phase^2) is
+    // Le * T * 2 om / (om^2 + 4).
+    for (int s = 0; s < ne; ++s) {
+      const float* sp = sph + 7 * s;
+      const float dl0 = sp[0] - x, dl1 = sp[1] - y, dl2 = sp[2] - z;
+      const float d2 = dot3(dl0, dl1, dl2, dl0, dl1, dl2);
+      const float d = sqrtf(d2);
+      const float a0 = dl0 / d, a1 = dl1 / d, a2 = dl2 / d;
+      const float om = cone_one_minus(sp[3], d2);
+      const float ua = rng.uniform(), ub = rng.uniform();
+      const float v = ua * om;
+      const float ct = 1.0f - v;
+      const float st = sqrtf(fmaxf(0.0f, v * (2.0f - v)));
+      float sphi, cphi;
+      gsincos(kTwoPi * ub, &sphi, &cphi);
+      const float sg = copysignf(1.0f, a2);
+      const float k = -1.0f / (sg + a2);
+      const float m = (a0 * a1) * k;
+      const float b10 = 1.0f + ((sg * a0) * a0) * k, b11 = sg * m, b12 = -(sg * a0);
+      const float b20 = m, b21 = sg + (a1 * a1) * k, b22 = -a1;
+      const float sc = st * cphi, ss = st * sphi;
+      const float l0 = (sc * b10 + ss * b20) + ct * a0;
+      const float l1 = (sc * b11 + ss * b21) + ct * a1;
+      const float l2 = (sc * b12 + ss * b22) + ct * a2;
+      const float bq = dot3(l0, l1, l2, dl0, dl1, dl2);
+      const float th = bq - sqrtf(fmaxf(0.0f, bq * bq - (d2 - sp[3] * sp[3])));
+      bool blocked = false;
+      for (int mm = 0; mm < ns; ++mm) {
+        float tm;
+        if (mm != s && sphere_hit(sph + 7 * mm, x, y, z, l0, l1, l2, &tm) && tm < th) blocked = true;
+      }
+      if (blocked) continue;
+      float b0, b1;
+      const float texit = box(x, y, z, l0, l1, l2, &b0, &b1) ? fminf(th, b1) : 0.0f;
+      float Tsh = 1.0f, ts = 0.0f;
+      for (uint32_t step = 0; step < kMaxSteps; ++step) {
+        const float u = rng.uniform();
+        ts = ts - glog(1.0f - u) / sb;
+        if (ts >= texit) break;
+        float dd;
+        const float stt = sigma_t(V, x + ts * l0, y + ts * l1, z + ts * l2, &dd);
+        Tsh = Tsh * (1.0f - stt / sb);
+      }
+      const float g = Tsh * ((2.0f * om) / (om * om + 4.0f));
+      L0 = L0 + tr0 * (sp[4] * g);
+      L1 = L1 + tr1 * (sp[5] * g);
+      L2 = L2 + tr2 * (sp[6] * g);
+    }
+    // After the last allowed vertex only a continuation reaching an area light can still add
+    // radiance; without area lights the path ends here.
+    const bool last = n >= D.max_bounces;
+    if (last && ns == 0) { kind = GSC_KIND_MAXDEPTH; break; }
+    if (!last && !D.C_inf) {
       const float lum = (0.2126f * raw0 + 0.7152f * raw1) + 0.0722f * raw2;
       const float Tr = fminf(fmaxf(D.C * lum, 0.0f), 1.0f);
       if (Tr < 0.9f) {
@@ -220,7 +342,14 @@ __device__ PathResult trace_path(const TraceDesc& D, const Vol& V, const float* 
     wx = r * cp; wy = r * sp; wz = cz;
     ox = x; oy = y; oz = z;
     float bb0, bb1;
-    if (!box(ox, oy, oz, wx, wy, wz, &bb0, &bb1)) { kind = GSC_KIND_ESCAPE; break; }
+    if (!box(ox, oy, oz, wx, wy, wz, &bb0, &bb1)) {
+      float e0, e1, e2;
+      if (escape_light(sph, ns, D.strategy, ox, oy, oz, wx, wy, wz, &e0, &e1, &e2)) {
+        L0 = L0 + tr0 * e0; L1 = L1 + tr1 * e1; L2 = L2 + tr2 * e2;
+      }
+      kind = GSC_KIND_ESCAPE;
+      break;
+    }
     t0 = 0.0f;
     t1 = bb1;
   }
@@ -239,11 +368,13 @@ __global__ void __launch_bounds__(kTraceBlock) trace_kernel(const TraceDesc* __r
                                                             int R, unsigned long long* path_vertices) {
   __shared__ float s_tf[kMaxTf * 4];
   __shared__ float s_lights[kMaxLights * 6];
+  __shared__ float s_spheres[kMaxLights * 7];
   const int64_t block0 = (int64_t)blockIdx.x * kTraceBlock;
   const int r = find_segment(req_pstart, R, block0);
   const TraceDesc& D = descs[r];
   for (int i = threadIdx.x; i < 4 * D.P; i += kTraceBlock) s_tf[i] = D.tf[i];
   for (int i = threadIdx.x; i < 6 * D.n_lights; i += kTraceBlock) s_lights[i] = D.lights[i];
+  for (int i = threadIdx.x; i < 7 * D.n_spheres; i += kTraceBlock) s_spheres[i] = D.spheres[i];
   __syncthreads();
   const int W = D.cam.w, H = D.cam.h;
   const int64_t plane = (int64_t)W * H;
@@ -255,7 +386,7 @@ __global__ void __launch_bounds__(kTraceBlock) trace_kernel(const TraceDesc* __r
     const int px = D.cam.x0 + lx, py = D.cam.y0 + ly;
     const uint32_t K = D.K;
     if (D.spp == 1u) {
-      const PathResult pr = trace_path(D, V, s_lights, px, py, 0u);
+      const PathResult pr = trace_path(D, V, s_lights, s_spheres, px, py, 0u);
       verts = pr.n;
       const uint32_t lvl = pr.n ? (min(pr.n, K) - 1u) : 0xFFFFFFFFu;
       for (uint32_t l = 0; l < K; ++l) {
@@ -279,7 +410,7 @@ __global__ void __launch_bounds__(kTraceBlock) trace_kernel(const TraceDesc* __r
         o[0] = 0.0f; o[1] = 0.0f; o[2] = 0.0f;
       }
       for (uint32_t smp = 0; smp < D.spp; ++smp) {
-        const PathResult pr = trace_path(D, V, s_lights, px, py, smp);
+        const PathResult pr = trace_path(D, V, s_lights, s_spheres, px, py, smp);
         verts += pr.n;
         if (pr.n) {
           float* o = D.targets + 3 * ((min(pr.n, K) - 1u) * plane + lp);

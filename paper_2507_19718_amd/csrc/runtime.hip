@@ -116,7 +116,7 @@ struct gsc_scene {
   float4* cells = nullptr;         // density in the cell-corner layout (32 B per trilinear cell)
   int32_t nx = 0, ny = 0, nz = 0;
   float dmax = 1.0f;
-  std::vector<float> tf, lights;
+  std::vector<float> tf, lights, spheres;
 };
 
 struct gsc_ctx {
@@ -539,19 +539,36 @@ float max_alpha(const float* tf, int P) {
   return m;
 }
 
-void check_volume_host(gsc_ctx* ctx, const float* tf, int P, const float* lights, int nl) {
+void check_volume_host(gsc_ctx* ctx, const float* tf, int P, const float* lights, int nl,
+                       const float* spheres, int ns) {
   if (P < 2 || P > kMaxTf) invalid(ctx, "tf_points must be in [2, 64]");
-  if (nl < 1 || nl > kMaxLights) invalid(ctx, "n_lights must be in [1, 8]");
-  if (!tf || !lights) invalid(ctx, "tf_rgba / lights is NULL");
+  if (nl < 0 || nl > kMaxLights) invalid(ctx, "n_lights must be in [0, 8]");
+  if (ns < 0 || ns > kMaxLights) invalid(ctx, "n_spheres must be in [0, 8]");
+  if (nl + ns < 1) invalid(ctx, "the scene needs at least one light");
+  if (!tf) invalid(ctx, "tf_rgba is NULL");
+  if (nl > 0 && !lights) invalid(ctx, "lights is NULL");
+  if (ns > 0 && !spheres) invalid(ctx, "spheres is NULL");
   for (int i = 0; i < 4 * P; ++i) if (!std::isfinite(tf[i])) invalid(ctx, "transfer function not finite");
   if (!(max_alpha(tf, P) > 0.0f)) invalid(ctx, "transfer function opacity is zero everywhere (no majorant)");
   for (int i = 0; i < 6 * nl; ++i) if (!std::isfinite(lights[i])) invalid(ctx, "lights not finite");
+  for (int s = 0; s < ns; ++s) {
+    const float* sp = spheres + 7 * s;
+    for (int i = 0; i < 7; ++i) if (!std::isfinite(sp[i])) invalid(ctx, "spheres not finite");
+    if (!(sp[3] > 0.0f)) invalid(ctx, "sphere light radius must be positive");
+    // Squared distance from the centre to the unit cube must exceed r^2.
+    double d2 = 0.0;
+    for (int a = 0; a < 3; ++a) {
+      const double c = sp[a], q = std::min(std::max(c, 0.0), 1.0);
+      d2 += (c - q) * (c - q);
+    }
+    if (!(d2 > (double)sp[3] * sp[3])) invalid(ctx, "sphere lights must lie outside the unit cube");
+  }
 }
 
 TraceDesc make_trace_desc(const float* density, const float4* cells, int nx, int ny, int nz, float dmax,
                           const float* tf,
-                          int P, const float* lights, int nl, const gsc_camera& cam,
-                          const gsc_trace_params& tp) {
+                          int P, const float* lights, int nl, const float* spheres, int ns,
+                          const gsc_camera& cam, const gsc_trace_params& tp) {
   TraceDesc d;
   std::memset(&d, 0, sizeof(d));
   d.density = density;
@@ -561,8 +578,11 @@ TraceDesc make_trace_desc(const float* density, const float4* cells, int nx, int
   d.majorant = dmax * max_alpha(tf, P);
   d.P = P;
   d.n_lights = nl;
+  d.n_spheres = ns;
+  d.strategy = tp.strategy;
   std::memcpy(d.tf, tf, sizeof(float) * 4 * P);
-  std::memcpy(d.lights, lights, sizeof(float) * 6 * nl);
+  if (nl > 0) std::memcpy(d.lights, lights, sizeof(float) * 6 * nl);
+  if (ns > 0) std::memcpy(d.spheres, spheres, sizeof(float) * 7 * ns);
   d.cam = to_dev(cam);
   d.seed = tp.seed;
   d.frame = tp.frame;
@@ -582,6 +602,8 @@ void check_trace_params(gsc_ctx* ctx, const gsc_trace_params* tp) {
   if (tp->num_levels < 1 || tp->num_levels > 8) invalid(ctx, "num_levels must be in [1, 8]");
   if (!tp->C_inf && !std::isfinite(tp->C)) invalid(ctx, "C must be finite unless C_inf is set");
   if (!std::isfinite(tp->eps) || tp->eps < 0.0f) invalid(ctx, "eps must be finite and >= 0");
+  if (tp->strategy != GSC_STRATEGY_NEE && tp->strategy != GSC_STRATEGY_UNIFORM)
+    invalid(ctx, "strategy must be GSC_STRATEGY_NEE or GSC_STRATEGY_UNIFORM");
 }
 
 // AdamW hyper-parameters of one group at `step`: bias corrections s1 = lr / (1 - b1^t) and
@@ -680,7 +702,8 @@ gsc_status render_batch(gsc_ctx* ctx, gsc_scene* const* scenes, const gsc_frame_
     gsc_scene* sc = scenes[i];
     td[i] = make_trace_desc(nullptr, sc->cells, sc->nx, sc->ny, sc->nz, sc->dmax, sc->tf.data(),
                             (int)sc->tf.size() / 4, sc->lights.data(), (int)sc->lights.size() / 6,
-                            reqs[i].cam, reqs[i].trace);
+                            sc->spheres.data(), (int)sc->spheres.size() / 7, reqs[i].cam,
+                            reqs[i].trace);
     td[i].pix_off = tlaunch;
     td[i].targets = ctx->targets.as<float>() + 3 * pix_base[i];
     td[i].records = (char*)ctx->records.p + sizeof(gsc_path_record) * rec_base[i];
@@ -906,13 +929,15 @@ gsc_status gsc_trace_targets(gsc_ctx* ctx, const gsc_volume* vol, const gsc_came
     if (!vol || !vol->density) invalid(ctx, "volume or density is NULL");
     if (vol->nx < 1 || vol->ny < 1 || vol->nz < 1) invalid(ctx, "volume dimensions must be >= 1");
     if (!(vol->density_max > 0.0f) || !std::isfinite(vol->density_max)) invalid(ctx, "density_max must be positive");
-    check_volume_host(ctx, vol->tf_rgba, vol->tf_points, vol->lights, vol->n_lights);
+    check_volume_host(ctx, vol->tf_rgba, vol->tf_points, vol->lights, vol->n_lights, vol->spheres,
+                      vol->n_spheres);
     check_camera(ctx, cam);
     check_trace_params(ctx, params);
     if (!targets) invalid(ctx, "targets is NULL");
     if (records && params->spp != 1) invalid(ctx, "records require spp == 1");
     TraceDesc d = make_trace_desc(vol->density, nullptr, vol->nx, vol->ny, vol->nz, vol->density_max,
-                                  vol->tf_rgba, vol->tf_points, vol->lights, vol->n_lights, *cam, *params);
+                                  vol->tf_rgba, vol->tf_points, vol->lights, vol->n_lights,
+                                  vol->spheres, vol->n_spheres, *cam, *params);
     d.pix_off = 0;
     d.targets = targets;
     d.records = records;
@@ -1119,7 +1144,8 @@ gsc_status gsc_scene_create(gsc_ctx* ctx, const gsc_volume* vol, const gsc_gauss
     if (!vol || !vol->density) invalid(ctx, "volume or density is NULL");
     if (vol->nx < 1 || vol->ny < 1 || vol->nz < 1) invalid(ctx, "volume dimensions must be >= 1");
     if (!(vol->density_max > 0.0f)) invalid(ctx, "density_max must be positive");
-    check_volume_host(ctx, vol->tf_rgba, vol->tf_points, vol->lights, vol->n_lights);
+    check_volume_host(ctx, vol->tf_rgba, vol->tf_points, vol->lights, vol->n_lights, vol->spheres,
+                      vol->n_spheres);
     check_levels(ctx, init_levels, K);
     gsc_scene* sc = new gsc_scene();
     sc->alloc = ctx->alloc;
@@ -1136,6 +1162,7 @@ gsc_status gsc_scene_create(gsc_ctx* ctx, const gsc_volume* vol, const gsc_gauss
       sc->dmax = vol->density_max;
       sc->tf.assign(vol->tf_rgba, vol->tf_rgba + 4 * vol->tf_points);
       sc->lights.assign(vol->lights, vol->lights + 6 * vol->n_lights);
+      sc->spheres.assign(vol->spheres, vol->spheres + 7 * vol->n_spheres);
       const size_t vb = cells_bytes(vol->nx, vol->ny, vol->nz);
       sc->cells = (float4*)sc->alloc.get(vb);
       if (!sc->cells) oom(ctx, "scene volume", vb);
@@ -1184,12 +1211,14 @@ void gsc_scene_destroy(gsc_ctx* ctx, gsc_scene* sc) {
 }
 
 gsc_status gsc_scene_set_optics(gsc_ctx* ctx, gsc_scene* sc, const float* tf_rgba, int32_t tf_points,
-                                const float* lights, int32_t n_lights) {
+                                const float* lights, int32_t n_lights, const float* spheres,
+                                int32_t n_spheres) {
   return guarded(ctx, [&]() -> gsc_status {
     if (!sc) invalid(ctx, "scene is NULL");
-    check_volume_host(ctx, tf_rgba, tf_points, lights, n_lights);
+    check_volume_host(ctx, tf_rgba, tf_points, lights, n_lights, spheres, n_spheres);
     sc->tf.assign(tf_rgba, tf_rgba + 4 * tf_points);
     sc->lights.assign(lights, lights + 6 * n_lights);
+    sc->spheres.assign(spheres, spheres + 7 * n_spheres);
     return GSC_OK;
   });
 }
@@ -1293,7 +1322,7 @@ void run_init_points(gsc_ctx* ctx, const gsc_volume* vol, int64_t n, uint64_t se
   gsc_trace_params tp{};
   tp.seed = seed;
   TraceDesc d = make_trace_desc(vol->density, nullptr, vol->nx, vol->ny, vol->nz, vol->density_max,
-                                vol->tf_rgba, vol->tf_points, nullptr, 0, cam, tp);
+                                vol->tf_rgba, vol->tf_points, nullptr, 0, nullptr, 0, cam, tp);
   need(ctx, ctx->trace_tab, ctx->alloc, sizeof(TraceDesc) + sizeof(int64_t), "trace descriptor");
   upload(ctx, ctx->trace_tab.p, &d, sizeof(TraceDesc));
   need(ctx, ctx->ini_tries, ctx->alloc, 4 * (size_t)n, "init attempts");
