@@ -158,7 +158,8 @@ def trace(vol, cam, seed: int, frame: int, spp: int, max_bounces: int, K: int, C
           eps: float = 0.0, records: bool = True, second_moment: bool = False,
           kinds: bool = False, strategy: int = STRATEGY_NEE):
     """Per-path-length targets [K][h][w][3] (mean over spp), optional second moments and
-    per-pixel records (L[3], beta, n, kind) for spp == 1.  C = inf disables Algorithm 1.
+    per-path records (L[3], beta, n, kind): [h][w] for spp == 1, [spp][h][w] otherwise.
+    C = inf disables Algorithm 1.
     strategy: next-event estimation with MIS for area lights (0) or phase sampling only (1)."""
     d = _f32(vol.density)
     nz, ny, nx = d.shape
@@ -169,7 +170,7 @@ def trace(vol, cam, seed: int, frame: int, spp: int, max_bounces: int, K: int, C
     H, W = cam.h, cam.w
     targets = np.zeros((K, H, W, 3), dtype=np.float32)
     tsq = np.zeros_like(targets) if second_moment else None
-    rec = np.zeros((H, W, 5), dtype=np.uint32) if records else None
+    rec = np.zeros((spp, H, W, 5), dtype=np.uint32) if records else None
     stats = np.zeros(2, dtype=np.uint32)
     kc = np.zeros((H, W, 4), dtype=np.uint32) if kinds else None
     c_inf = 1 if math.isinf(C) else 0
@@ -185,6 +186,8 @@ def trace(vol, cam, seed: int, frame: int, spp: int, max_bounces: int, K: int, C
     if kinds:
         out["kind_counts"] = kc
     if records:
+        if spp == 1:
+            rec = rec[0]
         out["L"] = rec[..., :3].copy().view(np.float32)
         out["beta"] = rec[..., 3].copy().view(np.float32)
         out["n"] = (rec[..., 4] & 0xFFFF).astype(np.int32)
@@ -298,8 +301,15 @@ def loss_grad(images: np.ndarray, targets: np.ndarray, hdr: bool):
 def composite(n: np.ndarray, kind: np.ndarray, L: np.ndarray, beta: np.ndarray,
               cache: np.ndarray) -> np.ndarray:
     """Per pixel: EARLY -> max(cache[l], 0) / beta; natural termination with n >= 1 -> the
-    unbiased NEE radiance when its luminance is positive, else max(cache[l], 0) / beta;
-    no interaction -> 0.  l = min(n, K) - 1.  fp32, elementwise."""
+    unbiased path radiance when its luminance is positive, else max(cache[l], 0) / beta;
+    no interaction -> 0.  l = min(n, K) - 1.  fp32, elementwise.  With a leading sample axis
+    (records of several samples per pixel) the pixel is the mean of its samples' values,
+    summed in sample order."""
+    if n.ndim == 3:
+        acc = np.zeros(n.shape[1:] + (3,), dtype=np.float32)
+        for s in range(n.shape[0]):
+            acc = (acc + composite(n[s], kind[s], L[s], beta[s], cache)).astype(np.float32)
+        return (acc / np.float32(n.shape[0])).astype(np.float32)
     K = cache.shape[0]
     H, W = n.shape
     out = np.zeros((H, W, 3), dtype=np.float32)

@@ -673,7 +673,7 @@ double ora_ratio_tracking_mean(const float* d, int nx, int ny, int nz, float dma
 
 // The tracer.  targets [K][h][w][3] receive the per-level mean over spp of the path's NEE
 // radiance (written to level min(n, K) - 1, zero elsewhere); targets_sq (optional) the per-level
-// mean of squares; records (optional; sample 0) five words per pixel:
+// mean of squares; records (optional) [spp][h][w], five words per path:
 // L[3] (f32), beta (f32), n | kind << 16 (u32); kind_counts (optional) [h][w][4] per-kind counts.
 int ora_trace(const float* density, int nx, int ny, int nz, float dmax, const float* tf, int P,
               const float* lights, int nl, const float* spheres, int ns, int strategy,
@@ -697,10 +697,16 @@ int ora_trace(const float* density, int nx, int ny, int nz, float dmax, const fl
     int lx = (int)(p % W), ly = (int)(p / W);
     int px = cam.x0 + lx, py = cam.y0 + ly;
     std::vector<float> sum(3 * K, 0.f), sq(3 * K, 0.f);
-    PathOut first{};
     for (uint32_t s = 0; s < spp; ++s) {
       PathOut po = ora_trace_path(V, lights, nl, spheres, ns, cam, tp, px, py, s);
-      if (s == 0) first = po;
+      if (records) {
+        uint32_t* rec = records + 5 * ((size_t)s * plane + p);
+        std::memcpy(&rec[0], &po.L[0], 4);
+        std::memcpy(&rec[1], &po.L[1], 4);
+        std::memcpy(&rec[2], &po.L[2], 4);
+        std::memcpy(&rec[3], &po.beta, 4);
+        rec[4] = (uint32_t)po.n | ((uint32_t)po.kind << 16);
+      }
       total_len += (uint64_t)po.n;
       if (kind_counts) kind_counts[4 * p + po.kind] += 1u;
       if (po.n >= 1) {
@@ -717,14 +723,6 @@ int ora_trace(const float* density, int nx, int ny, int nz, float dmax, const fl
         targets[idx] = (spp == 1) ? sum[3 * l + c] : sum[3 * l + c] / (float)spp;
         if (targets_sq) targets_sq[idx] = (spp == 1) ? sq[3 * l + c] : sq[3 * l + c] / (float)spp;
       }
-    if (records) {
-      uint32_t* rec = records + 5 * p;
-      std::memcpy(&rec[0], &first.L[0], 4);
-      std::memcpy(&rec[1], &first.L[1], 4);
-      std::memcpy(&rec[2], &first.L[2], 4);
-      std::memcpy(&rec[3], &first.beta, 4);
-      rec[4] = (uint32_t)first.n | ((uint32_t)first.kind << 16);
-    }
   }
   if (path_stats) { path_stats[0] = (uint32_t)(total_len & 0xFFFFFFFFu); path_stats[1] = (uint32_t)(total_len >> 32); }
   return 0;

@@ -1,12 +1,15 @@
 """Experiment harness on the hot-path calls: synthetic stand-ins for the paper's studies of the
-sampling coefficient C and of cold-start training (Evaluation), and of the hyper-parameter
-ablation (supplement: regularisation and covariance learning rate).
+sampling coefficient C and of cold-start training (Evaluation), of the hyper-parameter
+ablation (supplement: regularisation and covariance learning rate), and of the image-quality
+comparison against uniform and next-event-estimation path tracing under two small spherical
+area lights (Evaluation: scenes and baselines).
 
 Everything runs through the library's entry points: `gsc_cache_init` for volume-shaped initial
 caches, `gsc_render_frame` for cached frames (trace + splat + train + composite), and
 `gsc_trace_targets` for the references (no early termination, many samples per pixel).
 
-    python -m paper_2507_19718_amd.experiments [--workload orbit1k] [--what C,cold,ablation]
+    python -m paper_2507_19718_amd.experiments [--workload orbit1k] [--lights point|area]
+        [--what C,cold,ablation,estimators]
 
 prints one JSON object per study.
 """
@@ -20,8 +23,8 @@ from typing import Dict, List, Sequence
 
 import torch
 
-from . import (Context, Scene, Volume, frame_request, gsc_cache_init, gsc_render_frame,
-               gsc_trace_targets, trace_params)
+from . import (STRATEGY_NEE, STRATEGY_UNIFORM, Context, Scene, Volume, frame_request,
+               gsc_cache_init, gsc_render_frame, gsc_trace_targets, trace_params)
 
 
 def reference_radiance(ctx: Context, vol: Volume, cam, K: int, B: int, seed: int, spp: int = 1024,
@@ -40,11 +43,19 @@ def reference_radiance(ctx: Context, vol: Volume, cam, K: int, B: int, seed: int
     return (acc / spp).float()
 
 
-def path_traced(ctx: Context, vol: Volume, cam, K: int, B: int, seed: int, frame: int) -> torch.Tensor:
-    """One 1-spp path-traced image (next-event estimation, no cache): the uncached baseline."""
+def path_traced(ctx: Context, vol: Volume, cam, K: int, B: int, seed: int, frame: int,
+                strategy: int = STRATEGY_NEE) -> torch.Tensor:
+    """One 1-spp path-traced image (no cache): the uncached baseline, with next-event
+    estimation (MIS for area lights) or phase sampling only."""
     tg = torch.empty((K, cam.h, cam.w, 3), device="cuda")
-    gsc_trace_targets(ctx, vol, cam, trace_params(seed, frame, 1, B, K, C=math.inf), tg)
+    gsc_trace_targets(ctx, vol, cam, trace_params(seed, frame, 1, B, K, C=math.inf, strategy=strategy), tg)
     return tg.sum(0)
+
+
+def psnr_ldr(a: torch.Tensor, ref: torch.Tensor) -> float:
+    """PSNR in dB of images clamped to [0, 1] (display range), peak 1."""
+    m = float(((a.double().clamp(0, 1) - ref.double().clamp(0, 1)) ** 2).mean())
+    return float("inf") if m == 0 else -10.0 * math.log10(m)
 
 
 def mse(a: torch.Tensor, ref: torch.Tensor) -> float:
@@ -141,6 +152,35 @@ def study_ablation(ctx, wl, vol, gv, init_levels, ref_still, still_cam, orbit: i
     return {"study": "ablation", "orbit_frames": orbit, "still_frames": still, "mse_at_still_frames": out}
 
 
+def study_estimators(ctx, wl, gv, init_levels, ref, cam, warm: int = 32, measure: int = 16) -> Dict:
+    """Per-frame MSE / PSNR against the reference and ms per frame of 1-spp uniform path
+    tracing, 1-spp next-event estimation (MIS), and the cached composite after `warm`
+    training frames (static camera)."""
+    out = {}
+    for name, strat in (("PT_uniform", STRATEGY_UNIFORM), ("PT_nee", STRATEGY_NEE)):
+        imgs, ms = [], 0.0
+        for f in range(measure):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            img = path_traced(ctx, gv, cam, wl.K, wl.max_bounces, wl.seed, 70_000 + f, strat)
+            torch.cuda.synchronize()
+            ms += (time.perf_counter() - t) * 1e3
+            imgs.append(img)
+        out[name] = {"mse": sum(mse(i, ref) for i in imgs) / measure,
+                     "psnr_ldr_db": sum(psnr_ldr(i, ref) for i in imgs) / measure,
+                     "ms_per_frame": round(ms / measure, 3)}
+    scene = fresh_scene(ctx, gv, init_levels)
+    n = warm + measure
+    r = run_frames(ctx, scene, [cam] * n, wl, wl.C, wl.lr, wl.weight_decay, wl.seed,
+                   keep=range(warm, n))
+    imgs = [r["images"][i] for i in range(warm, n)]
+    out["GSCache"] = {"mse": sum(mse(i, ref) for i in imgs) / measure,
+                      "psnr_ldr_db": sum(psnr_ldr(i, ref) for i in imgs) / measure,
+                      "ms_per_frame": round(r["ms_per_frame"], 3), "warm_frames": warm}
+    scene.destroy()
+    return {"study": "estimators", "measured_frames": measure, "results": out}
+
+
 def main():
     import synth
     ap = argparse.ArgumentParser()
@@ -150,9 +190,14 @@ def main():
     ap.add_argument("--ref-spp", type=int, default=1024)
     ap.add_argument("--orbit", type=int, default=256)
     ap.add_argument("--still", type=int, default=256)
+    ap.add_argument("--lights", choices=("point", "area"), default="point",
+                    help="the workload's point lights, or two spherical area lights instead")
     args = ap.parse_args()
     wl = synth.workload(args.workload)
     vol = wl.volume()
+    if args.lights == "area":
+        vol.lights = vol.lights[:0]
+        vol.spheres = synth.sphere_lights(2)
     ctx = Context(0)
     gv = Volume.from_synth(vol)
     cam = wl.camera()
@@ -161,13 +206,15 @@ def main():
     torch.cuda.synchronize()
     init_ms = (time.perf_counter() - t) * 1e3
     ref = reference_radiance(ctx, gv, cam, wl.K, wl.max_bounces, wl.seed, spp=args.ref_spp)
-    head = {"workload": wl.name, "width": cam.w, "height": cam.h, "levels": wl.K,
+    head = {"workload": wl.name, "lights": args.lights, "width": cam.w, "height": cam.h, "levels": wl.K,
             "init_points": args.init_points, "init_ms": round(init_ms, 2), "ref_spp": args.ref_spp}
     what = set(args.what.split(","))
     if "C" in what:
         print(json.dumps({**head, **study_C(ctx, wl, vol, gv, init_levels, ref, cam)}), flush=True)
     if "cold" in what:
         print(json.dumps({**head, **study_cold_start(ctx, wl, vol, gv, init_levels, ref, cam)}), flush=True)
+    if "estimators" in what:
+        print(json.dumps({**head, **study_estimators(ctx, wl, gv, init_levels, ref, cam)}), flush=True)
     if "ablation" in what:
         print(json.dumps({**head, **study_ablation(ctx, wl, vol, gv, init_levels, ref, cam,
                                                    orbit=args.orbit, still=args.still)}), flush=True)

@@ -53,3 +53,20 @@ def test_studies_run(env):
     assert set(a["mse_at_still_frames"]) == {"ours", "-REG", "-CO", "-CO,-REG"}
     for v in a["mse_at_still_frames"].values():
         assert all(math.isfinite(x) for x in v.values())
+
+
+def test_estimator_study_with_area_lights(env):
+    """Under area lights both uncached estimators and the cache produce finite errors, and
+    MIS next-event estimation beats phase sampling alone at 1 spp."""
+    ex, e, gsc = env["ex"], env, env["gsc"]
+    vol = e["wl"].volume()
+    vol.lights = vol.lights[:0]
+    vol.spheres = synth.sphere_lights(2)
+    gv = gsc.Volume.from_synth(vol)
+    ref = ex.reference_radiance(e["ctx"], gv, e["cam"], e["wl"].K, e["wl"].max_bounces, 6, spp=256)
+    assert float(ref.max()) > 0
+    r = ex.study_estimators(e["ctx"], e["wl"], gv, e["init"], ref, e["cam"], warm=4, measure=4)
+    res = r["results"]
+    assert set(res) == {"PT_uniform", "PT_nee", "GSCache"}
+    assert all(math.isfinite(v["mse"]) for v in res.values())
+    assert res["PT_nee"]["mse"] < res["PT_uniform"]["mse"]

@@ -189,3 +189,30 @@ def test_targets_have_one_level_per_pixel(ora, tiny_volume):
     has = out["n"] >= 1
     hh, ww = np.nonzero(has)
     assert np.array_equal(out["targets"][lvl[has], hh, ww], out["L"][has])
+
+
+def test_records_of_every_sample(ora, tiny_volume):
+    """Several samples per pixel: sample s's record is that sample's path (sample 0 equals the
+    1-spp record, the stream being the same), the level targets are the per-level means of the
+    records' radiance, and with a zero cache and no early termination the composite is the
+    path-traced estimate (the sum of the level targets)."""
+    cam = synth.workload("tiny").camera().crop(32, 32, 40, 40)
+    spp, K = 4, 3
+    one = ora.trace(tiny_volume, cam, seed=4, frame=2, spp=1, max_bounces=3, K=K, C=math.inf)
+    many = ora.trace(tiny_volume, cam, seed=4, frame=2, spp=spp, max_bounces=3, K=K, C=math.inf)
+    assert many["L"].shape == (spp, cam.h, cam.w, 3)
+    assert np.array_equal(many["L"][0], one["L"]) and np.array_equal(many["n"][0], one["n"])
+    lvl = np.minimum(many["n"], K) - 1
+    acc = np.zeros((K, cam.h, cam.w, 3), np.float32)
+    for s in range(spp):
+        for l in range(K):
+            acc[l] = acc[l] + np.where((lvl[s] == l)[..., None], many["L"][s], np.float32(0))
+    assert np.array_equal(acc / np.float32(spp), many["targets"])
+    zero_cache = np.zeros((K, cam.h, cam.w, 3), np.float32)
+    comp = ora.composite(many["n"], many["kind"], many["L"], many["beta"], zero_cache)
+    assert np.allclose(comp, many["targets"].sum(0), rtol=1e-6, atol=0)
+    # Two identical samples average to the single-sample composite exactly.
+    cache = np.abs(np.random.default_rng(0).normal(size=(K, cam.h, cam.w, 3))).astype(np.float32)
+    two = [np.stack([one[k]] * 2) for k in ("n", "kind", "L", "beta")]
+    assert np.array_equal(ora.composite(*two, cache),
+                          ora.composite(one["n"], one["kind"], one["L"], one["beta"], cache))
