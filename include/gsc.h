@@ -168,7 +168,7 @@ typedef struct {
   uint32_t strategy;       /* GSC_STRATEGY_NEE (0) or GSC_STRATEGY_UNIFORM (1)             */
 } gsc_trace_params;
 
-/* DEVICE, one per pixel (spp == 1 only): the path's accumulated NEE radiance L, the product
+/* DEVICE, one per path ([spp][h][w], sample-major): the path's accumulated radiance L, the product
  * beta of the survival probabilities of Algorithm 1 at termination (Eq. 3), its length n
  * (real collisions) in the low 16 bits of n_kind and the termination kind in the high 16 bits:
  * 0 no interaction, 1 left the volume, 2 reached max_bounces, 3 terminated early. */
@@ -213,7 +213,8 @@ typedef struct {
 /* HOST.  One frame of one viewer of one scene. */
 typedef struct {
   gsc_camera cam;
-  gsc_trace_params trace;  /* num_levels must equal the scene's K                          */
+  gsc_trace_params trace;  /* num_levels must equal the scene's K; 1 <= spp <= 4096: the   *
+                            * splat, loss and optimiser step run once whatever spp is       */
   int32_t loss;            /* 0 = L2, 1 = HDR (Eq. 4)                                      */
   int32_t train;           /* 0: render only (no backward, no optimiser step)              */
   uint32_t viewport_frames;/* t >= 1 of Eq. 5                                               */
@@ -270,7 +271,7 @@ gsc_status gsc_ctx_trim(gsc_ctx* ctx);
  * targets: [K][h][w][3], written completely: level min(n,K)-1 of pixel p receives the
  * path's accumulated radiance (next-event estimates plus light hits on leaving the volume),
  * every other level 0; mean over spp.
- * records: [h][w] gsc_path_record, or NULL; must be NULL when spp > 1.
+ * records: [spp][h][w] gsc_path_record (sample s of pixel p at s h w + p), or NULL.
  * stats: HOST or NULL; non-NULL synchronises the stream and fills ms_trace, paths and
  * path_vertices. */
 gsc_status gsc_trace_targets(gsc_ctx* ctx, const gsc_volume* vol, const gsc_camera* cam,
@@ -321,11 +322,13 @@ gsc_status gsc_splat_backward(gsc_ctx* ctx, const gsc_binning* bin, const gsc_ga
  * loss (DEVICE scalar, fp32).  If records is not NULL also writes the cached composite image
  * [h][w][3]: early termination -> max(cache, 0) / beta; natural termination with nonzero
  * radiance -> the radiance, with zero radiance -> max(cache, 0) / beta; no interaction -> 0,
- * where cache = images[min(n,K)-1] (Method: "Natural Path Termination", Eq. 3). */
+ * where cache = images[min(n,K)-1] (Method: "Natural Path Termination", Eq. 3).  records
+ * holds spp >= 1 samples per pixel ([spp][h][w]); the composite pixel is the mean of its
+ * samples' values, summed in sample order. */
 gsc_status gsc_loss_composite(gsc_ctx* ctx, const float* images, const float* targets,
-                              const gsc_path_record* records, int32_t num_levels, int32_t w,
-                              int32_t h, int32_t loss, float* dL_dimages, float* loss_out,
-                              float* composite);
+                              const gsc_path_record* records, int32_t spp, int32_t num_levels,
+                              int32_t w, int32_t h, int32_t loss, float* dL_dimages,
+                              float* loss_out, float* composite);
 
 /* One AdamW step over `count` elements (Method: "Regularization"): m = b1 m + (1-b1) g;
  * v = b2 v + (1-b2) g^2; p = p (1 - lr wd); p = p - s1 m / (sqrt(v) s2 + eps) with
@@ -384,7 +387,8 @@ gsc_status gsc_scene_copy_state(gsc_ctx* ctx, gsc_scene* dst, const gsc_scene* s
 /* Resident bytes: the cell-corner grid (32 (nx+1)(ny+1)(nz+1)) + 3 x 14 fp32 per Gaussian
  * (parameters and two moments). */
 size_t gsc_scene_footprint_bytes(const gsc_scene* scene);
-/* Transient bytes one frame of w x h needs, for an instance estimate. */
+/* Transient bytes one frame of w x h at one sample per pixel needs, for an instance
+ * estimate; each further sample per pixel adds 20 bytes per pixel (its path records). */
 size_t gsc_frame_footprint_bytes(const gsc_scene* scene, int32_t w, int32_t h,
                                  uint64_t instance_estimate);
 

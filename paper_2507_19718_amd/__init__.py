@@ -250,8 +250,10 @@ def trace_params(seed: int, frame: int, spp: int, max_bounces: int, K: int, C: f
 def gsc_trace_targets(ctx: Context, vol: Volume, cam, params: gsc_trace_params,
                       targets: torch.Tensor, records: Optional[torch.Tensor] = None,
                       stats: bool = False):
-    """targets: [K][h][w][3] float32; records: [h][w][5] int32/uint32-sized tensor or None."""
+    """targets: [K][h][w][3] float32; records: [spp][h][w][5] 4-byte words, or None."""
     _f32_cuda(targets, "targets")
+    _check_bytes(targets, 12 * params.num_levels * cam.w * cam.h, "targets")
+    _check_bytes(records, 20 * params.spp * cam.w * cam.h, "records")
     vs = vol.struct()
     cs = camera_struct(cam)
     st = gsc_frame_stats() if stats else None
@@ -381,10 +383,20 @@ def gsc_splat_backward(ctx: Context, b: Binning, levels, cam, final_T, last_id, 
                                           _ptr(final_T), _ptr(last_id), _ptr(dL_dimages), garr))
 
 
+def _check_bytes(t: Optional[torch.Tensor], need: int, what: str):
+    if t is not None and t.numel() * t.element_size() < need:
+        raise ValueError(f"{what} holds {t.numel() * t.element_size()} bytes, needs {need}")
+
+
 def gsc_loss_composite(ctx: Context, images, targets, records, K: int, w: int, h: int, loss: int,
-                       dL_dimages, loss_out, composite=None):
+                       dL_dimages, loss_out, composite=None, spp: int = 1):
+    """records: [spp][h][w][5] 4-byte words (or None with composite None)."""
+    for t, name in ((images, "images"), (targets, "targets"), (dL_dimages, "dL_dimages")):
+        _check_bytes(t, 12 * K * w * h, name)
+    _check_bytes(records, 20 * spp * w * h, "records")
+    _check_bytes(composite, 12 * w * h, "composite")
     ctx.check(ctx._lib.gsc_loss_composite(ctx.handle, _ptr(images), _ptr(targets), _ptr(records),
-                                          K, w, h, loss, _ptr(dL_dimages), _ptr(loss_out),
+                                          spp, K, w, h, loss, _ptr(dL_dimages), _ptr(loss_out),
                                           _ptr(composite)))
 
 
@@ -505,10 +517,10 @@ def frame_request(cam, seed: int, frame: int, K: int, max_bounces: int, loss: in
                   train: bool = True, viewport_frames: int = 1,
                   lr=(1.16e-3, 1e-3, 0.0, 1.25e-2, 1.5e-1), beta1=0.9, beta2=0.999, eps=1e-8,
                   weight_decay=0.0, C: float = 0.5,
-                  strategy: int = STRATEGY_NEE) -> gsc_frame_request:
+                  strategy: int = STRATEGY_NEE, spp: int = 1) -> gsc_frame_request:
     r = gsc_frame_request()
     r.cam = camera_struct(cam)
-    r.trace = trace_params(seed, frame, 1, max_bounces, K, C, strategy=strategy)
+    r.trace = trace_params(seed, frame, spp, max_bounces, K, C, strategy=strategy)
     r.loss = loss
     r.train = 1 if train else 0
     r.viewport_frames = viewport_frames

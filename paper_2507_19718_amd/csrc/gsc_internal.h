@@ -65,7 +65,7 @@ struct TraceDesc {
   float eps;
   int64_t pix_off;      // first launch index of this request (a multiple of the block size)
   float* targets;       // [K][h][w][3]
-  void* records;        // [h][w] x 20 B or NULL
+  void* records;        // [spp][h][w] x 20 B or NULL
 };
 
 // Per-Gaussian projected record, 48 B, gathered by the splat kernels:
@@ -159,7 +159,7 @@ hipError_t launch_trace(hipStream_t st, const TraceDesc* descs, const int64_t* r
 
 int loss_num_partials(int64_t pixels);
 hipError_t launch_loss_composite(hipStream_t st, const float* images, const float* targets,
-                                 const void* records, int K, int w, int h, int loss,
+                                 const void* records, int spp, int K, int w, int h, int loss,
                                  float* dL_dimages, double* partials, float* loss_out,
                                  float* composite);
 // One AdamW parameter group of a fused multi-group step (hyper-parameters prepared on the host).

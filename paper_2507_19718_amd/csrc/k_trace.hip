@@ -412,6 +412,14 @@ __global__ void __launch_bounds__(kTraceBlock) trace_kernel(const TraceDesc* __r
       for (uint32_t smp = 0; smp < D.spp; ++smp) {
         const PathResult pr = trace_path(D, V, s_lights, s_spheres, px, py, smp);
         verts += pr.n;
+        if (D.records) {
+          uint32_t* rec = (uint32_t*)D.records + 5 * ((int64_t)smp * plane + lp);
+          rec[0] = __float_as_uint(pr.L0);
+          rec[1] = __float_as_uint(pr.L1);
+          rec[2] = __float_as_uint(pr.L2);
+          rec[3] = __float_as_uint(pr.beta);
+          rec[4] = pr.n | (pr.kind << 16);
+        }
         if (pr.n) {
           float* o = D.targets + 3 * ((min(pr.n, K) - 1u) * plane + lp);
           o[0] = o[0] + pr.L0;

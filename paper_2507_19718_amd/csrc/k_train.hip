@@ -13,7 +13,7 @@ constexpr int kLossThreads = 256;
 // summed afterwards in a fixed order.
 __global__ void __launch_bounds__(kLossThreads) loss_composite_kernel(
     const float* __restrict__ images, const float* __restrict__ targets,
-    const uint32_t* __restrict__ records, int K, int64_t P, int loss, float inv_k,
+    const uint32_t* __restrict__ records, int spp, int K, int64_t P, int loss, float inv_k,
     float* __restrict__ dL, double* __restrict__ partials, float* __restrict__ composite) {
   __shared__ double red[kLossThreads];
   const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -39,27 +39,34 @@ __global__ void __launch_bounds__(kLossThreads) loss_composite_kernel(
       }
     }
     if (composite) {
-      const uint32_t* rec = records + 5 * p;
-      const float L0 = __uint_as_float(rec[0]), L1 = __uint_as_float(rec[1]),
-                  L2 = __uint_as_float(rec[2]), beta = __uint_as_float(rec[3]);
-      const uint32_t n = rec[4] & 0xffffu, kind = rec[4] >> 16;
-      float o0 = 0.0f, o1 = 0.0f, o2 = 0.0f;
-      if (n >= 1u) {
-        const float lum = (0.2126f * L0 + 0.7152f * L1) + 0.0722f * L2;
-        const bool use_cache = (kind == (uint32_t)GSC_KIND_EARLY) || !(lum > 0.0f);
-        if (use_cache) {
-          const uint32_t lvl = (n < (uint32_t)K ? n : (uint32_t)K) - 1u;
-          const float* cv = images + 3 * ((int64_t)lvl * P + p);
-          o0 = fmaxf(cv[0], 0.0f) / beta;
-          o1 = fmaxf(cv[1], 0.0f) / beta;
-          o2 = fmaxf(cv[2], 0.0f) / beta;
-        } else {
-          o0 = L0; o1 = L1; o2 = L2;
+      // Per sample: the path's own radiance, or the cache of its length divided by beta; the
+      // pixel is the mean over samples, summed in sample order.
+      float a0 = 0.0f, a1 = 0.0f, a2 = 0.0f;
+      for (int smp = 0; smp < spp; ++smp) {
+        const uint32_t* rec = records + 5 * ((int64_t)smp * P + p);
+        const float L0 = __uint_as_float(rec[0]), L1 = __uint_as_float(rec[1]),
+                    L2 = __uint_as_float(rec[2]), beta = __uint_as_float(rec[3]);
+        const uint32_t n = rec[4] & 0xffffu, kind = rec[4] >> 16;
+        float o0 = 0.0f, o1 = 0.0f, o2 = 0.0f;
+        if (n >= 1u) {
+          const float lum = (0.2126f * L0 + 0.7152f * L1) + 0.0722f * L2;
+          const bool use_cache = (kind == (uint32_t)GSC_KIND_EARLY) || !(lum > 0.0f);
+          if (use_cache) {
+            const uint32_t lvl = (n < (uint32_t)K ? n : (uint32_t)K) - 1u;
+            const float* cv = images + 3 * ((int64_t)lvl * P + p);
+            o0 = fmaxf(cv[0], 0.0f) / beta;
+            o1 = fmaxf(cv[1], 0.0f) / beta;
+            o2 = fmaxf(cv[2], 0.0f) / beta;
+          } else {
+            o0 = L0; o1 = L1; o2 = L2;
+          }
         }
+        a0 = a0 + o0; a1 = a1 + o1; a2 = a2 + o2;
       }
-      composite[3 * p + 0] = o0;
-      composite[3 * p + 1] = o1;
-      composite[3 * p + 2] = o2;
+      const float fs = (float)spp;
+      composite[3 * p + 0] = a0 / fs;
+      composite[3 * p + 1] = a1 / fs;
+      composite[3 * p + 2] = a2 / fs;
     }
   }
   red[threadIdx.x] = acc;
@@ -131,7 +138,7 @@ __global__ void __launch_bounds__(256) adam_groups_kernel(const AdamGroup* __res
 int loss_num_partials(int64_t pixels) { return (int)((pixels + kLossThreads - 1) / kLossThreads); }
 
 hipError_t launch_loss_composite(hipStream_t st, const float* images, const float* targets,
-                                 const void* records, int K, int w, int h, int loss,
+                                 const void* records, int spp, int K, int w, int h, int loss,
                                  float* dL_dimages, double* partials, float* loss_out,
                                  float* composite) {
   const int64_t P = (int64_t)w * h;
@@ -140,7 +147,7 @@ hipError_t launch_loss_composite(hipStream_t st, const float* images, const floa
   const float kf = (float)(3.0 * (double)P);
   const float inv_k = 1.0f / kf;
   hipLaunchKernelGGL(loss_composite_kernel, dim3(nb), dim3(kLossThreads), 0, st, images, targets,
-                     (const uint32_t*)records, K, P, loss, inv_k, dL_dimages, partials, composite);
+                     (const uint32_t*)records, spp, K, P, loss, inv_k, dL_dimages, partials, composite);
   hipLaunchKernelGGL(loss_final_kernel, dim3(1), dim3(256), 0, st, partials, nb, inv_k, loss_out);
   return hipGetLastError();
 }

@@ -648,7 +648,7 @@ gsc_status render_batch(gsc_ctx* ctx, gsc_scene* const* scenes, const gsc_frame_
     check_camera(ctx, &reqs[i].cam);
     check_trace_params(ctx, &reqs[i].trace);
     if ((int)reqs[i].trace.num_levels != scenes[i]->K) invalid(ctx, "trace.num_levels must equal the scene's K");
-    if (reqs[i].trace.spp != 1) invalid(ctx, "frames trace 1 sample per pixel");
+    if (reqs[i].trace.spp > 4096) invalid(ctx, "frames trace at most 4096 samples per pixel");
     if (reqs[i].loss != 0 && reqs[i].loss != 1) invalid(ctx, "loss must be 0 (L2) or 1 (HDR)");
     if (reqs[i].viewport_frames < 1) invalid(ctx, "viewport_frames must be >= 1");
   }
@@ -678,7 +678,7 @@ gsc_status render_batch(gsc_ctx* ctx, gsc_scene* const* scenes, const gsc_frame_
     pix_base[i] = pix;
     rec_base[i] = rpix;
     pix += (int64_t)sc->K * reqs[i].cam.w * reqs[i].cam.h;
-    rpix += (int64_t)reqs[i].cam.w * reqs[i].cam.h;
+    rpix += (int64_t)reqs[i].trace.spp * reqs[i].cam.w * reqs[i].cam.h;
   }
   plan_batch(ctx, b, specs);
   const Alloc& a = ctx->alloc;
@@ -744,7 +744,7 @@ gsc_status render_batch(gsc_ctx* ctx, gsc_scene* const* scenes, const gsc_frame_
   GSC_TRY(launch_loss_composite(st, ctx->images.as<float>() + 3 * pix_base[i],
                                   ctx->targets.as<float>() + 3 * pix_base[i],
                                   (char*)ctx->records.p + sizeof(gsc_path_record) * rec_base[i],
-                                  scenes[i]->K, w, h, reqs[i].loss,
+                                  (int)reqs[i].trace.spp, scenes[i]->K, w, h, reqs[i].loss,
                                   ctx->dL.as<float>() + 3 * pix_base[i],
                                   ctx->partials.as<double>() + (size_t)max_partials * i,
                                   ctx->losses.as<float>() + i, images[i]));
@@ -814,7 +814,7 @@ gsc_status render_batch(gsc_ctx* ctx, gsc_scene* const* scenes, const gsc_frame_
       fs.instances = b->n_instances;
       fs.tiles = (uint64_t)b->n_tiles;
       fs.pixels = (uint64_t)reqs[i].cam.w * reqs[i].cam.h;
-      fs.paths = fs.pixels;
+      fs.paths = fs.pixels * reqs[i].trace.spp;
       fs.path_vertices = ctx->host_u64[1];
       fs.loss = (double)losses[i];
       fs.adam_skipped = (reqs[i].train && !std::isfinite(losses[i])) ? 1 : 0;
@@ -934,7 +934,6 @@ gsc_status gsc_trace_targets(gsc_ctx* ctx, const gsc_volume* vol, const gsc_came
     check_camera(ctx, cam);
     check_trace_params(ctx, params);
     if (!targets) invalid(ctx, "targets is NULL");
-    if (records && params->spp != 1) invalid(ctx, "records require spp == 1");
     TraceDesc d = make_trace_desc(vol->density, nullptr, vol->nx, vol->ny, vol->nz, vol->density_max,
                                   vol->tf_rgba, vol->tf_points, vol->lights, vol->n_lights,
                                   vol->spheres, vol->n_spheres, *cam, *params);
@@ -1102,18 +1101,19 @@ gsc_status gsc_splat_backward(gsc_ctx* ctx, const gsc_binning* bin, const gsc_ga
 }
 
 gsc_status gsc_loss_composite(gsc_ctx* ctx, const float* images, const float* targets,
-                              const gsc_path_record* records, int32_t num_levels, int32_t w,
-                              int32_t h, int32_t loss, float* dL_dimages, float* loss_out,
-                              float* composite) {
+                              const gsc_path_record* records, int32_t spp, int32_t num_levels,
+                              int32_t w, int32_t h, int32_t loss, float* dL_dimages,
+                              float* loss_out, float* composite) {
   return guarded(ctx, [&]() -> gsc_status {
     if (!images || !targets || !dL_dimages || !loss_out) invalid(ctx, "NULL argument");
+    if (spp < 1) invalid(ctx, "spp must be >= 1");
     if (num_levels < 1 || num_levels > 8) invalid(ctx, "num_levels must be in [1, 8]");
     if (w < 1 || h < 1 || w > 16384 || h > 16384) invalid(ctx, "image size out of range");
     if (loss != 0 && loss != 1) invalid(ctx, "loss must be 0 or 1");
     if ((records == nullptr) != (composite == nullptr)) invalid(ctx, "records and composite go together");
     const int np = loss_num_partials((int64_t)w * h);
     need(ctx, ctx->partials, ctx->alloc, 8 * (size_t)np, "loss partials");
-    GSC_TRY(launch_loss_composite(ctx->stream, images, targets, records, num_levels, w, h, loss,
+    GSC_TRY(launch_loss_composite(ctx->stream, images, targets, records, spp, num_levels, w, h, loss,
                                   dL_dimages, ctx->partials.as<double>(), loss_out, composite));
     return GSC_OK;
   });

@@ -9,7 +9,7 @@ caches, `gsc_render_frame` for cached frames (trace + splat + train + composite)
 `gsc_trace_targets` for the references (no early termination, many samples per pixel).
 
     python -m paper_2507_19718_amd.experiments [--workload orbit1k] [--lights point|area]
-        [--what C,cold,ablation,estimators]
+        [--what C,cold,ablation,estimators,spp]
 
 prints one JSON object per study.
 """
@@ -44,11 +44,11 @@ def reference_radiance(ctx: Context, vol: Volume, cam, K: int, B: int, seed: int
 
 
 def path_traced(ctx: Context, vol: Volume, cam, K: int, B: int, seed: int, frame: int,
-                strategy: int = STRATEGY_NEE) -> torch.Tensor:
-    """One 1-spp path-traced image (no cache): the uncached baseline, with next-event
-    estimation (MIS for area lights) or phase sampling only."""
+                strategy: int = STRATEGY_NEE, spp: int = 1) -> torch.Tensor:
+    """A path-traced image (no cache) at `spp` samples per pixel: the uncached baseline, with
+    next-event estimation (MIS for area lights) or phase sampling only."""
     tg = torch.empty((K, cam.h, cam.w, 3), device="cuda")
-    gsc_trace_targets(ctx, vol, cam, trace_params(seed, frame, 1, B, K, C=math.inf, strategy=strategy), tg)
+    gsc_trace_targets(ctx, vol, cam, trace_params(seed, frame, spp, B, K, C=math.inf, strategy=strategy), tg)
     return tg.sum(0)
 
 
@@ -181,6 +181,43 @@ def study_estimators(ctx, wl, gv, init_levels, ref, cam, warm: int = 32, measure
     return {"study": "estimators", "measured_frames": measure, "results": out}
 
 
+def study_spp(ctx, wl, gv, init_levels, ref, cam, spps=(1, 2, 4, 8, 16, 32, 64), warm: int = 16,
+              measure: int = 8) -> Dict:
+    """Cost and error against samples per pixel: per spp, cached frames (static camera, `warm`
+    then `measure` frames) with the frame statistics' times, and the composite MSE, next to
+    uncached next-event-estimation path tracing at the same spp.  The cache stages run once per
+    frame whatever spp is, concurrently with the trace (a second stream), so the stage times
+    overlap the trace; the time the cache adds to a frame is its total minus the trace."""
+    rows = []
+    for spp in spps:
+        scene = fresh_scene(ctx, gv, init_levels)
+        img = torch.empty((cam.h, cam.w, 3), device="cuda")
+        acc = {k: 0.0 for k in ("ms_trace", "ms_project_bin", "ms_forward", "ms_loss",
+                                "ms_backward", "ms_adam", "ms_total")}
+        err = 0.0
+        for i in range(warm + measure):
+            req = frame_request(cam, wl.seed, i, wl.K, wl.max_bounces, loss=wl.loss, lr=wl.lr,
+                                weight_decay=wl.weight_decay, C=wl.C, viewport_frames=i + 1, spp=spp)
+            st = gsc_render_frame(ctx, scene, req, img, stats=True)
+            if i >= warm:
+                for k in acc:
+                    acc[k] += st[k] / measure
+                err += mse(img, ref) / measure
+        scene.destroy()
+        pt_err, pt_ms = 0.0, 0.0
+        for f in range(measure):
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            img_pt = path_traced(ctx, gv, cam, wl.K, wl.max_bounces, wl.seed, 80_000 + f, spp=spp)
+            torch.cuda.synchronize()
+            pt_ms += (time.perf_counter() - t) * 1e3 / measure
+            pt_err += mse(img_pt, ref) / measure
+        rows.append({"spp": spp, **{k: round(v, 3) for k, v in acc.items()},
+                     "ms_added_by_cache": round(acc["ms_total"] - acc["ms_trace"], 3), "mse_cached": err,
+                     "mse_path_traced": pt_err, "ms_path_traced": round(pt_ms, 3)})
+    return {"study": "spp", "warm_frames": warm, "measured_frames": measure, "rows": rows}
+
+
 def main():
     import synth
     ap = argparse.ArgumentParser()
@@ -213,6 +250,8 @@ def main():
         print(json.dumps({**head, **study_C(ctx, wl, vol, gv, init_levels, ref, cam)}), flush=True)
     if "cold" in what:
         print(json.dumps({**head, **study_cold_start(ctx, wl, vol, gv, init_levels, ref, cam)}), flush=True)
+    if "spp" in what:
+        print(json.dumps({**head, **study_spp(ctx, wl, gv, init_levels, ref, cam)}), flush=True)
     if "estimators" in what:
         print(json.dumps({**head, **study_estimators(ctx, wl, gv, init_levels, ref, cam)}), flush=True)
     if "ablation" in what:

@@ -109,9 +109,11 @@ def test_area_light_arguments_validated(gsc, gctx):
         gpu_trace(gsc, gctx, area_volume(wl), cam, 1, 0, 1, 3, 1, 0.5, 2)
 
 
-def test_scene_with_area_lights_matches_oracle_frame(gsc, gctx):
+@pytest.mark.parametrize("spp", [1, 4])
+def test_scene_with_area_lights_matches_oracle_frame(gsc, gctx, spp):
     """A resident scene built with point lights, its lights then replaced by sphere lights: two
-    training frames match the oracle pipeline (loss, composite, parameters)."""
+    training frames (1 and 4 samples per pixel) match the oracle pipeline (loss, composite,
+    parameters)."""
     wl = synth.workload("tiny")
     vol = wl.volume()
     cam = wl.camera()
@@ -128,9 +130,11 @@ def test_scene_with_area_lights_matches_oracle_frame(gsc, gctx):
             state.append(dict(params=to_np(s["params"]), m=to_np(s["m"]), v=to_np(s["v"]), step=s["step"]))
         cur = [unpack(state[l]["params"], levels_np[l].n) for l in range(K)]
         req = gsc.frame_request(cam, wl.seed, frame, K, wl.max_bounces, loss=wl.loss, lr=wl.lr,
-                                weight_decay=wl.weight_decay, C=wl.C)
+                                weight_decay=wl.weight_decay, C=wl.C, spp=spp)
         stats = gsc.gsc_render_frame(gctx, scene, req, image, stats=True)
-        ref = oracle_frame(state, cur, area, cam, wl, frame, K, wl.loss, wl.lr, wl.weight_decay, 1)
+        assert stats["paths"] == spp * cam.w * cam.h
+        ref = oracle_frame(state, cur, area, cam, wl, frame, K, wl.loss, wl.lr, wl.weight_decay, 1,
+                           spp=spp)
         assert abs(stats["loss"] - ref["loss"]) <= 1e-4 * abs(ref["loss"]), (frame, stats["loss"], ref["loss"])
         okpix = ~ref["boundary"].any(0)
         assert rel_l2(to_np(image)[okpix], ref["composite"][okpix]) <= 1e-5

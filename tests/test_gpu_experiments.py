@@ -70,3 +70,15 @@ def test_estimator_study_with_area_lights(env):
     assert set(res) == {"PT_uniform", "PT_nee", "GSCache"}
     assert all(math.isfinite(v["mse"]) for v in res.values())
     assert res["PT_nee"]["mse"] < res["PT_uniform"]["mse"]
+
+
+def test_spp_study_cache_cost_constant(env):
+    """Several samples per pixel: the cache stages cost the same at 1 and 8 spp (they run once
+    per frame), the trace does not."""
+    ex, e = env["ex"], env
+    ref = ex.reference_radiance(e["ctx"], e["gv"], e["cam"], e["wl"].K, e["wl"].max_bounces, 7, spp=128)
+    r = ex.study_spp(e["ctx"], e["wl"], e["gv"], e["init"], ref, e["cam"], spps=(1, 8), warm=2, measure=3)
+    a, b = r["rows"]
+    assert (a["spp"], b["spp"]) == (1, 8)
+    assert all(math.isfinite(x["mse_cached"]) and math.isfinite(x["mse_path_traced"]) for x in (a, b))
+    assert b["mse_path_traced"] < a["mse_path_traced"]

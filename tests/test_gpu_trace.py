@@ -97,9 +97,24 @@ def test_trace_targets_one_level_per_pixel_and_records(gsc, gctx):
     assert (beta > 0).all() and (beta <= 1).all()
 
 
-def test_trace_rejects_records_with_spp(gsc, gctx):
+def test_trace_records_every_sample(gsc, gctx):
+    """Several samples per pixel: one record per path, [spp][h][w], as the oracle's."""
     wl = synth.workload("tiny")
     vol = wl.volume()
-    cam = wl.camera()
-    with pytest.raises(gsc.GscError):
-        gpu_trace(gsc, gctx, vol, cam, 1, 0, 4, 3, 1, 0.5, records=True)
+    cam = wl.camera().crop(16, 24, 80, 72)
+    spp, K = 4, 3
+    tg = torch.empty((K, cam.h, cam.w, 3), device="cuda")
+    rec = torch.empty((spp, cam.h, cam.w, 5), dtype=torch.int32, device="cuda")
+    gsc.gsc_trace_targets(gctx, gsc.Volume.from_synth(vol), cam,
+                          gsc.trace_params(11, 2, spp, 3, K, 0.5), tg, rec)
+    ora = oracle.trace(vol, cam, 11, 2, spp, 3, K, C=0.5)
+    r = to_np(rec).view(np.uint32)
+    same = np.all(r[..., :3].view(np.float32) == ora["L"], axis=-1) & \
+        (r[..., 3].view(np.float32) == ora["beta"]) & \
+        ((r[..., 4] & 0xFFFF) == ora["n"]) & ((r[..., 4] >> 16) == ora["kind"])
+    assert same.mean() >= 0.999, same.mean()
+    assert np.mean(np.all(to_np(tg) == ora["targets"], axis=(0, 3))) >= 0.999
+    # A record buffer for fewer samples is refused on the host before any launch.
+    with pytest.raises(ValueError):
+        gsc.gsc_trace_targets(gctx, gsc.Volume.from_synth(vol), cam,
+                              gsc.trace_params(11, 2, spp, 3, K, 0.5), tg, rec[:2])

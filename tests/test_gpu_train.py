@@ -26,17 +26,18 @@ def gctx(gsc):
     return gsc.Context(0)
 
 
-@pytest.mark.parametrize("hdr", [0, 1])
-def test_loss_and_composite(gsc, gctx, hdr):
-    rng = np.random.default_rng(hdr)
+@pytest.mark.parametrize("hdr,spp", [(0, 1), (1, 1), (1, 5)])
+def test_loss_and_composite(gsc, gctx, hdr, spp):
+    rng = np.random.default_rng(hdr + 10 * spp)
     K, h, w = 3, 37, 53
     images = rng.normal(0.3, 0.5, size=(K, h, w, 3)).astype(np.float32)
     targets = np.maximum(rng.normal(0.3, 0.6, size=(K, h, w, 3)), 0).astype(np.float32)
-    n = rng.integers(0, 6, size=(h, w)).astype(np.uint32)
-    kind = np.where(n == 0, 0, rng.integers(1, 4, size=(h, w))).astype(np.uint32)
-    L = np.where(rng.random((h, w, 1)) < 0.3, 0.0, rng.uniform(0, 2, (h, w, 3))).astype(np.float32)
-    beta = rng.uniform(0.05, 1.0, size=(h, w)).astype(np.float32)
-    rec = np.zeros((h, w, 5), np.uint32)
+    shp = (spp, h, w) if spp > 1 else (h, w)
+    n = rng.integers(0, 6, size=shp).astype(np.uint32)
+    kind = np.where(n == 0, 0, rng.integers(1, 4, size=shp)).astype(np.uint32)
+    L = np.where(rng.random(shp + (1,)) < 0.3, 0.0, rng.uniform(0, 2, shp + (3,))).astype(np.float32)
+    beta = rng.uniform(0.05, 1.0, size=shp).astype(np.float32)
+    rec = np.zeros(shp + (5,), np.uint32)
     rec[..., :3] = L.view(np.uint32)
     rec[..., 3] = beta.view(np.uint32)
     rec[..., 4] = n | (kind << 16)
@@ -45,7 +46,7 @@ def test_loss_and_composite(gsc, gctx, hdr):
     loss = torch.empty(1, device="cuda")
     comp = torch.empty((h, w, 3), device="cuda")
     gsc.gsc_loss_composite(gctx, dev(images), dev(targets), dev(rec.view(np.int32)), K, w, h, hdr,
-                           dL, loss, comp)
+                           dL, loss, comp, spp=spp)
     ref_loss, ref_g = oracle.loss_grad(images, targets, hdr=bool(hdr))
     assert abs(float(loss.item()) - ref_loss) <= 1e-5 * abs(ref_loss)
     assert np.max(np.abs(to_np(dL) - ref_g) / np.maximum(np.abs(ref_g), 1e-30)) <= 1e-6
@@ -69,7 +70,7 @@ def test_adam_bit_exact(gsc, gctx):
     assert np.array_equal(to_np(tp), p) and np.array_equal(to_np(tm), m) and np.array_equal(to_np(tv), v)
 
 
-def oracle_frame(state, levels_np, vol, cam, wl, frame, K, loss, lrs, wd, t_view):
+def oracle_frame(state, levels_np, vol, cam, wl, frame, K, loss, lrs, wd, t_view, spp=1):
     """One frame of the oracle pipeline from a given state (per level: params/m/v/step)."""
     projs, fws, images = [], [], []
     for g in levels_np:
@@ -79,7 +80,7 @@ def oracle_frame(state, levels_np, vol, cam, wl, frame, K, loss, lrs, wd, t_view
         fws.append(fw)
         images.append(fw["image"])
     images = np.stack(images)
-    tr = oracle.trace(vol, cam, wl.seed, frame, 1, wl.max_bounces, K, C=wl.C)
+    tr = oracle.trace(vol, cam, wl.seed, frame, spp, wl.max_bounces, K, C=wl.C)
     lval, dL = oracle.loss_grad(images, tr["targets"], hdr=bool(loss))
     comp = oracle.composite(tr["n"], tr["kind"], tr["L"], tr["beta"], images)
     new_levels = []
