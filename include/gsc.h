@@ -231,6 +231,13 @@ void gsc_ctx_destroy(gsc_ctx* ctx);
 const char* gsc_ctx_last_error(const gsc_ctx* ctx);
 gsc_status gsc_ctx_set_stream(gsc_ctx* ctx, void* hip_stream);
 gsc_status gsc_ctx_set_deterministic(gsc_ctx* ctx, int32_t on);
+/* Frames (gsc_render_frame / gsc_render_frames) bin each tile's list only up to the depth by
+ * which every pixel of the tile has surely stopped blending (on by default): a Gaussian whose
+ * splat gives alpha >= o/2 over all pixels of a tile multiplies their transmittance by at most
+ * 1 - o/2, and once these factors reach 0.5e-4 no later entry can be blended (blending stops
+ * below 1e-4), so the cut lists give the same images, gradients and parameter updates as the
+ * full ones with fewer instances.  gsc_project_bin always builds full lists. */
+gsc_status gsc_ctx_set_list_cut(gsc_ctx* ctx, int32_t on);
 /* After GSC_E_CAPACITY: the instance count the failed call needed. */
 uint64_t gsc_ctx_required_capacity(const gsc_ctx* ctx);
 /* Per-kernel timing: while on, every kernel launch of the context is bracketed by HIP events

@@ -148,6 +148,10 @@ class Context:
             idx += 1
         return out
 
+    def set_list_cut(self, on: bool):
+        """Frames bin only the list prefixes that can reach a pixel (default on)."""
+        self.check(self._lib.gsc_ctx_set_list_cut(self.handle, 1 if on else 0))
+
     def counters(self):
         c = _abi.gsc_counters()
         self.check(self._lib.gsc_ctx_counters(self.handle, ctypes.byref(c)))

@@ -16,6 +16,16 @@
 //            per wavefront and one tile per lane; the wave walks the chunk's rectangles in depth
 //            order and every covered lane appends the id to its tile's run, so within a tile
 //            ids come out in (depth, id) order (details at the kernel).
+//
+// Optional list cut (frames): front-to-back blending stops at a pixel once its transmittance
+// would fall below 1e-4, so the entries of a tile's list behind the point where every pixel of
+// the tile has surely stopped are never read.  Each Gaussian carries a saturation core (the
+// tiles where it multiplies every unterminated pixel's transmittance by at most 1 - o/2, see the
+// projection) and its weight -ln(1 - o/2); the count pass also sums the weights per
+// (chunk, tile), and the scan keeps, per tile, the chunks up to the first one at which the
+// running weight reaches -ln(0.5e-4): from there on every pixel of the tile has stopped, with a
+// factor 2 to spare for rounding.  Placement skips the later chunks, so the cut lists give the
+// same splat forward and backward results as the full ones.
 #include "gsc_dev.h"
 
 namespace gsc {
@@ -39,58 +49,33 @@ struct BinWork {          // per segment, for the workgroup -> work item maps
 // floor(kDiffWords / TX) tile rows.
 constexpr int kDiffWords = 12288;
 
+// -ln(0.5e-4) in the 2^-16 units of the saturation weights.
+constexpr uint32_t kCutWeight = 649035u;
+
 __global__ void __launch_bounds__(256) gather_rect_kernel(const int64_t* __restrict__ seg_gstart,
                                                           int S, int64_t G,
                                                           const uint32_t* __restrict__ sorted_ids,
                                                           const uint64_t* __restrict__ rect,
-                                                          uint64_t* __restrict__ rect_sorted) {
+                                                          uint64_t* __restrict__ rect_sorted,
+                                                          const uint64_t* __restrict__ core,
+                                                          const uint32_t* __restrict__ core_w,
+                                                          uint64_t* __restrict__ core_sorted,
+                                                          uint32_t* __restrict__ w_sorted) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= G) return;
   const int s = find_segment(seg_gstart, S, i);
-  rect_sorted[i] = rect[seg_gstart[s] + sorted_ids[i]];
+  const int64_t src = seg_gstart[s] + sorted_ids[i];
+  rect_sorted[i] = rect[src];
+  if (core) {
+    core_sorted[i] = core[src];
+    w_sorted[i] = core_w[src];
+  }
 }
 
-// One workgroup per (segment, chunk, band of tile rows): counts[chunk][tile] = the number of the
-// chunk's tile rectangles that contain the tile, for every tile of the band.
-__global__ void __launch_bounds__(256) bin_count_kernel(const BinWork* __restrict__ work,
-                                                        const int64_t* __restrict__ block_start,
-                                                        int S, int64_t total_blocks,
-                                                        const uint64_t* __restrict__ rect_sorted,
-                                                        uint32_t* __restrict__ counts) {
-  __shared__ int32_t D[kDiffWords];
-  const int64_t blk = blockIdx.x;
-  if (blk >= total_blocks) return;
-  const int s = find_segment(block_start, S, blk);
-  const BinWork W = work[s];
-  const int64_t l = blk - W.count_start;
-  const int band = (int)(l % W.n_bands);
-  const int c = (int)(l / W.n_bands);
-  const int TX = W.TX;
-  const int b0 = band * W.band_rows;
-  const int R = min(W.band_rows, W.TY - b0);
-  const int words = R * TX;
-  for (int k = threadIdx.x; k < words; k += 256) D[k] = 0;
-  __syncthreads();
-  const int64_t g0 = (int64_t)c * kChunk;
-  const int cnt_g = (int)((W.n - g0) < kChunk ? (W.n - g0) : kChunk);
-  const uint64_t* rs = rect_sorted + W.g_off + g0;
-  for (int k = threadIdx.x; k < cnt_g; k += 256) {
-    const uint64_t r = rs[k];
-    const int tx0 = (int)(r & 0xffffu), tx1 = (int)((r >> 16) & 0xffffu);
-    const int ty0 = (int)((r >> 32) & 0xffffu), ty1 = (int)(r >> 48);
-    if (tx0 > tx1) continue;                       // culled (empty rectangle)
-    const int y0 = max(ty0, b0) - b0, y1 = min(ty1, b0 + R - 1) - b0;
-    if (y0 > y1) continue;                         // outside the band
-    const bool right = tx1 + 1 < TX, below = y1 + 1 < R;
-    atomicAdd(&D[y0 * TX + tx0], 1);
-    if (right) atomicAdd(&D[y0 * TX + tx1 + 1], -1);
-    if (below) {
-      atomicAdd(&D[(y1 + 1) * TX + tx0], -1);
-      if (right) atomicAdd(&D[(y1 + 1) * TX + tx1 + 1], 1);
-    }
-  }
-  __syncthreads();
-  for (int x = threadIdx.x; x < TX; x += 256) {    // down the columns
+// 2D prefix sum in place of a band's difference array D[R][TX] (down the columns, then along
+// the rows, one wavefront per row).  Ends with a barrier.
+__device__ __forceinline__ void band_prefix_sum(int32_t* D, int R, int TX) {
+  for (int x = threadIdx.x; x < TX; x += 256) {
     int run = 0;
     for (int y = 0; y < R; ++y) {
       run += D[y * TX + x];
@@ -99,7 +84,7 @@ __global__ void __launch_bounds__(256) bin_count_kernel(const BinWork* __restric
   }
   __syncthreads();
   const int lane = __lane_id();
-  for (int y = threadIdx.x >> 6; y < R; y += 4) {  // along the rows, one wavefront per row
+  for (int y = threadIdx.x >> 6; y < R; y += 4) {
     int carry = 0;
     for (int xb = 0; xb < TX; xb += 64) {
       const int x = xb + lane;
@@ -114,8 +99,71 @@ __global__ void __launch_bounds__(256) bin_count_kernel(const BinWork* __restric
     }
   }
   __syncthreads();
-  uint32_t* out = counts + W.ct_off + (int64_t)c * ((int64_t)TX * W.TY) + (int64_t)b0 * TX;
-  for (int k = threadIdx.x; k < words; k += 256) out[k] = (uint32_t)D[k];
+}
+
+// Adds w at the corners of the rectangle's part inside the band (rows b0 .. b0 + R - 1).
+__device__ __forceinline__ void band_rect_add(int32_t* D, uint64_t r, int w, int b0, int R, int TX) {
+  const int tx0 = (int)(r & 0xffffu), tx1 = (int)((r >> 16) & 0xffffu);
+  const int ty0 = (int)((r >> 32) & 0xffffu), ty1 = (int)(r >> 48);
+  if (tx0 > tx1) return;                         // culled (empty rectangle)
+  const int y0 = max(ty0, b0) - b0, y1 = min(ty1, b0 + R - 1) - b0;
+  if (y0 > y1) return;                           // outside the band
+  const bool right = tx1 + 1 < TX, below = y1 + 1 < R;
+  atomicAdd(&D[y0 * TX + tx0], w);
+  if (right) atomicAdd(&D[y0 * TX + tx1 + 1], -w);
+  if (below) {
+    atomicAdd(&D[(y1 + 1) * TX + tx0], -w);
+    if (right) atomicAdd(&D[(y1 + 1) * TX + tx1 + 1], w);
+  }
+}
+
+// One workgroup per (segment, chunk, band of tile rows): counts[chunk][tile] = the number of the
+// chunk's tile rectangles that contain the tile, for every tile of the band; with wsum, also
+// wsum[chunk][tile] = the sum of the weights of the chunk's saturation cores that contain it.
+__global__ void __launch_bounds__(256) bin_count_kernel(const BinWork* __restrict__ work,
+                                                        const int64_t* __restrict__ block_start,
+                                                        int S, int64_t total_blocks,
+                                                        const uint64_t* __restrict__ rect_sorted,
+                                                        uint32_t* __restrict__ counts,
+                                                        const uint64_t* __restrict__ core_sorted,
+                                                        const uint32_t* __restrict__ w_sorted,
+                                                        uint32_t* __restrict__ wsum) {
+  __shared__ int32_t D[kDiffWords];
+  const int64_t blk = blockIdx.x;
+  if (blk >= total_blocks) return;
+  const int s = find_segment(block_start, S, blk);
+  const BinWork W = work[s];
+  const int64_t l = blk - W.count_start;
+  const int band = (int)(l % W.n_bands);
+  const int c = (int)(l / W.n_bands);
+  const int TX = W.TX;
+  const int b0 = band * W.band_rows;
+  const int R = min(W.band_rows, W.TY - b0);
+  const int words = R * TX;
+  const int64_t g0 = (int64_t)c * kChunk;
+  const int cnt_g = (int)((W.n - g0) < kChunk ? (W.n - g0) : kChunk);
+  const int64_t out_off = W.ct_off + (int64_t)c * ((int64_t)TX * W.TY) + (int64_t)b0 * TX;
+  for (int k = threadIdx.x; k < words; k += 256) D[k] = 0;
+  __syncthreads();
+  const uint64_t* rs = rect_sorted + W.g_off + g0;
+  for (int k = threadIdx.x; k < cnt_g; k += 256) band_rect_add(D, rs[k], 1, b0, R, TX);
+  __syncthreads();
+  band_prefix_sum(D, R, TX);
+  for (int k = threadIdx.x; k < words; k += 256) {
+    counts[out_off + k] = (uint32_t)D[k];
+    D[k] = 0;
+  }
+  if (!wsum) return;
+  __syncthreads();
+  const uint64_t* cs = core_sorted + W.g_off + g0;
+  const uint32_t* ws = w_sorted + W.g_off + g0;
+  for (int k = threadIdx.x; k < cnt_g; k += 256) {
+    const int w = (int)ws[k];
+    if (w) band_rect_add(D, cs[k], w, b0, R, TX);
+  }
+  __syncthreads();
+  band_prefix_sum(D, R, TX);
+  for (int k = threadIdx.x; k < words; k += 256) wsum[out_off + k] = (uint32_t)D[k];
 }
 
 // Placement.  One workgroup per (segment, group of kPlaceChunks consecutive chunks, 16x16-tile
@@ -133,15 +181,18 @@ __global__ void __launch_bounds__(256) bin_count_kernel(const BinWork* __restric
 constexpr int kRegion = 16;      // tiles per region side
 constexpr int kQueue = 128;      // compaction queue entries per wave (a ring)
 constexpr int kPlaceChunks = 1;  // chunks per placement workgroup
+static_assert(kPlaceChunks == 1, "the list cut decides a tile's liveness once per workgroup");
 
 __device__ __forceinline__ uint32_t lane_rank(uint64_t m) {
   return __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
 }
 
-// Places n <= 64 queued Gaussians (lane i holds entry i) into the runs of the wave's tiles.
+// Places n <= 64 queued Gaussians (lane i holds entry i) into the runs of the wave's live tiles
+// (bit t of `live_t`: tile (ox + (t & 15), oy + (t >> 4)), whose cursor lane t holds), all
+// inside [bx0, bx1] x [by0, by1].
 __device__ __forceinline__ void place_batch(uint32_t* __restrict__ values, uint64_t& cur, int lane,
-                                            int n, uint64_t r, uint32_t id, int bx0, int by0,
-                                            int bx1, int by1) {
+                                            int n, uint64_t r, uint32_t id, int ox, int oy,
+                                            uint64_t live_t, int bx0, int by0, int bx1, int by1) {
   const bool live = lane < n;
   const uint32_t xr = (uint32_t)r, yr = (uint32_t)(r >> 32);
   const int tx0 = (int)(xr & 0xffffu), tx1 = (int)(xr >> 16);
@@ -164,9 +215,10 @@ __device__ __forceinline__ void place_batch(uint32_t* __restrict__ values, uint6
     const bool rowin = live && ty0 <= ty && ty <= ty1;
     for (int tx = x0; tx <= x1; ++tx) {
       const bool cov = rowin && tx0 <= tx && tx <= tx1;
+      const int t = (tx - ox) + 16 * (ty - oy);
+      if (!((live_t >> t) & 1ull)) continue;
       const uint64_t m = __ballot(cov);
       if (m == 0ull) continue;
-      const int t = (tx - bx0) + 16 * (ty - by0);
       const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)cur, t);
       const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(cur >> 32), t);
       const uint64_t base = ((uint64_t)hi << 32) | lo;
@@ -185,7 +237,8 @@ __global__ void __launch_bounds__(256) bin_place_kernel(const BinWork* __restric
                                                         const uint64_t* __restrict__ tile_start,
                                                         const uint64_t* __restrict__ n_instances,
                                                         uint64_t capacity,
-                                                        uint32_t* __restrict__ values) {
+                                                        uint32_t* __restrict__ values,
+                                                        const int32_t* __restrict__ cut) {
   __shared__ uint64_t sh_rect[kChunk];
   __shared__ uint32_t sh_id[kChunk];
   __shared__ uint64_t q_rect[4][kQueue];
@@ -208,16 +261,40 @@ __global__ void __launch_bounds__(256) bin_place_kernel(const BinWork* __restric
   const int rx = region % RX, ry = region / RX;
   const int c0 = cg * kPlaceChunks;
   const int c1 = min(c0 + kPlaceChunks, W.n_chunks);
-  const int bx0 = rx * kRegion, by0 = ry * kRegion + 4 * wave;
-  const bool wave_live = by0 < W.TY;
-  const int bx1 = min(bx0 + kRegion, W.TX) - 1, by1 = min(by0 + 4, W.TY) - 1;
-  // Lane t's tile cursor: where the tile's run continues (first, chunk c0's run).
+  const int ox = rx * kRegion, oy = ry * kRegion + 4 * wave;   // the wave's block origin
+  int bx0 = ox, by0 = oy;
+  int bx1 = min(bx0 + kRegion, W.TX) - 1, by1 = min(by0 + 4, W.TY) - 1;
+  // Lane t's tile cursor: where the tile's run continues (first, chunk c0's run).  With a list
+  // cut, only the tiles whose lists still take chunk c0 are live.
   uint64_t cur = 0ull;
+  bool tile_live = false;
   {
     const int col = bx0 + (lane & 15), row = by0 + (lane >> 4);
-    if (wave_live && col <= bx1 && row <= by1)
-      cur = tile_start[W.tile_base + (int64_t)row * W.TX + col] +
-            counts[W.ct_off + (int64_t)c0 * ((int64_t)W.TX * W.TY) + (int64_t)row * W.TX + col];
+    if (by0 < W.TY && col <= bx1 && row <= by1) {
+      const int64_t tl = (int64_t)row * W.TX + col;
+      cur = tile_start[W.tile_base + tl] +
+            counts[W.ct_off + (int64_t)c0 * ((int64_t)W.TX * W.TY) + tl];
+      tile_live = !cut || c0 <= cut[W.tile_base + tl];
+    }
+  }
+  const uint64_t live_tiles = __ballot(tile_live);
+  const bool wave_live = live_tiles != 0ull;
+  if (!__syncthreads_or(wave_live)) return;    // every tile of the region is cut here
+  if (wave_live && cut) {
+    // Shrink the block to the bounding box of its live tiles (lane t = tile (t & 15, t >> 4)).
+    int lx0 = tile_live ? (lane & 15) : 16, lx1 = tile_live ? (lane & 15) : -1;
+    int ly0 = tile_live ? (lane >> 4) : 4, ly1 = tile_live ? (lane >> 4) : -1;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+      lx0 = min(lx0, __shfl_xor(lx0, off, 64));
+      lx1 = max(lx1, __shfl_xor(lx1, off, 64));
+      ly0 = min(ly0, __shfl_xor(ly0, off, 64));
+      ly1 = max(ly1, __shfl_xor(ly1, off, 64));
+    }
+    bx0 = ox + __builtin_amdgcn_readfirstlane(lx0);
+    bx1 = ox + __builtin_amdgcn_readfirstlane(lx1);
+    by0 = oy + __builtin_amdgcn_readfirstlane(ly0);
+    by1 = oy + __builtin_amdgcn_readfirstlane(ly1);
   }
   uint64_t* qr = q_rect[wave];
   uint32_t* qi = q_id[wave];
@@ -258,7 +335,7 @@ __global__ void __launch_bounds__(256) bin_place_kernel(const BinWork* __restric
         const uint64_t qrr = qr[(head + lane) & (kQueue - 1)];
         const uint32_t qid = qi[(head + lane) & (kQueue - 1)];
         head += 64;
-        place_batch(values, cur, lane, 64, qrr, qid, bx0, by0, bx1, by1);
+        place_batch(values, cur, lane, 64, qrr, qid, ox, oy, live_tiles, bx0, by0, bx1, by1);
       }
     }
   }
@@ -271,30 +348,42 @@ __global__ void __launch_bounds__(256) bin_place_kernel(const BinWork* __restric
       qrr = qr[(head + lane) & (kQueue - 1)];
       qid = qi[(head + lane) & (kQueue - 1)];
     }
-    place_batch(values, cur, lane, n, qrr, qid, bx0, by0, bx1, by1);
+    place_batch(values, cur, lane, n, qrr, qid, ox, oy, live_tiles, bx0, by0, bx1, by1);
   }
 }
 
-// Per tile: exclusive scan over chunks (in place) and the tile total.
+// Per tile: exclusive scan over chunks (in place) and the tile total.  With wsum, chunks after
+// the one at which the running saturation weight reaches kCutWeight add nothing, and cut[tile]
+// is the last chunk kept.
 __global__ void __launch_bounds__(256) chunk_scan_kernel(const BinWork* __restrict__ work,
                                                          const int64_t* __restrict__ seg_tstart,
                                                          int S, int64_t n_tiles,
                                                          uint32_t* __restrict__ counts,
-                                                         uint32_t* __restrict__ tile_total) {
+                                                         uint32_t* __restrict__ tile_total,
+                                                         const uint32_t* __restrict__ wsum,
+                                                         int32_t* __restrict__ cut) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n_tiles) return;
   const int s = find_segment(seg_tstart, S, t);
   const BinWork W = work[s];
   const int64_t lt = t - W.tile_base;
   const int64_t T = (int64_t)W.TX * W.TY;
-  uint32_t run = 0u;
+  uint32_t run = 0u, weight = 0u;
+  int last = W.n_chunks - 1;
   for (int c = 0; c < W.n_chunks; ++c) {
     const int64_t k = W.ct_off + (int64_t)c * T + lt;
     const uint32_t v = counts[k];
     counts[k] = run;
-    run += v;
+    if (c <= last) {
+      run += v;
+      if (wsum) {
+        weight += wsum[k];
+        if (weight >= kCutWeight) last = c;
+      }
+    }
   }
   tile_total[t] = run;
+  if (cut) cut[t] = last;
 }
 
 // Exclusive scan of u32 into u64, three phases over blocks of 1024 items.
@@ -459,31 +548,33 @@ int64_t bin_fill_work(void* host, const Seg* segs, int S, int64_t* total_chunk_t
 
 hipError_t launch_gather_rect(hipStream_t st, const int64_t* seg_gstart, int S, int64_t G,
                               const uint32_t* sorted_ids, const uint64_t* rect,
-                              uint64_t* rect_sorted) {
+                              uint64_t* rect_sorted, const uint64_t* core, const uint32_t* core_w,
+                              uint64_t* core_sorted, uint32_t* w_sorted) {
   if (G == 0) return hipSuccess;
   hipLaunchKernelGGL(gather_rect_kernel, dim3(nblk(G, 256)), dim3(256), 0, st, seg_gstart, S, G,
-                     sorted_ids, rect, rect_sorted);
+                     sorted_ids, rect, rect_sorted, core, core_w, core_sorted, w_sorted);
   return hipGetLastError();
 }
 
 hipError_t launch_bin_count(hipStream_t st, const void* work_dev, int S, int64_t total_blocks,
-                            const uint64_t* rect_sorted, uint32_t* counts) {
+                            const uint64_t* rect_sorted, uint32_t* counts,
+                            const uint64_t* core_sorted, const uint32_t* w_sorted, uint32_t* wsum) {
   if (total_blocks == 0) return hipSuccess;
   const BinWork* W = (const BinWork*)work_dev;
   const int64_t* cs = (const int64_t*)(W + S) + S;
   hipLaunchKernelGGL(bin_count_kernel, dim3((unsigned)total_blocks), dim3(256), 0, st, W, cs, S,
-                     total_blocks, rect_sorted, counts);
+                     total_blocks, rect_sorted, counts, core_sorted, w_sorted, wsum);
   return hipGetLastError();
 }
 
 hipError_t launch_bin_scan(hipStream_t st, const void* work_dev, int S, const int64_t* seg_tstart,
                            int64_t n_tiles, uint32_t* counts, uint32_t* tile_total,
                            uint64_t* partial, uint64_t* tile_start, uint64_t* ranges,
-                           uint64_t* n_instances) {
+                           uint64_t* n_instances, const uint32_t* wsum, int32_t* cut) {
   const BinWork* W = (const BinWork*)work_dev;
   if (n_tiles == 0) return hipSuccess;
   hipLaunchKernelGGL(chunk_scan_kernel, dim3(nblk(n_tiles, 256)), dim3(256), 0, st, W, seg_tstart,
-                     S, n_tiles, counts, tile_total);
+                     S, n_tiles, counts, tile_total, wsum, cut);
   const int64_t nb = (n_tiles + kScanBlock - 1) / kScanBlock;
   hipLaunchKernelGGL(scan_reduce_kernel, dim3((unsigned)nb), dim3(kScanThreads), 0, st, tile_total,
                      n_tiles, partial);
@@ -499,13 +590,14 @@ size_t bin_scan_partials(int64_t n_tiles) { return (size_t)((n_tiles + kScanBloc
 hipError_t launch_bin_place(hipStream_t st, const void* work_dev, int S, int64_t total_waves,
                             const uint32_t* sorted_ids, const uint64_t* rect_sorted,
                             const uint32_t* counts, const uint64_t* tile_start,
-                            const uint64_t* n_instances, uint64_t capacity, uint32_t* values) {
+                            const uint64_t* n_instances, uint64_t capacity, uint32_t* values,
+                            const int32_t* cut) {
   if (total_waves == 0) return hipSuccess;
   const BinWork* W = (const BinWork*)work_dev;
   const int64_t* ws = (const int64_t*)(W + S);
   hipLaunchKernelGGL(bin_place_kernel, dim3((unsigned)total_waves), dim3(256), 0, st, W, ws, S,
                      total_waves, sorted_ids, rect_sorted, counts, tile_start, n_instances,
-                     capacity, values);
+                     capacity, values, cut);
   return hipGetLastError();
 }
 

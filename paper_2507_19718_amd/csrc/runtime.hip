@@ -81,6 +81,10 @@ struct gsc_binning {
   DevBuf counts, tile_total, partial, tile_start, ranges, scalars, values, n_contrib, grad2d;
   // heaviest-first tile schedules of the splat kernels
   DevBuf ord_key, ord_val, ord_ktmp, ord_vtmp, ord_hist, ord_tab, tile_work;
+  // list cut: per-Gaussian saturation cores and weights, [chunk][tile] weight sums, per-tile
+  // last kept chunk
+  DevBuf core, core_w, core_sorted, w_sorted, wsum, cut;
+  bool list_cut = false;
   uint64_t n_instances = 0;
   uint64_t capacity = 0;
   bool forward_done = false;
@@ -101,7 +105,8 @@ struct gsc_binning {
     DevBuf* all[] = {&tables, &rec, &depth_key, &rect, &tiles, &ids, &keys_tmp, &ids_tmp, &hist,
                      &rect_sorted, &counts, &tile_total, &partial, &tile_start, &ranges, &scalars,
                      &values, &n_contrib, &grad2d, &view_window, &view_screen, &ord_key, &ord_val,
-                     &ord_ktmp, &ord_vtmp, &ord_hist, &ord_tab, &tile_work};
+                     &ord_ktmp, &ord_vtmp, &ord_hist, &ord_tab, &tile_work, &core, &core_w,
+                     &core_sorted, &w_sorted, &wsum, &cut};
     for (DevBuf* b : all) b->release(alloc);
   }
 };
@@ -128,6 +133,7 @@ struct gsc_ctx {
   bool sticky = false;
   uint64_t required = 0;
   int deterministic = 0;
+  int list_cut = 1;                // frames bin only the list prefixes that can reach a pixel
   // pinned staging ring for descriptor uploads
   char* pinned = nullptr;
   size_t pinned_cap = 0, pinned_head = 0;
@@ -414,12 +420,27 @@ gsc_status run_project_bin(gsc_ctx* ctx, gsc_binning* b, uint64_t capacity_hint)
   need(ctx, b->tile_start, a, 8 * (size_t)std::max<int64_t>(b->n_tiles, 1), "tile starts");
   need(ctx, b->ranges, a, 16 * (size_t)std::max<int64_t>(b->n_tiles, 1), "tile ranges");
   need(ctx, b->scalars, a, 64, "scalars");
+  const bool lc = b->list_cut;
+  if (lc) {
+    need(ctx, b->core, a, 8 * Gp, "saturation cores");
+    need(ctx, b->core_w, a, 4 * Gp, "saturation weights");
+    need(ctx, b->core_sorted, a, 8 * Gp, "sorted saturation cores");
+    need(ctx, b->w_sorted, a, 4 * Gp, "sorted saturation weights");
+    need(ctx, b->wsum, a, 4 * (size_t)std::max<int64_t>(b->chunk_tiles, 1), "chunk weight sums");
+    need(ctx, b->cut, a, 4 * (size_t)std::max<int64_t>(b->n_tiles, 1), "tile cuts");
+  }
+  uint64_t* core = lc ? b->core.as<uint64_t>() : nullptr;
+  uint32_t* core_w = lc ? b->core_w.as<uint32_t>() : nullptr;
+  uint64_t* core_sorted = lc ? b->core_sorted.as<uint64_t>() : nullptr;
+  uint32_t* w_sorted = lc ? b->w_sorted.as<uint32_t>() : nullptr;
+  uint32_t* wsum = lc ? b->wsum.as<uint32_t>() : nullptr;
+  int32_t* cut = lc ? b->cut.as<int32_t>() : nullptr;
   hipStream_t st = ctx->stream;
   GSC_TRY(hipMemsetAsync(b->scalars.p, 0, 64, st));
   { ProfScope ps_(ctx, P_PROJECT, st);
   GSC_TRY(launch_project(st, b->d_segs(), b->d_gstart(), b->S, b->d_cams(), G, b->rec.as<SplatRec>(),
                          b->depth_key.as<uint32_t>(), b->rect.as<uint64_t>(), b->tiles.as<uint32_t>(),
-                         b->ids.as<uint32_t>()));
+                         b->ids.as<uint32_t>(), core, core_w));
   }
   // The sort consumes a copy of the depth keys (the originals serve the key view); the odd
   // passes of the sort use rect_sorted as key scratch before the gather fills it.
@@ -431,16 +452,17 @@ gsc_status run_project_bin(gsc_ctx* ctx, gsc_binning* b, uint64_t capacity_hint)
   }
   { ProfScope ps_(ctx, P_GATHER, st);
   GSC_TRY(launch_gather_rect(st, b->d_gstart(), b->S, G, b->ids.as<uint32_t>(), b->rect.as<uint64_t>(),
-                             b->rect_sorted.as<uint64_t>()));
+                             b->rect_sorted.as<uint64_t>(), core, core_w, core_sorted, w_sorted));
   }
   { ProfScope ps_(ctx, P_COUNT, st);
   GSC_TRY(launch_bin_count(st, b->d_work(), b->S, b->count_blocks, b->rect_sorted.as<uint64_t>(),
-                           b->counts.as<uint32_t>()));
+                           b->counts.as<uint32_t>(), core_sorted, w_sorted, wsum));
   }
   { ProfScope ps_(ctx, P_SCAN, st);
   GSC_TRY(launch_bin_scan(st, b->d_work(), b->S, b->d_tstart(), b->n_tiles, b->counts.as<uint32_t>(),
                           b->tile_total.as<uint32_t>(), b->partial.as<uint64_t>(),
-                          b->tile_start.as<uint64_t>(), b->ranges.as<uint64_t>(), b->d_ninst()));
+                          b->tile_start.as<uint64_t>(), b->ranges.as<uint64_t>(), b->d_ninst(),
+                          wsum, cut));
   }
   uint64_t cap = capacity_hint;
   uint64_t n_inst = 0;
@@ -453,7 +475,8 @@ gsc_status run_project_bin(gsc_ctx* ctx, gsc_binning* b, uint64_t capacity_hint)
   { ProfScope ps_(ctx, P_PLACE, st);
   GSC_TRY(launch_bin_place(st, b->d_work(), b->S, b->bin_waves, b->ids.as<uint32_t>(),
                            b->rect_sorted.as<uint64_t>(), b->counts.as<uint32_t>(),
-                           b->tile_start.as<uint64_t>(), b->d_ninst(), cap, b->values.as<uint32_t>()));
+                           b->tile_start.as<uint64_t>(), b->d_ninst(), cap, b->values.as<uint32_t>(),
+                           cut));
   }
   if (capacity_hint != 0) n_inst = read_u64(ctx, b->d_ninst());
   b->n_instances = n_inst;
@@ -728,6 +751,7 @@ gsc_status render_batch(gsc_ctx* ctx, gsc_scene* const* scenes, const gsc_frame_
   if (timing) GSC_TRY(hipEventRecord(ctx->tev[7], ctx->side));
   GSC_TRY(hipEventRecord(ctx->ev_join, ctx->side));
   // ---- splat the cache images ---------------------------------------------------------------------
+  b->list_cut = ctx->list_cut != 0;
   gsc_status s = run_project_bin(ctx, b, 0);
   if (s != GSC_OK) {
     GSC_TRY(hipStreamWaitEvent(st, ctx->ev_join, 0));
@@ -901,6 +925,12 @@ gsc_status gsc_ctx_set_deterministic(gsc_ctx* ctx, int32_t on) {
   if (!ctx) return GSC_E_INVALID_ARG;
   if (on) { ctx->err = "deterministic backward reduction is not available"; return GSC_E_UNSUPPORTED; }
   ctx->deterministic = 0;
+  return GSC_OK;
+}
+
+gsc_status gsc_ctx_set_list_cut(gsc_ctx* ctx, int32_t on) {
+  if (!ctx) return GSC_E_INVALID_ARG;
+  ctx->list_cut = on ? 1 : 0;
   return GSC_OK;
 }
 
