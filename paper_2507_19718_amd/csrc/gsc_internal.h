@@ -116,7 +116,7 @@ hipError_t launch_segmented_sort(hipStream_t st, const void* table_dev, int n_bl
 
 size_t bin_work_bytes(int S);
 int64_t bin_fill_work(void* host, const Seg* segs, int S, int64_t* total_chunk_tiles,
-                      int64_t* total_count_blocks);
+                      int64_t* total_count_blocks, int64_t* total_regions);
 size_t bin_scan_partials(int64_t n_tiles);
 hipError_t launch_gather_rect(hipStream_t st, const int64_t* seg_gstart, int S, int64_t G,
                               const uint32_t* sorted_ids, const uint64_t* rect,
@@ -128,12 +128,16 @@ hipError_t launch_bin_count(hipStream_t st, const void* work_dev, int S, int64_t
 hipError_t launch_bin_scan(hipStream_t st, const void* work_dev, int S, const int64_t* seg_tstart,
                            int64_t n_tiles, uint32_t* counts, uint32_t* tile_total,
                            uint64_t* partial, uint64_t* tile_start, uint64_t* ranges,
-                           uint64_t* n_instances, const uint32_t* wsum, int32_t* cut);
-hipError_t launch_bin_place(hipStream_t st, const void* work_dev, int S, int64_t total_waves,
-                            const uint32_t* sorted_ids, const uint64_t* rect_sorted,
-                            const uint32_t* counts, const uint64_t* tile_start,
-                            const uint64_t* n_instances, uint64_t capacity, uint32_t* values,
-                            const int32_t* cut);
+                           uint64_t* n_instances, const uint32_t* wsum, int32_t* cut,
+                           int32_t* region_n);
+hipError_t launch_bin_regions(hipStream_t st, int64_t n_regions, const int32_t* region_n,
+                              uint64_t* region_start, uint64_t* n_blocks);
+hipError_t launch_bin_place(hipStream_t st, const void* work_dev, int S, int64_t n_regions,
+                            const uint64_t* region_start, const uint64_t* n_blocks,
+                            int64_t grid_blocks, const uint32_t* sorted_ids,
+                            const uint64_t* rect_sorted, const uint32_t* counts,
+                            const uint64_t* tile_start, const uint64_t* n_instances,
+                            uint64_t capacity, uint32_t* values, const int32_t* cut);
 hipError_t launch_binning_keys(hipStream_t st, const int64_t* seg_tstart, int S,
                                const int64_t* seg_goff, int64_t n_tiles, const uint64_t* tile_start,
                                const uint64_t* n_instances, uint64_t n_host,

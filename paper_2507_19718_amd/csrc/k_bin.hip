@@ -33,7 +33,7 @@ namespace gsc {
 namespace {
 
 struct BinWork {          // per segment, for the workgroup -> work item maps
-  int64_t wave_start;     // first placement workgroup of this segment
+  int64_t region_base;    // global index of this segment's first 16x16-tile region
   int64_t count_start;    // first counting workgroup of this segment
   int64_t g_off;
   int64_t n;
@@ -229,8 +229,10 @@ __device__ __forceinline__ void place_batch(uint32_t* __restrict__ values, uint6
 }
 
 __global__ void __launch_bounds__(256) bin_place_kernel(const BinWork* __restrict__ work,
-                                                        const int64_t* __restrict__ block_start,
-                                                        int S, int64_t total_blocks,
+                                                        const int64_t* __restrict__ seg_rbase,
+                                                        int S, int64_t n_regions,
+                                                        const uint64_t* __restrict__ region_start,
+                                                        const uint64_t* __restrict__ n_blocks,
                                                         const uint32_t* __restrict__ sorted_ids,
                                                         const uint64_t* __restrict__ rect_sorted,
                                                         const uint32_t* __restrict__ counts,
@@ -243,24 +245,23 @@ __global__ void __launch_bounds__(256) bin_place_kernel(const BinWork* __restric
   __shared__ uint32_t sh_id[kChunk];
   __shared__ uint64_t q_rect[4][kQueue];
   __shared__ uint32_t q_id[4][kQueue];
-  const int64_t blk = blockIdx.x;
-  if (blk >= total_blocks) return;
+  // Workgroups are packed region by region, each region's chunks [0, region_n) consecutively:
+  // consecutive workgroups (which the dispatcher spreads over the XCDs round-robin) take
+  // different depth slices of the same region, so every XCD gets a share of the heavily
+  // covered central regions, and chunks no tile of a region needs get no workgroup.
+  const uint64_t blk = blockIdx.x;
+  if (blk >= *n_blocks) return;
   if (*n_instances > capacity) return;
   const int lane = __lane_id();
   const int wave = threadIdx.x >> 6;
-  const int s = find_segment(block_start, S, blk);
+  const int64_t g = find_segment(region_start, (int)n_regions, blk);
+  const int s = find_segment(seg_rbase, S, g);
   const BinWork W = work[s];
-  // Chunk group fastest: consecutive workgroups (which the dispatcher spreads over the XCDs
-  // round-robin) take different depth slices of the same region, so every XCD gets a share of
-  // the heavily covered central regions.
-  const int64_t l = blk - W.wave_start;
   const int RX = (W.TX + kRegion - 1) / kRegion;
-  const int NG = (W.n_chunks + kPlaceChunks - 1) / kPlaceChunks;
-  const int cg = (int)(l % NG);
-  const int region = (int)(l / NG);
+  const int region = (int)(g - W.region_base);
   const int rx = region % RX, ry = region / RX;
-  const int c0 = cg * kPlaceChunks;
-  const int c1 = min(c0 + kPlaceChunks, W.n_chunks);
+  const int c0 = (int)(blk - region_start[g]);
+  const int c1 = c0 + 1;
   const int ox = rx * kRegion, oy = ry * kRegion + 4 * wave;   // the wave's block origin
   int bx0 = ox, by0 = oy;
   int bx1 = min(bx0 + kRegion, W.TX) - 1, by1 = min(by0 + 4, W.TY) - 1;
@@ -353,15 +354,16 @@ __global__ void __launch_bounds__(256) bin_place_kernel(const BinWork* __restric
 }
 
 // Per tile: exclusive scan over chunks (in place) and the tile total.  With wsum, chunks after
-// the one at which the running saturation weight reaches kCutWeight add nothing, and cut[tile]
-// is the last chunk kept.
+// the one at which the running saturation weight reaches kCutWeight add nothing.  cut[tile] is
+// the last kept chunk that has entries for the tile (-1: none), so placement can skip the rest.
 __global__ void __launch_bounds__(256) chunk_scan_kernel(const BinWork* __restrict__ work,
                                                          const int64_t* __restrict__ seg_tstart,
                                                          int S, int64_t n_tiles,
                                                          uint32_t* __restrict__ counts,
                                                          uint32_t* __restrict__ tile_total,
                                                          const uint32_t* __restrict__ wsum,
-                                                         int32_t* __restrict__ cut) {
+                                                         int32_t* __restrict__ cut,
+                                                         int32_t* __restrict__ region_n) {
   const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n_tiles) return;
   const int s = find_segment(seg_tstart, S, t);
@@ -369,21 +371,37 @@ __global__ void __launch_bounds__(256) chunk_scan_kernel(const BinWork* __restri
   const int64_t lt = t - W.tile_base;
   const int64_t T = (int64_t)W.TX * W.TY;
   uint32_t run = 0u, weight = 0u;
-  int last = W.n_chunks - 1;
-  for (int c = 0; c < W.n_chunks; ++c) {
-    const int64_t k = W.ct_off + (int64_t)c * T + lt;
-    const uint32_t v = counts[k];
-    counts[k] = run;
-    if (c <= last) {
-      run += v;
-      if (wsum) {
-        weight += wsum[k];
-        if (weight >= kCutWeight) last = c;
+  int last = W.n_chunks - 1, last_nz = -1;
+  // Eight chunks' loads in flight at a time (the loop is latency-bound otherwise).
+  constexpr int kAhead = 8;
+  for (int cb = 0; cb < W.n_chunks; cb += kAhead) {
+    uint32_t v[kAhead], ws[kAhead];
+#pragma unroll
+    for (int j = 0; j < kAhead; ++j) {
+      const int64_t k = W.ct_off + (int64_t)(cb + j) * T + lt;
+      v[j] = (cb + j < W.n_chunks) ? counts[k] : 0u;
+      ws[j] = (wsum && cb + j < W.n_chunks) ? wsum[k] : 0u;
+    }
+#pragma unroll
+    for (int j = 0; j < kAhead; ++j) {
+      const int c = cb + j;
+      if (c >= W.n_chunks) break;
+      counts[W.ct_off + (int64_t)c * T + lt] = run;
+      if (c <= last) {
+        run += v[j];
+        if (v[j]) last_nz = c;
+        weight += ws[j];
+        if (wsum && weight >= kCutWeight) last = c;
       }
     }
   }
   tile_total[t] = run;
-  if (cut) cut[t] = last;
+  cut[t] = last_nz;
+  // The region's chunk count for placement: 1 + the largest cut of its tiles (zeroed before).
+  const int RX = (W.TX + kRegion - 1) / kRegion;
+  const int tx = (int)(lt % W.TX), ty = (int)(lt / W.TX);
+  if (last_nz >= 0)
+    atomicMax(&region_n[W.region_base + (int64_t)(ty / kRegion) * RX + tx / kRegion], last_nz + 1);
 }
 
 // Exclusive scan of u32 into u64, three phases over blocks of 1024 items.
@@ -420,6 +438,24 @@ __global__ void __launch_bounds__(kScanThreads) scan_reduce_kernel(const uint32_
   uint64_t total;
   block_exclusive_scan(s, tmp, &total);
   if (threadIdx.x == 0) partial[blockIdx.x] = total;
+}
+
+// Single workgroup: region_start[g] = sum of region_n over the regions before g, total to *sum.
+__global__ void __launch_bounds__(kScanThreads) region_scan_kernel(const int32_t* __restrict__ region_n,
+                                                                   int64_t n,
+                                                                   uint64_t* __restrict__ region_start,
+                                                                   uint64_t* __restrict__ sum) {
+  __shared__ uint64_t tmp[kScanThreads];
+  uint64_t carry = 0ull;
+  for (int64_t base = 0; base < n; base += kScanThreads) {
+    const int64_t i = base + threadIdx.x;
+    const uint64_t v = (i < n) ? (uint64_t)region_n[i] : 0ull;
+    uint64_t total;
+    const uint64_t ex = block_exclusive_scan(v, tmp, &total);
+    if (i < n) region_start[i] = carry + ex;
+    carry += total;
+  }
+  if (threadIdx.x == 0) *sum = carry;
 }
 
 // Single workgroup: exclusive scan of the block partials (any count), total to *sum.
@@ -513,17 +549,18 @@ inline unsigned nblk(int64_t n, int bs) { return (unsigned)((n + bs - 1) / bs); 
 
 size_t bin_work_bytes(int S) { return sizeof(BinWork) * (size_t)S + 2 * sizeof(int64_t) * (size_t)S; }
 
-// Host: fills [BinWork x S][int64 place start x S][int64 count start x S]; returns the placement
-// workgroup count, the counting workgroup count and the [chunk][tile] count total.
+// Host: fills [BinWork x S][int64 first region x S][int64 count start x S]; returns the
+// placement workgroup count when every region visits every chunk (an upper bound), the counting
+// workgroup count, the [chunk][tile] count total and the region count.
 int64_t bin_fill_work(void* host, const Seg* segs, int S, int64_t* total_chunk_tiles,
-                      int64_t* total_count_blocks) {
+                      int64_t* total_count_blocks, int64_t* total_regions) {
   BinWork* W = (BinWork*)host;
   int64_t* ws = (int64_t*)(W + S);
   int64_t* cs = ws + S;
-  int64_t waves = 0, ct = 0, cblk = 0;
+  int64_t waves = 0, ct = 0, cblk = 0, regions = 0;
   for (int s = 0; s < S; ++s) {
     const Seg& g = segs[s];
-    W[s].wave_start = waves;
+    W[s].region_base = regions;
     W[s].count_start = cblk;
     W[s].g_off = g.g_off;
     W[s].n = g.n;
@@ -534,15 +571,17 @@ int64_t bin_fill_work(void* host, const Seg* segs, int S, int64_t* total_chunk_t
     W[s].n_chunks = (int32_t)((g.n + kChunk - 1) / kChunk);
     W[s].band_rows = std::max(1, std::min(g.TY, kDiffWords / std::max(g.TX, 1)));
     W[s].n_bands = (g.TY + W[s].band_rows - 1) / W[s].band_rows;
-    ws[s] = waves;
+    ws[s] = regions;
     cs[s] = cblk;
-    waves += (int64_t)((W[s].n_chunks + kPlaceChunks - 1) / kPlaceChunks) *
-             ((g.TY + kRegion - 1) / kRegion) * ((g.TX + kRegion - 1) / kRegion);
+    const int64_t nreg = (int64_t)((g.TY + kRegion - 1) / kRegion) * ((g.TX + kRegion - 1) / kRegion);
+    regions += nreg;
+    waves += (int64_t)W[s].n_chunks * nreg;
     cblk += (int64_t)W[s].n_chunks * W[s].n_bands;
     ct += (int64_t)W[s].n_chunks * g.TX * g.TY;
   }
   *total_chunk_tiles = ct;
   *total_count_blocks = cblk;
+  *total_regions = regions;
   return waves;
 }
 
@@ -570,11 +609,12 @@ hipError_t launch_bin_count(hipStream_t st, const void* work_dev, int S, int64_t
 hipError_t launch_bin_scan(hipStream_t st, const void* work_dev, int S, const int64_t* seg_tstart,
                            int64_t n_tiles, uint32_t* counts, uint32_t* tile_total,
                            uint64_t* partial, uint64_t* tile_start, uint64_t* ranges,
-                           uint64_t* n_instances, const uint32_t* wsum, int32_t* cut) {
+                           uint64_t* n_instances, const uint32_t* wsum, int32_t* cut,
+                           int32_t* region_n) {
   const BinWork* W = (const BinWork*)work_dev;
   if (n_tiles == 0) return hipSuccess;
   hipLaunchKernelGGL(chunk_scan_kernel, dim3(nblk(n_tiles, 256)), dim3(256), 0, st, W, seg_tstart,
-                     S, n_tiles, counts, tile_total, wsum, cut);
+                     S, n_tiles, counts, tile_total, wsum, cut, region_n);
   const int64_t nb = (n_tiles + kScanBlock - 1) / kScanBlock;
   hipLaunchKernelGGL(scan_reduce_kernel, dim3((unsigned)nb), dim3(kScanThreads), 0, st, tile_total,
                      n_tiles, partial);
@@ -587,17 +627,27 @@ hipError_t launch_bin_scan(hipStream_t st, const void* work_dev, int S, const in
 
 size_t bin_scan_partials(int64_t n_tiles) { return (size_t)((n_tiles + kScanBlock - 1) / kScanBlock) + 1; }
 
-hipError_t launch_bin_place(hipStream_t st, const void* work_dev, int S, int64_t total_waves,
-                            const uint32_t* sorted_ids, const uint64_t* rect_sorted,
-                            const uint32_t* counts, const uint64_t* tile_start,
-                            const uint64_t* n_instances, uint64_t capacity, uint32_t* values,
-                            const int32_t* cut) {
-  if (total_waves == 0) return hipSuccess;
+hipError_t launch_bin_regions(hipStream_t st, int64_t n_regions, const int32_t* region_n,
+                              uint64_t* region_start, uint64_t* n_blocks) {
+  if (n_regions == 0) return hipSuccess;
+  hipLaunchKernelGGL(region_scan_kernel, dim3(1), dim3(kScanThreads), 0, st, region_n, n_regions,
+                     region_start, n_blocks);
+  return hipGetLastError();
+}
+
+hipError_t launch_bin_place(hipStream_t st, const void* work_dev, int S, int64_t n_regions,
+                            const uint64_t* region_start, const uint64_t* n_blocks,
+                            int64_t grid_blocks, const uint32_t* sorted_ids,
+                            const uint64_t* rect_sorted, const uint32_t* counts,
+                            const uint64_t* tile_start, const uint64_t* n_instances,
+                            uint64_t capacity, uint32_t* values, const int32_t* cut) {
+  if (grid_blocks == 0) return hipSuccess;
+  if (grid_blocks > 0x7fffffffLL) return hipErrorInvalidValue;
   const BinWork* W = (const BinWork*)work_dev;
   const int64_t* ws = (const int64_t*)(W + S);
-  hipLaunchKernelGGL(bin_place_kernel, dim3((unsigned)total_waves), dim3(256), 0, st, W, ws, S,
-                     total_waves, sorted_ids, rect_sorted, counts, tile_start, n_instances,
-                     capacity, values, cut);
+  hipLaunchKernelGGL(bin_place_kernel, dim3((unsigned)grid_blocks), dim3(256), 0, st, W, ws, S,
+                     n_regions, region_start, n_blocks, sorted_ids, rect_sorted, counts, tile_start,
+                     n_instances, capacity, values, cut);
   return hipGetLastError();
 }
 

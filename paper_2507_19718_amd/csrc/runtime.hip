@@ -73,7 +73,7 @@ struct gsc_binning {
   std::vector<int64_t> seg_gstart, seg_tstart;
   int64_t G = 0, n_tiles = 0, pixels = 0;
   int n_sort_blocks = 0;
-  int64_t bin_waves = 0, count_blocks = 0, chunk_tiles = 0;
+  int64_t bin_waves = 0, count_blocks = 0, chunk_tiles = 0, n_regions = 0;
   // device tables: [Seg x S][DevCam x R][int64 gstart x S][int64 tstart x S][sort table][bin work]
   DevBuf tables;
   size_t off_cams = 0, off_gstart = 0, off_tstart = 0, off_sort = 0, off_work = 0;
@@ -83,7 +83,7 @@ struct gsc_binning {
   DevBuf ord_key, ord_val, ord_ktmp, ord_vtmp, ord_hist, ord_tab, tile_work;
   // list cut: per-Gaussian saturation cores and weights, [chunk][tile] weight sums, per-tile
   // last kept chunk
-  DevBuf core, core_w, core_sorted, w_sorted, wsum, cut;
+  DevBuf core, core_w, core_sorted, w_sorted, wsum, cut, region_start, region_n;
   bool list_cut = false;
   uint64_t n_instances = 0;
   uint64_t capacity = 0;
@@ -106,7 +106,7 @@ struct gsc_binning {
                      &rect_sorted, &counts, &tile_total, &partial, &tile_start, &ranges, &scalars,
                      &values, &n_contrib, &grad2d, &view_window, &view_screen, &ord_key, &ord_val,
                      &ord_ktmp, &ord_vtmp, &ord_hist, &ord_tab, &tile_work, &core, &core_w,
-                     &core_sorted, &w_sorted, &wsum, &cut};
+                     &core_sorted, &w_sorted, &wsum, &cut, &region_start, &region_n};
     for (DevBuf* b : all) b->release(alloc);
   }
 };
@@ -238,6 +238,15 @@ uint64_t read_u64(gsc_ctx* ctx, const uint64_t* dev) {
   GSC_TRY(hipMemcpyAsync(ctx->host_u64, dev, sizeof(uint64_t), hipMemcpyDeviceToHost, ctx->stream));
   GSC_TRY(hipStreamSynchronize(ctx->stream));
   return ctx->host_u64[0];
+}
+
+// Two consecutive device words in one synchronising read.
+void read_u64x2(gsc_ctx* ctx, const uint64_t* dev, uint64_t* a, uint64_t* b) {
+  GSC_TRY(hipMemcpyAsync(ctx->host_u64 + 2, dev, 2 * sizeof(uint64_t), hipMemcpyDeviceToHost,
+                         ctx->stream));
+  GSC_TRY(hipStreamSynchronize(ctx->stream));
+  *a = ctx->host_u64[2];
+  *b = ctx->host_u64[3];
 }
 
 const char* const kProfNames[] = {"project", "depth_sort", "bin_count", "bin_scan", "bin_place",
@@ -393,7 +402,7 @@ void plan_batch(gsc_ctx* ctx, gsc_binning* b, const std::vector<ReqSpec>& reqs) 
   std::memcpy(host.data() + b->off_tstart, b->seg_tstart.data(), sizeof(int64_t) * b->S);
   sort_fill_table(host.data() + b->off_sort, seg_n.data(), seg_off.data(), b->S);
   b->bin_waves = bin_fill_work(host.data() + b->off_work, b->segs.data(), b->S, &b->chunk_tiles,
-                                &b->count_blocks);
+                                &b->count_blocks, &b->n_regions);
   need(ctx, b->tables, b->alloc, off, "descriptor tables");
   upload(ctx, b->tables.p, host.data(), off);
   b->forward_done = false;
@@ -427,16 +436,19 @@ gsc_status run_project_bin(gsc_ctx* ctx, gsc_binning* b, uint64_t capacity_hint)
     need(ctx, b->core_sorted, a, 8 * Gp, "sorted saturation cores");
     need(ctx, b->w_sorted, a, 4 * Gp, "sorted saturation weights");
     need(ctx, b->wsum, a, 4 * (size_t)std::max<int64_t>(b->chunk_tiles, 1), "chunk weight sums");
-    need(ctx, b->cut, a, 4 * (size_t)std::max<int64_t>(b->n_tiles, 1), "tile cuts");
   }
+  need(ctx, b->cut, a, 4 * (size_t)std::max<int64_t>(b->n_tiles, 1), "tile cuts");
+  need(ctx, b->region_start, a, 8 * (size_t)std::max<int64_t>(b->n_regions, 1), "region starts");
+  need(ctx, b->region_n, a, 4 * (size_t)std::max<int64_t>(b->n_regions, 1), "region chunk counts");
   uint64_t* core = lc ? b->core.as<uint64_t>() : nullptr;
   uint32_t* core_w = lc ? b->core_w.as<uint32_t>() : nullptr;
   uint64_t* core_sorted = lc ? b->core_sorted.as<uint64_t>() : nullptr;
   uint32_t* w_sorted = lc ? b->w_sorted.as<uint32_t>() : nullptr;
   uint32_t* wsum = lc ? b->wsum.as<uint32_t>() : nullptr;
-  int32_t* cut = lc ? b->cut.as<int32_t>() : nullptr;
+  int32_t* cut = b->cut.as<int32_t>();
   hipStream_t st = ctx->stream;
   GSC_TRY(hipMemsetAsync(b->scalars.p, 0, 64, st));
+  GSC_TRY(hipMemsetAsync(b->region_n.p, 0, 4 * (size_t)b->n_regions, st));
   { ProfScope ps_(ctx, P_PROJECT, st);
   GSC_TRY(launch_project(st, b->d_segs(), b->d_gstart(), b->S, b->d_cams(), G, b->rec.as<SplatRec>(),
                          b->depth_key.as<uint32_t>(), b->rect.as<uint64_t>(), b->tiles.as<uint32_t>(),
@@ -462,18 +474,24 @@ gsc_status run_project_bin(gsc_ctx* ctx, gsc_binning* b, uint64_t capacity_hint)
   GSC_TRY(launch_bin_scan(st, b->d_work(), b->S, b->d_tstart(), b->n_tiles, b->counts.as<uint32_t>(),
                           b->tile_total.as<uint32_t>(), b->partial.as<uint64_t>(),
                           b->tile_start.as<uint64_t>(), b->ranges.as<uint64_t>(), b->d_ninst(),
-                          wsum, cut));
+                          wsum, cut, b->region_n.as<int32_t>()));
+  GSC_TRY(launch_bin_regions(st, b->n_regions, b->region_n.as<int32_t>(), b->region_start.as<uint64_t>(),
+                             b->d_ninst() + 1));
   }
   uint64_t cap = capacity_hint;
   uint64_t n_inst = 0;
+  // Placement workgroups: the exact count when the sizes are read back anyway, else the bound
+  // of every region visiting every chunk (the surplus workgroups exit at once).
+  uint64_t place_blocks = (uint64_t)b->bin_waves;
   if (cap == 0) {
-    n_inst = read_u64(ctx, b->d_ninst());
+    read_u64x2(ctx, b->d_ninst(), &n_inst, &place_blocks);
     cap = n_inst;
   }
   need(ctx, b->values, a, 4 * (size_t)std::max<uint64_t>(cap, 1), "instance values");
   b->capacity = cap;
   { ProfScope ps_(ctx, P_PLACE, st);
-  GSC_TRY(launch_bin_place(st, b->d_work(), b->S, b->bin_waves, b->ids.as<uint32_t>(),
+  GSC_TRY(launch_bin_place(st, b->d_work(), b->S, b->n_regions, b->region_start.as<uint64_t>(),
+                           b->d_ninst() + 1, (int64_t)place_blocks, b->ids.as<uint32_t>(),
                            b->rect_sorted.as<uint64_t>(), b->counts.as<uint32_t>(),
                            b->tile_start.as<uint64_t>(), b->d_ninst(), cap, b->values.as<uint32_t>(),
                            cut));
