@@ -99,8 +99,7 @@ hipError_t launch_init_level(hipStream_t st, const float* mean3, int64_t n, cons
                              float* grot, float* gls, float* grgb, float* glogit);
 hipError_t launch_project(hipStream_t st, const Seg* segs, const int64_t* seg_gstart, int S,
                           const DevCam* cams, int64_t G, SplatRec* rec, uint32_t* depth_key,
-                          uint64_t* rect, uint32_t* tiles, uint32_t* ids, uint64_t* core,
-                          uint32_t* core_w);
+                          uint64_t* rect, uint32_t* tiles, uint32_t* ids, uint64_t* core);
 hipError_t launch_project_backward(hipStream_t st, const Seg* segs, const int64_t* seg_gstart, int S,
                                    const DevCam* cams, int64_t G, const float* grad2d,
                                    float* grads14);
@@ -120,11 +119,10 @@ int64_t bin_fill_work(void* host, const Seg* segs, int S, int64_t* total_chunk_t
 size_t bin_scan_partials(int64_t n_tiles);
 hipError_t launch_gather_rect(hipStream_t st, const int64_t* seg_gstart, int S, int64_t G,
                               const uint32_t* sorted_ids, const uint64_t* rect,
-                              uint64_t* rect_sorted, const uint64_t* core, const uint32_t* core_w,
-                              uint64_t* core_sorted, uint32_t* w_sorted);
+                              uint64_t* rect_sorted, const uint64_t* core, uint64_t* core_sorted);
 hipError_t launch_bin_count(hipStream_t st, const void* work_dev, int S, int64_t total_blocks,
                             const uint64_t* rect_sorted, uint32_t* counts,
-                            const uint64_t* core_sorted, const uint32_t* w_sorted, uint32_t* wsum);
+                            const uint64_t* core_sorted, uint32_t* wsum);
 hipError_t launch_bin_scan(hipStream_t st, const void* work_dev, int S, const int64_t* seg_tstart,
                            int64_t n_tiles, uint32_t* counts, uint32_t* tile_total,
                            uint64_t* partial, uint64_t* tile_start, uint64_t* ranges,

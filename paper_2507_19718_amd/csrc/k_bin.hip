@@ -58,18 +58,13 @@ __global__ void __launch_bounds__(256) gather_rect_kernel(const int64_t* __restr
                                                           const uint64_t* __restrict__ rect,
                                                           uint64_t* __restrict__ rect_sorted,
                                                           const uint64_t* __restrict__ core,
-                                                          const uint32_t* __restrict__ core_w,
-                                                          uint64_t* __restrict__ core_sorted,
-                                                          uint32_t* __restrict__ w_sorted) {
+                                                          uint64_t* __restrict__ core_sorted) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= G) return;
   const int s = find_segment(seg_gstart, S, i);
   const int64_t src = seg_gstart[s] + sorted_ids[i];
   rect_sorted[i] = rect[src];
-  if (core) {
-    core_sorted[i] = core[src];
-    w_sorted[i] = core_w[src];
-  }
+  if (core) core_sorted[i] = core[src];
 }
 
 // 2D prefix sum in place of a band's difference array D[R][TX] (down the columns, then along
@@ -126,7 +121,6 @@ __global__ void __launch_bounds__(256) bin_count_kernel(const BinWork* __restric
                                                         const uint64_t* __restrict__ rect_sorted,
                                                         uint32_t* __restrict__ counts,
                                                         const uint64_t* __restrict__ core_sorted,
-                                                        const uint32_t* __restrict__ w_sorted,
                                                         uint32_t* __restrict__ wsum) {
   __shared__ int32_t D[kDiffWords];
   const int64_t blk = blockIdx.x;
@@ -156,10 +150,13 @@ __global__ void __launch_bounds__(256) bin_count_kernel(const BinWork* __restric
   if (!wsum) return;
   __syncthreads();
   const uint64_t* cs = core_sorted + W.g_off + g0;
-  const uint32_t* ws = w_sorted + W.g_off + g0;
   for (int k = threadIdx.x; k < cnt_g; k += 256) {
-    const int w = (int)ws[k];
-    if (w) band_rect_add(D, cs[k], w, b0, R, TX);
+    const uint64_t c = cs[k];
+    const int w = (int)(c >> 48);
+    if (!w) continue;
+    const uint64_t r = (c & 0x7ffull) | (((c >> 11) & 0x7ffull) << 16) |
+                       (((c >> 22) & 0x7ffull) << 32) | (((c >> 33) & 0x7ffull) << 48);
+    band_rect_add(D, r, w, b0, R, TX);
   }
   __syncthreads();
   band_prefix_sum(D, R, TX);
@@ -587,22 +584,21 @@ int64_t bin_fill_work(void* host, const Seg* segs, int S, int64_t* total_chunk_t
 
 hipError_t launch_gather_rect(hipStream_t st, const int64_t* seg_gstart, int S, int64_t G,
                               const uint32_t* sorted_ids, const uint64_t* rect,
-                              uint64_t* rect_sorted, const uint64_t* core, const uint32_t* core_w,
-                              uint64_t* core_sorted, uint32_t* w_sorted) {
+                              uint64_t* rect_sorted, const uint64_t* core, uint64_t* core_sorted) {
   if (G == 0) return hipSuccess;
   hipLaunchKernelGGL(gather_rect_kernel, dim3(nblk(G, 256)), dim3(256), 0, st, seg_gstart, S, G,
-                     sorted_ids, rect, rect_sorted, core, core_w, core_sorted, w_sorted);
+                     sorted_ids, rect, rect_sorted, core, core_sorted);
   return hipGetLastError();
 }
 
 hipError_t launch_bin_count(hipStream_t st, const void* work_dev, int S, int64_t total_blocks,
                             const uint64_t* rect_sorted, uint32_t* counts,
-                            const uint64_t* core_sorted, const uint32_t* w_sorted, uint32_t* wsum) {
+                            const uint64_t* core_sorted, uint32_t* wsum) {
   if (total_blocks == 0) return hipSuccess;
   const BinWork* W = (const BinWork*)work_dev;
   const int64_t* cs = (const int64_t*)(W + S) + S;
   hipLaunchKernelGGL(bin_count_kernel, dim3((unsigned)total_blocks), dim3(256), 0, st, W, cs, S,
-                     total_blocks, rect_sorted, counts, core_sorted, w_sorted, wsum);
+                     total_blocks, rect_sorted, counts, core_sorted, wsum);
   return hipGetLastError();
 }
 

@@ -17,31 +17,31 @@ constexpr uint64_t kEmptyRect = 0x0000000100000001ull;   // tx0 = 1 > tx1 = 0: c
 // exp), so every such pixel that has not terminated multiplies its transmittance by at most
 // 1 - o / 2.  The weight is -ln(1 - o / 2) in 2^-16 units, rounded down.  No core when
 // o / 2 < 1/255 (such a pair may be skipped) or when the conic is too close to singular for its
-// quadratic form to keep its sign under rounding.
+// quadratic form to keep its sign under rounding.  Packed in one word: tile columns cx0, cx1 and
+// rows cy0, cy1 in 11-bit fields (bits 0, 11, 22, 33), the weight (< 2^16) in bits 48..63; a
+// Gaussian without a core has weight 0.
 constexpr float kCoreQ = 1.3f;
 
-__device__ __forceinline__ void saturation_core(const Projected& P, const DevCam& cam,
-                                                uint64_t* core, uint32_t* weight) {
-  *core = kEmptyRect;
-  *weight = 0u;
-  if (!P.tiles || !(P.o >= (2.0f / 255.0f) * 1.01f)) return;
+__device__ __forceinline__ uint64_t saturation_core(const Projected& P, const DevCam& cam) {
+  if (!P.tiles || !(P.o >= (2.0f / 255.0f) * 1.01f)) return 0ull;
   const float rho = fabsf(P.B) / sqrtf(P.A * P.Cc);
-  if (!(rho < 0.999f)) return;
+  if (!(rho < 0.999f)) return 0ull;
   // Corner value A hx^2 + 2 |B| hx hy + C hy^2 = kCoreQ for hx = sqrt(kCoreQ / (2 A (1 + rho))).
   const float hx = sqrtf(kCoreQ / ((2.0f * P.A) * (1.0f + rho)));
   const float hy = sqrtf(kCoreQ / ((2.0f * P.Cc) * (1.0f + rho)));
   const int i0 = max(P.px0, (int)ceilf(P.u - hx)), i1 = min(P.px1, (int)floorf(P.u + hx));
   const int j0 = max(P.py0, (int)ceilf(P.v - hy)), j1 = min(P.py1, (int)floorf(P.v + hy));
-  if (i0 > i1 || j0 > j1) return;
+  if (i0 > i1 || j0 > j1) return 0ull;
   // Window-local tiles whose pixels (clipped to the render window) lie in [i0, i1] x [j0, j1].
   const int TX = (cam.w + 15) >> 4, TY = (cam.h + 15) >> 4;
   const int lx0 = i0 - cam.x0, lx1 = i1 - cam.x0, ly0 = j0 - cam.y0, ly1 = j1 - cam.y0;
   const int cx0 = (lx0 + 15) >> 4, cy0 = (ly0 + 15) >> 4;
   const int cx1 = (lx1 >= cam.w - 1) ? TX - 1 : ((lx1 + 1) >> 4) - 1;
   const int cy1 = (ly1 >= cam.h - 1) ? TY - 1 : ((ly1 + 1) >> 4) - 1;
-  if (cx0 > cx1 || cy0 > cy1) return;
-  *core = (uint64_t)cx0 | ((uint64_t)cx1 << 16) | ((uint64_t)cy0 << 32) | ((uint64_t)cy1 << 48);
-  *weight = (uint32_t)(-logf(1.0f - 0.5f * P.o) * (65536.0f * 0.999f));
+  if (cx0 > cx1 || cy0 > cy1) return 0ull;
+  const uint64_t w = (uint64_t)(-logf(1.0f - 0.5f * P.o) * (65536.0f * 0.999f));
+  return (uint64_t)cx0 | ((uint64_t)cx1 << 11) | ((uint64_t)cy0 << 22) | ((uint64_t)cy1 << 33) |
+         (w << 48);
 }
 
 __global__ void __launch_bounds__(256) project_kernel(const Seg* __restrict__ segs,
@@ -52,8 +52,7 @@ __global__ void __launch_bounds__(256) project_kernel(const Seg* __restrict__ se
                                                       uint64_t* __restrict__ rect,
                                                       uint32_t* __restrict__ tiles,
                                                       uint32_t* __restrict__ ids,
-                                                      uint64_t* __restrict__ core,
-                                                      uint32_t* __restrict__ core_w) {
+                                                      uint64_t* __restrict__ core) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= G) return;
   const int s = find_segment(seg_gstart, S, i);
@@ -76,13 +75,7 @@ __global__ void __launch_bounds__(256) project_kernel(const Seg* __restrict__ se
                     : kEmptyRect;
   tiles[i] = P.tiles;
   ids[i] = (uint32_t)lid;
-  if (core) {
-    uint64_t cr;
-    uint32_t cw;
-    saturation_core(P, cam, &cr, &cw);
-    core[i] = cr;
-    core_w[i] = cw;
-  }
+  if (core) core[i] = saturation_core(P, cam);
 }
 
 // Adjoint of the projection.  grad2d is SoA [9][G]: du, dv, dA, dB, dCc, do, dr, dg, db
@@ -271,11 +264,10 @@ inline unsigned blocks_for(int64_t n, int bs) { return (unsigned)((n + bs - 1) /
 
 hipError_t launch_project(hipStream_t st, const Seg* segs, const int64_t* seg_gstart, int S,
                           const DevCam* cams, int64_t G, SplatRec* rec, uint32_t* depth_key,
-                          uint64_t* rect, uint32_t* tiles, uint32_t* ids, uint64_t* core,
-                          uint32_t* core_w) {
+                          uint64_t* rect, uint32_t* tiles, uint32_t* ids, uint64_t* core) {
   if (G == 0) return hipSuccess;
   hipLaunchKernelGGL(project_kernel, dim3(blocks_for(G, 256)), dim3(256), 0, st, segs, seg_gstart,
-                     S, cams, G, rec, depth_key, rect, tiles, ids, core, core_w);
+                     S, cams, G, rec, depth_key, rect, tiles, ids, core);
   return hipGetLastError();
 }
 

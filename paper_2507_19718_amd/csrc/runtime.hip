@@ -81,9 +81,9 @@ struct gsc_binning {
   DevBuf counts, tile_total, partial, tile_start, ranges, scalars, values, n_contrib, grad2d;
   // heaviest-first tile schedules of the splat kernels
   DevBuf ord_key, ord_val, ord_ktmp, ord_vtmp, ord_hist, ord_tab, tile_work;
-  // list cut: per-Gaussian saturation cores and weights, [chunk][tile] weight sums, per-tile
-  // last kept chunk
-  DevBuf core, core_w, core_sorted, w_sorted, wsum, cut, region_start, region_n;
+  // list cut: per-Gaussian saturation cores (with their weights), [chunk][tile] weight sums,
+  // per-tile last kept chunk, per-region placement chunk counts and first workgroups
+  DevBuf core, core_sorted, wsum, cut, region_start, region_n;
   bool list_cut = false;
   uint64_t n_instances = 0;
   uint64_t capacity = 0;
@@ -105,8 +105,8 @@ struct gsc_binning {
     DevBuf* all[] = {&tables, &rec, &depth_key, &rect, &tiles, &ids, &keys_tmp, &ids_tmp, &hist,
                      &rect_sorted, &counts, &tile_total, &partial, &tile_start, &ranges, &scalars,
                      &values, &n_contrib, &grad2d, &view_window, &view_screen, &ord_key, &ord_val,
-                     &ord_ktmp, &ord_vtmp, &ord_hist, &ord_tab, &tile_work, &core, &core_w,
-                     &core_sorted, &w_sorted, &wsum, &cut, &region_start, &region_n};
+                     &ord_ktmp, &ord_vtmp, &ord_hist, &ord_tab, &tile_work, &core,
+                     &core_sorted, &wsum, &cut, &region_start, &region_n};
     for (DevBuf* b : all) b->release(alloc);
   }
 };
@@ -432,18 +432,14 @@ gsc_status run_project_bin(gsc_ctx* ctx, gsc_binning* b, uint64_t capacity_hint)
   const bool lc = b->list_cut;
   if (lc) {
     need(ctx, b->core, a, 8 * Gp, "saturation cores");
-    need(ctx, b->core_w, a, 4 * Gp, "saturation weights");
     need(ctx, b->core_sorted, a, 8 * Gp, "sorted saturation cores");
-    need(ctx, b->w_sorted, a, 4 * Gp, "sorted saturation weights");
     need(ctx, b->wsum, a, 4 * (size_t)std::max<int64_t>(b->chunk_tiles, 1), "chunk weight sums");
   }
   need(ctx, b->cut, a, 4 * (size_t)std::max<int64_t>(b->n_tiles, 1), "tile cuts");
   need(ctx, b->region_start, a, 8 * (size_t)std::max<int64_t>(b->n_regions, 1), "region starts");
   need(ctx, b->region_n, a, 4 * (size_t)std::max<int64_t>(b->n_regions, 1), "region chunk counts");
   uint64_t* core = lc ? b->core.as<uint64_t>() : nullptr;
-  uint32_t* core_w = lc ? b->core_w.as<uint32_t>() : nullptr;
   uint64_t* core_sorted = lc ? b->core_sorted.as<uint64_t>() : nullptr;
-  uint32_t* w_sorted = lc ? b->w_sorted.as<uint32_t>() : nullptr;
   uint32_t* wsum = lc ? b->wsum.as<uint32_t>() : nullptr;
   int32_t* cut = b->cut.as<int32_t>();
   hipStream_t st = ctx->stream;
@@ -452,7 +448,7 @@ gsc_status run_project_bin(gsc_ctx* ctx, gsc_binning* b, uint64_t capacity_hint)
   { ProfScope ps_(ctx, P_PROJECT, st);
   GSC_TRY(launch_project(st, b->d_segs(), b->d_gstart(), b->S, b->d_cams(), G, b->rec.as<SplatRec>(),
                          b->depth_key.as<uint32_t>(), b->rect.as<uint64_t>(), b->tiles.as<uint32_t>(),
-                         b->ids.as<uint32_t>(), core, core_w));
+                         b->ids.as<uint32_t>(), core));
   }
   // The sort consumes a copy of the depth keys (the originals serve the key view); the odd
   // passes of the sort use rect_sorted as key scratch before the gather fills it.
@@ -464,11 +460,11 @@ gsc_status run_project_bin(gsc_ctx* ctx, gsc_binning* b, uint64_t capacity_hint)
   }
   { ProfScope ps_(ctx, P_GATHER, st);
   GSC_TRY(launch_gather_rect(st, b->d_gstart(), b->S, G, b->ids.as<uint32_t>(), b->rect.as<uint64_t>(),
-                             b->rect_sorted.as<uint64_t>(), core, core_w, core_sorted, w_sorted));
+                             b->rect_sorted.as<uint64_t>(), core, core_sorted));
   }
   { ProfScope ps_(ctx, P_COUNT, st);
   GSC_TRY(launch_bin_count(st, b->d_work(), b->S, b->count_blocks, b->rect_sorted.as<uint64_t>(),
-                           b->counts.as<uint32_t>(), core_sorted, w_sorted, wsum));
+                           b->counts.as<uint32_t>(), core_sorted, wsum));
   }
   { ProfScope ps_(ctx, P_SCAN, st);
   GSC_TRY(launch_bin_scan(st, b->d_work(), b->S, b->d_tstart(), b->n_tiles, b->counts.as<uint32_t>(),
