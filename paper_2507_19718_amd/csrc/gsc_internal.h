@@ -150,8 +150,8 @@ hipError_t launch_splat_forward(hipStream_t st, const Seg* segs, const int64_t* 
                                 unsigned long long* stats, const uint32_t* order,
                                 uint32_t* tile_work);
 // Keys ordering tiles by decreasing work (work NULL: list length from ranges).
-hipError_t launch_tile_order_keys(hipStream_t st, const uint64_t* ranges, const uint32_t* work,
-                                  int64_t n_tiles, uint32_t* key, uint32_t* val);
+hipError_t launch_tile_order(hipStream_t st, const uint64_t* ranges, const uint32_t* work,
+                             int64_t n_tiles, uint32_t* order);
 hipError_t launch_splat_backward(hipStream_t st, const Seg* segs, const int64_t* seg_tstart, int S,
                                  const DevCam* cams, int64_t n_tiles, const uint64_t* ranges,
                                  const uint32_t* values, const SplatRec* rec, const float* final_T,

@@ -369,17 +369,50 @@ __global__ void __launch_bounds__(64) splat_backward_kernel(
   }
 }
 
-// Sort keys for scheduling tiles heaviest first: the bitwise complement of a work estimate (the
-// list length, or the entries the forward processed), with the tile index as value.
-__global__ void __launch_bounds__(256) tile_order_keys_kernel(const uint64_t* __restrict__ ranges,
-                                                              const uint32_t* __restrict__ work,
-                                                              int64_t n_tiles, uint32_t* __restrict__ key,
-                                                              uint32_t* __restrict__ val) {
-  const int64_t t = (int64_t)blockIdx.x * 256 + threadIdx.x;
-  if (t >= n_tiles) return;
-  const uint64_t w = work ? (uint64_t)work[t] : ranges[2 * t + 1] - ranges[2 * t];
-  key[t] = ~(uint32_t)(w > 0xffffffffull ? 0xffffffffull : w);
-  val[t] = (uint32_t)t;
+// Heaviest-first tile schedule, by a bucket sort in one workgroup: a tile's work estimate (the
+// list length, or the entries the forward processed) falls into one of 256 buckets of width
+// 2^(1/8) in log scale; order[] lists the tiles bucket by bucket, heaviest first.  The order
+// within a bucket is whatever the LDS atomics give: it only schedules, no result depends on it.
+constexpr int kOrderThreads = 1024;
+
+__device__ __forceinline__ int work_bucket(uint32_t w) {
+  if (w == 0u) return 0;
+  const int lg = 31 - __builtin_clz(w);                             // floor(log2 w)
+  const int frac = lg >= 3 ? (int)((w >> (lg - 3)) & 7u) : (int)((w << (3 - lg)) & 7u);
+  return min(255, 1 + 8 * lg + frac);
+}
+
+__global__ void __launch_bounds__(kOrderThreads) tile_order_kernel(const uint64_t* __restrict__ ranges,
+                                                                   const uint32_t* __restrict__ work,
+                                                                   int64_t n_tiles,
+                                                                   uint32_t* __restrict__ order) {
+  __shared__ uint32_t cnt[256];
+  const int tid = threadIdx.x;
+  for (int i = tid; i < 256; i += kOrderThreads) cnt[i] = 0u;
+  __syncthreads();
+  auto bucket = [&](int64_t t) -> int {
+    const uint64_t w = work ? (uint64_t)work[t] : ranges[2 * t + 1] - ranges[2 * t];
+    return 255 - work_bucket((uint32_t)(w > 0xffffffffull ? 0xffffffffull : w));
+  };
+  for (int64_t t = tid; t < n_tiles; t += kOrderThreads) atomicAdd(&cnt[bucket(t)], 1u);
+  __syncthreads();
+  if (tid < 64) {                                   // exclusive scan of the 256 counts, 4 per lane
+    uint32_t c[4], s = 0u;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) { c[j] = cnt[4 * tid + j]; s += c[j]; }
+    uint32_t incl = s;
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) {
+      const uint32_t u = (uint32_t)__shfl_up((int)incl, off, 64);
+      if (tid >= off) incl += u;
+    }
+    uint32_t run = incl - s;
+#pragma unroll
+    for (int j = 0; j < 4; ++j) { cnt[4 * tid + j] = run; run += c[j]; }
+  }
+  __syncthreads();
+  for (int64_t t = tid; t < n_tiles; t += kOrderThreads)
+    order[atomicAdd(&cnt[bucket(t)], 1u)] = (uint32_t)t;
 }
 
 }  // namespace
@@ -411,11 +444,11 @@ hipError_t launch_splat_backward(hipStream_t st, const Seg* segs, const int64_t*
   return hipGetLastError();
 }
 
-hipError_t launch_tile_order_keys(hipStream_t st, const uint64_t* ranges, const uint32_t* work,
-                                  int64_t n_tiles, uint32_t* key, uint32_t* val) {
+hipError_t launch_tile_order(hipStream_t st, const uint64_t* ranges, const uint32_t* work,
+                             int64_t n_tiles, uint32_t* order) {
   if (n_tiles == 0) return hipSuccess;
-  hipLaunchKernelGGL(tile_order_keys_kernel, dim3((unsigned)((n_tiles + 255) / 256)), dim3(256), 0, st,
-                     ranges, work, n_tiles, key, val);
+  hipLaunchKernelGGL(tile_order_kernel, dim3(1), dim3(kOrderThreads), 0, st, ranges, work, n_tiles,
+                     order);
   return hipGetLastError();
 }
 

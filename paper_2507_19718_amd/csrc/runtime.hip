@@ -80,7 +80,7 @@ struct gsc_binning {
   DevBuf rec, depth_key, rect, tiles, ids, keys_tmp, ids_tmp, hist, rect_sorted;
   DevBuf counts, tile_total, partial, tile_start, ranges, scalars, values, n_contrib, grad2d;
   // heaviest-first tile schedules of the splat kernels
-  DevBuf ord_key, ord_val, ord_ktmp, ord_vtmp, ord_hist, ord_tab, tile_work;
+  DevBuf ord_val, tile_work;
   // list cut: per-Gaussian saturation cores (with their weights), [chunk][tile] weight sums,
   // per-tile last kept chunk, per-region placement chunk counts and first workgroups
   DevBuf core, core_sorted, wsum, cut, region_start, region_n;
@@ -104,8 +104,8 @@ struct gsc_binning {
   void free_all() {
     DevBuf* all[] = {&tables, &rec, &depth_key, &rect, &tiles, &ids, &keys_tmp, &ids_tmp, &hist,
                      &rect_sorted, &counts, &tile_total, &partial, &tile_start, &ranges, &scalars,
-                     &values, &n_contrib, &grad2d, &view_window, &view_screen, &ord_key, &ord_val,
-                     &ord_ktmp, &ord_vtmp, &ord_hist, &ord_tab, &tile_work, &core,
+                     &values, &n_contrib, &grad2d, &view_window, &view_screen, &ord_val,
+                     &tile_work, &core,
                      &core_sorted, &wsum, &cut, &region_start, &region_n};
     for (DevBuf* b : all) b->release(alloc);
   }
@@ -507,30 +507,13 @@ gsc_status run_project_bin(gsc_ctx* ctx, gsc_binning* b, uint64_t capacity_hint)
   return GSC_OK;
 }
 
-// Heaviest-first tile schedule for a splat launch: tiles sorted by decreasing work estimate
-// (work NULL: list length), ties in tile order.  Single-wave workgroups start in that order, so
-// the long tiles do not end up in the launch's tail.
+// Heaviest-first tile schedule for a splat launch: tiles in decreasing buckets of a work estimate
+// (work NULL: list length).  Single-wave workgroups start in that order, so the long tiles do not
+// end up in the launch's tail.
 const uint32_t* tile_order(gsc_ctx* ctx, gsc_binning* b, const uint32_t* work) {
-  const int64_t n = b->n_tiles;
-  const Alloc& a = b->alloc;
-  need(ctx, b->ord_key, a, 4 * (size_t)n, "tile order keys");
-  need(ctx, b->ord_val, a, 4 * (size_t)n, "tile order");
-  need(ctx, b->ord_ktmp, a, 4 * (size_t)n, "tile order keys (sort)");
-  need(ctx, b->ord_vtmp, a, 4 * (size_t)n, "tile order (sort)");
-  const int64_t seg_n[1] = {n}, seg_off[1] = {0};
-  const int nb = sort_count_blocks(seg_n, 1);
-  const size_t tab = sort_table_bytes(nb, 1);
-  std::vector<char> host(tab, 0);
-  sort_fill_table(host.data(), seg_n, seg_off, 1);
-  need(ctx, b->ord_tab, a, tab, "tile order sort table");
-  upload(ctx, b->ord_tab.p, host.data(), tab);
-  need(ctx, b->ord_hist, a, 4 * sort_hist_words(std::max(nb, 1), 1), "tile order histograms");
-  hipStream_t st = ctx->stream;
-  GSC_TRY(launch_tile_order_keys(st, b->ranges.as<uint64_t>(), work, n, b->ord_key.as<uint32_t>(),
-                                 b->ord_val.as<uint32_t>()));
-  GSC_TRY(launch_segmented_sort(st, b->ord_tab.p, nb, 1, b->ord_key.as<uint32_t>(),
-                                b->ord_val.as<uint32_t>(), b->ord_ktmp.as<uint32_t>(),
-                                b->ord_vtmp.as<uint32_t>(), b->ord_hist.as<uint32_t>()));
+  need(ctx, b->ord_val, b->alloc, 4 * (size_t)std::max<int64_t>(b->n_tiles, 1), "tile order");
+  GSC_TRY(launch_tile_order(ctx->stream, b->ranges.as<uint64_t>(), work, b->n_tiles,
+                            b->ord_val.as<uint32_t>()));
   return b->ord_val.as<uint32_t>();
 }
 
