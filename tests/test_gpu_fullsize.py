@@ -121,3 +121,51 @@ def test_fullsize_sampled_trace(full, gsc):
     sub = t[:, 500:532, 900:948]
     same = np.all(sub == ora["targets"], axis=(0, 3))
     assert same.mean() >= 0.999, same.mean()
+
+
+def test_fullsize_frame_composite_sampled(full, gsc):
+    """The benchmark's own configuration: one gsc_render_frame of the whole 1080p workload (all
+    levels in one batch, the trace on its second stream, cut tile lists), render only.  Sampled
+    composite pixels equal the oracle's composite of the oracle's per-level forward and the
+    oracle's traced record at that pixel."""
+    wl = full["wl"]
+    cam = full["cam"]
+    vol = wl.volume()
+    K = wl.K
+    scene = gsc.Scene(full["ctx"], gsc.Volume.from_synth(vol),
+                      [gsc.level_to_device(g) for g in full["levels_np"]])
+    image = torch.empty((cam.h, cam.w, 3), device="cuda")
+    req = gsc.frame_request(cam, wl.seed, 7, K, wl.max_bounces, loss=wl.loss, train=False, C=wl.C)
+    gsc.gsc_render_frame(full["ctx"], scene, req, image)
+    comp = to_np(image)
+    scene.destroy()
+    # The frame's own trace, for the rare pixel whose path differs from the oracle's in the last
+    # bit (the trace's bar is statistical): such pixels are skipped.
+    rec = torch.empty((cam.h, cam.w, 5), dtype=torch.int32, device="cuda")
+    tg = torch.empty((K, cam.h, cam.w, 3), device="cuda")
+    gsc.gsc_trace_targets(full["ctx"], gsc.Volume.from_synth(vol), cam,
+                          gsc.trace_params(wl.seed, 7, 1, wl.max_bounces, K, wl.C), tg, rec)
+    rec = to_np(rec).view(np.uint32)
+    rng = np.random.default_rng(2)
+    px = np.concatenate([rng.integers(0, cam.w, 14), [cam.w // 2, cam.w - 1]])
+    py = np.concatenate([rng.integers(0, cam.h, 14), [cam.h // 2, cam.h - 1]])
+    checked = 0
+    for x, y in zip(px, py):
+        pc = cam.crop(int(x), int(y), 1, 1)
+        imgs, boundary = [], False
+        for g in full["levels_np"]:
+            fw = oracle.forward(oracle.project(g, pc), g.rgb, pc)
+            boundary = boundary or bool(fw["boundary"][0, 0])
+            imgs.append(fw["image"])
+        if boundary:
+            continue
+        tr = oracle.trace(vol, pc, wl.seed, 7, 1, wl.max_bounces, K, C=wl.C)
+        r = rec[y, x]
+        if not (np.array_equal(r[:3].view(np.float32), tr["L"][0, 0]) and
+                (r[4] & 0xFFFF) == tr["n"][0, 0] and (r[4] >> 16) == tr["kind"][0, 0]):
+            continue
+        ref = oracle.composite(tr["n"], tr["kind"], tr["L"], tr["beta"], np.stack(imgs))[0, 0]
+        got = comp[y, x].astype(np.float64)
+        assert np.all(np.abs(got - ref) <= 1e-5 * max(1.0, float(np.abs(ref).max()))), (x, y, got, ref)
+        checked += 1
+    assert checked >= 10
