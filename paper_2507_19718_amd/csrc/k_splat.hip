@@ -125,6 +125,31 @@ __device__ __forceinline__ void window_masks(uint32_t wx, uint32_t wy, int xbase
   }
 }
 
+// The same masks computed in vector registers, one entry per lane, for a whole batch at once:
+// the forward then reads each entry's masks with readlane instead of rebuilding them on the
+// scalar unit, which is its busier unit.  (The adjoint is bound by vector issue and keeps the
+// scalar version.)
+__device__ __forceinline__ void window_masks_v(uint32_t wx, uint32_t wy, int xbase, int ybase,
+                                               uint64_t m[kPx]) {
+  const int lo = max((int)(wx & 0xffffu) - xbase, 0);
+  const int hi = min((int)(wx >> 16) - xbase, 15);
+  const uint32_t c16 = (lo <= hi) ? ((2u << hi) - (1u << lo)) : 0u;
+  const uint32_t c32 = c16 | (c16 << 16);
+  const uint64_t c64 = ((uint64_t)c32 << 32) | (uint64_t)c32;
+  const int ylo = (int)(wy & 0xffffu) - ybase, yhi = (int)(wy >> 16) - ybase;
+#pragma unroll
+  for (int p = 0; p < kPx; ++p) {
+    const int glo = max(ylo - 4 * p, 0), ghi = min(yhi - 4 * p, 3);
+    m[p] = (glo <= ghi) ? (c64 & (~0ull >> (48 - 16 * ghi)) & (~0ull << (16 * glo))) : 0ull;
+  }
+}
+
+__device__ __forceinline__ uint64_t rl64(uint64_t v, int k) {
+  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, k);
+  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), k);
+  return ((uint64_t)hi << 32) | lo;
+}
+
 __device__ __forceinline__ bool lane_in(uint64_t mask) {
   return __builtin_amdgcn_inverse_ballot_w64(mask);
 }
@@ -161,6 +186,8 @@ __global__ void __launch_bounds__(64) splat_forward_kernel(
       keep = may_touch(q0, q1, q2, tc);
     }
     uint64_t mask = __ballot(keep);
+    uint64_t wm[kPx];                      // each lane's entry: its slots' window masks
+    window_masks_v(__float_as_uint(q2.y), __float_as_uint(q2.z), tc.xbase, tc.ybase, wm);
     const uint32_t rel0 = (uint32_t)(bs - tc.start);
     while (mask) {
       if ((done[0] & done[1] & done[2] & done[3]) == ~0ull) break;
@@ -171,7 +198,8 @@ __global__ void __launch_bounds__(64) splat_forward_kernel(
       const float Cc = rl(q1.x, k), o = rl(q1.y, k);
       const float cr = rl(q1.z, k), cg = rl(q1.w, k), cb = rl(q2.x, k);
       uint64_t win[kPx];
-      window_masks(rlu(q2.y, k), rlu(q2.z, k), tc.xbase, tc.ybase, win);
+#pragma unroll
+      for (int p = 0; p < kPx; ++p) win[p] = rl64(wm[p], k);
       const float dx = u - tc.fi;
       const float adx = (A * dx) * dx;
       const float bdx = B * dx;
