@@ -260,12 +260,12 @@ __global__ void __launch_bounds__(64) splat_forward_kernel(
   }
 }
 
-// Sum over each 16-lane row; lane 15 of the row receives it (row shifts with zero fill).
+// Sum over each 16-lane row; lane 15 of the row receives it (a prefix sum by row shifts of
+// 1, 2, 4 and 8 lanes with zero fill).
 __device__ __forceinline__ float row_total(float v) {
   float t = v;
-  t = t + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x111, 0xf, 0xf, true));
-  t = t + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x112, 0xf, 0xf, true));
-  t = t + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(v), 0x113, 0xf, 0xf, true));
+  t = t + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(t), 0x111, 0xf, 0xf, true));
+  t = t + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(t), 0x112, 0xf, 0xf, true));
   t = t + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(t), 0x114, 0xf, 0xf, true));
   t = t + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(t), 0x118, 0xf, 0xf, true));
   return t;
