@@ -297,7 +297,7 @@ def main():
     ms_step = 1000.0 * elapsed / args.steps
 
     per_frame_inst = cnt["instances"] / max(cnt["binnings"], 1)
-    chunk = 2048                     # depth-ordered Gaussians per binning chunk (library constant)
+    chunk = 1024                     # depth-ordered Gaussians per binning chunk (library constant)
     TX, TY = (cam.w + 15) // 16, (cam.h + 15) // 16
     c = dict(gaussians=float(sum(g.n for g in levels)), instances=per_frame_inst,
              pixel_levels=float(cam.w * cam.h * wl.K), paths=float(cam.w * cam.h), K=wl.K,

@@ -18,7 +18,7 @@ namespace gsc {
 constexpr int kTile = 16;               // 16x16 pixel tiles
 constexpr int kMaxTf = 64;
 constexpr int kMaxLights = 8;
-constexpr int kChunk = 2048;            // depth-ordered Gaussians per binning chunk
+constexpr int kChunk = 1024;            // depth-ordered Gaussians per binning chunk
 
 struct DevCam {
   float R[9];

@@ -369,8 +369,8 @@ __global__ void __launch_bounds__(256) chunk_scan_kernel(const BinWork* __restri
   const int64_t T = (int64_t)W.TX * W.TY;
   uint32_t run = 0u, weight = 0u;
   int last = W.n_chunks - 1, last_nz = -1;
-  // Eight chunks' loads in flight at a time (the loop is latency-bound otherwise).
-  constexpr int kAhead = 8;
+  // Sixteen chunks' loads in flight at a time (the loop is latency-bound otherwise).
+  constexpr int kAhead = 16;
   for (int cb = 0; cb < W.n_chunks; cb += kAhead) {
     uint32_t v[kAhead], ws[kAhead];
 #pragma unroll
