@@ -233,6 +233,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--copy-probe", action="store_true",
                     help="only run a plain 1 GiB device copy 5 times (calibrates HBM counters)")
+    ap.add_argument("--deterministic", action="store_true",
+                    help="sum the splat adjoint in fixed point (bit-reproducible gradients)")
     ap.add_argument("--serve-seconds", type=float, default=8.0,
                     help="length of the Poisson request log replayed served vs plain (0: skip)")
     args = ap.parse_args()
@@ -259,6 +261,7 @@ def main():
     wl, vol, levels = build_inputs(args.workload)
     cam = wl.camera()
     ctx = gsc.Context(0)
+    ctx.set_deterministic(args.deterministic)
     scene = gsc.Scene(ctx, gsc.Volume.from_synth(vol), [gsc.level_to_device(g) for g in levels])
     image = torch.empty((cam.h, cam.w, 3), device="cuda")
     frame = 0
@@ -384,7 +387,8 @@ def main():
         "config": {"workload": f"{wl.name}: {wl.width}x{wl.height}, {wl.volume_res}^3 fBm, "
                                f"{wl.K} levels x {wl.levels[0]} Gaussians, B={wl.max_bounces}, "
                                f"C={wl.C}, HDR loss, AdamW wd={wl.weight_decay}, 1 spp",
-                   "parallelism": "single GPU"},
+                   "parallelism": "single GPU",
+                   "adjoint_sums": "fixed-point (deterministic)" if args.deterministic else "float atomics"},
         "roofline": roofline,
         "cpu_baseline": cpu,
         "frame_roofline_frac": round(frame_frac, 4),

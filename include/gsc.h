@@ -34,9 +34,10 @@
  *     instance counts are 64-bit.
  *   - Threading: a context is used by one host thread at a time; several contexts may share a
  *     device (one per concurrently running stream).
- *   - Determinism: every output is deterministic except the float-atomic sums of
- *     gsc_splat_backward (order of accumulation across tiles); a fixed-order mode is not
- *     provided (gsc_ctx_set_deterministic(ctx, 1) returns GSC_E_UNSUPPORTED).
+ *   - Determinism: every output is deterministic except, by default, the float-atomic sums of
+ *     the splat adjoint (gsc_splat_backward and the training step of the frame calls), whose
+ *     order of accumulation across tiles varies from run to run.  gsc_ctx_set_deterministic
+ *     makes them reproducible bit for bit.
  */
 #ifndef GSC_H_
 #define GSC_H_
@@ -230,6 +231,15 @@ void gsc_ctx_destroy(gsc_ctx* ctx);
 /* HOST string, valid until the next call on ctx. */
 const char* gsc_ctx_last_error(const gsc_ctx* ctx);
 gsc_status gsc_ctx_set_stream(gsc_ctx* ctx, void* hip_stream);
+/* on != 0: the splat adjoint (gsc_splat_backward, and the training step of gsc_render_frame /
+ * gsc_render_frames) sums each Gaussian's per-tile gradient partials as 64-bit fixed-point
+ * integers instead of float atomics, so its gradients, and the parameters AdamW then writes, are
+ * the same bit for bit on every run.  A first pass over the tiles finds the largest |partial| of
+ * each gradient component of each Gaussian; a second rounds every partial to 2^-41 of that and
+ * adds the integers; the sum converts back to float.  The result differs from the float-atomic
+ * one by the rounding of the partials (a relative 2^-41 of the largest partial each) and of the
+ * float sums.  Costs a second pass of the adjoint and 108 bytes of device memory per Gaussian.
+ * Off by default; the setting stays until changed.  Returns GSC_E_INVALID_ARG for a NULL ctx. */
 gsc_status gsc_ctx_set_deterministic(gsc_ctx* ctx, int32_t on);
 /* Frames (gsc_render_frame / gsc_render_frames) bin each tile's list only up to the depth by
  * which every pixel of the tile has surely stopped blending (on by default): a Gaussian whose

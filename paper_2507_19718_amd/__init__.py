@@ -152,6 +152,10 @@ class Context:
         """Frames bin only the list prefixes that can reach a pixel (default on)."""
         self.check(self._lib.gsc_ctx_set_list_cut(self.handle, 1 if on else 0))
 
+    def set_deterministic(self, on: bool):
+        """Sum the splat adjoint in fixed point so gradients repeat bit for bit (default off)."""
+        self.check(self._lib.gsc_ctx_set_deterministic(self.handle, 1 if on else 0))
+
     def counters(self):
         c = _abi.gsc_counters()
         self.check(self._lib.gsc_ctx_counters(self.handle, ctypes.byref(c)))

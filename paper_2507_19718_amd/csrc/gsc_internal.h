@@ -152,12 +152,14 @@ hipError_t launch_splat_forward(hipStream_t st, const Seg* segs, const int64_t* 
 // Keys ordering tiles by decreasing work (work NULL: list length from ranges).
 hipError_t launch_tile_order(hipStream_t st, const uint64_t* ranges, const uint32_t* work,
                              int64_t n_tiles, uint32_t* order);
+// gmax NULL: float atomics into grad2d (zeroed by the caller).  Otherwise the deterministic
+// fixed-point accumulation (gmax[9 G] and gfix[9 G] zeroed by the caller); grad2d is overwritten.
 hipError_t launch_splat_backward(hipStream_t st, const Seg* segs, const int64_t* seg_tstart, int S,
                                  const DevCam* cams, int64_t n_tiles, const uint64_t* ranges,
                                  const uint32_t* values, const SplatRec* rec, const float* final_T,
                                  const uint32_t* n_contrib, const float* dL_dimages,
-                                 float* grad2d, int64_t G, int deterministic,
-                                 const uint32_t* order);
+                                 float* grad2d, int64_t G, const uint32_t* order, uint32_t* gmax,
+                                 unsigned long long* gfix);
 
 int64_t trace_align(int64_t pixels);
 hipError_t launch_trace(hipStream_t st, const TraceDesc* descs, const int64_t* req_pstart, int R,

@@ -260,6 +260,28 @@ __global__ void __launch_bounds__(64) splat_forward_kernel(
   }
 }
 
+// The adjoint's ways of accumulating the per-(tile, Gaussian) partials: float atomics into grad2d;
+// or, deterministically, a first pass that finds the largest |partial| of each gradient component
+// of each Gaussian and a second that adds round(partial * scale) as 64-bit integers, with
+// scale = 2^(40 - e) for a largest |partial| in [2^e, 2^(e+1)).  Every rounded partial is below
+// 2^41 and a Gaussian has at most one partial per tile (at most 2^20 tiles in an image), so the
+// integer sum stays below 2^61; each partial is kept to 2^-41 of the Gaussian's largest.
+enum { kAdjointAtomic = 0, kAdjointMax = 1, kAdjointFixed = 2 };
+
+__device__ __forceinline__ double fixed_scale(uint32_t max_bits) {
+  const float m = __uint_as_float(max_bits);
+  return m > 0.0f ? ldexp(1.0, 45 - ilogbf(m)) : 0.0;
+}
+
+__global__ void __launch_bounds__(256) fixed_to_float_kernel(const uint32_t* __restrict__ gmax,
+                                                             const unsigned long long* __restrict__ gfix,
+                                                             int64_t G, float* __restrict__ grad2d) {
+  const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+  if (i >= 9 * G) return;
+  const double sc = fixed_scale(gmax[i]);
+  grad2d[i] = sc > 0.0 ? (float)((double)(long long)gfix[i] / sc) : 0.0f;
+}
+
 // Sum over each 16-lane row; lane 15 of the row receives it (a prefix sum by row shifts of
 // 1, 2, 4 and 8 lanes with zero fill).
 __device__ __forceinline__ float row_total(float v) {
@@ -277,7 +299,8 @@ __global__ void __launch_bounds__(64) splat_backward_kernel(
     const uint32_t* __restrict__ values, const SplatRec* __restrict__ rec,
     const float* __restrict__ final_T, const uint32_t* __restrict__ n_contrib,
     const float* __restrict__ dL_dimages, float* __restrict__ grad2d, int64_t G,
-    const uint32_t* __restrict__ order) {
+    const uint32_t* __restrict__ order, int mode, uint32_t* __restrict__ gmax,
+    unsigned long long* __restrict__ gfix) {
   __shared__ float part[4][64][kPartStride];
   const int64_t t = order ? (int64_t)order[blockIdx.x] : (int64_t)blockIdx.x;
   const Tile tc = tile_setup(segs, seg_tstart, S, cams, ranges, t);
@@ -385,12 +408,28 @@ __global__ void __launch_bounds__(64) splat_backward_kernel(
     }
     if (has == 0ull) continue;
     __syncthreads();
-    if ((has >> lane) & 1ull) {
-      const int64_t gi = tc.g_off + (int64_t)my_id;
+    const bool mine = (has >> lane) & 1ull;
+    const int64_t gi = tc.g_off + (int64_t)my_id;
+    if (mode == kAdjointAtomic) {
+      if (mine) {
+#pragma unroll
+        for (int a = 0; a < 9; ++a) {
+          const float acc = (part[0][lane][a] + part[1][lane][a]) + (part[2][lane][a] + part[3][lane][a]);
+          if (acc != 0.0f) unsafeAtomicAdd(&grad2d[(int64_t)a * G + gi], acc);
+        }
+      }
+    } else if (mine) {
 #pragma unroll
       for (int a = 0; a < 9; ++a) {
         const float acc = (part[0][lane][a] + part[1][lane][a]) + (part[2][lane][a] + part[3][lane][a]);
-        if (acc != 0.0f) unsafeAtomicAdd(&grad2d[(int64_t)a * G + gi], acc);
+        const int64_t at = (int64_t)a * G + gi;
+        if (mode == kAdjointMax) {
+          if (acc != 0.0f) atomicMax(&gmax[at], __float_as_uint(fabsf(acc)));
+        } else {
+          // Integer sums do not depend on the order in which the atomics land.
+          const long long q = llrint((double)acc * fixed_scale(gmax[at]));
+          if (q) atomicAdd(&gfix[at], (unsigned long long)q);
+        }
       }
     }
     __syncthreads();
@@ -462,13 +501,25 @@ hipError_t launch_splat_backward(hipStream_t st, const Seg* segs, const int64_t*
                                  const DevCam* cams, int64_t n_tiles, const uint64_t* ranges,
                                  const uint32_t* values, const SplatRec* rec, const float* final_T,
                                  const uint32_t* n_contrib, const float* dL_dimages,
-                                 float* grad2d, int64_t G, int deterministic,
-                                 const uint32_t* order) {
-  (void)deterministic;
+                                 float* grad2d, int64_t G, const uint32_t* order, uint32_t* gmax,
+                                 unsigned long long* gfix) {
   if (n_tiles == 0) return hipSuccess;
+  if (!gmax) {
+    hipLaunchKernelGGL(splat_backward_kernel, dim3((unsigned)n_tiles), dim3(64), 0, st, segs,
+                       seg_tstart, S, cams, ranges, values, rec, final_T, n_contrib, dL_dimages,
+                       grad2d, G, order, (int)kAdjointAtomic, gmax, gfix);
+    return hipGetLastError();
+  }
+  // Deterministic: gmax [9][G] and gfix [9][G] must be zero on entry.
   hipLaunchKernelGGL(splat_backward_kernel, dim3((unsigned)n_tiles), dim3(64), 0, st, segs,
                      seg_tstart, S, cams, ranges, values, rec, final_T, n_contrib, dL_dimages,
-                     grad2d, G, order);
+                     grad2d, G, order, (int)kAdjointMax, gmax, gfix);
+  hipLaunchKernelGGL(splat_backward_kernel, dim3((unsigned)n_tiles), dim3(64), 0, st, segs,
+                     seg_tstart, S, cams, ranges, values, rec, final_T, n_contrib, dL_dimages,
+                     grad2d, G, order, (int)kAdjointFixed, gmax, gfix);
+  if (G > 0)
+    hipLaunchKernelGGL(fixed_to_float_kernel, dim3((unsigned)((9 * G + 255) / 256)), dim3(256), 0,
+                       st, gmax, gfix, G, grad2d);
   return hipGetLastError();
 }
 

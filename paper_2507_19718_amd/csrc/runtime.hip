@@ -84,6 +84,7 @@ struct gsc_binning {
   // list cut: per-Gaussian saturation cores (with their weights), [chunk][tile] weight sums,
   // per-tile last kept chunk, per-region placement chunk counts and first workgroups
   DevBuf core, core_sorted, wsum, cut, region_start, region_n;
+  DevBuf gfix;                     // deterministic adjoint: [9][G] fixed-point sums, [9][G] maxima
   bool list_cut = false;
   uint64_t n_instances = 0;
   uint64_t capacity = 0;
@@ -106,7 +107,7 @@ struct gsc_binning {
                      &rect_sorted, &counts, &tile_total, &partial, &tile_start, &ranges, &scalars,
                      &values, &n_contrib, &grad2d, &view_window, &view_screen, &ord_val,
                      &tile_work, &core,
-                     &core_sorted, &wsum, &cut, &region_start, &region_n};
+                     &core_sorted, &wsum, &cut, &region_start, &region_n, &gfix};
     for (DevBuf* b : all) b->release(alloc);
   }
 };
@@ -538,13 +539,22 @@ void run_forward(gsc_ctx* ctx, gsc_binning* b, float* images, float* final_T, in
 void run_backward(gsc_ctx* ctx, gsc_binning* b, const float* final_T, const float* dL,
                   float* grads14) {
   need(ctx, b->grad2d, b->alloc, 4 * 9 * (size_t)std::max<int64_t>(b->G, 1), "2D gradients");
-  GSC_TRY(hipMemsetAsync(b->grad2d.p, 0, 4 * 9 * (size_t)b->G, ctx->stream));
+  uint32_t* gmax = nullptr;
+  unsigned long long* gfix = nullptr;
+  if (ctx->deterministic) {
+    need(ctx, b->gfix, b->alloc, 12 * 9 * (size_t)std::max<int64_t>(b->G, 1), "fixed-point gradients");
+    GSC_TRY(hipMemsetAsync(b->gfix.p, 0, 12 * 9 * (size_t)b->G, ctx->stream));
+    gfix = b->gfix.as<unsigned long long>();
+    gmax = (uint32_t*)(gfix + 9 * (size_t)b->G);
+  } else {
+    GSC_TRY(hipMemsetAsync(b->grad2d.p, 0, 4 * 9 * (size_t)b->G, ctx->stream));
+  }
   const uint32_t* order = tile_order(ctx, b, b->tile_work.as<uint32_t>());
   { ProfScope ps_(ctx, P_BWD, ctx->stream);
   GSC_TRY(launch_splat_backward(ctx->stream, b->d_segs(), b->d_tstart(), b->S, b->d_cams(), b->n_tiles,
                                 b->ranges.as<uint64_t>(), b->values.as<uint32_t>(),
                                 b->rec.as<SplatRec>(), final_T, b->n_contrib.as<uint32_t>(), dL,
-                                b->grad2d.as<float>(), b->G, ctx->deterministic, order));
+                                b->grad2d.as<float>(), b->G, order, gmax, gfix));
   }
   { ProfScope ps_(ctx, P_PBWD, ctx->stream);
   GSC_TRY(launch_project_backward(ctx->stream, b->d_segs(), b->d_gstart(), b->S, b->d_cams(), b->G,
@@ -920,8 +930,7 @@ gsc_status gsc_ctx_set_stream(gsc_ctx* ctx, void* hip_stream) {
 
 gsc_status gsc_ctx_set_deterministic(gsc_ctx* ctx, int32_t on) {
   if (!ctx) return GSC_E_INVALID_ARG;
-  if (on) { ctx->err = "deterministic backward reduction is not available"; return GSC_E_UNSUPPORTED; }
-  ctx->deterministic = 0;
+  ctx->deterministic = on ? 1 : 0;
   return GSC_OK;
 }
 
