@@ -358,9 +358,7 @@ __global__ void __launch_bounds__(64) splat_backward_kernel(
       const float mAdx = -A * dx, mBdx = -B * dx;
       const float inv_o = __builtin_amdgcn_rcpf(o);
       const uint32_t rel = rel0 + (uint32_t)k;
-      // dL/dpower summed over the lane's pixels with weights 1, dy and dy^2: dx is the same for
-      // all four, so the conic, mean and opacity sums follow from these three moments.
-      float m0 = 0.0f, m1 = 0.0f, m2 = 0.0f;
+      float su = 0.0f, sv = 0.0f, sA = 0.0f, sB = 0.0f, sC = 0.0f, so = 0.0f;
       float sr = 0.0f, sg = 0.0f, sb = 0.0f;
       uint64_t any = 0ull;
 #pragma unroll
@@ -390,16 +388,15 @@ __global__ void __launch_bounds__(64) splat_backward_kernel(
         // alpha not clamped: it depends on power and opacity (dL/do = dL/dpower / o).
         const bool unclamped = lane_in(__builtin_amdgcn_ballot_w64(!(oe > kAlphaMax)));
         const float dpow = unclamped ? dal * az : 0.0f;
-        const float tdy = dpow * dy;
-        m0 += dpow;
-        m1 += tdy;
-        m2 = fmaf(tdy, dy, m2);
+        so = fmaf(dpow, inv_o, so);
+        sA = fmaf(dpow, hdx2, sA);
+        sC = fmaf(dpow, (-0.5f * dy) * dy, sC);
+        sB = fmaf(dpow, -dx * dy, sB);
+        su = fmaf(dpow, fmaf(-B, dy, mAdx), su);
+        sv = fmaf(dpow, fmaf(-Cc, dy, mBdx), sv);
       }
       if (any == 0ull) continue;
       has |= 1ull << k;
-      // power = -A dx^2 / 2 - B dx dy - C dy^2 / 2 with dx = u - x, dy = v - y.
-      const float so = m0 * inv_o, sA = m0 * hdx2, sC = -0.5f * m2, sB = -dx * m1;
-      const float su = fmaf(-B, m1, mAdx * m0), sv = fmaf(-Cc, m1, mBdx * m0);
       const float r0 = row_total(su), r1 = row_total(sv), r2 = row_total(sA);
       const float r3 = row_total(sB), r4 = row_total(sC), r5 = row_total(so);
       const float r6 = row_total(sr), r7 = row_total(sg), r8 = row_total(sb);
