@@ -401,6 +401,22 @@ gsc_status gsc_scene_state(const gsc_scene* scene, int32_t l, float** params, fl
                            int64_t* n, int64_t* step);
 /* Copies parameters, moments and step counters from src to dst (same level sizes). */
 gsc_status gsc_scene_copy_state(gsc_ctx* ctx, gsc_scene* dst, const gsc_scene* src);
+/* Checkpoint of the cache's optimiser state (all levels' parameters, AdamW moments and step
+ * counts) to the HOST file `path`: one JSON header line
+ *   {"format":"gsc-scene-state","version":1,"dtype":"float32","byte_order":"little",
+ *    "levels":[{"n":N,"step":S},...]}
+ * (written without the line break shown here) and a newline, then per level params, m and v,
+ * each 14 n little-endian float32 in the layout of gsc_scene_state.  The volume, transfer
+ * function and lights are not saved (they belong to the scene's creation and gsc_scene_set_optics),
+ * nor is Eq. 5's viewport count, which each frame request carries.  Waits for the work already
+ * enqueued on the context's stream, then copies through host memory; synchronous.  A failed write
+ * returns GSC_E_INVALID_ARG and leaves an incomplete file. */
+gsc_status gsc_scene_save(gsc_ctx* ctx, const gsc_scene* scene, const char* path);
+/* Restores a state written by gsc_scene_save into `scene`, whose level count and sizes must
+ * equal the file's.  The header, the level sizes and the file length are checked before the
+ * device is touched (GSC_E_INVALID_ARG, scene unchanged); the copies are ordered after the
+ * work already enqueued on the context's stream and complete before the call returns. */
+gsc_status gsc_scene_load(gsc_ctx* ctx, gsc_scene* scene, const char* path);
 /* Resident bytes: the cell-corner grid (32 (nx+1)(ny+1)(nz+1)) + 3 x 14 fp32 per Gaussian
  * (parameters and two moments). */
 size_t gsc_scene_footprint_bytes(const gsc_scene* scene);

@@ -12,6 +12,7 @@ from __future__ import annotations
 
 import ctypes
 import math
+import os
 import weakref
 from typing import Dict, List, Optional, Sequence
 
@@ -513,6 +514,16 @@ class Scene:
 
     def copy_state_from(self, other: "Scene"):
         self.ctx.check(self.ctx._lib.gsc_scene_copy_state(self.ctx.handle, self.handle, other.handle))
+
+    def save(self, path: str):
+        """Checkpoints every level's parameters, AdamW moments and step count to a file."""
+        self.ctx.check(self.ctx._lib.gsc_scene_save(self.ctx.handle, self.handle,
+                                                    os.fsencode(path)))
+
+    def load(self, path: str):
+        """Restores a checkpoint written by save() (same level count and sizes)."""
+        self.ctx.check(self.ctx._lib.gsc_scene_load(self.ctx.handle, self.handle,
+                                                    os.fsencode(path)))
 
     def footprint_bytes(self) -> int:
         return int(self.ctx._lib.gsc_scene_footprint_bytes(self.handle))

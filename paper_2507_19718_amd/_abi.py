@@ -143,6 +143,8 @@ _SIGNATURES = {
     "gsc_scene_state": (c_int32, [c_void_p, c_int32, P(c_void_p), P(c_void_p), P(c_void_p),
                                   P(c_int64), P(c_int64)]),
     "gsc_scene_copy_state": (c_int32, [c_void_p, c_void_p, c_void_p]),
+    "gsc_scene_save": (c_int32, [c_void_p, c_void_p, ctypes.c_char_p]),
+    "gsc_scene_load": (c_int32, [c_void_p, c_void_p, ctypes.c_char_p]),
     "gsc_scene_footprint_bytes": (c_size_t, [c_void_p]),
     "gsc_frame_footprint_bytes": (c_size_t, [c_void_p, c_int32, c_int32, c_uint64]),
     "gsc_render_frame": (c_int32, [c_void_p, c_void_p, P(gsc_frame_request), c_void_p,

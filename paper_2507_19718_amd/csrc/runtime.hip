@@ -856,6 +856,55 @@ gsc_status render_batch(gsc_ctx* ctx, gsc_scene* const* scenes, const gsc_frame_
 
 }  // namespace
 
+// ---- checkpoint of the cache state ---------------------------------------------------------
+// File: one header line of JSON written in exactly this form,
+//   {"format":"gsc-scene-state","version":1,"dtype":"float32","byte_order":"little","levels":[{"n":N,"step":S},...]}\n
+// then, per level, params, m and v, each 14 n float32 in the [pos][rot][log_scale][rgb][opacity]
+// layout of the scene.  The loader accepts exactly what the writer produces.
+namespace {
+
+constexpr const char* kStateMagic = "{\"format\":\"gsc-scene-state\",\"version\":1,\"dtype\":\"float32\","
+                                    "\"byte_order\":\"little\",\"levels\":[";
+
+bool host_is_little_endian() {
+  const uint32_t one = 1u;
+  unsigned char b;
+  std::memcpy(&b, &one, 1);
+  return b == 1;
+}
+
+struct File {
+  FILE* f = nullptr;
+  ~File() { if (f) std::fclose(f); }
+};
+
+// Parses the header line; returns the per-level (n, step) pairs or fails with a message.
+std::vector<std::pair<int64_t, int64_t>> parse_state_header(gsc_ctx* ctx, const std::string& line) {
+  const size_t m = std::strlen(kStateMagic);
+  if (line.compare(0, m, kStateMagic) != 0) invalid(ctx, "not a scene state file (header mismatch)");
+  std::vector<std::pair<int64_t, int64_t>> lv;
+  size_t pos = m;
+  for (;;) {
+    if (pos < line.size() && line[pos] == ']') break;
+    if (!lv.empty()) {
+      if (pos >= line.size() || line[pos] != ',') invalid(ctx, "malformed level list in scene state header");
+      ++pos;
+    }
+    long long n = -1, step = -1;
+    int used = 0;
+    if (std::sscanf(line.c_str() + pos, "{\"n\":%lld,\"step\":%lld}%n", &n, &step, &used) != 2 || used == 0)
+      invalid(ctx, "malformed level entry in scene state header");
+    if (n < 0 || step < 0) invalid(ctx, "negative size or step in scene state header");
+    lv.emplace_back((int64_t)n, (int64_t)step);
+    pos += (size_t)used;
+    if (lv.size() > 64) invalid(ctx, "too many levels in scene state header");
+  }
+  if (line.compare(pos, std::string::npos, "]}") != 0) invalid(ctx, "malformed end of scene state header");
+  return lv;
+}
+
+}  // namespace
+
 // =============================================================================================
 // C ABI
 // =============================================================================================
@@ -1292,6 +1341,82 @@ gsc_status gsc_scene_copy_state(gsc_ctx* ctx, gsc_scene* dst, const gsc_scene* s
       GSC_TRY(hipMemcpyAsync(dst->v[l], src->v[l], bytes, hipMemcpyDeviceToDevice, ctx->stream));
       dst->step[l] = src->step[l];
     }
+    return GSC_OK;
+  });
+}
+
+
+gsc_status gsc_scene_save(gsc_ctx* ctx, const gsc_scene* sc, const char* path) {
+  return guarded(ctx, [&]() -> gsc_status {
+    if (!sc || !path) invalid(ctx, "NULL scene or path");
+    if (!host_is_little_endian()) invalid(ctx, "scene state files are little-endian; host is not");
+    std::string hdr = kStateMagic;
+    for (int l = 0; l < sc->K; ++l) {
+      char buf[96];
+      std::snprintf(buf, sizeof buf, "%s{\"n\":%lld,\"step\":%lld}", l ? "," : "", (long long)sc->n[l],
+                    (long long)sc->step[l]);
+      hdr += buf;
+    }
+    hdr += "]}\n";
+    File out;
+    out.f = std::fopen(path, "wb");
+    if (!out.f) invalid(ctx, std::string("cannot open ") + path + " for writing");
+    if (std::fwrite(hdr.data(), 1, hdr.size(), out.f) != hdr.size()) invalid(ctx, "write failed");
+    std::vector<float> host;
+    for (int l = 0; l < sc->K; ++l) {
+      const size_t cnt = 14 * (size_t)sc->n[l];
+      if (cnt == 0) continue;
+      host.resize(cnt);
+      for (float* dev : {sc->params[l], sc->m[l], sc->v[l]}) {
+        GSC_TRY(hipMemcpyAsync(host.data(), dev, 4 * cnt, hipMemcpyDeviceToHost, ctx->stream));
+        GSC_TRY(hipStreamSynchronize(ctx->stream));
+        if (std::fwrite(host.data(), 4, cnt, out.f) != cnt) invalid(ctx, "write failed");
+      }
+    }
+    if (std::fclose(out.f) != 0) { out.f = nullptr; invalid(ctx, "write failed"); }
+    out.f = nullptr;
+    return GSC_OK;
+  });
+}
+
+gsc_status gsc_scene_load(gsc_ctx* ctx, gsc_scene* sc, const char* path) {
+  return guarded(ctx, [&]() -> gsc_status {
+    if (!sc || !path) invalid(ctx, "NULL scene or path");
+    if (!host_is_little_endian()) invalid(ctx, "scene state files are little-endian; host is not");
+    File in;
+    in.f = std::fopen(path, "rb");
+    if (!in.f) invalid(ctx, std::string("cannot open ") + path);
+    std::string line;
+    for (int c; (c = std::fgetc(in.f)) != '\n';) {
+      if (c == EOF) invalid(ctx, "scene state file ends inside its header");
+      line.push_back((char)c);
+      if (line.size() > (1u << 16)) invalid(ctx, "scene state header too long");
+    }
+    const auto lv = parse_state_header(ctx, line);
+    if ((int)lv.size() != sc->K) invalid(ctx, "scene state file holds a different number of levels");
+    size_t payload = 0;
+    for (int l = 0; l < sc->K; ++l) {
+      if (lv[l].first != sc->n[l]) invalid(ctx, "scene state file holds different level sizes");
+      payload += 3 * 14 * 4 * (size_t)sc->n[l];
+    }
+    const long start = std::ftell(in.f);
+    if (start < 0 || std::fseek(in.f, 0, SEEK_END) != 0) invalid(ctx, "cannot size scene state file");
+    const long end = std::ftell(in.f);
+    if (end < 0 || (size_t)(end - start) != payload) invalid(ctx, "scene state file has the wrong length");
+    if (std::fseek(in.f, start, SEEK_SET) != 0) invalid(ctx, "cannot read scene state file");
+    // Everything is validated; only now is the device touched.
+    std::vector<float> host;
+    for (int l = 0; l < sc->K; ++l) {
+      const size_t cnt = 14 * (size_t)sc->n[l];
+      if (cnt == 0) continue;
+      host.resize(cnt);
+      for (float* dev : {sc->params[l], sc->m[l], sc->v[l]}) {
+        if (std::fread(host.data(), 4, cnt, in.f) != cnt) invalid(ctx, "read failed");
+        GSC_TRY(hipMemcpyAsync(dev, host.data(), 4 * cnt, hipMemcpyHostToDevice, ctx->stream));
+        GSC_TRY(hipStreamSynchronize(ctx->stream));
+      }
+    }
+    for (int l = 0; l < sc->K; ++l) sc->step[l] = lv[l].second;
     return GSC_OK;
   });
 }
