@@ -67,12 +67,35 @@ __global__ void __launch_bounds__(256) gather_rect_kernel(const int64_t* __restr
   if (core) core_sorted[i] = core[src];
 }
 
+// Inclusive prefix sum over the 64 lanes by DPP: row shifts of 1, 2, 4 and 8 lanes (zero fill)
+// scan each 16-lane row, then lane 15 of rows 0 and 2 is added to rows 1 and 3, and lane 31 to
+// rows 2 and 3.  Every lane of the wavefront must be active.
+__device__ __forceinline__ int wave_inclusive_scan(int v) {
+  v += __builtin_amdgcn_update_dpp(0, v, 0x111, 0xf, 0xf, true);
+  v += __builtin_amdgcn_update_dpp(0, v, 0x112, 0xf, 0xf, true);
+  v += __builtin_amdgcn_update_dpp(0, v, 0x114, 0xf, 0xf, true);
+  v += __builtin_amdgcn_update_dpp(0, v, 0x118, 0xf, 0xf, true);
+  v += __builtin_amdgcn_update_dpp(0, v, 0x142, 0xa, 0xf, false);
+  v += __builtin_amdgcn_update_dpp(0, v, 0x143, 0xc, 0xf, false);
+  return v;
+}
+
 // 2D prefix sum in place of a band's difference array D[R][TX] (down the columns, then along
 // the rows, one wavefront per row).  Ends with a barrier.
 __device__ __forceinline__ void band_prefix_sum(int32_t* D, int R, int TX) {
   for (int x = threadIdx.x; x < TX; x += 256) {
-    int run = 0;
-    for (int y = 0; y < R; ++y) {
+    int run = 0, y = 0;
+    for (; y + 8 <= R; y += 8) {             // eight loads in flight, then the running sums
+      int t[8];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) t[j] = D[(y + j) * TX + x];
+#pragma unroll
+      for (int j = 0; j < 8; ++j) {
+        run += t[j];
+        D[(y + j) * TX + x] = run;
+      }
+    }
+    for (; y < R; ++y) {
       run += D[y * TX + x];
       D[y * TX + x] = run;
     }
@@ -83,14 +106,9 @@ __device__ __forceinline__ void band_prefix_sum(int32_t* D, int R, int TX) {
     int carry = 0;
     for (int xb = 0; xb < TX; xb += 64) {
       const int x = xb + lane;
-      int v = (x < TX) ? D[y * TX + x] : 0;
-#pragma unroll
-      for (int off = 1; off < 64; off <<= 1) {
-        const int u = __shfl_up(v, off, 64);
-        if (lane >= off) v += u;
-      }
+      const int v = wave_inclusive_scan((x < TX) ? D[y * TX + x] : 0);
       if (x < TX) D[y * TX + x] = carry + v;
-      carry += __shfl(v, 63, 64);
+      carry += __builtin_amdgcn_readlane(v, 63);
     }
   }
   __syncthreads();

@@ -205,15 +205,19 @@ def slab_volume(d: np.ndarray, seed: int, n_slabs: int = 32, density: float = 50
         c = g.uniform(0.2, 0.8, size=3)
         half = g.uniform(0.0025, 0.01)
         rad = g.uniform(0.1, 0.3)
-        for z0 in range(0, res, 32):
-            z1 = min(res, z0 + 32)
+        # Voxels farther than rad + half from the centre along any axis cannot be in the slab
+        # (|p - c|^2 = dist^2 + inplane^2 <= half^2 + rad^2), so only that box is visited.
+        lo = np.searchsorted(x, c - (rad + half) - 2.0 / res)
+        hi = np.searchsorted(x, c + (rad + half) + 2.0 / res)
+        py = x[None, lo[1]:hi[1], None] - c[1]
+        px = x[None, None, lo[0]:hi[0]] - c[0]
+        for z0 in range(lo[2], hi[2], 32):
+            z1 = min(hi[2], z0 + 32)
             pz = x[z0:z1, None, None] - c[2]
-            py = x[None, :, None] - c[1]
-            px = x[None, None, :] - c[0]
             dist = px * nrm[0] + py * nrm[1] + pz * nrm[2]
             inplane2 = px * px + py * py + pz * pz - dist * dist
             m = (np.abs(dist) <= half) & (inplane2 <= rad * rad)
-            sl = d[z0:z1]
+            sl = d[z0:z1, lo[1]:hi[1], lo[0]:hi[0]]
             sl[m] = np.maximum(sl[m], np.float32(density))
     return d
 
