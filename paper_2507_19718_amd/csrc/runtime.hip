@@ -6,6 +6,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <functional>
 #include <new>
 #include <string>
 #include <vector>
@@ -411,7 +412,11 @@ void plan_batch(gsc_ctx* ctx, gsc_binning* b, const std::vector<ReqSpec>& reqs) 
 
 // Projection, depth sort and binning of a planned batch.  capacity_hint 0: exact sizing with one
 // read-back of the instance count.
-gsc_status run_project_bin(gsc_ctx* ctx, gsc_binning* b, uint64_t capacity_hint) {
+// after_count, if set, is called once the per-(chunk, tile) counts are enqueued.  Frames start
+// the tracer there: it then overlaps the scans, the placement and the forward splat, and stays
+// off the LDS-heavy sort and count kernels.
+gsc_status run_project_bin(gsc_ctx* ctx, gsc_binning* b, uint64_t capacity_hint,
+                           const std::function<void()>& after_count = {}) {
   const Alloc& a = b->alloc;
   const int64_t G = b->G;
   const int64_t Gp = std::max<int64_t>(G, 1);
@@ -467,6 +472,7 @@ gsc_status run_project_bin(gsc_ctx* ctx, gsc_binning* b, uint64_t capacity_hint)
   GSC_TRY(launch_bin_count(st, b->d_work(), b->S, b->count_blocks, b->rect_sorted.as<uint64_t>(),
                            b->counts.as<uint32_t>(), core_sorted, wsum));
   }
+  if (after_count) after_count();
   { ProfScope ps_(ctx, P_SCAN, st);
   GSC_TRY(launch_bin_scan(st, b->d_work(), b->S, b->d_tstart(), b->n_tiles, b->counts.as<uint32_t>(),
                           b->tile_total.as<uint32_t>(), b->partial.as<uint64_t>(),
@@ -746,24 +752,33 @@ gsc_status render_batch(gsc_ctx* ctx, gsc_scene* const* scenes, const gsc_frame_
   std::memcpy(th.data(), td.data(), sizeof(TraceDesc) * n);
   std::memcpy(th.data() + sizeof(TraceDesc) * n, tstart.data(), sizeof(int64_t) * n);
   upload(ctx, ctx->trace_tab.p, th.data(), tbytes);
-  GSC_TRY(hipMemsetAsync(ctx->vertices.p, 0, 8, st));
-  GSC_TRY(hipEventRecord(ctx->ev_fork, st));
-  GSC_TRY(hipStreamWaitEvent(ctx->side, ctx->ev_fork, 0));
-  if (timing) GSC_TRY(hipEventRecord(ctx->tev[6], ctx->side));
-  { ProfScope ps_(ctx, P_TRACE, ctx->side);
-  GSC_TRY(launch_trace(ctx->side, ctx->trace_tab.as<TraceDesc>(),
-                       (const int64_t*)((char*)ctx->trace_tab.p + sizeof(TraceDesc) * n), n, tlaunch,
-                       ctx->vertices.as<unsigned long long>()));
-  }
-  if (timing) GSC_TRY(hipEventRecord(ctx->tev[7], ctx->side));
-  GSC_TRY(hipEventRecord(ctx->ev_join, ctx->side));
+  // The trace is independent of the cache; it runs on the side stream from the end of the
+  // binning counts, overlapping the scans, the placement and the forward splat (measured faster
+  // than starting it with the frame, after the depth sort, before the placement or after the
+  // binning: 93.4 against 91.5, 91.0, 92.2 and 91.5 frames/s at 1080p).
+  bool traced = false;
+  auto start_trace = [&]() {
+    GSC_TRY(hipMemsetAsync(ctx->vertices.p, 0, 8, st));
+    GSC_TRY(hipEventRecord(ctx->ev_fork, st));
+    GSC_TRY(hipStreamWaitEvent(ctx->side, ctx->ev_fork, 0));
+    if (timing) GSC_TRY(hipEventRecord(ctx->tev[6], ctx->side));
+    { ProfScope ps_(ctx, P_TRACE, ctx->side);
+    GSC_TRY(launch_trace(ctx->side, ctx->trace_tab.as<TraceDesc>(),
+                         (const int64_t*)((char*)ctx->trace_tab.p + sizeof(TraceDesc) * n), n, tlaunch,
+                         ctx->vertices.as<unsigned long long>()));
+    }
+    if (timing) GSC_TRY(hipEventRecord(ctx->tev[7], ctx->side));
+    GSC_TRY(hipEventRecord(ctx->ev_join, ctx->side));
+    traced = true;
+  };
   // ---- splat the cache images ---------------------------------------------------------------------
   b->list_cut = ctx->list_cut != 0;
-  gsc_status s = run_project_bin(ctx, b, 0);
+  gsc_status s = run_project_bin(ctx, b, 0, start_trace);
   if (s != GSC_OK) {
-    GSC_TRY(hipStreamWaitEvent(st, ctx->ev_join, 0));
+    if (traced) GSC_TRY(hipStreamWaitEvent(st, ctx->ev_join, 0));
     return s;
   }
+  if (!traced) start_trace();
   if (timing) GSC_TRY(hipEventRecord(ctx->tev[1], st));
   run_forward(ctx, b, ctx->images.as<float>(), ctx->final_T.as<float>(), ctx->last_id.as<int32_t>());
   if (timing) GSC_TRY(hipEventRecord(ctx->tev[2], st));
