@@ -70,6 +70,7 @@ def algorithmic_bytes(kernel: str, c: dict) -> float:
         "splat_backward": 20.0 * P + 36.0 * G,
         "project_backward": 148.0 * G,
         "adam": 14 * 28.0 * G,           # p, m, v, g in; p, m, v out
+        "project_backward_adam": 372.0 * G,  # 36 B screen gradients; p, m, v in and out
     }
     return table.get(kernel, 0.0)
 

@@ -12,6 +12,21 @@
 
 namespace gsc {
 
+// AdamW on element i of one parameter group (decoupled weight decay folded into wdf = 1 - lr wd,
+// bias corrections into s1 = lr / (1 - b1^t) and s2 = 1 / sqrt(1 - b2^t)); every operation is
+// separately rounded, in this order, wherever the step runs.
+__device__ __forceinline__ void adamw_element(float* p, float* m, float* v, int64_t i, float g,
+                                              const AdamGroup& G) {
+  const float mn = G.b1 * m[i] + G.omb1 * g;
+  const float vn = G.b2 * v[i] + G.omb2 * (g * g);
+  float q = p[i] * G.wdf;
+  const float den = sqrtf(vn) * G.s2 + G.eps;
+  q = q - (G.s1 * mn) / den;
+  m[i] = mn;
+  v[i] = vn;
+  p[i] = q;
+}
+
 // ---------------------------------------------------------------------------------------------
 // Philox4x32-10 (Salmon, Moraes, Dror, Shaw, "Parallel Random Numbers: As Easy as 1, 2, 3",
 // SC'11): ten rounds of two 32x32->64-bit multiplications of counter words 0 and 2 by the

@@ -103,6 +103,13 @@ hipError_t launch_project(hipStream_t st, const Seg* segs, const int64_t* seg_gs
 hipError_t launch_project_backward(hipStream_t st, const Seg* segs, const int64_t* seg_gstart, int S,
                                    const DevCam* cams, int64_t G, const float* grad2d,
                                    float* grads14);
+struct AdamGroup;
+// The same chain rule followed, per Gaussian, by its AdamW step: groups[5 s + k] holds parameter
+// group k (pos, rot, log_scale, rgb, opacity_logit) of segment s, with p, m, v at the group's
+// base; segments whose p is NULL are not trained.  No gradient array is written.
+hipError_t launch_project_backward_adam(hipStream_t st, const Seg* segs, const int64_t* seg_gstart,
+                                        int S, const DevCam* cams, int64_t G, const float* grad2d,
+                                        const AdamGroup* groups);
 hipError_t launch_fill_u32(hipStream_t st, uint32_t* p, uint32_t value, int64_t count);
 
 size_t sort_table_bytes(int n_blocks, int S);
@@ -180,8 +187,6 @@ struct AdamGroup {
   const float* guard;     // the step is skipped when *guard is not finite (nullptr: never)
   float b1, b2, omb1, omb2, s1, s2, wdf, eps;
 };
-hipError_t launch_adam_groups(hipStream_t st, const AdamGroup* groups_dev, int n_groups,
-                              int64_t max_n);
 hipError_t launch_adam(hipStream_t st, float* param, float* m, float* v, const float* grad,
                        int64_t count, float b1, float b2, float omb1, float omb2, float s1,
                        float s2, float wdf, float eps, const float* guard);

@@ -81,36 +81,20 @@ __global__ void __launch_bounds__(256) project_kernel(const Seg* __restrict__ se
 // Adjoint of the projection.  grad2d is SoA [9][G]: du, dv, dA, dB, dCc, do, dr, dg, db
 // (accumulated by the splat backward).  Writes (overwrites) the gradients of the 14 parameters.
 // The forward quantities are recomputed in fp32 exactly as the projection computes them.
-__global__ void __launch_bounds__(256) project_backward_kernel(
-    const Seg* __restrict__ segs, const int64_t* __restrict__ seg_gstart, int S,
-    const DevCam* __restrict__ cams, int64_t G, const float* __restrict__ grad2d,
-    float* __restrict__ grads14) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= G) return;
-  const int s = find_segment(seg_gstart, S, i);
-  const Seg sg = segs[s];
-  const int64_t lid = i - sg.g_off;
-  const DevCam cam = cams[sg.cam];
-  const float gu = grad2d[0 * G + i], gv = grad2d[1 * G + i];
-  const float gA = grad2d[2 * G + i], gB = grad2d[3 * G + i], gC = grad2d[4 * G + i];
-  const float go = grad2d[5 * G + i];
-  // Gradient layout per segment: [pos 3n][rot 4n][log_scale 3n][rgb 3n][opacity_logit n].
-  float* base = grads14 + 14 * sg.g_off;
-  const int64_t nn = sg.n;
-  float* gp = base + 3 * lid;
-  float* gq = base + 3 * nn + 4 * lid;
-  float* gs = base + 7 * nn + 3 * lid;
-  float* gc = base + 10 * nn + 3 * lid;
-  gc[0] = grad2d[6 * G + i];
-  gc[1] = grad2d[7 * G + i];
-  gc[2] = grad2d[8 * G + i];
+// Chain rule of one Gaussian (level-local index lid of segment sg) from the screen-space
+// gradients (u, v, conic A, B, C, opacity o) to its mean, quaternion, log-scales and opacity
+// logit.  Reads the Gaussian's parameters; writes gp[3], gq[4], gs[3] and *gl.
+__device__ __forceinline__ void project_grads(const Seg& sg, const DevCam& cam, int64_t lid,
+                                              float gu, float gv, float gA, float gB, float gC,
+                                              float go, float* gp, float* gq, float* gs,
+                                              float* gl) {
   const float* pos = sg.pos + 3 * lid;
   const float* rot = sg.rot + 4 * lid;
   const float* ls = sg.ls + 3 * lid;
   const float logit = sg.logit[lid];
   const Projected P = project_one(pos, rot, ls, logit, cam);
   // Opacity: o = sigmoid(logit).
-  base[13 * nn + lid] = go * (P.o * (1.0f - P.o));
+  *gl = go * (P.o * (1.0f - P.o));
   if (P.tiles == 0u) {
     gp[0] = gp[1] = gp[2] = 0.0f;
     gq[0] = gq[1] = gq[2] = gq[3] = 0.0f;
@@ -253,6 +237,93 @@ __global__ void __launch_bounds__(256) project_backward_kernel(
   gq[3] = (dqz - qz * dot) * iq;
 }
 
+__global__ void __launch_bounds__(256) project_backward_kernel(
+    const Seg* __restrict__ segs, const int64_t* __restrict__ seg_gstart, int S,
+    const DevCam* __restrict__ cams, int64_t G, const float* __restrict__ grad2d,
+    float* __restrict__ grads14) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= G) return;
+  const int s = find_segment(seg_gstart, S, i);
+  const Seg sg = segs[s];
+  const int64_t lid = i - sg.g_off;
+  // Gradient layout per segment: [pos 3n][rot 4n][log_scale 3n][rgb 3n][opacity_logit n].
+  float* base = grads14 + 14 * sg.g_off;
+  const int64_t nn = sg.n;
+  float* gc = base + 10 * nn + 3 * lid;
+  gc[0] = grad2d[6 * G + i];
+  gc[1] = grad2d[7 * G + i];
+  gc[2] = grad2d[8 * G + i];
+  project_grads(sg, cams[sg.cam], lid, grad2d[0 * G + i], grad2d[1 * G + i], grad2d[2 * G + i],
+                grad2d[3 * G + i], grad2d[4 * G + i], grad2d[5 * G + i], base + 3 * lid,
+                base + 3 * nn + 4 * lid, base + 7 * nn + 3 * lid, base + 13 * nn + lid);
+}
+
+// The chain rule and the AdamW step in one pass.  Each thread takes the chain rule of one
+// Gaussian; its 14 gradients go to LDS, and when the workgroup's 256 Gaussians lie in one
+// segment (all but the few workgroups that straddle a boundary) the AdamW updates then run
+// over each parameter group's contiguous range, so every parameter, moment and gradient access
+// is coalesced.  A straddling workgroup updates each Gaussian from its own thread.
+constexpr int kGradWidth[5] = {3, 4, 3, 3, 1};
+constexpr int kGradFirst[5] = {0, 3, 7, 10, 13};
+
+__global__ void __launch_bounds__(256) project_backward_adam_kernel(
+    const Seg* __restrict__ segs, const int64_t* __restrict__ seg_gstart, int S,
+    const DevCam* __restrict__ cams, int64_t G, const float* __restrict__ grad2d,
+    const AdamGroup* __restrict__ groups) {
+  __shared__ float gsh[14][256];
+  const int tid = threadIdx.x;
+  const int64_t first = (int64_t)blockIdx.x * 256;
+  const int64_t i = first + tid;
+  const int count = (int)((G - first) < 256 ? (G - first) : 256);
+  const int s_first = find_segment(seg_gstart, S, first);
+  const int s_last = find_segment(seg_gstart, S, first + count - 1);
+  float gr14[14];
+  int s = s_first;
+  bool live = false;
+  if (i < G) {
+    s = find_segment(seg_gstart, S, i);
+    const AdamGroup& g0 = groups[5 * s];
+    live = g0.p != nullptr && !(g0.guard && !isfinite(*g0.guard));
+    if (live) {
+      const Seg sg = segs[s];
+      const int64_t lid = i - sg.g_off;
+      project_grads(sg, cams[sg.cam], lid, grad2d[0 * G + i], grad2d[1 * G + i], grad2d[2 * G + i],
+                    grad2d[3 * G + i], grad2d[4 * G + i], grad2d[5 * G + i], gr14, gr14 + 3,
+                    gr14 + 7, gr14 + 13);
+      gr14[10] = grad2d[6 * G + i];
+      gr14[11] = grad2d[7 * G + i];
+      gr14[12] = grad2d[8 * G + i];
+    }
+  }
+  if (s_first != s_last) {                 // straddles a segment boundary: per-thread updates
+    if (!live) return;
+    const Seg sg = segs[s];
+    const int64_t lid = i - sg.g_off;
+#pragma unroll
+    for (int k = 0; k < 5; ++k) {
+      const AdamGroup& gk = groups[5 * s + k];
+#pragma unroll
+      for (int c = 0; c < kGradWidth[k]; ++c)
+        adamw_element(gk.p, gk.m, gk.v, kGradWidth[k] * lid + c, gr14[kGradFirst[k] + c], gk);
+    }
+    return;
+  }
+  // One segment: liveness is uniform over the workgroup.
+  const AdamGroup& g0 = groups[5 * s_first];
+  if (g0.p == nullptr || (g0.guard && !isfinite(*g0.guard))) return;
+#pragma unroll
+  for (int k = 0; k < 14; ++k) gsh[k][tid] = gr14[k];
+  __syncthreads();
+  const int64_t lid0 = first - segs[s_first].g_off;
+#pragma unroll
+  for (int k = 0; k < 5; ++k) {
+    const AdamGroup& gk = groups[5 * s_first + k];
+    const int w = kGradWidth[k];
+    for (int e = tid; e < w * count; e += 256)
+      adamw_element(gk.p, gk.m, gk.v, w * lid0 + e, gsh[kGradFirst[k] + e % w][e / w], gk);
+  }
+}
+
 __global__ void fill_u32_kernel(uint32_t* p, uint32_t v, int64_t n) {
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i < n) p[i] = v;
@@ -277,6 +348,15 @@ hipError_t launch_project_backward(hipStream_t st, const Seg* segs, const int64_
   if (G == 0) return hipSuccess;
   hipLaunchKernelGGL(project_backward_kernel, dim3(blocks_for(G, 256)), dim3(256), 0, st, segs,
                      seg_gstart, S, cams, G, grad2d, grads14);
+  return hipGetLastError();
+}
+
+hipError_t launch_project_backward_adam(hipStream_t st, const Seg* segs, const int64_t* seg_gstart,
+                                        int S, const DevCam* cams, int64_t G, const float* grad2d,
+                                        const AdamGroup* groups) {
+  if (G == 0) return hipSuccess;
+  hipLaunchKernelGGL(project_backward_adam_kernel, dim3(blocks_for(G, 256)), dim3(256), 0, st, segs,
+                     seg_gstart, S, cams, G, grad2d, groups);
   return hipGetLastError();
 }
 

@@ -101,36 +101,9 @@ __global__ void __launch_bounds__(256) adam_kernel(float* __restrict__ param, fl
   if (guard && !isfinite(*guard)) return;
   const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
-  const float g = grad[i];
-  const float mn = b1 * m[i] + omb1 * g;
-  const float vn = b2 * v[i] + omb2 * (g * g);
-  float p = param[i] * wdf;
-  const float den = sqrtf(vn) * s2 + eps;
-  p = p - (s1 * mn) / den;
-  m[i] = mn;
-  v[i] = vn;
-  param[i] = p;
-}
-
-// Several parameter groups in one launch: blockIdx.y selects the group, each thread updates
-// kAdamItems elements strided by the grid; same arithmetic as adam_kernel.
-constexpr int kAdamItems = 8;
-
-__global__ void __launch_bounds__(256) adam_groups_kernel(const AdamGroup* __restrict__ groups) {
-  const AdamGroup G = groups[blockIdx.y];
-  if (G.guard && !isfinite(*G.guard)) return;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < G.n; i += stride) {
-    const float g = G.g[i];
-    const float mn = G.b1 * G.m[i] + G.omb1 * g;
-    const float vn = G.b2 * G.v[i] + G.omb2 * (g * g);
-    float p = G.p[i] * G.wdf;
-    const float den = sqrtf(vn) * G.s2 + G.eps;
-    p = p - (G.s1 * mn) / den;
-    G.m[i] = mn;
-    G.v[i] = vn;
-    G.p[i] = p;
-  }
+  AdamGroup G;
+  G.b1 = b1; G.b2 = b2; G.omb1 = omb1; G.omb2 = omb2; G.s1 = s1; G.s2 = s2; G.wdf = wdf; G.eps = eps;
+  adamw_element(param, m, v, i, grad[i], G);
 }
 
 }  // namespace
@@ -161,16 +134,5 @@ hipError_t launch_adam(hipStream_t st, float* param, float* m, float* v, const f
   return hipGetLastError();
 }
 
-hipError_t launch_adam_groups(hipStream_t st, const AdamGroup* groups_dev, int n_groups,
-                              int64_t max_n) {
-  if (n_groups == 0 || max_n == 0) return hipSuccess;
-  const int64_t per_block = 256 * (int64_t)kAdamItems;
-  const unsigned bx = (unsigned)((max_n + per_block - 1) / per_block);
-  for (int g0 = 0; g0 < n_groups; g0 += 65535) {   // grid y limit
-    const int ng = (n_groups - g0) < 65535 ? (n_groups - g0) : 65535;
-    hipLaunchKernelGGL(adam_groups_kernel, dim3(bx, (unsigned)ng), dim3(256), 0, st, groups_dev + g0);
-  }
-  return hipGetLastError();
-}
 
 }  // namespace gsc

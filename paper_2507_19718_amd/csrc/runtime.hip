@@ -253,11 +253,12 @@ void read_u64x2(gsc_ctx* ctx, const uint64_t* dev, uint64_t* a, uint64_t* b) {
 
 const char* const kProfNames[] = {"project", "depth_sort", "bin_count", "bin_scan", "bin_place",
                                   "splat_forward", "trace", "loss_composite", "splat_backward",
-                                  "project_backward", "adam", "gather_rect"};
-constexpr int kProfCount = 12;
+                                  "project_backward", "adam", "gather_rect",
+                                  "project_backward_adam"};
+constexpr int kProfCount = 13;
 constexpr int kStatWords = 4;   // splat forward counters (gsc_counters)
 enum { P_PROJECT, P_SORT, P_COUNT, P_SCAN, P_PLACE, P_FWD, P_TRACE, P_LOSS, P_BWD, P_PBWD, P_ADAM,
-       P_GATHER };
+       P_GATHER, P_PBADAM };
 
 hipEvent_t pool_event(gsc_ctx* ctx) {
   if (!ctx->ev_pool.empty()) {
@@ -542,8 +543,8 @@ void run_forward(gsc_ctx* ctx, gsc_binning* b, float* images, float* final_T, in
   b->forward_done = true;
 }
 
-void run_backward(gsc_ctx* ctx, gsc_binning* b, const float* final_T, const float* dL,
-                  float* grads14) {
+// The splat adjoint into b->grad2d ([9][G] screen-space gradients).
+void run_splat_adjoint(gsc_ctx* ctx, gsc_binning* b, const float* final_T, const float* dL) {
   need(ctx, b->grad2d, b->alloc, 4 * 9 * (size_t)std::max<int64_t>(b->G, 1), "2D gradients");
   uint32_t* gmax = nullptr;
   unsigned long long* gfix = nullptr;
@@ -562,6 +563,12 @@ void run_backward(gsc_ctx* ctx, gsc_binning* b, const float* final_T, const floa
                                 b->rec.as<SplatRec>(), final_T, b->n_contrib.as<uint32_t>(), dL,
                                 b->grad2d.as<float>(), b->G, order, gmax, gfix));
   }
+}
+
+// The splat adjoint and the chain rule to the 14 parameter gradients per Gaussian.
+void run_backward(gsc_ctx* ctx, gsc_binning* b, const float* final_T, const float* dL,
+                  float* grads14) {
+  run_splat_adjoint(ctx, b, final_T, dL);
   { ProfScope ps_(ctx, P_PBWD, ctx->stream);
   GSC_TRY(launch_project_backward(ctx->stream, b->d_segs(), b->d_gstart(), b->S, b->d_cams(), b->G,
                                   b->grad2d.as<float>(), grads14));
@@ -728,7 +735,6 @@ gsc_status render_batch(gsc_ctx* ctx, gsc_scene* const* scenes, const gsc_frame_
   for (int i = 0; i < n; ++i) max_partials = std::max(max_partials, loss_num_partials((int64_t)reqs[i].cam.w * reqs[i].cam.h));
   need(ctx, ctx->partials, a, 8 * (size_t)max_partials * n, "loss partials");
   need(ctx, ctx->losses, a, 4 * (size_t)n, "losses");
-  need(ctx, ctx->grads14, a, 4 * 14 * (size_t)std::max<int64_t>(b->G, 1), "parameter gradients");
   need(ctx, ctx->vertices, a, 8, "vertex counter");
   // ---- trace on the side stream (independent of the cache) --------------------------------------
   std::vector<TraceDesc> td(n);
@@ -801,39 +807,37 @@ gsc_status render_batch(gsc_ctx* ctx, gsc_scene* const* scenes, const gsc_frame_
   bool any_train = false;
   for (int i = 0; i < n; ++i) any_train = any_train || reqs[i].train;
   if (any_train) {
-    run_backward(ctx, b, ctx->final_T.as<float>(), ctx->dL.as<float>(), ctx->grads14.as<float>());
+    run_splat_adjoint(ctx, b, ctx->final_T.as<float>(), ctx->dL.as<float>());
     if (timing) GSC_TRY(hipEventRecord(ctx->tev[4], st));
-    // One fused AdamW launch over every (request, level, parameter group).
-    std::vector<AdamGroup> groups;
-    int64_t max_n = 0;
+    // One launch over every Gaussian of the batch: chain rule, then AdamW on its 14 parameters
+    // with the group's learning rate (Eq. 5 factor included).  groups[5 s + k]: segment s, group k.
+    std::vector<AdamGroup> groups(5 * (size_t)b->S);
     int si = 0;
     for (int i = 0; i < n; ++i) {
       gsc_scene* sc = scenes[i];
       const double eta = 1.0 / (1.0 + std::log((double)reqs[i].viewport_frames));
       for (int l = 0; l < sc->K; ++l, ++si) {
-        if (!reqs[i].train) continue;
-        const Seg& sg = b->segs[si];
         const int64_t nn = sc->n[l];
-        if (nn == 0) continue;
-        const int64_t step = sc->step[l] + 1;
-        float* g = ctx->grads14.as<float>() + 14 * sg.g_off;
-        const int64_t off[6] = {0, 3 * nn, 7 * nn, 10 * nn, 13 * nn, 14 * nn};
-        for (int grp = 0; grp < 5; ++grp) {
-          groups.push_back(adam_params(sc->params[l] + off[grp], sc->m[l] + off[grp],
-                                       sc->v[l] + off[grp], g + off[grp], off[grp + 1] - off[grp],
-                                       (double)reqs[i].lr[grp] * eta, reqs[i].beta1, reqs[i].beta2,
-                                       reqs[i].eps, reqs[i].weight_decay, step,
-                                       ctx->losses.as<float>() + i));
-          max_n = std::max(max_n, off[grp + 1] - off[grp]);
+        if (!reqs[i].train || nn == 0) {
+          for (int grp = 0; grp < 5; ++grp) groups[5 * si + grp].p = nullptr;
+          continue;
         }
+        const int64_t step = sc->step[l] + 1;
+        const int64_t off[6] = {0, 3 * nn, 7 * nn, 10 * nn, 13 * nn, 14 * nn};
+        for (int grp = 0; grp < 5; ++grp)
+          groups[5 * si + grp] = adam_params(sc->params[l] + off[grp], sc->m[l] + off[grp],
+                                             sc->v[l] + off[grp], nullptr, off[grp + 1] - off[grp],
+                                             (double)reqs[i].lr[grp] * eta, reqs[i].beta1,
+                                             reqs[i].beta2, reqs[i].eps, reqs[i].weight_decay, step,
+                                             ctx->losses.as<float>() + i);
         sc->step[l] = step;
       }
     }
-    if (!groups.empty()) {
-      need(ctx, ctx->adam_tab, ctx->alloc, sizeof(AdamGroup) * groups.size(), "AdamW groups");
-      upload(ctx, ctx->adam_tab.p, groups.data(), sizeof(AdamGroup) * groups.size());
-      ProfScope ps_(ctx, P_ADAM, st);
-      GSC_TRY(launch_adam_groups(st, ctx->adam_tab.as<AdamGroup>(), (int)groups.size(), max_n));
+    need(ctx, ctx->adam_tab, ctx->alloc, sizeof(AdamGroup) * groups.size(), "AdamW groups");
+    upload(ctx, ctx->adam_tab.p, groups.data(), sizeof(AdamGroup) * groups.size());
+    { ProfScope ps_(ctx, P_PBADAM, st);
+    GSC_TRY(launch_project_backward_adam(st, b->d_segs(), b->d_gstart(), b->S, b->d_cams(), b->G,
+                                         b->grad2d.as<float>(), ctx->adam_tab.as<AdamGroup>()));
     }
   } else if (timing) {
     GSC_TRY(hipEventRecord(ctx->tev[4], st));
