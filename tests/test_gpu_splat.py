@@ -220,3 +220,24 @@ def test_splat_counters_match_oracle(gsc, gctx):
     assert c["evaluations"] >= c["contributors"]
     assert 0 < c["tile_entries"] <= ob["keys"].size
     assert c["binnings"] == 1 and c["instances"] == ob["keys"].size
+
+
+def test_capacity_overflow_reports_the_need_and_a_retry_succeeds(gsc, gctx):
+    """A capacity hint one instance short makes gsc_project_bin fail with GSC_E_CAPACITY and
+    report the exact instance count; binning again with that count gives the oracle's binning,
+    as does a generous hint."""
+    wl = synth.workload("tiny")
+    cam = wl.camera()
+    levels_np = wl.gaussians()
+    levels = [gsc.level_to_device(g) for g in levels_np]
+    ob = oracle.bin_levels([oracle.project(g, cam) for g in levels_np], cam)
+    need = int(ob["keys"].size)
+    with pytest.raises(gsc.GscError) as e:
+        gsc.gsc_project_bin(gctx, levels, cam, capacity_hint=need - 1)
+    assert e.value.status == gsc.GSC_E_CAPACITY
+    assert gctx.required_capacity() == need
+    for hint in (gctx.required_capacity(), 3 * need):
+        view = gsc.gsc_binning_view(gctx, gsc.gsc_project_bin(gctx, levels, cam, capacity_hint=hint))
+        assert view["n_instances"] == need
+        assert np.array_equal(u32(view["values"]), ob["values"])
+        assert np.array_equal(u64(view["ranges"]), ob["ranges"])
