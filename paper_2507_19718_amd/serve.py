@@ -109,12 +109,14 @@ class ContinuousBatcher:
                  before_launch: Optional[Callable[[int, List[Request]], None]] = None,
                  executor: Optional[Callable[[int, List[Request]], None]] = None,
                  footprint: Optional[Callable[[Request], int]] = None,
-                 after_batch: Optional[Callable[[int, List[Request], List[torch.Tensor]], None]] = None):
+                 after_batch: Optional[Callable[[int, List[Request], List[torch.Tensor]], None]] = None,
+                 deterministic: bool = False):
         """executor(slot, batch) runs a batch to completion (default: gsc_render_frames on the
         slot's context, then a stream synchronise); footprint(r) gives a request's transient
         bytes (default: gsc_frame_footprint_bytes of its scene).  before_launch(slot, batch)
         runs on the scheduler thread before a batch starts; after_batch(slot, batch, images)
-        after the default executor finished it (for snapshots in tests)."""
+        after the default executor finished it (for snapshots in tests).  deterministic: the
+        slots' contexts sum the splat adjoint in fixed point (bit-reproducible training)."""
         self.scenes = scenes
         self.n_slots = slots
         self.budget = hbm_budget
@@ -125,6 +127,8 @@ class ContinuousBatcher:
         self._footprint = footprint
         self.executor = executor if executor is not None else self._gpu_executor
         self.slots = [Context(0, torch.cuda.Stream()) for _ in range(slots)] if executor is None else []
+        for c in self.slots:
+            c.set_deterministic(deterministic)
         self.images: Dict[tuple, torch.Tensor] = {}
         self.batches: List[List[int]] = []
 

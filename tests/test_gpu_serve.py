@@ -95,6 +95,59 @@ def test_alone_equals_mix(gsc):
             assert st["step"] == mix_state[l]["step"]
 
 
+def test_alone_equals_mix_bit_for_bit_with_the_deterministic_adjoint(gsc):
+    """With fixed-point adjoint sums nothing in a frame depends on the order of atomics, so a
+    request served in a mixed batch and the same request run alone from a snapshot give the
+    same image and the same parameters, moments and step counts bit for bit."""
+    import paper_2507_19718_amd.serve as serve
+    ctx = gsc.Context(0)
+    ctx.set_deterministic(True)
+    specs, init = make_scenes(gsc, ctx)
+    snaps, results = {}, {}
+    sample = set(range(1, 36, 4))
+
+    def before(slot, batch):
+        for r in batch:
+            if r.idx in sample:
+                vol, levels = init[r.scene]
+                sn = gsc.Scene(ctx, gsc.Volume.from_synth(vol), levels)
+                sn.copy_state_from(specs[r.scene].scene)
+                ctx.synchronize()
+                snaps[r.idx] = sn
+
+    def after(slot, batch, images):
+        for r, img in zip(batch, images):
+            if r.idx in sample:
+                sc = specs[r.scene].scene
+                results[r.idx] = (img.clone(), [sc.state(l) for l in range(specs[r.scene].K)])
+
+    b = serve.ContinuousBatcher(specs, slots=2, before_launch=before, after_batch=after, max_batch=3,
+                                deterministic=True)
+    reqs = requests(seed=12)
+    b.run(reqs, realtime=False)
+    torch.cuda.synchronize()
+    assert any(len(x) > 1 for x in b.batches), "no batching happened"
+    alone = gsc.Context(0)
+    alone.set_deterministic(True)
+    checked = 0
+    for r in reqs:
+        if r.idx not in sample:
+            continue
+        sn, spec = snaps[r.idx], specs[r.scene]
+        img = torch.empty((r.cam.h, r.cam.w, 3), device="cuda")
+        gsc.gsc_render_frame(alone, sn, serve._req_struct(spec, r), img)
+        alone.synchronize()
+        mix_img, mix_state = results[r.idx]
+        assert torch.equal(img, mix_img), r.idx
+        for l in range(spec.K):
+            st = sn.state(l)
+            for k in ("params", "m", "v"):
+                assert torch.equal(st[k], mix_state[l][k]), (r.idx, l, k)
+            assert st["step"] == mix_state[l]["step"]
+        checked += 1
+    assert checked == len(sample)
+
+
 def test_plain_and_served_reach_same_state(gsc):
     import paper_2507_19718_amd.serve as serve
     ctx = gsc.Context(0)
