@@ -436,7 +436,8 @@ gsc_status gsc_render_frame(gsc_ctx* ctx, gsc_scene* scene, const gsc_frame_requ
 /* A batch of n frames of distinct scenes, executed stage by stage with one launch per stage
  * over all (request, level) pairs.  The scenes must be pairwise distinct (one training step
  * per scene per batch).  images[i] is request i's composite [h_i][w_i][3]; stats: HOST array
- * of n or NULL.  Results equal n separate gsc_render_frame calls up to float-atomic order. */
+ * of n or NULL.  Results equal n separate gsc_render_frame calls up to float-atomic order,
+ * and bit for bit with gsc_ctx_set_deterministic. */
 gsc_status gsc_render_frames(gsc_ctx* ctx, gsc_scene* const* scenes,
                              const gsc_frame_request* reqs, float* const* images, int32_t n,
                              gsc_frame_stats* stats);
