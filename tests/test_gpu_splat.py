@@ -241,3 +241,39 @@ def test_capacity_overflow_reports_the_need_and_a_retry_succeeds(gsc, gctx):
         assert view["n_instances"] == need
         assert np.array_equal(u32(view["values"]), ob["values"])
         assert np.array_equal(u64(view["ranges"]), ob["ranges"])
+
+
+def test_degenerate_levels_and_windows(gsc, gctx):
+    """An empty level between two non-empty ones, a 1x1 window and a level of transparent
+    Gaussians (alpha below 1/255 everywhere): binning stays bit-exact, an empty or transparent
+    level renders background (T = 1, last id -1) with zero gradients, and the 1x1 window's pixel
+    matches the oracle."""
+    base = synth.orbit_camera(96, 72, azimuth_deg=15.0)
+    full = synth.random_gaussians(400, 21, 0, log_scale_mean=math.log(0.05))
+    empty = synth.random_gaussians(0, 22, 1)
+    faint = synth.random_gaussians(300, 23, 2, log_scale_mean=math.log(0.05))
+    faint.opacity_logit[:] = np.float32(np.log(0.001 / 0.999))      # o = 0.001 < 1/255
+    levels_np = [full, empty, faint]
+    for cam in (base, base.crop(40, 30, 1, 1)):
+        print(f"degenerate: window {cam.w}x{cam.h}", flush=True)
+        levels, b, view, keys = run_bin(gsc, gctx, levels_np, cam)
+        check_binning(view, keys, levels_np, cam)
+        K = len(levels)
+        img = torch.empty((K, cam.h, cam.w, 3), device="cuda")
+        T = torch.empty((K, cam.h, cam.w), device="cuda")
+        last = torch.empty((K, cam.h, cam.w), dtype=torch.int32, device="cuda")
+        gsc.gsc_splat_forward(gctx, b, img, T, last)
+        for l in (1, 2):
+            assert torch.all(img[l] == 0) and torch.all(T[l] == 1) and torch.all(last[l] == -1)
+        pr = oracle.project(full, cam)
+        fw = oracle.forward(pr, full.rgb, cam)
+        ok = ~fw["boundary"]
+        good, info = forward_close(to_np(img[0]), fw["image"], ok)
+        assert good, info
+        assert np.array_equal(to_np(last[0])[ok], fw["last_id"][ok])
+        dL = torch.ones((K, cam.h, cam.w, 3), device="cuda")
+        grads = [{k: torch.full_like(lv[k], 7.0) for k in gsc.PARAM_NAMES} for lv in levels]
+        gsc.gsc_splat_backward(gctx, b, levels, cam, T, last, dL, grads)
+        for l in (1, 2):
+            for k in gsc.PARAM_NAMES:
+                assert torch.all(grads[l][k] == 0), (l, k)
