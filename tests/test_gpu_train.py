@@ -168,3 +168,29 @@ def test_render_frame_skips_step_on_nonfinite_loss(gsc, gctx):
         assert stats["adam_skipped"] == 1
         after = to_np(scene.state(0)["params"])
         assert np.array_equal(np.nan_to_num(before), np.nan_to_num(after))
+
+
+def test_render_frame_with_an_empty_level(gsc, gctx):
+    """A scene whose middle level holds no Gaussian trains like any other: the empty level's
+    step count stays 0, the other levels take a step per frame, and loss and composite stay
+    finite."""
+    wl = synth.workload("tiny")
+    vol = wl.volume()
+    cam = wl.camera()
+    a = synth.tiny_gaussians(1024, 31)
+    b = synth.tiny_gaussians(512, 32, 2)
+    e = synth.random_gaussians(0, 33, 1)
+    scene = gsc.Scene(gctx, gsc.Volume.from_synth(vol), [gsc.level_to_device(g) for g in (a, e, b)])
+    image = torch.empty((cam.h, cam.w, 3), device="cuda")
+    before = [to_np(scene.state(l)["params"]) for l in (0, 2)]
+    for frame in range(3):
+        req = gsc.frame_request(cam, wl.seed, frame, 3, wl.max_bounces, loss=wl.loss, lr=wl.lr,
+                                weight_decay=wl.weight_decay, C=wl.C)
+        stats = gsc.gsc_render_frame(gctx, scene, req, image, stats=True)
+        assert math.isfinite(stats["loss"]) and not stats["adam_skipped"]
+    assert scene.state(1)["n"] == 0 and scene.state(1)["step"] == 0
+    for i, l in enumerate((0, 2)):
+        st = scene.state(l)
+        assert st["step"] == 3
+        assert not np.array_equal(to_np(st["params"]), before[i])
+    assert np.isfinite(to_np(image)).all()
