@@ -56,7 +56,7 @@ typedef enum {
                             * how many were needed; retry with a larger hint                */
   GSC_E_OUT_OF_MEMORY = 3, /* the allocator returned NULL                                   */
   GSC_E_DEVICE = 4,        /* a HIP runtime error; sticky for the context                   */
-  GSC_E_UNSUPPORTED = 5
+  GSC_E_UNSUPPORTED = 5     /* reserved: no call of this version returns it                  */
 } gsc_status;
 
 typedef struct gsc_ctx gsc_ctx;
