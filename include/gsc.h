@@ -6,9 +6,9 @@
  * heuristic (Algorithm 1) and writes every terminated path's attenuated radiance into the
  * target buffer of its length (Method: "Cache Training"), and each level takes one AdamW step
  * against those noisy targets under the HDR loss (Eq. 4) with the viewport learning-rate
- * schedule (Eq. 5).  The renderer hands the cache only "the attenuated radiance value and the
- * path length that produced it" (Introduction); the library is exposed through a C-style API
- * (Method: "Implementation").
+ * schedule (Eq. 5).  All the renderer gives the cache per path is the radiance it carried,
+ * already attenuated, and the number of interactions of that path (Introduction); the library
+ * is exposed through a C-style API (Method: "Implementation").
  *
  * Conventions
  *   - Pointers are DEVICE pointers unless marked HOST.  The caller owns every buffer it
@@ -314,7 +314,9 @@ gsc_status gsc_binning_view(gsc_ctx* ctx, const gsc_binning* bin, gsc_binning_in
 gsc_status gsc_binning_keys(gsc_ctx* ctx, const gsc_binning* bin, uint64_t* keys);
 void gsc_binning_release(gsc_ctx* ctx, gsc_binning* bin);
 
-/* Front-to-back alpha blending of every level's tiles: per pixel, over the tile list in
+/* Rasterisation of the cache images (Method: "A Path Space Radiance Cache": every frame each
+ * level is splatted with the 3D Gaussian splatting rasteriser before the tracer runs).
+ * Front-to-back alpha blending of every level's tiles: per pixel, over the tile list in
  * order, alpha = min(0.99, o exp(power)), pairs with power > 0, alpha < 1/255 or the pixel
  * outside the Gaussian's window are skipped, and blending stops before T (1 - alpha) < 1e-4;
  * background 0.  images [K][h][w][3], final_T [K][h][w], last_id [K][h][w] (level-local id of
@@ -323,7 +325,9 @@ void gsc_binning_release(gsc_ctx* ctx, gsc_binning* bin);
 gsc_status gsc_splat_forward(gsc_ctx* ctx, gsc_binning* bin, float* images, float* final_T,
                              int32_t* last_id);
 
-/* Adjoint of gsc_splat_forward followed by the adjoint of the projection: given dL/dimages
+/* The gradient step of cache training (Method: "Cache Training": the levels are optimised
+ * every frame against the traced per-length targets; "Optimization and Hyperparameters").
+ * Adjoint of gsc_splat_forward followed by the adjoint of the projection: given dL/dimages
  * [K][h][w][3], writes the gradients of all 14 parameters of every Gaussian of every level
  * (grads[l] has the shapes of levels[l]; overwritten).  Walks each tile back to front from
  * the stored last contributor, recovering transmittance from final_T by division (no
@@ -395,8 +399,11 @@ gsc_status gsc_scene_set_optics(gsc_ctx* ctx, gsc_scene* scene, const float* tf_
 /* DEVICE pointers to the scene's current parameters of level l. */
 gsc_status gsc_scene_level(const gsc_scene* scene, int32_t l, gsc_gaussians* out);
 /* DEVICE pointers to level l's optimiser state: params, m and v are each [14 n] floats laid out
- * [pos 3n][rot 4n][log_scale 3n][rgb 3n][opacity_logit n]; *step is the number of AdamW steps
- * taken.  Valid until the scene is destroyed. */
+ * [pos 3n][rot 4n][log_scale 3n][rgb 3n][opacity_logit n]; *step (HOST) is the number of AdamW
+ * steps taken.  The step count is kept on the device, where a frame advances it only when its
+ * update ran (a frame with a non-finite loss skips AdamW and leaves moments and count as they
+ * were), so this call waits for the device before it reads the count.  The pointers are valid
+ * until the scene is destroyed. */
 gsc_status gsc_scene_state(const gsc_scene* scene, int32_t l, float** params, float** m, float** v,
                            int64_t* n, int64_t* step);
 /* Copies parameters, moments and step counters from src to dst (same level sizes). */

@@ -186,7 +186,17 @@ struct AdamGroup {
   int64_t n;
   const float* guard;     // the step is skipped when *guard is not finite (nullptr: never)
   float b1, b2, omb1, omb2, s1, s2, wdf, eps;
+  // Frames: the level's AdamW step count lives on the device.  launch_adam_factors sets s1, s2
+  // from t = *step + 1 (in double from lr, beta1, beta2); launch_adam_commit advances *step
+  // once the update ran, i.e. only when *guard is finite.  nullptr: s1, s2 given by the host.
+  int64_t* step;
+  double lr, b1d, b2d;
 };
+// Bias corrections of every group of the table from its device step count (groups whose p or
+// step is NULL are left alone).
+hipError_t launch_adam_factors(hipStream_t st, AdamGroup* groups, int n_groups);
+// Advances the step count of each segment's level (groups[5 s]) whose update ran.
+hipError_t launch_adam_commit(hipStream_t st, const AdamGroup* groups, int S);
 hipError_t launch_adam(hipStream_t st, float* param, float* m, float* v, const float* grad,
                        int64_t count, float b1, float b2, float omb1, float omb2, float s1,
                        float s2, float wdf, float eps, const float* guard);

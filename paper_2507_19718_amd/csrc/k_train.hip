@@ -106,6 +106,28 @@ __global__ void __launch_bounds__(256) adam_kernel(float* __restrict__ param, fl
   adamw_element(param, m, v, i, grad[i], G);
 }
 
+// s1 = lr / (1 - beta1^t) and s2 = 1 / sqrt(1 - beta2^t) in double, then rounded, with
+// t = steps taken + 1 read from the device (Optimization: AdamW with bias correction).
+__global__ void adam_factors_kernel(AdamGroup* __restrict__ groups, int n) {
+  const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (i >= n) return;
+  AdamGroup& g = groups[i];
+  if (g.p == nullptr || g.step == nullptr) return;
+  const double t = (double)(*g.step + 1);
+  g.s1 = (float)(g.lr / (1.0 - pow(g.b1d, t)));
+  g.s2 = (float)(1.0 / sqrt(1.0 - pow(g.b2d, t)));
+}
+
+// One thread per segment: the level's step count advances only if its update was not skipped.
+__global__ void adam_commit_kernel(const AdamGroup* __restrict__ groups, int S) {
+  const int s = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (s >= S) return;
+  const AdamGroup& g = groups[5 * s];
+  if (g.p == nullptr || g.step == nullptr) return;
+  if (g.guard && !isfinite(*g.guard)) return;
+  *g.step += 1;
+}
+
 }  // namespace
 
 int loss_num_partials(int64_t pixels) { return (int)((pixels + kLossThreads - 1) / kLossThreads); }
@@ -134,5 +156,18 @@ hipError_t launch_adam(hipStream_t st, float* param, float* m, float* v, const f
   return hipGetLastError();
 }
 
+
+hipError_t launch_adam_factors(hipStream_t st, AdamGroup* groups, int n_groups) {
+  if (n_groups <= 0) return hipSuccess;
+  hipLaunchKernelGGL(adam_factors_kernel, dim3((unsigned)((n_groups + 63) / 64)), dim3(64), 0, st,
+                     groups, n_groups);
+  return hipGetLastError();
+}
+
+hipError_t launch_adam_commit(hipStream_t st, const AdamGroup* groups, int S) {
+  if (S <= 0) return hipSuccess;
+  hipLaunchKernelGGL(adam_commit_kernel, dim3((unsigned)((S + 63) / 64)), dim3(64), 0, st, groups, S);
+  return hipGetLastError();
+}
 
 }  // namespace gsc

@@ -119,7 +119,8 @@ struct gsc_scene {
   std::vector<int64_t> n;
   std::vector<float*> params;      // per level: [pos 3n][rot 4n][ls 3n][rgb 3n][logit n]
   std::vector<float*> m, v;
-  std::vector<int64_t> step;       // Adam steps taken per level
+  int64_t* d_step = nullptr;       // DEVICE [K]: AdamW steps taken per level (advanced only by
+                                   // updates that ran, i.e. with a finite loss)
   float4* cells = nullptr;         // density in the cell-corner layout (32 B per trilinear cell)
   int32_t nx = 0, ny = 0, nz = 0;
   float dmax = 1.0f;
@@ -661,6 +662,8 @@ AdamGroup adam_params(float* p, float* m, float* v, const float* g, int64_t coun
   a.s2 = (float)(1.0 / std::sqrt(1.0 - std::pow(b2, (double)step)));
   a.wdf = (float)(1.0 - lr * wd);
   a.eps = (float)eps;
+  a.step = nullptr;
+  a.lr = lr; a.b1d = b1; a.b2d = b2;
   return a;
 }
 
@@ -822,23 +825,27 @@ gsc_status render_batch(gsc_ctx* ctx, gsc_scene* const* scenes, const gsc_frame_
           for (int grp = 0; grp < 5; ++grp) groups[5 * si + grp].p = nullptr;
           continue;
         }
-        const int64_t step = sc->step[l] + 1;
         const int64_t off[6] = {0, 3 * nn, 7 * nn, 10 * nn, 13 * nn, 14 * nn};
-        for (int grp = 0; grp < 5; ++grp)
+        // The bias corrections come from the level's device step count (set on the device
+        // below), so a frame whose loss is not finite leaves moments and count untouched.
+        for (int grp = 0; grp < 5; ++grp) {
           groups[5 * si + grp] = adam_params(sc->params[l] + off[grp], sc->m[l] + off[grp],
                                              sc->v[l] + off[grp], nullptr, off[grp + 1] - off[grp],
                                              (double)reqs[i].lr[grp] * eta, reqs[i].beta1,
-                                             reqs[i].beta2, reqs[i].eps, reqs[i].weight_decay, step,
+                                             reqs[i].beta2, reqs[i].eps, reqs[i].weight_decay, 1,
                                              ctx->losses.as<float>() + i);
-        sc->step[l] = step;
+          groups[5 * si + grp].step = sc->d_step + l;
+        }
       }
     }
     need(ctx, ctx->adam_tab, ctx->alloc, sizeof(AdamGroup) * groups.size(), "AdamW groups");
     upload(ctx, ctx->adam_tab.p, groups.data(), sizeof(AdamGroup) * groups.size());
+    GSC_TRY(launch_adam_factors(st, ctx->adam_tab.as<AdamGroup>(), (int)groups.size()));
     { ProfScope ps_(ctx, P_PBADAM, st);
     GSC_TRY(launch_project_backward_adam(st, b->d_segs(), b->d_gstart(), b->S, b->d_cams(), b->G,
                                          b->grad2d.as<float>(), ctx->adam_tab.as<AdamGroup>()));
     }
+    GSC_TRY(launch_adam_commit(st, ctx->adam_tab.as<AdamGroup>(), b->S));
   } else if (timing) {
     GSC_TRY(hipEventRecord(ctx->tev[4], st));
   }
@@ -1258,6 +1265,7 @@ gsc_status gsc_scene_create(gsc_ctx* ctx, const gsc_volume* vol, const gsc_gauss
       for (float* p : sc->m) sc->alloc.put(p);
       for (float* p : sc->v) sc->alloc.put(p);
       sc->alloc.put(sc->cells);
+      sc->alloc.put(sc->d_step);
       delete sc;
     };
     try {
@@ -1271,6 +1279,9 @@ gsc_status gsc_scene_create(gsc_ctx* ctx, const gsc_volume* vol, const gsc_gauss
       sc->cells = (float4*)sc->alloc.get(vb);
       if (!sc->cells) oom(ctx, "scene volume", vb);
       GSC_TRY(launch_build_cells(ctx->stream, vol->density, vol->nx, vol->ny, vol->nz, sc->cells));
+      sc->d_step = (int64_t*)sc->alloc.get(8 * (size_t)K);
+      if (!sc->d_step) oom(ctx, "scene step counts", 8 * (size_t)K);
+      GSC_TRY(hipMemsetAsync(sc->d_step, 0, 8 * (size_t)K, ctx->stream));
       for (int l = 0; l < K; ++l) {
         const int64_t nn = init_levels[l].n;
         const size_t bytes = 4 * 14 * (size_t)std::max<int64_t>(nn, 1);
@@ -1280,7 +1291,6 @@ gsc_status gsc_scene_create(gsc_ctx* ctx, const gsc_volume* vol, const gsc_gauss
         sc->params.push_back(p); sc->m.push_back(m); sc->v.push_back(v);
         if (!p || !m || !v) oom(ctx, "scene parameters", bytes);
         sc->n.push_back(nn);
-        sc->step.push_back(0);
         if (nn > 0) {
           const gsc_gaussians& g = init_levels[l];
           GSC_TRY(hipMemcpyAsync(p, g.pos, 12 * nn, hipMemcpyDeviceToDevice, ctx->stream));
@@ -1311,6 +1321,7 @@ void gsc_scene_destroy(gsc_ctx* ctx, gsc_scene* sc) {
   for (float* p : sc->m) sc->alloc.put(p);
   for (float* p : sc->v) sc->alloc.put(p);
   sc->alloc.put(sc->cells);
+  sc->alloc.put(sc->d_step);
   delete sc;
 }
 
@@ -1343,7 +1354,9 @@ gsc_status gsc_scene_state(const gsc_scene* sc, int32_t l, float** params, float
   *m = sc->m[l];
   *v = sc->v[l];
   *n = sc->n[l];
-  *step = sc->step[l];
+  // The count lives on the device and advances with the frames' updates: wait for the device.
+  if (hipDeviceSynchronize() != hipSuccess) return GSC_E_DEVICE;
+  if (hipMemcpy(step, sc->d_step + l, 8, hipMemcpyDeviceToHost) != hipSuccess) return GSC_E_DEVICE;
   return GSC_OK;
 }
 
@@ -1358,8 +1371,9 @@ gsc_status gsc_scene_copy_state(gsc_ctx* ctx, gsc_scene* dst, const gsc_scene* s
       GSC_TRY(hipMemcpyAsync(dst->params[l], src->params[l], bytes, hipMemcpyDeviceToDevice, ctx->stream));
       GSC_TRY(hipMemcpyAsync(dst->m[l], src->m[l], bytes, hipMemcpyDeviceToDevice, ctx->stream));
       GSC_TRY(hipMemcpyAsync(dst->v[l], src->v[l], bytes, hipMemcpyDeviceToDevice, ctx->stream));
-      dst->step[l] = src->step[l];
     }
+    GSC_TRY(hipMemcpyAsync(dst->d_step, src->d_step, 8 * (size_t)src->K, hipMemcpyDeviceToDevice,
+                           ctx->stream));
     return GSC_OK;
   });
 }
@@ -1369,11 +1383,15 @@ gsc_status gsc_scene_save(gsc_ctx* ctx, const gsc_scene* sc, const char* path) {
   return guarded(ctx, [&]() -> gsc_status {
     if (!sc || !path) invalid(ctx, "NULL scene or path");
     if (!host_is_little_endian()) invalid(ctx, "scene state files are little-endian; host is not");
+    std::vector<int64_t> steps(sc->K);
+    GSC_TRY(hipMemcpyAsync(steps.data(), sc->d_step, 8 * (size_t)sc->K, hipMemcpyDeviceToHost,
+                           ctx->stream));
+    GSC_TRY(hipStreamSynchronize(ctx->stream));
     std::string hdr = kStateMagic;
     for (int l = 0; l < sc->K; ++l) {
       char buf[96];
       std::snprintf(buf, sizeof buf, "%s{\"n\":%lld,\"step\":%lld}", l ? "," : "", (long long)sc->n[l],
-                    (long long)sc->step[l]);
+                    (long long)steps[l]);
       hdr += buf;
     }
     hdr += "]}\n";
@@ -1435,7 +1453,11 @@ gsc_status gsc_scene_load(gsc_ctx* ctx, gsc_scene* sc, const char* path) {
         GSC_TRY(hipStreamSynchronize(ctx->stream));
       }
     }
-    for (int l = 0; l < sc->K; ++l) sc->step[l] = lv[l].second;
+    std::vector<int64_t> steps(sc->K);
+    for (int l = 0; l < sc->K; ++l) steps[l] = lv[l].second;
+    GSC_TRY(hipMemcpyAsync(sc->d_step, steps.data(), 8 * (size_t)sc->K, hipMemcpyHostToDevice,
+                           ctx->stream));
+    GSC_TRY(hipStreamSynchronize(ctx->stream));
     return GSC_OK;
   });
 }

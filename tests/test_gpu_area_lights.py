@@ -13,7 +13,7 @@ import torch
 
 import oracle
 import synth
-from tests.gpu_common import rel_l2, to_np
+from tests.gpu_common import adamw_params_close, rel_l2, to_np
 from tests.test_gpu_train import oracle_frame, unpack
 
 pytestmark = pytest.mark.gpu
@@ -140,4 +140,6 @@ def test_scene_with_area_lights_matches_oracle_frame(gsc, gctx, spp):
         assert rel_l2(to_np(image)[okpix], ref["composite"][okpix]) <= 1e-5
         for l in range(K):
             got = to_np(scene.state(l)["params"])
-            assert np.max(np.abs(got - ref["levels"][l]["params"])) <= 4 * max(wl.lr)
+            good, info = adamw_params_close(got, ref["levels"][l]["params"], state[l]["params"],
+                                            ref["levels"][l]["grads"], wl.lr, levels_np[l].n)
+            assert good, (frame, l, info)
