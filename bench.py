@@ -35,7 +35,8 @@ sys.path.insert(0, ROOT)
 
 METRIC = "GS-cache frames/s @1080p (trace+splat fwd/bwd) & p50/p99 ms, served vs plain"
 HBM_PEAK_GBS = 8000.0
-FP32_PEAK_TFLOPS = 157.3
+FP32_PEAK_TFLOPS = 157.3          # published: packed fp32 FMA, 256 CUs x 2.4 GHz x 128 lanes x 2 x 2
+FP32_NONPACKED_TFLOPS = 78.6      # the same without packed fp32 (the build disables it)
 
 
 def log(msg):
@@ -83,18 +84,21 @@ def algorithmic_bytes(kernel: str, c: dict) -> float:
 #   adjoint 65: test (14), T / (1 - alpha) with 1 - alpha (2), w = alpha T (1), colour gradients
 #               (6), dL/dalpha = T sum_k (c_k - B_k) g_k (9), background update (9),
 #               dL/dpower (1), opacity (2), conic A, C, B (4 + 4 + 3), mean u, v (5 + 5)
-# The forward tests every entry a pixel examines and blends `blended` of them; the adjoint walks
-# each pixel's list up to its last contributor (`contributors` entries), tests them all and runs
-# the full adjoint on the blended ones.
+# Only pairs the kernels actually evaluate are charged: the counting variants of the kernels
+# (gsc_ctx_set_work_counters, one frame after the timed region) count the (pixel, entry) pairs
+# whose pixel was live in the Gaussian's window when its wavefront evaluated the entry, i.e.
+# after the tile-ellipse cull, the window masks and the pixels' termination.  The forward tests
+# `fwd_tested` pairs and blends `blended` of them; the adjoint tests `bwd_tested` and runs the
+# full adjoint on the `bwd_blended` ones.
 F_TEST, F_BLEND, F_ADJOINT = 14.0, 9.0, 65.0
 
 
-def algorithmic_flops(kernel: str, cnt: dict, frames: int) -> float:
-    ev, bl, ncs = (cnt[k] / frames for k in ("evaluations", "blended", "contributors"))
+def algorithmic_flops(kernel: str, w: dict) -> float:
+    """Per frame, from the counted frame's work counters `w`."""
     if kernel == "splat_forward":
-        return F_TEST * ev + F_BLEND * bl
+        return F_TEST * w["fwd_tested"] + F_BLEND * w["blended"]
     if kernel == "splat_backward":
-        return F_TEST * ncs + (F_ADJOINT - F_TEST) * bl
+        return F_TEST * (w["bwd_tested"] - w["bwd_blended"]) + F_ADJOINT * w["bwd_blended"]
     return 0.0
 
 
@@ -131,6 +135,51 @@ def measured_traffic(kernel: str):
                     return None
                 return nbytes if sha is not None and parts[5] == sha else None
     return None
+
+
+def ceilings(ctx, volume_res: int, gaussians: int):
+    """Measured ceilings of the kernels' bounds (the survey's micro-benchmarks): a plain device
+    copy (HBM), random 32-byte reads over a working set the size of the scene's cell-corner
+    grid (the tracer), float atomic adds to random elements of a [9][G] gradient array (the
+    adjoint), and the vector ALU's fp32 FMA and exp rates (the splat kernels)."""
+    import torch
+    out = {}
+    n = 1 << 28                                   # 1 GiB of fp32
+    src = torch.ones(n, device="cuda")
+    dst = torch.empty_like(src)
+    dst.copy_(src)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(5):
+        dst.copy_(src)
+    e1.record()
+    torch.cuda.synchronize()
+    out["hbm_copy_GBs"] = round(5 * 2 * 4 * n / (e0.elapsed_time(e1) * 1e-3) / 1e9, 1)
+    del src, dst
+    cells = torch.empty(32 * (volume_res + 1) ** 3, dtype=torch.uint8, device="cuda")
+    cells.fill_(1)
+    threads, per = 256 * 4096, 64
+    ctx.probe_gather(cells, threads, per)
+    ms = min(ctx.probe_gather(cells, threads, per) for _ in range(3))
+    out["gather32_lookups_per_s"] = round(threads * per / (ms * 1e-3), 1)
+    out["gather32_GBs"] = round(32 * threads * per / (ms * 1e-3) / 1e9, 1)
+    out["gather32_working_set_GB"] = round(cells.numel() / 1e9, 2)
+    del cells
+    buf = torch.zeros(9 * gaussians, dtype=torch.float32, device="cuda")
+    threads, per = 256 * 4096, 16
+    ctx.probe_atomics(buf, threads, per)
+    ms = min(ctx.probe_atomics(buf, threads, per) for _ in range(3))
+    out["atomic_add_f32_per_s"] = round(threads * per / (ms * 1e-3), 1)
+    del buf
+    threads, iters = 256 * 8192, 1024
+    ctx.probe_valu(threads, iters, 0)
+    ms = min(ctx.probe_valu(threads, iters, 0) for _ in range(3))
+    out["valu_fma_TFLOPs"] = round(2.0 * 8 * threads * iters / (ms * 1e-3) / 1e12, 2)
+    ctx.probe_valu(threads, 256, 1)
+    ms = min(ctx.probe_valu(threads, 256, 1) for _ in range(3))
+    out["valu_exp_per_s"] = round(8 * threads * 256 / (ms * 1e-3), 1)
+    return out
 
 
 def cpu_baseline(wl, vol, levels, crop=256):
@@ -299,6 +348,17 @@ def main():
     elapsed = t1 - t0
     fps = args.steps / elapsed
     ms_step = 1000.0 * elapsed / args.steps
+    # One more frame (not timed) through the counting variants of the splat kernels: the pairs
+    # each kernel actually evaluates, for the algorithmic work of the rooflines.
+    ctx.set_work_counters(True)
+    step()
+    torch.cuda.synchronize()
+    ctx.set_work_counters(False)
+    cnt2 = ctx.counters()
+    work = {k: cnt2[k] - cnt[k] for k in cnt2}
+    log(f"work counters (one frame): " + ", ".join(f"{k}={work[k]}" for k in work))
+    ceil = ceilings(ctx, wl.volume_res, int(sum(g.n for g in levels)))
+    log(f"ceilings: {ceil}")
 
     per_frame_inst = cnt["instances"] / max(cnt["binnings"], 1)
     chunk = 1024                     # depth-ordered Gaussians per binning chunk (library constant)
@@ -314,7 +374,7 @@ def main():
         per_frame_ms = v["ms"] / args.steps
         info = {"ms_per_frame": round(per_frame_ms, 4), "launches": v["launches"]}
         if name in ALU_KERNELS:
-            fl = algorithmic_flops(name, cnt, args.steps)
+            fl = algorithmic_flops(name, work)
             info["algorithmic_TFLOPs"] = round(fl / (per_frame_ms * 1e-3) / 1e12, 2) if per_frame_ms > 0 else None
         else:
             b = algorithmic_bytes(name, c)
@@ -325,10 +385,17 @@ def main():
     launches_per_frame = prof[dominant]["launches"] / args.steps
     traffic = measured_traffic(dominant)
     if dominant in ALU_KERNELS:
-        per_launch = algorithmic_flops(dominant, cnt, args.steps) / launches_per_frame
+        per_launch = algorithmic_flops(dominant, work) / launches_per_frame
         achieved = per_launch / (per_launch_ms * 1e-3) / 1e12
         roofline = {"bound": "alu", "achieved": round(achieved, 2), "peak": FP32_PEAK_TFLOPS,
-                    "unit": "TFLOP/s", "frac": round(achieved / FP32_PEAK_TFLOPS, 4)}
+                    "unit": "TFLOP/s", "frac": round(achieved / FP32_PEAK_TFLOPS, 4),
+                    "frac_vs_nonpacked_78.6": round(achieved / FP32_NONPACKED_TFLOPS, 4),
+                    "measured_ceiling_TFLOPs": ceil["valu_fma_TFLOPs"],
+                    "frac_vs_measured": round(achieved / ceil["valu_fma_TFLOPs"], 4)}
+        if dominant == "splat_backward":
+            at = work["bwd_atomics"] / launches_per_frame / (per_launch_ms * 1e-3)
+            roofline["atomics_per_s"] = round(at, 1)
+            roofline["atomics_frac_vs_measured"] = round(at / ceil["atomic_add_f32_per_s"], 4)
     else:
         per_launch = algorithmic_bytes(dominant, c) / launches_per_frame
         achieved = per_launch / (per_launch_ms * 1e-3) / 1e9
@@ -338,13 +405,16 @@ def main():
                      "algorithmic_per_launch": per_launch})
     # Frame-level fraction: sum over kernels of the time their algorithmic work needs at the
     # vendor peak (bytes at HBM peak, or fp32 operations at the vector peak) over the frame time.
-    t_min = 0.0
+    t_min = t_min_meas = 0.0
     for name in kernels:
         if name in ALU_KERNELS:
-            t_min += algorithmic_flops(name, cnt, args.steps) / (FP32_PEAK_TFLOPS * 1e12)
+            t_min += algorithmic_flops(name, work) / (FP32_PEAK_TFLOPS * 1e12)
+            t_min_meas += algorithmic_flops(name, work) / (ceil["valu_fma_TFLOPs"] * 1e12)
         else:
             t_min += algorithmic_bytes(name, c) / (HBM_PEAK_GBS * 1e9)
+            t_min_meas += algorithmic_bytes(name, c) / (ceil["hbm_copy_GBs"] * 1e9)
     frame_frac = t_min / (ms_step * 1e-3)
+    frame_frac_meas = t_min_meas / (ms_step * 1e-3)
 
     # Cache initialisation with the paper's sizes (N = 300k, 3 levels: 300k / 150k / 75k) on this
     # volume (Method: "Cache Initialization"); the paper reports 411 ms on average.
@@ -393,6 +463,8 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "frame_roofline_frac": round(frame_frac, 4),
+        "frame_roofline_frac_measured_ceilings": round(frame_frac_meas, 4),
+        "ceilings": ceil,
         "kernels": kernels,
         "counters": {"instances_per_frame": int(per_frame_inst), "gaussians": int(c["gaussians"]),
                      "gaussian_pixel_evals_per_frame": int(cnt["evaluations"] / args.steps),
@@ -400,6 +472,14 @@ def main():
                      "adjoint_walk_pairs_per_frame": int(cnt["contributors"] / args.steps),
                      "tile_entries_per_frame": int(cnt["tile_entries"] / args.steps),
                      "gaussian_pixel_evals_per_s": round(cnt["evaluations"] / elapsed, 1),
+                     "tested_pairs_per_frame_forward": int(work["fwd_tested"]),
+                     "tested_pairs_per_frame_adjoint": int(work["bwd_tested"]),
+                     "blended_pairs_adjoint": int(work["bwd_blended"]),
+                     "slot_evaluations_forward": int(work["fwd_slots"]),
+                     "slot_evaluations_adjoint": int(work["bwd_slots"]),
+                     "adjoint_entries_walked": int(work["bwd_entries"]),
+                     "adjoint_atomics": int(work["bwd_atomics"]),
+                     "tested_pairs_forward_per_s": round(work["fwd_tested"] * fps, 1),
                      "paths_per_frame": int(c["paths"]),
                      "path_vertices_per_frame": int(stats["path_vertices"]),
                      "paths_per_s": round(c["paths"] * fps, 1)},

@@ -272,11 +272,41 @@ typedef struct gsc_counters {
   uint64_t blended;
   uint64_t contributors;
   uint64_t tile_entries;
+  /* Counted only while gsc_ctx_set_work_counters is on (the kernels' counting variants): */
+  uint64_t fwd_tested;     /* forward: (pixel, entry) pairs evaluated (pixels live in the
+                              Gaussian's window when the entry was walked) */
+  uint64_t fwd_slots;      /* forward: 64-pixel slot evaluations (one wave instruction stream) */
+  uint64_t bwd_tested;     /* adjoint: (pixel, entry) pairs evaluated */
+  uint64_t bwd_blended;    /* adjoint: pairs that blended (alpha >= 1/255, before the stop) */
+  uint64_t bwd_slots;      /* adjoint: 64-pixel slot evaluations */
+  uint64_t bwd_entries;    /* adjoint: (tile, entry) pairs walked after the tile-ellipse cull */
+  uint64_t bwd_atomics;    /* adjoint: float atomics issued into the screen-space gradients */
 } gsc_counters;
 /* Fills *out; synchronises the context's stream.  GSC_E_INVALID_ARG for NULL. */
 gsc_status gsc_ctx_counters(gsc_ctx* ctx, gsc_counters* out);
+/* on != 0: later splat launches on ctx run counting variants of the forward and adjoint kernels
+ * that also fill the fwd_* and bwd_* counters (a few scalar instructions per slot; the default
+ * kernels do not count them).  For measurement only; results are unchanged. */
+gsc_status gsc_ctx_set_work_counters(gsc_ctx* ctx, int32_t on);
 /* Frees the context's cached workspace (binning buffers, frame scratch). */
 gsc_status gsc_ctx_trim(gsc_ctx* ctx);
+
+/* ---- ceiling micro-benchmarks (measurement only) ----------------------------------------
+ * Each enqueues one kernel on the context's stream between two events, waits for it, and
+ * writes its duration in milliseconds to *ms (HOST).  threads: a positive multiple of 256.
+ * They measure the ceilings the hot-path kernels are compared with: the tracer's random reads
+ * of a density grid, the adjoint's float atomics, and the splat kernels' vector ALU. */
+/* threads x per_thread random 32-byte reads (per_thread a multiple of 8) from `cells`, an array
+ * of n_cells 32-byte cells; out [threads] receives one sum per thread. */
+gsc_status gsc_probe_gather(gsc_ctx* ctx, const void* cells, uint64_t n_cells, uint32_t threads,
+                            int32_t per_thread, float* out, double* ms);
+/* threads x per_thread float atomic adds of 1 to random elements of buf [n]. */
+gsc_status gsc_probe_atomics(gsc_ctx* ctx, float* buf, uint64_t n, uint32_t threads,
+                             int32_t per_thread, double* ms);
+/* threads x iters x 8 independent fp32 FMAs (mode 0) or exponentials exp(x) evaluated as
+ * 2^(x log2 e) (mode 1); out [threads] receives one value per thread. */
+gsc_status gsc_probe_valu(gsc_ctx* ctx, float* out, uint32_t threads, int32_t iters, int32_t mode,
+                          double* ms);
 
 /* ---- the hot path ----------------------------------------------------------------------- */
 /* Delta-tracking volume path tracer with next-event estimation to every light (ratio-tracked

@@ -157,6 +157,35 @@ class Context:
         """Sum the splat adjoint in fixed point so gradients repeat bit for bit (default off)."""
         self.check(self._lib.gsc_ctx_set_deterministic(self.handle, 1 if on else 0))
 
+    def probe_gather(self, cells: torch.Tensor, threads: int, per_thread: int) -> float:
+        """ms for threads x per_thread random 32-byte reads of `cells` (a uint8/float tensor whose
+        size is a multiple of 32 bytes)."""
+        out = torch.empty(threads, dtype=torch.float32, device=cells.device)
+        ms = ctypes.c_double()
+        self.check(self._lib.gsc_probe_gather(self.handle, cells.data_ptr(), cells.numel() * cells.element_size() // 32,
+                                              threads, per_thread, out.data_ptr(), ctypes.byref(ms)))
+        return ms.value
+
+    def probe_atomics(self, buf: torch.Tensor, threads: int, per_thread: int) -> float:
+        """ms for threads x per_thread float atomic adds to random elements of buf (float32)."""
+        assert buf.dtype == torch.float32
+        ms = ctypes.c_double()
+        self.check(self._lib.gsc_probe_atomics(self.handle, buf.data_ptr(), buf.numel(), threads,
+                                               per_thread, ctypes.byref(ms)))
+        return ms.value
+
+    def probe_valu(self, threads: int, iters: int, mode: int) -> float:
+        """ms for threads x iters x 8 fp32 FMAs (mode 0) or exponentials (mode 1)."""
+        out = torch.empty(threads, dtype=torch.float32, device="cuda")
+        ms = ctypes.c_double()
+        self.check(self._lib.gsc_probe_valu(self.handle, out.data_ptr(), threads, iters, mode,
+                                            ctypes.byref(ms)))
+        return ms.value
+
+    def set_work_counters(self, on: bool):
+        """Run the counting variants of the splat kernels (fills the fwd_* / bwd_* counters)."""
+        self.check(self._lib.gsc_ctx_set_work_counters(self.handle, 1 if on else 0))
+
     def counters(self):
         c = _abi.gsc_counters()
         self.check(self._lib.gsc_ctx_counters(self.handle, ctypes.byref(c)))

@@ -91,7 +91,10 @@ class gsc_level_buffers(Structure):
 
 class gsc_counters(Structure):
     _fields_ = [("instances", c_uint64), ("binnings", c_uint64), ("evaluations", c_uint64),
-                ("blended", c_uint64), ("contributors", c_uint64), ("tile_entries", c_uint64)]
+                ("blended", c_uint64), ("contributors", c_uint64), ("tile_entries", c_uint64),
+                ("fwd_tested", c_uint64), ("fwd_slots", c_uint64), ("bwd_tested", c_uint64),
+                ("bwd_blended", c_uint64), ("bwd_slots", c_uint64), ("bwd_entries", c_uint64),
+                ("bwd_atomics", c_uint64)]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}
@@ -109,6 +112,7 @@ _SIGNATURES = {
     "gsc_ctx_set_stream": (c_int32, [c_void_p, c_void_p]),
     "gsc_ctx_set_deterministic": (c_int32, [c_void_p, c_int32]),
     "gsc_ctx_set_list_cut": (c_int32, [c_void_p, c_int32]),
+    "gsc_ctx_set_work_counters": (c_int32, [c_void_p, c_int32]),
     "gsc_ctx_required_capacity": (c_uint64, [c_void_p]),
     "gsc_ctx_trim": (c_int32, [c_void_p]),
     "gsc_ctx_synchronize": (c_int32, [c_void_p]),
@@ -117,6 +121,11 @@ _SIGNATURES = {
     "gsc_ctx_profile_read": (c_int32, [c_void_p, c_int32, ctypes.c_char_p, c_size_t, P(c_double),
                                        P(c_int64)]),
     "gsc_ctx_counters": (c_int32, [c_void_p, P(gsc_counters)]),
+    "gsc_probe_gather": (c_int32, [c_void_p, c_void_p, c_uint64, ctypes.c_uint32, c_int32, c_void_p,
+                                   P(c_double)]),
+    "gsc_probe_atomics": (c_int32, [c_void_p, c_void_p, c_uint64, ctypes.c_uint32, c_int32,
+                                    P(c_double)]),
+    "gsc_probe_valu": (c_int32, [c_void_p, c_void_p, ctypes.c_uint32, c_int32, c_int32, P(c_double)]),
     "gsc_init_points": (c_int32, [c_void_p, P(gsc_volume), c_int64, c_uint64, c_void_p, c_void_p]),
     "gsc_knn_mean3": (c_int32, [c_void_p, c_void_p, c_int64, c_void_p]),
     "gsc_cache_init": (c_int32, [c_void_p, P(gsc_volume), c_int64, c_int32, c_uint64,

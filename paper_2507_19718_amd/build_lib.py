@@ -12,7 +12,7 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libgsc.so")
 SOURCES = ["k_project.hip", "k_sort.hip", "k_bin.hip", "k_splat.hip", "k_trace.hip",
-           "k_train.hip", "k_init.hip", "runtime.hip"]
+           "k_train.hip", "k_init.hip", "k_probe.hip", "runtime.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 # fp32 in program order (no FMA contraction), correctly rounded division and square root,
 # fp32 denormals kept, no packed-fp32 instructions.

@@ -155,7 +155,7 @@ hipError_t launch_splat_forward(hipStream_t st, const Seg* segs, const int64_t* 
                                 const uint32_t* values, const SplatRec* rec, float* images,
                                 float* final_T, int32_t* last_id, uint32_t* n_contrib,
                                 unsigned long long* stats, const uint32_t* order,
-                                uint32_t* tile_work);
+                                uint32_t* tile_work, bool count);
 // Keys ordering tiles by decreasing work (work NULL: list length from ranges).
 hipError_t launch_tile_order(hipStream_t st, const uint64_t* ranges, const uint32_t* work,
                              int64_t n_tiles, uint32_t* order);
@@ -166,7 +166,7 @@ hipError_t launch_splat_backward(hipStream_t st, const Seg* segs, const int64_t*
                                  const uint32_t* values, const SplatRec* rec, const float* final_T,
                                  const uint32_t* n_contrib, const float* dL_dimages,
                                  float* grad2d, int64_t G, const uint32_t* order, uint32_t* gmax,
-                                 unsigned long long* gfix);
+                                 unsigned long long* gfix, unsigned long long* stats, bool count);
 
 int64_t trace_align(int64_t pixels);
 hipError_t launch_trace(hipStream_t st, const TraceDesc* descs, const int64_t* req_pstart, int R,
@@ -200,5 +200,12 @@ hipError_t launch_adam_commit(hipStream_t st, const AdamGroup* groups, int S);
 hipError_t launch_adam(hipStream_t st, float* param, float* m, float* v, const float* grad,
                        int64_t count, float b1, float b2, float omb1, float omb2, float s1,
                        float s2, float wdf, float eps, const float* guard);
+
+// Ceiling micro-benchmarks (k_probe.hip).  threads: a multiple of 256.
+hipError_t launch_probe_gather(hipStream_t st, const float4* cells, uint64_t n_cells,
+                               uint32_t threads, int per_thread, float* out);
+hipError_t launch_probe_atomic(hipStream_t st, float* buf, uint64_t n, uint32_t threads,
+                               int per_thread);
+hipError_t launch_probe_valu(hipStream_t st, float* out, uint32_t threads, int iters, int mode);
 
 }  // namespace gsc

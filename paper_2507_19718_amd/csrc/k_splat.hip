@@ -154,6 +154,16 @@ __device__ __forceinline__ bool lane_in(uint64_t mask) {
   return __builtin_amdgcn_inverse_ballot_w64(mask);
 }
 
+// Work counters (stats words, all sums over the launch): the forward always adds
+// [0] list positions each pixel examined, [1] blended pairs, [2] each pixel's walk length,
+// [3] entries its wavefront evaluated after the cull; with kCount also [4] (pixel, entry) pairs
+// tested (lanes live in an evaluated slot) and [5] slot evaluations.  The adjoint with kCount
+// adds [6] pairs tested, [7] pairs blended, [8] slot evaluations, [9] entries walked after the
+// cull and [10] float atomics issued.
+enum { kStEval = 0, kStBlend, kStContrib, kStEntries, kStFwdTested, kStFwdSlots, kStBwdTested,
+       kStBwdBlend, kStBwdSlots, kStBwdEntries, kStBwdAtomics, kStWords };
+
+template <bool kCount>
 __global__ void __launch_bounds__(64) splat_forward_kernel(
     const Seg* __restrict__ segs, const int64_t* __restrict__ seg_tstart, int S,
     const DevCam* __restrict__ cams, const uint64_t* __restrict__ ranges,
@@ -168,6 +178,7 @@ __global__ void __launch_bounds__(64) splat_forward_kernel(
   uint32_t nc[kPx], stop[kPx];
   uint64_t done[kPx];                    // lanes finished (terminated, or outside the image)
   uint32_t n_blend = 0u, n_entries = 0u;
+  uint64_t n_tested = 0u, n_slots = 0u;
 #pragma unroll
   for (int p = 0; p < kPx; ++p) {
     T[p] = 1.0f; C0[p] = 0.0f; C1[p] = 0.0f; C2[p] = 0.0f;
@@ -208,6 +219,7 @@ __global__ void __launch_bounds__(64) splat_forward_kernel(
       for (int p = 0; p < kPx; ++p) {
         const uint64_t act = win[p] & ~done[p];
         if (act == 0ull) continue;
+        if (kCount) { n_tested += (uint64_t)__popcll(act); ++n_slots; }
         const float dy = v - tc.fj[p];
         const float power = -0.5f * (adx + (Cc * dy) * dy) - bdx * dy;
         const float alpha = fminf(kAlphaMax, o * __expf(power));
@@ -252,10 +264,14 @@ __global__ void __launch_bounds__(64) splat_forward_kernel(
       ncs += __shfl_xor(ncs, off, 64);
     }
     if (lane == 0) {
-      atomicAdd(&stats[0], (unsigned long long)ev);
-      atomicAdd(&stats[1], (unsigned long long)n_blend);
-      atomicAdd(&stats[2], (unsigned long long)ncs);
-      atomicAdd(&stats[3], (unsigned long long)n_entries);
+      atomicAdd(&stats[kStEval], (unsigned long long)ev);
+      atomicAdd(&stats[kStBlend], (unsigned long long)n_blend);
+      atomicAdd(&stats[kStContrib], (unsigned long long)ncs);
+      atomicAdd(&stats[kStEntries], (unsigned long long)n_entries);
+      if (kCount) {
+        atomicAdd(&stats[kStFwdTested], (unsigned long long)n_tested);
+        atomicAdd(&stats[kStFwdSlots], (unsigned long long)n_slots);
+      }
     }
   }
 }
@@ -293,6 +309,7 @@ __device__ __forceinline__ float row_total(float v) {
   return t;
 }
 
+template <bool kCount>
 __global__ void __launch_bounds__(64) splat_backward_kernel(
     const Seg* __restrict__ segs, const int64_t* __restrict__ seg_tstart, int S,
     const DevCam* __restrict__ cams, const uint64_t* __restrict__ ranges,
@@ -300,7 +317,7 @@ __global__ void __launch_bounds__(64) splat_backward_kernel(
     const float* __restrict__ final_T, const uint32_t* __restrict__ n_contrib,
     const float* __restrict__ dL_dimages, float* __restrict__ grad2d, int64_t G,
     const uint32_t* __restrict__ order, int mode, uint32_t* __restrict__ gmax,
-    unsigned long long* __restrict__ gfix) {
+    unsigned long long* __restrict__ gfix, unsigned long long* __restrict__ stats) {
   __shared__ float part[4][64][kPartStride];
   const int64_t t = order ? (int64_t)order[blockIdx.x] : (int64_t)blockIdx.x;
   const Tile tc = tile_setup(segs, seg_tstart, S, cams, ranges, t);
@@ -328,6 +345,8 @@ __global__ void __launch_bounds__(64) splat_backward_kernel(
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) mx = max(mx, (uint32_t)__shfl_xor((int)mx, off, 64));
   const int64_t stop = tc.start + (int64_t)mx;
+  uint64_t n_tested = 0u, n_blended = 0u, n_slots = 0u, n_entries = 0u;
+  uint32_t n_atomics = 0u;
   for (int64_t be = stop; be > tc.start; be -= 64) {
     const int64_t bs = (be - 64) > tc.start ? (be - 64) : tc.start;
     const int n = (int)(be - bs);
@@ -346,6 +365,7 @@ __global__ void __launch_bounds__(64) splat_backward_kernel(
     while (mask) {
       const int k = 63 - __builtin_clzll(mask);          // back to front
       mask &= ~(1ull << k);
+      if (kCount) ++n_entries;
       const float u = rl(q0.x, k), v = rl(q0.y, k), A = rl(q0.z, k), B = rl(q0.w, k);
       const float Cc = rl(q1.x, k), o = rl(q1.y, k);
       const float cr = rl(q1.z, k), cg = rl(q1.w, k), cb = rl(q2.x, k);
@@ -372,6 +392,11 @@ __global__ void __launch_bounds__(64) splat_backward_kernel(
         const float alpha = fminf(kAlphaMax, oe);
         const uint64_t okm = act & __builtin_amdgcn_ballot_w64(!(power > 0.0f)) &
                              __builtin_amdgcn_ballot_w64(!(alpha < kAlphaMin));
+        if (kCount) {
+          n_tested += (uint64_t)__popcll(act);
+          n_blended += (uint64_t)__popcll(okm);
+          ++n_slots;
+        }
         any |= okm;
         const bool ok = lane_in(okm);
         const float az = ok ? alpha : 0.0f;
@@ -415,7 +440,10 @@ __global__ void __launch_bounds__(64) splat_backward_kernel(
 #pragma unroll
         for (int a = 0; a < 9; ++a) {
           const float acc = (part[0][lane][a] + part[1][lane][a]) + (part[2][lane][a] + part[3][lane][a]);
-          if (acc != 0.0f) unsafeAtomicAdd(&grad2d[(int64_t)a * G + gi], acc);
+          if (acc != 0.0f) {
+            unsafeAtomicAdd(&grad2d[(int64_t)a * G + gi], acc);
+            if (kCount) ++n_atomics;
+          }
         }
       }
     } else if (mine) {
@@ -433,6 +461,18 @@ __global__ void __launch_bounds__(64) splat_backward_kernel(
       }
     }
     __syncthreads();
+  }
+  if (kCount) {
+    uint64_t na = n_atomics;
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) na += __shfl_xor(na, off, 64);
+    if (lane == 0) {
+      atomicAdd(&stats[kStBwdTested], (unsigned long long)n_tested);
+      atomicAdd(&stats[kStBwdBlend], (unsigned long long)n_blended);
+      atomicAdd(&stats[kStBwdSlots], (unsigned long long)n_slots);
+      atomicAdd(&stats[kStBwdEntries], (unsigned long long)n_entries);
+      atomicAdd(&stats[kStBwdAtomics], (unsigned long long)na);
+    }
   }
 }
 
@@ -489,11 +529,16 @@ hipError_t launch_splat_forward(hipStream_t st, const Seg* segs, const int64_t* 
                                 const uint32_t* values, const SplatRec* rec, float* images,
                                 float* final_T, int32_t* last_id, uint32_t* n_contrib,
                                 unsigned long long* stats, const uint32_t* order,
-                                uint32_t* tile_work) {
+                                uint32_t* tile_work, bool count) {
   if (n_tiles == 0) return hipSuccess;
-  hipLaunchKernelGGL(splat_forward_kernel, dim3((unsigned)n_tiles), dim3(64), 0, st, segs,
-                     seg_tstart, S, cams, ranges, values, rec, images, final_T, last_id, n_contrib,
-                     stats, order, tile_work);
+  if (count && stats)
+    hipLaunchKernelGGL(splat_forward_kernel<true>, dim3((unsigned)n_tiles), dim3(64), 0, st, segs,
+                       seg_tstart, S, cams, ranges, values, rec, images, final_T, last_id,
+                       n_contrib, stats, order, tile_work);
+  else
+    hipLaunchKernelGGL(splat_forward_kernel<false>, dim3((unsigned)n_tiles), dim3(64), 0, st, segs,
+                       seg_tstart, S, cams, ranges, values, rec, images, final_T, last_id,
+                       n_contrib, stats, order, tile_work);
   return hipGetLastError();
 }
 
@@ -502,21 +547,26 @@ hipError_t launch_splat_backward(hipStream_t st, const Seg* segs, const int64_t*
                                  const uint32_t* values, const SplatRec* rec, const float* final_T,
                                  const uint32_t* n_contrib, const float* dL_dimages,
                                  float* grad2d, int64_t G, const uint32_t* order, uint32_t* gmax,
-                                 unsigned long long* gfix) {
+                                 unsigned long long* gfix, unsigned long long* stats, bool count) {
   if (n_tiles == 0) return hipSuccess;
   if (!gmax) {
-    hipLaunchKernelGGL(splat_backward_kernel, dim3((unsigned)n_tiles), dim3(64), 0, st, segs,
-                       seg_tstart, S, cams, ranges, values, rec, final_T, n_contrib, dL_dimages,
-                       grad2d, G, order, (int)kAdjointAtomic, gmax, gfix);
+    if (count && stats)
+      hipLaunchKernelGGL(splat_backward_kernel<true>, dim3((unsigned)n_tiles), dim3(64), 0, st, segs,
+                         seg_tstart, S, cams, ranges, values, rec, final_T, n_contrib, dL_dimages,
+                         grad2d, G, order, (int)kAdjointAtomic, gmax, gfix, stats);
+    else
+      hipLaunchKernelGGL(splat_backward_kernel<false>, dim3((unsigned)n_tiles), dim3(64), 0, st,
+                         segs, seg_tstart, S, cams, ranges, values, rec, final_T, n_contrib,
+                         dL_dimages, grad2d, G, order, (int)kAdjointAtomic, gmax, gfix, stats);
     return hipGetLastError();
   }
   // Deterministic: gmax [9][G] and gfix [9][G] must be zero on entry.
-  hipLaunchKernelGGL(splat_backward_kernel, dim3((unsigned)n_tiles), dim3(64), 0, st, segs,
+  hipLaunchKernelGGL(splat_backward_kernel<false>, dim3((unsigned)n_tiles), dim3(64), 0, st, segs,
                      seg_tstart, S, cams, ranges, values, rec, final_T, n_contrib, dL_dimages,
-                     grad2d, G, order, (int)kAdjointMax, gmax, gfix);
-  hipLaunchKernelGGL(splat_backward_kernel, dim3((unsigned)n_tiles), dim3(64), 0, st, segs,
+                     grad2d, G, order, (int)kAdjointMax, gmax, gfix, stats);
+  hipLaunchKernelGGL(splat_backward_kernel<false>, dim3((unsigned)n_tiles), dim3(64), 0, st, segs,
                      seg_tstart, S, cams, ranges, values, rec, final_T, n_contrib, dL_dimages,
-                     grad2d, G, order, (int)kAdjointFixed, gmax, gfix);
+                     grad2d, G, order, (int)kAdjointFixed, gmax, gfix, stats);
   if (G > 0)
     hipLaunchKernelGGL(fixed_to_float_kernel, dim3((unsigned)((9 * G + 255) / 256)), dim3(256), 0,
                        st, gmax, gfix, G, grad2d);

@@ -161,7 +161,8 @@ struct gsc_ctx {
   int64_t prof_n[16] = {};
   uint64_t acc_instances = 0, acc_frames = 0;
   DevBuf adam_tab;                 // fused AdamW group table
-  DevBuf d_stats;                  // splat forward counters: evaluations, blended, contributors, entries
+  DevBuf d_stats;                  // splat work counters (kStatWords words)
+  bool work_counters = false;      // detailed counting variants of the splat kernels
 };
 
 namespace {
@@ -257,7 +258,7 @@ const char* const kProfNames[] = {"project", "depth_sort", "bin_count", "bin_sca
                                   "project_backward", "adam", "gather_rect",
                                   "project_backward_adam"};
 constexpr int kProfCount = 13;
-constexpr int kStatWords = 4;   // splat forward counters (gsc_counters)
+constexpr int kStatWords = 11;  // splat work counters (gsc_counters; see k_splat.hip)
 enum { P_PROJECT, P_SORT, P_COUNT, P_SCAN, P_PLACE, P_FWD, P_TRACE, P_LOSS, P_BWD, P_PBWD, P_ADAM,
        P_GATHER, P_PBADAM };
 
@@ -539,7 +540,7 @@ void run_forward(gsc_ctx* ctx, gsc_binning* b, float* images, float* final_T, in
                                b->ranges.as<uint64_t>(), b->values.as<uint32_t>(),
                                b->rec.as<SplatRec>(), images, final_T, last_id,
                                b->n_contrib.as<uint32_t>(), ctx->d_stats.as<unsigned long long>(),
-                               order, b->tile_work.as<uint32_t>()));
+                               order, b->tile_work.as<uint32_t>(), ctx->work_counters));
   }
   b->forward_done = true;
 }
@@ -558,11 +559,16 @@ void run_splat_adjoint(gsc_ctx* ctx, gsc_binning* b, const float* final_T, const
     GSC_TRY(hipMemsetAsync(b->grad2d.p, 0, 4 * 9 * (size_t)b->G, ctx->stream));
   }
   const uint32_t* order = tile_order(ctx, b, b->tile_work.as<uint32_t>());
+  if (ctx->work_counters && !ctx->d_stats.p) {
+    need(ctx, ctx->d_stats, ctx->alloc, kStatWords * 8, "splat counters");
+    GSC_TRY(hipMemsetAsync(ctx->d_stats.p, 0, kStatWords * 8, ctx->stream));
+  }
   { ProfScope ps_(ctx, P_BWD, ctx->stream);
   GSC_TRY(launch_splat_backward(ctx->stream, b->d_segs(), b->d_tstart(), b->S, b->d_cams(), b->n_tiles,
                                 b->ranges.as<uint64_t>(), b->values.as<uint32_t>(),
                                 b->rec.as<SplatRec>(), final_T, b->n_contrib.as<uint32_t>(), dL,
-                                b->grad2d.as<float>(), b->G, order, gmax, gfix));
+                                b->grad2d.as<float>(), b->G, order, gmax, gfix,
+                                ctx->d_stats.as<unsigned long long>(), ctx->work_counters));
   }
 }
 
@@ -934,6 +940,27 @@ std::vector<std::pair<int64_t, int64_t>> parse_state_header(gsc_ctx* ctx, const 
 // =============================================================================================
 // C ABI
 // =============================================================================================
+// Ceiling micro-benchmarks: one launch between two events on the context stream.
+namespace {
+template <typename F>
+gsc_status timed_probe(gsc_ctx* ctx, double* ms, F&& launch) {
+  hipEvent_t a = pool_event(ctx), b = pool_event(ctx);
+  GSC_TRY(hipEventRecord(a, ctx->stream));
+  GSC_TRY(launch());
+  GSC_TRY(hipEventRecord(b, ctx->stream));
+  GSC_TRY(hipEventSynchronize(b));
+  *ms = elapsed(a, b);
+  ctx->ev_pool.push_back(a);
+  ctx->ev_pool.push_back(b);
+  return GSC_OK;
+}
+
+void check_probe_threads(gsc_ctx* ctx, uint32_t threads, int32_t per_thread) {
+  if (threads == 0 || threads % 256 != 0) invalid(ctx, "threads must be a positive multiple of 256");
+  if (per_thread < 1) invalid(ctx, "per_thread must be >= 1");
+}
+}  // namespace
+
 extern "C" {
 
 gsc_status gsc_ctx_create(int device, void* hip_stream, const gsc_allocator* alloc, gsc_ctx** out) {
@@ -956,7 +983,7 @@ gsc_status gsc_ctx_create(int device, void* hip_stream, const gsc_allocator* all
   for (int i = 0; i < 8 && ok; ++i) ok = hipEventCreate(&c->tev[i]) == hipSuccess;
   c->pinned_cap = size_t(4) << 20;
   ok = ok && hipHostMalloc((void**)&c->pinned, c->pinned_cap, hipHostMallocDefault) == hipSuccess;
-  ok = ok && hipHostMalloc((void**)&c->host_u64, 64, hipHostMallocDefault) == hipSuccess;
+  ok = ok && hipHostMalloc((void**)&c->host_u64, 8 * 32, hipHostMallocDefault) == hipSuccess;
   if (!ok) {
     gsc_ctx_destroy(c);
     return GSC_E_DEVICE;
@@ -1006,6 +1033,12 @@ gsc_status gsc_ctx_set_stream(gsc_ctx* ctx, void* hip_stream) {
 gsc_status gsc_ctx_set_deterministic(gsc_ctx* ctx, int32_t on) {
   if (!ctx) return GSC_E_INVALID_ARG;
   ctx->deterministic = on ? 1 : 0;
+  return GSC_OK;
+}
+
+gsc_status gsc_ctx_set_work_counters(gsc_ctx* ctx, int32_t on) {
+  if (!ctx) return GSC_E_INVALID_ARG;
+  ctx->work_counters = on != 0;
   return GSC_OK;
 }
 
@@ -1666,7 +1699,7 @@ gsc_status gsc_ctx_profile_read(gsc_ctx* ctx, int32_t index, char* name, size_t 
 gsc_status gsc_ctx_counters(gsc_ctx* ctx, gsc_counters* out) {
   return guarded(ctx, [&]() -> gsc_status {
     if (!out) invalid(ctx, "NULL argument");
-    uint64_t d[kStatWords] = {0, 0, 0, 0};
+    uint64_t d[kStatWords] = {};
     if (ctx->d_stats.p) {
       GSC_TRY(hipMemcpyAsync(ctx->host_u64, ctx->d_stats.p, sizeof(d), hipMemcpyDeviceToHost, ctx->stream));
       GSC_TRY(hipStreamSynchronize(ctx->stream));
@@ -1678,6 +1711,13 @@ gsc_status gsc_ctx_counters(gsc_ctx* ctx, gsc_counters* out) {
     out->blended = d[1];
     out->contributors = d[2];
     out->tile_entries = d[3];
+    out->fwd_tested = d[4];
+    out->fwd_slots = d[5];
+    out->bwd_tested = d[6];
+    out->bwd_blended = d[7];
+    out->bwd_slots = d[8];
+    out->bwd_entries = d[9];
+    out->bwd_atomics = d[10];
     return GSC_OK;
   });
 }
@@ -1688,6 +1728,42 @@ gsc_status gsc_copy(gsc_ctx* ctx, void* dst, const void* src, size_t bytes) {
     if (!dst || !src) invalid(ctx, "NULL pointer");
     GSC_TRY(hipMemcpyAsync(dst, src, bytes, hipMemcpyDefault, ctx->stream));
     return GSC_OK;
+  });
+}
+
+
+gsc_status gsc_probe_gather(gsc_ctx* ctx, const void* cells, uint64_t n_cells, uint32_t threads,
+                            int32_t per_thread, float* out, double* ms) {
+  return guarded(ctx, [&]() -> gsc_status {
+    if (!cells || !out || !ms) invalid(ctx, "NULL argument");
+    if (n_cells == 0) invalid(ctx, "n_cells must be >= 1");
+    check_probe_threads(ctx, threads, per_thread);
+    if (per_thread % 8 != 0) invalid(ctx, "per_thread must be a multiple of 8");
+    return timed_probe(ctx, ms, [&]() {
+      return launch_probe_gather(ctx->stream, (const float4*)cells, n_cells, threads, per_thread, out);
+    });
+  });
+}
+
+gsc_status gsc_probe_atomics(gsc_ctx* ctx, float* buf, uint64_t n, uint32_t threads,
+                             int32_t per_thread, double* ms) {
+  return guarded(ctx, [&]() -> gsc_status {
+    if (!buf || !ms) invalid(ctx, "NULL argument");
+    if (n == 0) invalid(ctx, "n must be >= 1");
+    check_probe_threads(ctx, threads, per_thread);
+    return timed_probe(ctx, ms, [&]() {
+      return launch_probe_atomic(ctx->stream, buf, n, threads, per_thread);
+    });
+  });
+}
+
+gsc_status gsc_probe_valu(gsc_ctx* ctx, float* out, uint32_t threads, int32_t iters, int32_t mode,
+                          double* ms) {
+  return guarded(ctx, [&]() -> gsc_status {
+    if (!out || !ms) invalid(ctx, "NULL argument");
+    if (mode != 0 && mode != 1) invalid(ctx, "mode must be 0 (fma) or 1 (exp)");
+    check_probe_threads(ctx, threads, iters);
+    return timed_probe(ctx, ms, [&]() { return launch_probe_valu(ctx->stream, out, threads, iters, mode); });
   });
 }
 
