@@ -140,6 +140,8 @@ def test_scene_with_area_lights_matches_oracle_frame(gsc, gctx, spp):
         assert rel_l2(to_np(image)[okpix], ref["composite"][okpix]) <= 1e-5
         for l in range(K):
             got = to_np(scene.state(l)["params"])
-            good, info = adamw_params_close(got, ref["levels"][l]["params"], state[l]["params"],
-                                            ref["levels"][l]["grads"], wl.lr, levels_np[l].n)
+            rl = ref["levels"][l]
+            good, info = adamw_params_close(got, rl["params"], state[l]["params"], rl["grads"],
+                                            state[l]["m"], state[l]["v"], state[l]["step"] + 1,
+                                            wl.lr, levels_np[l].n)
             assert good, (frame, l, info)

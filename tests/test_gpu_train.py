@@ -136,9 +136,10 @@ def test_render_frame_tiny_ten_steps(gsc, gctx):
         assert rel_l2(comp[okpix], ref["composite"][okpix]) <= 1e-5
         for l in range(K):
             s = scene.state(l)
-            good, info = adamw_params_close(to_np(s["params"]), ref["levels"][l]["params"],
-                                            state[l]["params"], ref["levels"][l]["grads"], wl.lr,
-                                            levels_np[l].n)
+            rl = ref["levels"][l]
+            good, info = adamw_params_close(to_np(s["params"]), rl["params"], state[l]["params"],
+                                            rl["grads"], state[l]["m"], state[l]["v"], state[l]["step"] + 1,
+                                            wl.lr, levels_np[l].n)
             assert good, (frame, l, info)
             assert s["step"] == frame + 1
     assert losses[-1] < losses[0]
