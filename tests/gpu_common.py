@@ -57,8 +57,18 @@ def grads_close(got: np.ndarray, ref: np.ndarray, tol: float = 1e-4):
 GROUP_OFFSETS = (0, 3, 7, 10, 13, 14)     # pos, rot, log_scale, rgb, opacity_logit (x n)
 
 
+def gaussians_at_pixels(window, culled, pixels, cam):
+    """Per Gaussian: does its integer pixel window (x0, x1, y0, y1, full-frame, inclusive) hold
+    any of the render window's pixels marked in `pixels` [h][w]?"""
+    hit = np.zeros(window.shape[0], dtype=bool)
+    for j, i in zip(*np.nonzero(pixels)):
+        x, y = cam.x0 + int(i), cam.y0 + int(j)
+        hit |= (window[:, 0] <= x) & (x <= window[:, 1]) & (window[:, 2] <= y) & (y <= window[:, 3])
+    return hit & ~np.asarray(culled, bool)
+
+
 def adamw_params_close(got, want, before, grads_ref, m_before, v_before, step, lrs, n,
-                       beta1=0.9, beta2=0.999, eps=1e-8):
+                       beta1=0.9, beta2=0.999, eps=1e-8, exclude=None):
     """Parameters after one training frame's AdamW step taken from the same state (p, m, v
     before the step) on both sides; step = the step number t of that update.  The gradients may
     differ by e, within the gradient bound |e| <= e_max = 1e-4 |g| + 2e-4 rms(g) of the group.
@@ -69,7 +79,9 @@ def adamw_params_close(got, want, before, grads_ref, m_before, v_before, step, l
     step is required (1.05 for an extremum between the sample points).  Every element must also
     stay within 4 lr (1 + max |p|) of where it started, and a group with lr 0 must not move at
     all.  A group whose reference gradient is rounding noise (rms below 1e-9 of the largest
-    group's) is held to the step bound only.  Returns (ok, info)."""
+    group's) is held to the step bound only, and so are the Gaussians in `exclude` (those whose
+    window holds a boundary pixel, where the two sides may legitimately blend different sets).
+    Returns (ok, info)."""
     got, want, before, g, mb, vb = (np.asarray(a, np.float64).ravel()
                                     for a in (got, want, before, grads_ref, m_before, v_before))
     t = float(step)
@@ -104,7 +116,11 @@ def adamw_params_close(got, want, before, grads_ref, m_before, v_before, step, l
         for f in np.linspace(-1.0, 1.0, 33):
             dr = np.maximum(dr, np.abs(r_of(gs + f * emax, ms, vs) - r0))
         allow = 1.05 * lr * dr + 2.4e-7 * (np.abs(want[s]) + lr * (1.0 + np.abs(r0))) + 1e-30
-        worst = float(np.max(np.abs(got[s] - want[s]) / allow))
+        ratio = np.abs(got[s] - want[s]) / allow
+        if exclude is not None:
+            w = GROUP_OFFSETS[k + 1] - GROUP_OFFSETS[k]
+            ratio = ratio[~np.repeat(np.asarray(exclude, bool), w)]
+        worst = float(np.max(ratio)) if ratio.size else 0.0
         if worst > 1.0:
             return False, (k, "step", worst)
     return True, None
