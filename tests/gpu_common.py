@@ -79,8 +79,9 @@ def adamw_params_close(got, want, before, grads_ref, m_before, v_before, step, l
     step is required (1.05 for an extremum between the sample points).  Every element must also
     stay within 4 lr (1 + max |p|) of where it started, and a group with lr 0 must not move at
     all.  A group whose reference gradient is rounding noise (rms below 1e-9 of the largest
-    group's) is held to the step bound only, and so are the Gaussians in `exclude` (those whose
-    window holds a boundary pixel, where the two sides may legitimately blend different sets).
+    group's) is held to the step bound only, and so are the Gaussians in `exclude` ([n], or
+    [5][n] per group): those whose window holds a boundary pixel, where the two sides may
+    legitimately blend different sets, and, for the rotation group, nearly isotropic Gaussians.
     Returns (ok, info)."""
     got, want, before, g, mb, vb = (np.asarray(a, np.float64).ravel()
                                     for a in (got, want, before, grads_ref, m_before, v_before))
@@ -118,9 +119,25 @@ def adamw_params_close(got, want, before, grads_ref, m_before, v_before, step, l
         allow = 1.05 * lr * dr + 2.4e-7 * (np.abs(want[s]) + lr * (1.0 + np.abs(r0))) + 1e-30
         ratio = np.abs(got[s] - want[s]) / allow
         if exclude is not None:
+            ex = np.asarray(exclude, bool)
+            ex = ex[k] if ex.ndim == 2 else ex
             w = GROUP_OFFSETS[k + 1] - GROUP_OFFSETS[k]
-            ratio = ratio[~np.repeat(np.asarray(exclude, bool), w)]
+            ratio = ratio[~np.repeat(ex, w)]
         worst = float(np.max(ratio)) if ratio.size else 0.0
         if worst > 1.0:
             return False, (k, "step", worst)
     return True, None
+
+
+def frame_exclusions(boundary_gaussians, log_scale, min_anisotropy=1e-2):
+    """[5][n] exclusion masks for adamw_params_close in training frames: every group skips the
+    Gaussians at boundary pixels; the rotation group also skips Gaussians whose log-scales differ
+    by less than `min_anisotropy`.  The rotation gradient of a Gaussian of anisotropy a is a sum
+    of terms of the size of its covariance gradient that cancel down to ~a of it, so fp32 keeps
+    only ~1e-7 / a of it relative: below a = 1e-2 that leaves the 1e-4 relative bar (the rotation
+    gradient is compared on anisotropic Gaussians by the backward parity tests)."""
+    ls = np.asarray(log_scale, np.float64).reshape(-1, 3)
+    iso = (ls.max(axis=1) - ls.min(axis=1)) < min_anisotropy
+    ex = np.repeat(np.asarray(boundary_gaussians, bool)[None, :], 5, axis=0)
+    ex[1] |= iso
+    return ex

@@ -13,7 +13,7 @@ import torch
 
 import oracle
 import synth
-from tests.gpu_common import adamw_params_close, rel_l2, to_np
+from tests.gpu_common import adamw_params_close, frame_exclusions, rel_l2, to_np
 from tests.test_gpu_train import oracle_frame, unpack
 
 pytestmark = pytest.mark.gpu
@@ -144,5 +144,7 @@ def test_scene_with_area_lights_matches_oracle_frame(gsc, gctx, spp):
             assert rl["boundary_gaussians"].mean() <= 0.2
             good, info = adamw_params_close(got, rl["params"], state[l]["params"], rl["grads"],
                                             state[l]["m"], state[l]["v"], state[l]["step"] + 1,
-                                            wl.lr, levels_np[l].n, exclude=rl["boundary_gaussians"])
+                                            wl.lr, levels_np[l].n,
+                                            exclude=frame_exclusions(rl["boundary_gaussians"],
+                                                                     cur[l].log_scale))
             assert good, (frame, l, info)

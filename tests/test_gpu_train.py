@@ -10,7 +10,8 @@ import torch
 import oracle
 import synth
 from oracle import backward as obwd
-from tests.gpu_common import adamw_params_close, gaussians_at_pixels, grads_close, rel_l2, to_np
+from tests.gpu_common import (adamw_params_close, frame_exclusions, gaussians_at_pixels,
+                               grads_close, rel_l2, to_np)
 
 pytestmark = pytest.mark.gpu
 
@@ -143,7 +144,9 @@ def test_render_frame_tiny_ten_steps(gsc, gctx):
             assert rl["boundary_gaussians"].mean() <= 0.2
             good, info = adamw_params_close(to_np(s["params"]), rl["params"], state[l]["params"],
                                             rl["grads"], state[l]["m"], state[l]["v"], state[l]["step"] + 1,
-                                            wl.lr, levels_np[l].n, exclude=rl["boundary_gaussians"])
+                                            wl.lr, levels_np[l].n,
+                                            exclude=frame_exclusions(rl["boundary_gaussians"],
+                                                                     cur[l].log_scale))
             assert good, (frame, l, info)
             assert s["step"] == frame + 1
     assert losses[-1] < losses[0]
