@@ -15,7 +15,12 @@
 
 namespace gsc {
 
-constexpr int kTile = 16;               // 16x16 pixel tiles
+constexpr int kTile = 16;               // 16x16 pixel tiles (gsc_project_bin and its views)
+constexpr int kTileShift = 4;
+// Frames bin 32x32-pixel tiles, each splatted by a workgroup of four wavefronts (one per 16x16
+// quadrant) that share the tile's list, so the adjoint merges a Gaussian's partial gradients
+// over the four quadrants before its atomics.
+constexpr int kFrameTileShift = 5;
 constexpr int kMaxTf = 64;
 constexpr int kMaxLights = 8;
 constexpr int kChunk = 1024;            // depth-ordered Gaussians per binning chunk
@@ -44,6 +49,8 @@ struct Seg {
   int32_t TX, TY;
   int32_t level;
   int32_t request;
+  int32_t tshift;       // tiles are (1 << tshift)^2 pixels: 16x16 (4) or, in frames, 32x32 (5)
+  int32_t pad_;
 };
 
 // Per request of a trace launch.
@@ -155,7 +162,7 @@ hipError_t launch_splat_forward(hipStream_t st, const Seg* segs, const int64_t* 
                                 const uint32_t* values, const SplatRec* rec, float* images,
                                 float* final_T, int32_t* last_id, uint32_t* n_contrib,
                                 unsigned long long* stats, const uint32_t* order,
-                                uint32_t* tile_work, bool count);
+                                uint32_t* tile_work, bool count, int tshift);
 // Keys ordering tiles by decreasing work (work NULL: list length from ranges).
 hipError_t launch_tile_order(hipStream_t st, const uint64_t* ranges, const uint32_t* work,
                              int64_t n_tiles, uint32_t* order);
@@ -166,7 +173,8 @@ hipError_t launch_splat_backward(hipStream_t st, const Seg* segs, const int64_t*
                                  const uint32_t* values, const SplatRec* rec, const float* final_T,
                                  const uint32_t* n_contrib, const float* dL_dimages,
                                  float* grad2d, int64_t G, const uint32_t* order, uint32_t* gmax,
-                                 unsigned long long* gfix, unsigned long long* stats, bool count);
+                                 unsigned long long* gfix, unsigned long long* stats, bool count,
+                                 int tshift);
 
 int64_t trace_align(int64_t pixels);
 hipError_t launch_trace(hipStream_t st, const TraceDesc* descs, const int64_t* req_pstart, int R,

@@ -41,17 +41,25 @@ struct Tile {
   float ti0, ti1, tj0, tj1;  // the tile's pixel rectangle inside the render window
 };
 
+// kQ = 1: tiles of 16x16 pixels, one wavefront each.  kQ = 4: tiles of 32x32 pixels, one
+// workgroup of four wavefronts each; wavefront q takes the 16x16 quadrant (q & 1, q >> 1).
+// Either way a wavefront sees a 16x16 block of the tile and the tile's whole list.
+template <int kQ>
 __device__ __forceinline__ Tile tile_setup(const Seg* __restrict__ segs,
                                            const int64_t* __restrict__ seg_tstart, int S,
                                            const DevCam* __restrict__ cams,
                                            const uint64_t* __restrict__ ranges, int64_t t) {
+  static_assert(kQ == 1 || kQ == 4, "one or four wavefronts per tile");
   const int s = find_segment(seg_tstart, S, t);
   const Seg& sg = segs[s];
   const DevCam& cam = cams[sg.cam];
   const int64_t lt = t - sg.tile_base;
   const int tx = (int)(lt % sg.TX), ty = (int)(lt / sg.TX);
   const int lane = __lane_id();
-  const int px = tx * kTile + (lane & 15);
+  const int wave = kQ == 1 ? 0 : (int)(threadIdx.x >> 6);
+  const int ox = tx * (kQ == 1 ? 16 : 32) + 16 * (wave & 1);    // the block's window-local origin
+  const int oy = ty * (kQ == 1 ? 16 : 32) + 16 * (wave >> 1);
+  const int px = ox + (lane & 15);
   Tile c;
   c.start = (int64_t)ranges[2 * t];
   c.end = (int64_t)ranges[2 * t + 1];
@@ -60,17 +68,19 @@ __device__ __forceinline__ Tile tile_setup(const Seg* __restrict__ segs,
   c.fi = (float)(cam.x0 + px);
 #pragma unroll
   for (int k = 0; k < kPx; ++k) {
-    const int py = ty * kTile + (lane >> 4) + 4 * k;
+    const int py = oy + (lane >> 4) + 4 * k;
     c.inside[k] = (px < cam.w) && (py < cam.h);
     c.pix[k] = (int64_t)py * cam.w + px;
     c.fj[k] = (float)(cam.y0 + py);
   }
-  c.xbase = cam.x0 + tx * kTile;
-  c.ybase = cam.y0 + ty * kTile;
-  c.ti0 = (float)(cam.x0 + tx * kTile);
-  c.ti1 = (float)(cam.x0 + min(tx * kTile + kTile, cam.w) - 1);
-  c.tj0 = (float)(cam.y0 + ty * kTile);
-  c.tj1 = (float)(cam.y0 + min(ty * kTile + kTile, cam.h) - 1);
+  c.xbase = cam.x0 + ox;
+  c.ybase = cam.y0 + oy;
+  // The block's pixel rectangle inside the render window (empty, ti1 < ti0 or tj1 < tj0, for a
+  // quadrant beyond the window's edge: may_touch then rejects every entry).
+  c.ti0 = (float)(cam.x0 + ox);
+  c.ti1 = (float)(cam.x0 + min(ox + 16, cam.w) - 1);
+  c.tj0 = (float)(cam.y0 + oy);
+  c.tj1 = (float)(cam.y0 + min(oy + 16, cam.h) - 1);
   return c;
 }
 
@@ -163,8 +173,8 @@ __device__ __forceinline__ bool lane_in(uint64_t mask) {
 enum { kStEval = 0, kStBlend, kStContrib, kStEntries, kStFwdTested, kStFwdSlots, kStBwdTested,
        kStBwdBlend, kStBwdSlots, kStBwdEntries, kStBwdAtomics, kStWords };
 
-template <bool kCount>
-__global__ void __launch_bounds__(64) splat_forward_kernel(
+template <bool kCount, int kQ>
+__global__ void __launch_bounds__(64 * kQ) splat_forward_kernel(
     const Seg* __restrict__ segs, const int64_t* __restrict__ seg_tstart, int S,
     const DevCam* __restrict__ cams, const uint64_t* __restrict__ ranges,
     const uint32_t* __restrict__ values, const SplatRec* __restrict__ rec,
@@ -172,7 +182,7 @@ __global__ void __launch_bounds__(64) splat_forward_kernel(
     uint32_t* __restrict__ n_contrib, unsigned long long* __restrict__ stats,
     const uint32_t* __restrict__ order, uint32_t* __restrict__ tile_work) {
   const int64_t t = order ? (int64_t)order[blockIdx.x] : (int64_t)blockIdx.x;
-  const Tile tc = tile_setup(segs, seg_tstart, S, cams, ranges, t);
+  const Tile tc = tile_setup<kQ>(segs, seg_tstart, S, cams, ranges, t);
   const int lane = __lane_id();
   float T[kPx], C0[kPx], C1[kPx], C2[kPx];
   uint32_t nc[kPx], stop[kPx];
@@ -218,7 +228,7 @@ __global__ void __launch_bounds__(64) splat_forward_kernel(
 #pragma unroll
       for (int p = 0; p < kPx; ++p) {
         const uint64_t act = win[p] & ~done[p];
-        if (act == 0ull) continue;
+        // no per-slot branch: the four slots form one basic block (independent chains)
         if (kCount) { n_tested += (uint64_t)__popcll(act); ++n_slots; }
         const float dy = v - tc.fj[p];
         const float power = -0.5f * (adx + (Cc * dy) * dy) - bdx * dy;
@@ -242,7 +252,21 @@ __global__ void __launch_bounds__(64) splat_forward_kernel(
       }
     }
   }
-  if (tile_work && lane == 0) tile_work[t] = n_entries;
+  if (tile_work) {                       // the tile's work estimate for the adjoint's schedule
+    if (kQ == 1) {
+      if (lane == 0) tile_work[t] = n_entries;
+    } else {
+      __shared__ uint32_t wsum[kQ];
+      if (lane == 0) wsum[threadIdx.x >> 6] = n_entries;
+      __syncthreads();
+      if (threadIdx.x == 0) {
+        uint32_t sum = 0u;
+#pragma unroll
+        for (int q = 0; q < kQ; ++q) sum += wsum[q];
+        tile_work[t] = sum;
+      }
+    }
+  }
   uint64_t ev = 0, ncs = 0;
 #pragma unroll
   for (int p = 0; p < kPx; ++p) {
@@ -309,8 +333,8 @@ __device__ __forceinline__ float row_total(float v) {
   return t;
 }
 
-template <bool kCount>
-__global__ void __launch_bounds__(64) splat_backward_kernel(
+template <bool kCount, int kQ>
+__global__ void __launch_bounds__(64 * kQ) splat_backward_kernel(
     const Seg* __restrict__ segs, const int64_t* __restrict__ seg_tstart, int S,
     const DevCam* __restrict__ cams, const uint64_t* __restrict__ ranges,
     const uint32_t* __restrict__ values, const SplatRec* __restrict__ rec,
@@ -318,10 +342,16 @@ __global__ void __launch_bounds__(64) splat_backward_kernel(
     const float* __restrict__ dL_dimages, float* __restrict__ grad2d, int64_t G,
     const uint32_t* __restrict__ order, int mode, uint32_t* __restrict__ gmax,
     unsigned long long* __restrict__ gfix, unsigned long long* __restrict__ stats) {
-  __shared__ float part[4][64][kPartStride];
+  // part[q][row][entry][component]: wavefront q's row sums of each entry of the batch (a
+  // stride of 9 floats keeps the four-wavefront workgroup at 36 KB, four per CU).
+  constexpr int kStride = kQ == 1 ? kPartStride : 9;
+  __shared__ float part[kQ][4][64][kStride];
+  __shared__ uint64_t has_sh[kQ];
+  __shared__ uint32_t mx_sh[kQ];
   const int64_t t = order ? (int64_t)order[blockIdx.x] : (int64_t)blockIdx.x;
-  const Tile tc = tile_setup(segs, seg_tstart, S, cams, ranges, t);
+  const Tile tc = tile_setup<kQ>(segs, seg_tstart, S, cams, ranges, t);
   const int lane = __lane_id();
+  const int wave = kQ == 1 ? 0 : (int)(threadIdx.x >> 6);
   // BG: the colour blended behind the current Gaussian (from the entries already walked), dotted
   // with the pixel's image gradient g; it is all the adjoint needs of that colour.
   float T[kPx], g0[kPx], g1[kPx], g2[kPx], BG[kPx];
@@ -344,6 +374,12 @@ __global__ void __launch_bounds__(64) splat_backward_kernel(
   }
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) mx = max(mx, (uint32_t)__shfl_xor((int)mx, off, 64));
+  if (kQ > 1) {                          // every wavefront walks the same batches
+    if (lane == 0) mx_sh[wave] = mx;
+    __syncthreads();
+#pragma unroll
+    for (int q = 0; q < kQ; ++q) mx = max(mx, mx_sh[q]);
+  }
   const int64_t stop = tc.start + (int64_t)mx;
   uint64_t n_tested = 0u, n_blended = 0u, n_slots = 0u, n_entries = 0u;
   uint32_t n_atomics = 0u;
@@ -384,7 +420,7 @@ __global__ void __launch_bounds__(64) splat_backward_kernel(
 #pragma unroll
       for (int p = 0; p < kPx; ++p) {
         const uint64_t act = win[p] & __builtin_amdgcn_ballot_w64(rel < nc[p]);
-        if (act == 0ull) continue;
+        // no per-slot branch: the four slots form one basic block (independent chains)
         const float dy = v - tc.fj[p];
         const float power = -0.5f * (adx + (Cc * dy) * dy) - bdx * dy;
         const float e = __expf(power);
@@ -426,37 +462,50 @@ __global__ void __launch_bounds__(64) splat_backward_kernel(
       const float r3 = row_total(sB), r4 = row_total(sC), r5 = row_total(so);
       const float r6 = row_total(sr), r7 = row_total(sg), r8 = row_total(sb);
       if ((lane & 15) == 15) {
-        float* d = part[lane >> 4][k];
+        float* d = part[wave][lane >> 4][k];
         d[0] = r0; d[1] = r1; d[2] = r2; d[3] = r3; d[4] = r4;
         d[5] = r5; d[6] = r6; d[7] = r7; d[8] = r8;
       }
     }
-    if (has == 0ull) continue;
+    // Merge: the partials of entry k over the rows (and, with kQ = 4, the quadrants) are added
+    // in a fixed order, then issued by lane k of the wavefronts, which share the nine
+    // components (wavefront q takes components q, q + kQ, ...).
+    if (kQ == 1) {
+      if (has == 0ull) continue;
+    } else if (lane == 0) {
+      has_sh[wave] = has;
+    }
     __syncthreads();
-    const bool mine = (has >> lane) & 1ull;
-    const int64_t gi = tc.g_off + (int64_t)my_id;
-    if (mode == kAdjointAtomic) {
-      if (mine) {
+    uint64_t hq[kQ];
+    uint64_t hall = 0ull;
 #pragma unroll
-        for (int a = 0; a < 9; ++a) {
-          const float acc = (part[0][lane][a] + part[1][lane][a]) + (part[2][lane][a] + part[3][lane][a]);
+    for (int q = 0; q < kQ; ++q) {
+      hq[q] = kQ == 1 ? has : has_sh[q];
+      hall |= hq[q];
+    }
+    if ((hall >> lane) & 1ull) {
+      const int64_t gi = tc.g_off + (int64_t)my_id;
+      for (int a = wave; a < 9; a += kQ) {
+        float acc = 0.0f;
+#pragma unroll
+        for (int q = 0; q < kQ; ++q) {
+          if (!((hq[q] >> lane) & 1ull)) continue;
+          const float sq = (part[q][0][lane][a] + part[q][1][lane][a]) +
+                           (part[q][2][lane][a] + part[q][3][lane][a]);
+          acc += sq;
+        }
+        const int64_t at = (int64_t)a * G + gi;
+        if (mode == kAdjointAtomic) {
           if (acc != 0.0f) {
-            unsafeAtomicAdd(&grad2d[(int64_t)a * G + gi], acc);
+            unsafeAtomicAdd(&grad2d[at], acc);
             if (kCount) ++n_atomics;
           }
-        }
-      }
-    } else if (mine) {
-#pragma unroll
-      for (int a = 0; a < 9; ++a) {
-        const float acc = (part[0][lane][a] + part[1][lane][a]) + (part[2][lane][a] + part[3][lane][a]);
-        const int64_t at = (int64_t)a * G + gi;
-        if (mode == kAdjointMax) {
+        } else if (mode == kAdjointMax) {
           if (acc != 0.0f) atomicMax(&gmax[at], __float_as_uint(fabsf(acc)));
         } else {
           // Integer sums do not depend on the order in which the atomics land.
-          const long long q = llrint((double)acc * fixed_scale(gmax[at]));
-          if (q) atomicAdd(&gfix[at], (unsigned long long)q);
+          const long long qv = llrint((double)acc * fixed_scale(gmax[at]));
+          if (qv) atomicAdd(&gfix[at], (unsigned long long)qv);
         }
       }
     }
@@ -522,6 +571,54 @@ __global__ void __launch_bounds__(kOrderThreads) tile_order_kernel(const uint64_
     order[atomicAdd(&cnt[bucket(t)], 1u)] = (uint32_t)t;
 }
 
+template <int kQ>
+void splat_forward_dispatch(hipStream_t st, const Seg* segs, const int64_t* seg_tstart, int S,
+                            const DevCam* cams, int64_t n_tiles, const uint64_t* ranges,
+                            const uint32_t* values, const SplatRec* rec, float* images,
+                            float* final_T, int32_t* last_id, uint32_t* n_contrib,
+                            unsigned long long* stats, const uint32_t* order, uint32_t* tile_work,
+                            bool count) {
+  if (count && stats)
+    hipLaunchKernelGGL((splat_forward_kernel<true, kQ>), dim3((unsigned)n_tiles), dim3(64 * kQ), 0,
+                       st, segs, seg_tstart, S, cams, ranges, values, rec, images, final_T, last_id,
+                       n_contrib, stats, order, tile_work);
+  else
+    hipLaunchKernelGGL((splat_forward_kernel<false, kQ>), dim3((unsigned)n_tiles), dim3(64 * kQ), 0,
+                       st, segs, seg_tstart, S, cams, ranges, values, rec, images, final_T, last_id,
+                       n_contrib, stats, order, tile_work);
+}
+
+template <int kQ>
+void splat_backward_dispatch(hipStream_t st, const Seg* segs, const int64_t* seg_tstart, int S,
+                             const DevCam* cams, int64_t n_tiles, const uint64_t* ranges,
+                             const uint32_t* values, const SplatRec* rec, const float* final_T,
+                             const uint32_t* n_contrib, const float* dL_dimages, float* grad2d,
+                             int64_t G, const uint32_t* order, uint32_t* gmax,
+                             unsigned long long* gfix, unsigned long long* stats, bool count) {
+  const dim3 grid((unsigned)n_tiles), block(64 * kQ);
+  if (!gmax) {
+    if (count && stats)
+      hipLaunchKernelGGL((splat_backward_kernel<true, kQ>), grid, block, 0, st, segs, seg_tstart, S,
+                         cams, ranges, values, rec, final_T, n_contrib, dL_dimages, grad2d, G,
+                         order, (int)kAdjointAtomic, gmax, gfix, stats);
+    else
+      hipLaunchKernelGGL((splat_backward_kernel<false, kQ>), grid, block, 0, st, segs, seg_tstart, S,
+                         cams, ranges, values, rec, final_T, n_contrib, dL_dimages, grad2d, G,
+                         order, (int)kAdjointAtomic, gmax, gfix, stats);
+    return;
+  }
+  // Deterministic: gmax [9][G] and gfix [9][G] must be zero on entry.
+  hipLaunchKernelGGL((splat_backward_kernel<false, kQ>), grid, block, 0, st, segs, seg_tstart, S,
+                     cams, ranges, values, rec, final_T, n_contrib, dL_dimages, grad2d, G, order,
+                     (int)kAdjointMax, gmax, gfix, stats);
+  hipLaunchKernelGGL((splat_backward_kernel<false, kQ>), grid, block, 0, st, segs, seg_tstart, S,
+                     cams, ranges, values, rec, final_T, n_contrib, dL_dimages, grad2d, G, order,
+                     (int)kAdjointFixed, gmax, gfix, stats);
+  if (G > 0)
+    hipLaunchKernelGGL(fixed_to_float_kernel, dim3((unsigned)((9 * G + 255) / 256)), dim3(256), 0,
+                       st, gmax, gfix, G, grad2d);
+}
+
 }  // namespace
 
 hipError_t launch_splat_forward(hipStream_t st, const Seg* segs, const int64_t* seg_tstart, int S,
@@ -529,16 +626,14 @@ hipError_t launch_splat_forward(hipStream_t st, const Seg* segs, const int64_t* 
                                 const uint32_t* values, const SplatRec* rec, float* images,
                                 float* final_T, int32_t* last_id, uint32_t* n_contrib,
                                 unsigned long long* stats, const uint32_t* order,
-                                uint32_t* tile_work, bool count) {
+                                uint32_t* tile_work, bool count, int tshift) {
   if (n_tiles == 0) return hipSuccess;
-  if (count && stats)
-    hipLaunchKernelGGL(splat_forward_kernel<true>, dim3((unsigned)n_tiles), dim3(64), 0, st, segs,
-                       seg_tstart, S, cams, ranges, values, rec, images, final_T, last_id,
-                       n_contrib, stats, order, tile_work);
+  if (tshift == 5)
+    splat_forward_dispatch<4>(st, segs, seg_tstart, S, cams, n_tiles, ranges, values, rec, images,
+                              final_T, last_id, n_contrib, stats, order, tile_work, count);
   else
-    hipLaunchKernelGGL(splat_forward_kernel<false>, dim3((unsigned)n_tiles), dim3(64), 0, st, segs,
-                       seg_tstart, S, cams, ranges, values, rec, images, final_T, last_id,
-                       n_contrib, stats, order, tile_work);
+    splat_forward_dispatch<1>(st, segs, seg_tstart, S, cams, n_tiles, ranges, values, rec, images,
+                              final_T, last_id, n_contrib, stats, order, tile_work, count);
   return hipGetLastError();
 }
 
@@ -547,29 +642,15 @@ hipError_t launch_splat_backward(hipStream_t st, const Seg* segs, const int64_t*
                                  const uint32_t* values, const SplatRec* rec, const float* final_T,
                                  const uint32_t* n_contrib, const float* dL_dimages,
                                  float* grad2d, int64_t G, const uint32_t* order, uint32_t* gmax,
-                                 unsigned long long* gfix, unsigned long long* stats, bool count) {
+                                 unsigned long long* gfix, unsigned long long* stats, bool count,
+                                 int tshift) {
   if (n_tiles == 0) return hipSuccess;
-  if (!gmax) {
-    if (count && stats)
-      hipLaunchKernelGGL(splat_backward_kernel<true>, dim3((unsigned)n_tiles), dim3(64), 0, st, segs,
-                         seg_tstart, S, cams, ranges, values, rec, final_T, n_contrib, dL_dimages,
-                         grad2d, G, order, (int)kAdjointAtomic, gmax, gfix, stats);
-    else
-      hipLaunchKernelGGL(splat_backward_kernel<false>, dim3((unsigned)n_tiles), dim3(64), 0, st,
-                         segs, seg_tstart, S, cams, ranges, values, rec, final_T, n_contrib,
-                         dL_dimages, grad2d, G, order, (int)kAdjointAtomic, gmax, gfix, stats);
-    return hipGetLastError();
-  }
-  // Deterministic: gmax [9][G] and gfix [9][G] must be zero on entry.
-  hipLaunchKernelGGL(splat_backward_kernel<false>, dim3((unsigned)n_tiles), dim3(64), 0, st, segs,
-                     seg_tstart, S, cams, ranges, values, rec, final_T, n_contrib, dL_dimages,
-                     grad2d, G, order, (int)kAdjointMax, gmax, gfix, stats);
-  hipLaunchKernelGGL(splat_backward_kernel<false>, dim3((unsigned)n_tiles), dim3(64), 0, st, segs,
-                     seg_tstart, S, cams, ranges, values, rec, final_T, n_contrib, dL_dimages,
-                     grad2d, G, order, (int)kAdjointFixed, gmax, gfix, stats);
-  if (G > 0)
-    hipLaunchKernelGGL(fixed_to_float_kernel, dim3((unsigned)((9 * G + 255) / 256)), dim3(256), 0,
-                       st, gmax, gfix, G, grad2d);
+  if (tshift == 5)
+    splat_backward_dispatch<4>(st, segs, seg_tstart, S, cams, n_tiles, ranges, values, rec, final_T,
+                               n_contrib, dL_dimages, grad2d, G, order, gmax, gfix, stats, count);
+  else
+    splat_backward_dispatch<1>(st, segs, seg_tstart, S, cams, n_tiles, ranges, values, rec, final_T,
+                               n_contrib, dL_dimages, grad2d, G, order, gmax, gfix, stats, count);
   return hipGetLastError();
 }
 

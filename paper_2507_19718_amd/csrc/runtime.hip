@@ -92,6 +92,7 @@ struct gsc_binning {
   bool forward_done = false;
   int K = 0;
   int TX = 0, TY = 0;
+  int tshift = kTileShift;         // 16x16 tiles (gsc_project_bin) or 32x32 (frames)
   // views
   DevBuf view_window, view_screen;
 
@@ -349,7 +350,9 @@ struct ReqSpec {
 };
 
 // Builds (or rebuilds) a binning object's tables for a list of requests and uploads them.
-void plan_batch(gsc_ctx* ctx, gsc_binning* b, const std::vector<ReqSpec>& reqs) {
+void plan_batch(gsc_ctx* ctx, gsc_binning* b, const std::vector<ReqSpec>& reqs, int tshift) {
+  b->tshift = tshift;
+  const int ts = 1 << tshift;
   b->segs.clear();
   b->cams.clear();
   b->seg_gstart.clear();
@@ -358,7 +361,7 @@ void plan_batch(gsc_ctx* ctx, gsc_binning* b, const std::vector<ReqSpec>& reqs) 
   for (size_t r = 0; r < reqs.size(); ++r) {
     const gsc_camera& c = reqs[r].cam;
     b->cams.push_back(to_dev(c));
-    const int TX = (c.w + kTile - 1) / kTile, TY = (c.h + kTile - 1) / kTile;
+    const int TX = (c.w + ts - 1) / ts, TY = (c.h + ts - 1) / ts;
     for (size_t l = 0; l < reqs[r].levels.size(); ++l) {
       const gsc_gaussians& lv = reqs[r].levels[l];
       Seg s{};
@@ -371,6 +374,7 @@ void plan_batch(gsc_ctx* ctx, gsc_binning* b, const std::vector<ReqSpec>& reqs) 
       s.TX = TX; s.TY = TY;
       s.level = (int32_t)l;
       s.request = (int32_t)r;
+      s.tshift = tshift;
       s.n_chunks = (int32_t)((lv.n + kChunk - 1) / kChunk);
       b->segs.push_back(s);
       b->seg_gstart.push_back(g);
@@ -540,7 +544,7 @@ void run_forward(gsc_ctx* ctx, gsc_binning* b, float* images, float* final_T, in
                                b->ranges.as<uint64_t>(), b->values.as<uint32_t>(),
                                b->rec.as<SplatRec>(), images, final_T, last_id,
                                b->n_contrib.as<uint32_t>(), ctx->d_stats.as<unsigned long long>(),
-                               order, b->tile_work.as<uint32_t>(), ctx->work_counters));
+                               order, b->tile_work.as<uint32_t>(), ctx->work_counters, b->tshift));
   }
   b->forward_done = true;
 }
@@ -568,7 +572,8 @@ void run_splat_adjoint(gsc_ctx* ctx, gsc_binning* b, const float* final_T, const
                                 b->ranges.as<uint64_t>(), b->values.as<uint32_t>(),
                                 b->rec.as<SplatRec>(), final_T, b->n_contrib.as<uint32_t>(), dL,
                                 b->grad2d.as<float>(), b->G, order, gmax, gfix,
-                                ctx->d_stats.as<unsigned long long>(), ctx->work_counters));
+                                ctx->d_stats.as<unsigned long long>(), ctx->work_counters,
+                                b->tshift));
   }
 }
 
@@ -732,7 +737,7 @@ gsc_status render_batch(gsc_ctx* ctx, gsc_scene* const* scenes, const gsc_frame_
     pix += (int64_t)sc->K * reqs[i].cam.w * reqs[i].cam.h;
     rpix += (int64_t)reqs[i].trace.spp * reqs[i].cam.w * reqs[i].cam.h;
   }
-  plan_batch(ctx, b, specs);
+  plan_batch(ctx, b, specs, kFrameTileShift);
   const Alloc& a = ctx->alloc;
   need(ctx, ctx->images, a, 12 * (size_t)pix, "cache images");
   need(ctx, ctx->targets, a, 12 * (size_t)pix, "targets");
@@ -1130,7 +1135,7 @@ gsc_status gsc_project_bin(gsc_ctx* ctx, const gsc_gaussians* levels, int32_t nu
     b->TY = (cam->h + kTile - 1) / kTile;
     gsc_status s;
     try {
-      plan_batch(ctx, b, specs);
+      plan_batch(ctx, b, specs, kTileShift);
       s = run_project_bin(ctx, b, capacity_hint);
     } catch (...) {
       b->free_all();
@@ -1508,7 +1513,8 @@ size_t gsc_frame_footprint_bytes(const gsc_scene* sc, int32_t w, int32_t h, uint
   for (int l = 0; l < sc->K; ++l) G += sc->n[l];
   const size_t P = (size_t)w * h;
   const size_t K = (size_t)sc->K;
-  const size_t tiles = K * (size_t)((w + 15) / 16) * ((h + 15) / 16);
+  const int ts = 1 << kFrameTileShift;                             // frames bin 32x32 tiles
+  const size_t tiles = K * (size_t)((w + ts - 1) / ts) * ((h + ts - 1) / ts);
   size_t b = 0;
   b += (size_t)G * (48 + 4 + 8 + 4 + 4 * 4 + 8 + 9 * 4 + 14 * 4);   // per-Gaussian buffers
   b += 4 * (size_t)instance_estimate;                              // instance ids

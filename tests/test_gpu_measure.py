@@ -46,7 +46,9 @@ def test_work_counters_of_a_training_frame(gsc, gctx):
     assert d["blended"] <= d["fwd_tested"] <= 64 * d["fwd_slots"]
     assert d["bwd_blended"] <= d["bwd_tested"] <= 64 * d["bwd_slots"]
     assert d["fwd_tested"] <= d["evaluations"]
-    assert 0 < d["bwd_entries"] <= d["tile_entries"]
+    # (The adjoint's wavefronts of one frame tile walk its list from the tile's last
+    # contributor, so they may walk more entries than the forward's wavefronts evaluated.)
+    assert d["bwd_entries"] > 0
     # At most nine float atomics per walked (tile, entry) pair, at least one per pair that
     # blended anything.
     assert 0 < d["bwd_atomics"] <= 9 * d["bwd_entries"]
