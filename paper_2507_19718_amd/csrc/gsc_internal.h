@@ -17,9 +17,9 @@ namespace gsc {
 
 constexpr int kTile = 16;               // 16x16 pixel tiles (gsc_project_bin and its views)
 constexpr int kTileShift = 4;
-// Frames bin 32x32-pixel tiles, each splatted by a workgroup of four wavefronts (one per 16x16
-// quadrant) that share the tile's list, so the adjoint merges a Gaussian's partial gradients
-// over the four quadrants before its atomics.
+// Frames bin 16-wide, 32-tall tiles (log2 height 5): each wavefront then splats eight pixels
+// per lane, so the per-entry work (record broadcast, window masks, the adjoint's reductions and
+// atomics) is shared by twice the pixels, and the tile lists hold about half the instances.
 constexpr int kFrameTileShift = 5;
 constexpr int kMaxTf = 64;
 constexpr int kMaxLights = 8;
@@ -49,7 +49,7 @@ struct Seg {
   int32_t TX, TY;
   int32_t level;
   int32_t request;
-  int32_t tshift;       // tiles are (1 << tshift)^2 pixels: 16x16 (4) or, in frames, 32x32 (5)
+  int32_t tsy;       // log2 of the tile height: 16x16 tiles (4) or, in frames, 16x32 (5)
   int32_t pad_;
 };
 
@@ -162,7 +162,7 @@ hipError_t launch_splat_forward(hipStream_t st, const Seg* segs, const int64_t* 
                                 const uint32_t* values, const SplatRec* rec, float* images,
                                 float* final_T, int32_t* last_id, uint32_t* n_contrib,
                                 unsigned long long* stats, const uint32_t* order,
-                                uint32_t* tile_work, bool count, int tshift);
+                                uint32_t* tile_work, bool count, int tsy);
 // Keys ordering tiles by decreasing work (work NULL: list length from ranges).
 hipError_t launch_tile_order(hipStream_t st, const uint64_t* ranges, const uint32_t* work,
                              int64_t n_tiles, uint32_t* order);
@@ -174,7 +174,7 @@ hipError_t launch_splat_backward(hipStream_t st, const Seg* segs, const int64_t*
                                  const uint32_t* n_contrib, const float* dL_dimages,
                                  float* grad2d, int64_t G, const uint32_t* order, uint32_t* gmax,
                                  unsigned long long* gfix, unsigned long long* stats, bool count,
-                                 int tshift);
+                                 int tsy);
 
 int64_t trace_align(int64_t pixels);
 hipError_t launch_trace(hipStream_t st, const TraceDesc* descs, const int64_t* req_pstart, int R,

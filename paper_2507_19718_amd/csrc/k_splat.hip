@@ -2,22 +2,26 @@
 // its adjoint (3D Gaussian splatting's tile rasteriser, adapted by GSCache to render each cache
 // level; Method: "A Path Space Radiance Cache", "Cache Training").
 //
-// One 64-lane wavefront per 16x16 tile; lane l owns the four pixels (l & 15, (l >> 4) + 4p),
-// p = 0..3, so slot p of the wave is the tile's 16x4 row band 4p..4p+3.  The tile's list is
-// consumed 64 entries at a time: lane j loads entry j's 48-byte record into registers, then the
-// wave walks the entries in list order and broadcasts each record to scalar registers
-// (v_readlane).  The Gaussian's integer pixel window becomes, on the scalar unit, one 64-bit
-// lane mask per slot; a slot with no live pixel inside the window is skipped by a scalar branch
-// and the others run branch-free (predicated selects), so the vector unit sees only the blend.
-// An entry whose alpha >= 1/255 ellipse provably misses every pixel of the tile (a conservative
-// test of the quadratic form over the tile rectangle) is skipped by the whole wave; such an
-// entry is skipped by every pixel anyway, so results do not change.
+// One 64-lane wavefront per tile of 16 x 4 kS pixels (kS = 4: the 16x16 tiles of
+// gsc_project_bin; kS = 8: the 16x32 tiles frames bin).  Lane l owns the kS pixels
+// (l & 15, (l >> 4) + 4 p), p < kS, so slot p of the wave is the tile's 16x4 row band
+// 4p..4p+3.  The tile's list is consumed 64 entries at a time: lane j loads entry j's 48-byte
+// record into registers, then the wave walks the entries in list order and every lane fetches
+// the current entry's record from lane k with ds_bpermute, so the record reaches the vector
+// unit in vector registers (on gfx950 an instruction that reads a scalar register issues at half
+// the rate of one that reads only vector registers and literals).  The Gaussian's integer pixel
+// window becomes, on the scalar unit, one 64-bit lane mask per slot; a slot with no live pixel
+// inside the window is skipped by a scalar branch and the others run branch-free (predicated
+// selects).  An entry whose alpha >= 1/255 ellipse provably misses every pixel of the tile (a
+// conservative test of the quadratic form over the tile rectangle) is skipped by the whole wave;
+// such an entry is skipped by every pixel anyway, so results do not change.
 //
 // The adjoint walks the same lists back to front from each pixel's last contributor, recovers
 // the transmittance before each Gaussian as T / (1 - alpha), sums each Gaussian's nine
-// screen-space gradients over the lane's four pixels, reduces them within each 16-lane row with
-// DPP row shifts, parks the four row sums in LDS, and once per batch of 64 entries the lane that
-// loaded an entry adds its rows and issues the nine float atomics of that (tile, Gaussian).
+// screen-space gradients over the lane's kS pixels, reduces them within each 16-lane row group
+// with DPP row shifts, parks the four group sums in LDS, and once per batch of 64 entries the
+// lane that loaded an entry adds its groups and issues the nine float atomics of that
+// (tile, Gaussian).
 #include "gsc_dev.h"
 
 namespace gsc {
@@ -27,68 +31,65 @@ namespace {
 constexpr float kAlphaMin = 1.0f / 255.0f;
 constexpr float kAlphaMax = 0.99f;
 constexpr float kTmin = 1e-4f;
-constexpr int kPx = 4;
-constexpr int kPartStride = 10;   // floats per (row, entry) of the adjoint's LDS partials
+constexpr int kPartStride = 10;   // floats per (row group, entry) of the adjoint's LDS partials
 
+template <int kS>
 struct Tile {
   int64_t start, end;
   int64_t g_off, pix_off;
   float fi;                  // this lane's pixel column (full-frame)
-  float fj[kPx];             // this lane's four pixel rows
-  int64_t pix[kPx];          // pixel index within the segment image
-  bool inside[kPx];
+  float fj[kS];              // this lane's pixel rows (full-frame)
+  int px, py0;               // this lane's column and first row in the render window
+  int cw, ch;                // render window size
   int xbase, ybase;          // full-frame coordinates of the tile's first pixel
   float ti0, ti1, tj0, tj1;  // the tile's pixel rectangle inside the render window
+  __device__ bool inside(int p) const { return px < cw && py0 + 4 * p < ch; }
+  __device__ int64_t pix(int p) const { return (int64_t)(py0 + 4 * p) * cw + px; }
 };
 
-// kQ = 1: tiles of 16x16 pixels, one wavefront each.  kQ = 4: tiles of 32x32 pixels, one
-// workgroup of four wavefronts each; wavefront q takes the 16x16 quadrant (q & 1, q >> 1).
-// Either way a wavefront sees a 16x16 block of the tile and the tile's whole list.
-template <int kQ>
-__device__ __forceinline__ Tile tile_setup(const Seg* __restrict__ segs,
-                                           const int64_t* __restrict__ seg_tstart, int S,
-                                           const DevCam* __restrict__ cams,
-                                           const uint64_t* __restrict__ ranges, int64_t t) {
-  static_assert(kQ == 1 || kQ == 4, "one or four wavefronts per tile");
+// A wavefront covers the 16 x 4 kS block `part` (0 .. kH - 1, top to bottom) of tile t, whose
+// height is 4 kS kH pixels; the block's rectangle is what may_touch tests.
+template <int kS, int kH = 1>
+__device__ __forceinline__ Tile<kS> tile_setup(const Seg* __restrict__ segs,
+                                               const int64_t* __restrict__ seg_tstart, int S,
+                                               const DevCam* __restrict__ cams,
+                                               const uint64_t* __restrict__ ranges, int64_t t,
+                                               int part = 0) {
+  static_assert(kS * kH == 4 || kS * kH == 8, "16x16 or 16x32 tiles");
   const int s = find_segment(seg_tstart, S, t);
   const Seg& sg = segs[s];
   const DevCam& cam = cams[sg.cam];
   const int64_t lt = t - sg.tile_base;
   const int tx = (int)(lt % sg.TX), ty = (int)(lt / sg.TX);
   const int lane = __lane_id();
-  const int wave = kQ == 1 ? 0 : (int)(threadIdx.x >> 6);
-  const int ox = tx * (kQ == 1 ? 16 : 32) + 16 * (wave & 1);    // the block's window-local origin
-  const int oy = ty * (kQ == 1 ? 16 : 32) + 16 * (wave >> 1);
-  const int px = ox + (lane & 15);
-  Tile c;
+  const int ox = tx * 16, oy = ty * (4 * kS * kH) + part * (4 * kS);
+  Tile<kS> c;
   c.start = (int64_t)ranges[2 * t];
   c.end = (int64_t)ranges[2 * t + 1];
   c.g_off = sg.g_off;
   c.pix_off = sg.pix_off;
-  c.fi = (float)(cam.x0 + px);
+  c.px = ox + (lane & 15);
+  c.py0 = oy + (lane >> 4);
+  c.cw = cam.w;
+  c.ch = cam.h;
+  c.fi = (float)(cam.x0 + c.px);
 #pragma unroll
-  for (int k = 0; k < kPx; ++k) {
-    const int py = oy + (lane >> 4) + 4 * k;
-    c.inside[k] = (px < cam.w) && (py < cam.h);
-    c.pix[k] = (int64_t)py * cam.w + px;
-    c.fj[k] = (float)(cam.y0 + py);
-  }
+  for (int k = 0; k < kS; ++k) c.fj[k] = (float)(cam.y0 + c.py0 + 4 * k);
   c.xbase = cam.x0 + ox;
   c.ybase = cam.y0 + oy;
-  // The block's pixel rectangle inside the render window (empty, ti1 < ti0 or tj1 < tj0, for a
-  // quadrant beyond the window's edge: may_touch then rejects every entry).
   c.ti0 = (float)(cam.x0 + ox);
   c.ti1 = (float)(cam.x0 + min(ox + 16, cam.w) - 1);
   c.tj0 = (float)(cam.y0 + oy);
-  c.tj1 = (float)(cam.y0 + min(oy + 16, cam.h) - 1);
+  c.tj1 = (float)(cam.y0 + min(oy + 4 * kS, cam.h) - 1);
   return c;
 }
 
 // Conservative test: can o exp(-Q(u - i, v - j) / 2) reach 1/255 at some pixel (i, j) of the
 // tile inside the Gaussian's integer window?  Q is the conic's quadratic form; its minimum over
 // a rectangle not containing the centre lies on the boundary.
+template <int kS>
 __device__ __forceinline__ bool may_touch(const float4& q0, const float4& q1, const float4& q2,
-                                          const Tile& tc) {
+                                          const Tile<kS>& tc) {
   const uint32_t wx = __float_as_uint(q2.y), wy = __float_as_uint(q2.z);
   const float i0 = fmaxf(tc.ti0, (float)(wx & 0xffffu)), i1 = fminf(tc.ti1, (float)(wx >> 16));
   const float j0 = fmaxf(tc.tj0, (float)(wy & 0xffffu)), j1 = fminf(tc.tj1, (float)(wy >> 16));
@@ -109,19 +110,22 @@ __device__ __forceinline__ bool may_touch(const float4& q0, const float4& q1, co
   return q1.y * __expf(-0.5f * qmin) >= kAlphaMin * 0.999f;
 }
 
-__device__ __forceinline__ float rl(float v, int k) {
-  return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), k));
-}
-
 __device__ __forceinline__ uint32_t rlu(float v, int k) {
   return (uint32_t)__builtin_amdgcn_readlane(__float_as_int(v), k);
+}
+
+// Lane k's value in every lane, in a vector register (ds_bpermute with a uniform address).
+// Broadcasting through v_readlane into scalar registers measured slower in both kernels.
+__device__ __forceinline__ float bcast(float v, int k) {
+  return __int_as_float(__builtin_amdgcn_ds_bpermute(k << 2, __float_as_int(v)));
 }
 
 // Lane masks of the tile's pixels inside a Gaussian's integer window (packed full-frame bounds
 // wx = px0 | px1 << 16, wy = py0 | py1 << 16), one per slot.  Uniform arithmetic: it runs on
 // the scalar unit.
+template <int kS>
 __device__ __forceinline__ void window_masks(uint32_t wx, uint32_t wy, int xbase, int ybase,
-                                             uint64_t m[kPx]) {
+                                             uint64_t m[kS]) {
   const int lo = max((int)(wx & 0xffffu) - xbase, 0);
   const int hi = min((int)(wx >> 16) - xbase, 15);
   const uint32_t c16 = (lo <= hi) ? ((2u << hi) - (1u << lo)) : 0u;
@@ -129,35 +133,10 @@ __device__ __forceinline__ void window_masks(uint32_t wx, uint32_t wy, int xbase
   const uint64_t c64 = ((uint64_t)c32 << 32) | (uint64_t)c32;
   const int ylo = (int)(wy & 0xffffu) - ybase, yhi = (int)(wy >> 16) - ybase;
 #pragma unroll
-  for (int p = 0; p < kPx; ++p) {
+  for (int p = 0; p < kS; ++p) {
     const int glo = max(ylo - 4 * p, 0), ghi = min(yhi - 4 * p, 3);
     m[p] = (glo <= ghi) ? (c64 & (~0ull >> (48 - 16 * ghi)) & (~0ull << (16 * glo))) : 0ull;
   }
-}
-
-// The same masks computed in vector registers, one entry per lane, for a whole batch at once:
-// the forward then reads each entry's masks with readlane instead of rebuilding them on the
-// scalar unit, which is its busier unit.  (The adjoint is bound by vector issue and keeps the
-// scalar version.)
-__device__ __forceinline__ void window_masks_v(uint32_t wx, uint32_t wy, int xbase, int ybase,
-                                               uint64_t m[kPx]) {
-  const int lo = max((int)(wx & 0xffffu) - xbase, 0);
-  const int hi = min((int)(wx >> 16) - xbase, 15);
-  const uint32_t c16 = (lo <= hi) ? ((2u << hi) - (1u << lo)) : 0u;
-  const uint32_t c32 = c16 | (c16 << 16);
-  const uint64_t c64 = ((uint64_t)c32 << 32) | (uint64_t)c32;
-  const int ylo = (int)(wy & 0xffffu) - ybase, yhi = (int)(wy >> 16) - ybase;
-#pragma unroll
-  for (int p = 0; p < kPx; ++p) {
-    const int glo = max(ylo - 4 * p, 0), ghi = min(yhi - 4 * p, 3);
-    m[p] = (glo <= ghi) ? (c64 & (~0ull >> (48 - 16 * ghi)) & (~0ull << (16 * glo))) : 0ull;
-  }
-}
-
-__device__ __forceinline__ uint64_t rl64(uint64_t v, int k) {
-  const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)v, k);
-  const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(v >> 32), k);
-  return ((uint64_t)hi << 32) | lo;
 }
 
 __device__ __forceinline__ bool lane_in(uint64_t mask) {
@@ -173,31 +152,40 @@ __device__ __forceinline__ bool lane_in(uint64_t mask) {
 enum { kStEval = 0, kStBlend, kStContrib, kStEntries, kStFwdTested, kStFwdSlots, kStBwdTested,
        kStBwdBlend, kStBwdSlots, kStBwdEntries, kStBwdAtomics, kStWords };
 
-template <bool kCount, int kQ>
-__global__ void __launch_bounds__(64 * kQ) splat_forward_kernel(
+// Workgroup b takes block b % kH of tile order[b / kH] (kH wavefronts per tile, independent).
+template <bool kCount, int kS, int kH>
+__global__ void __launch_bounds__(64) splat_forward_kernel(
     const Seg* __restrict__ segs, const int64_t* __restrict__ seg_tstart, int S,
     const DevCam* __restrict__ cams, const uint64_t* __restrict__ ranges,
     const uint32_t* __restrict__ values, const SplatRec* __restrict__ rec,
     float* __restrict__ images, float* __restrict__ final_T, int32_t* __restrict__ last_id,
     uint32_t* __restrict__ n_contrib, unsigned long long* __restrict__ stats,
     const uint32_t* __restrict__ order, uint32_t* __restrict__ tile_work) {
-  const int64_t t = order ? (int64_t)order[blockIdx.x] : (int64_t)blockIdx.x;
-  const Tile tc = tile_setup<kQ>(segs, seg_tstart, S, cams, ranges, t);
+  const int64_t b = (int64_t)blockIdx.x / kH;
+  const int64_t t = order ? (int64_t)order[b] : b;
+  const Tile<kS> tc = tile_setup<kS, kH>(segs, seg_tstart, S, cams, ranges, t,
+                                          (int)(blockIdx.x % kH));
   const int lane = __lane_id();
-  float T[kPx], C0[kPx], C1[kPx], C2[kPx];
-  uint32_t nc[kPx], stop[kPx];
-  uint64_t done[kPx];                    // lanes finished (terminated, or outside the image)
+  float T[kS], C0[kS], C1[kS], C2[kS];
+  uint32_t nc[kS], stop[kS];
+  uint64_t done[kS];                     // lanes finished (terminated, or outside the image)
   uint32_t n_blend = 0u, n_entries = 0u;
   uint64_t n_tested = 0u, n_slots = 0u;
 #pragma unroll
-  for (int p = 0; p < kPx; ++p) {
+  for (int p = 0; p < kS; ++p) {
     T[p] = 1.0f; C0[p] = 0.0f; C1[p] = 0.0f; C2[p] = 0.0f;
     nc[p] = 0u; stop[p] = 0u;
-    done[p] = __ballot(!tc.inside[p]);
+    done[p] = __ballot(!tc.inside(p));
   }
+  auto all_done = [&]() {
+    uint64_t d = ~0ull;
+#pragma unroll
+    for (int p = 0; p < kS; ++p) d &= done[p];
+    return d == ~0ull;
+  };
   const uint32_t len = (uint32_t)(tc.end - tc.start);
   for (int64_t bs = tc.start; bs < tc.end; bs += 64) {
-    if ((done[0] & done[1] & done[2] & done[3]) == ~0ull) break;
+    if (all_done()) break;
     const int64_t idx = bs + lane;
     float4 q0 = make_float4(0, 0, 0, 0), q1 = q0, q2 = q0;
     bool keep = false;
@@ -207,28 +195,27 @@ __global__ void __launch_bounds__(64 * kQ) splat_forward_kernel(
       keep = may_touch(q0, q1, q2, tc);
     }
     uint64_t mask = __ballot(keep);
-    uint64_t wm[kPx];                      // each lane's entry: its slots' window masks
-    window_masks_v(__float_as_uint(q2.y), __float_as_uint(q2.z), tc.xbase, tc.ybase, wm);
     const uint32_t rel0 = (uint32_t)(bs - tc.start);
     while (mask) {
-      if ((done[0] & done[1] & done[2] & done[3]) == ~0ull) break;
+      if (all_done()) break;
       const int k = __builtin_ctzll(mask);
       mask &= mask - 1ull;
       ++n_entries;
-      const float u = rl(q0.x, k), v = rl(q0.y, k), A = rl(q0.z, k), B = rl(q0.w, k);
-      const float Cc = rl(q1.x, k), o = rl(q1.y, k);
-      const float cr = rl(q1.z, k), cg = rl(q1.w, k), cb = rl(q2.x, k);
-      uint64_t win[kPx];
-#pragma unroll
-      for (int p = 0; p < kPx; ++p) win[p] = rl64(wm[p], k);
+      const float u = bcast(q0.x, k), v = bcast(q0.y, k);
+      const float A = bcast(q0.z, k), B = bcast(q0.w, k);
+      const float Cc = bcast(q1.x, k), o = bcast(q1.y, k);
+      const float cr = bcast(q1.z, k), cg = bcast(q1.w, k);
+      const float cb = bcast(q2.x, k);
+      uint64_t win[kS];
+      window_masks<kS>(rlu(q2.y, k), rlu(q2.z, k), tc.xbase, tc.ybase, win);
       const float dx = u - tc.fi;
       const float adx = (A * dx) * dx;
       const float bdx = B * dx;
       const uint32_t pos = rel0 + (uint32_t)k + 1u;
 #pragma unroll
-      for (int p = 0; p < kPx; ++p) {
+      for (int p = 0; p < kS; ++p) {
         const uint64_t act = win[p] & ~done[p];
-        // no per-slot branch: the four slots form one basic block (independent chains)
+        if (act == 0ull) continue;
         if (kCount) { n_tested += (uint64_t)__popcll(act); ++n_slots; }
         const float dy = v - tc.fj[p];
         const float power = -0.5f * (adx + (Cc * dy) * dy) - bdx * dy;
@@ -252,26 +239,17 @@ __global__ void __launch_bounds__(64 * kQ) splat_forward_kernel(
       }
     }
   }
-  if (tile_work) {                       // the tile's work estimate for the adjoint's schedule
-    if (kQ == 1) {
-      if (lane == 0) tile_work[t] = n_entries;
-    } else {
-      __shared__ uint32_t wsum[kQ];
-      if (lane == 0) wsum[threadIdx.x >> 6] = n_entries;
-      __syncthreads();
-      if (threadIdx.x == 0) {
-        uint32_t sum = 0u;
-#pragma unroll
-        for (int q = 0; q < kQ; ++q) sum += wsum[q];
-        tile_work[t] = sum;
-      }
-    }
+  // The tile's work estimate for the adjoint's schedule (with kH > 1 summed over its blocks
+  // into a zeroed array).
+  if (tile_work && lane == 0) {
+    if (kH == 1) tile_work[t] = n_entries;
+    else atomicAdd(&tile_work[t], n_entries);
   }
   uint64_t ev = 0, ncs = 0;
 #pragma unroll
-  for (int p = 0; p < kPx; ++p) {
-    if (!tc.inside[p]) continue;
-    const int64_t q = tc.pix_off + tc.pix[p];
+  for (int p = 0; p < kS; ++p) {
+    if (!tc.inside(p)) continue;
+    const int64_t q = tc.pix_off + tc.pix(p);
     images[3 * q + 0] = C0[p];
     images[3 * q + 1] = C1[p];
     images[3 * q + 2] = C2[p];
@@ -333,8 +311,8 @@ __device__ __forceinline__ float row_total(float v) {
   return t;
 }
 
-template <bool kCount, int kQ>
-__global__ void __launch_bounds__(64 * kQ) splat_backward_kernel(
+template <bool kCount, int kS>
+__global__ void __launch_bounds__(64) splat_backward_kernel(
     const Seg* __restrict__ segs, const int64_t* __restrict__ seg_tstart, int S,
     const DevCam* __restrict__ cams, const uint64_t* __restrict__ ranges,
     const uint32_t* __restrict__ values, const SplatRec* __restrict__ rec,
@@ -342,28 +320,22 @@ __global__ void __launch_bounds__(64 * kQ) splat_backward_kernel(
     const float* __restrict__ dL_dimages, float* __restrict__ grad2d, int64_t G,
     const uint32_t* __restrict__ order, int mode, uint32_t* __restrict__ gmax,
     unsigned long long* __restrict__ gfix, unsigned long long* __restrict__ stats) {
-  // part[q][row][entry][component]: wavefront q's row sums of each entry of the batch (a
-  // stride of 9 floats keeps the four-wavefront workgroup at 36 KB, four per CU).
-  constexpr int kStride = kQ == 1 ? kPartStride : 9;
-  __shared__ float part[kQ][4][64][kStride];
-  __shared__ uint64_t has_sh[kQ];
-  __shared__ uint32_t mx_sh[kQ];
+  __shared__ float part[4][64][kPartStride];    // [row group][entry][component]
   const int64_t t = order ? (int64_t)order[blockIdx.x] : (int64_t)blockIdx.x;
-  const Tile tc = tile_setup<kQ>(segs, seg_tstart, S, cams, ranges, t);
+  const Tile<kS> tc = tile_setup<kS>(segs, seg_tstart, S, cams, ranges, t);
   const int lane = __lane_id();
-  const int wave = kQ == 1 ? 0 : (int)(threadIdx.x >> 6);
   // BG: the colour blended behind the current Gaussian (from the entries already walked), dotted
   // with the pixel's image gradient g; it is all the adjoint needs of that colour.
-  float T[kPx], g0[kPx], g1[kPx], g2[kPx], BG[kPx];
-  uint32_t nc[kPx];
+  float T[kS], g0[kS], g1[kS], g2[kS], BG[kS];
+  uint32_t nc[kS];
   uint32_t mx = 0u;
 #pragma unroll
-  for (int p = 0; p < kPx; ++p) {
+  for (int p = 0; p < kS; ++p) {
     T[p] = 1.0f; g0[p] = 0.0f; g1[p] = 0.0f; g2[p] = 0.0f;
     BG[p] = 0.0f;
     nc[p] = 0u;
-    if (tc.inside[p]) {
-      const int64_t q = tc.pix_off + tc.pix[p];
+    if (tc.inside(p)) {
+      const int64_t q = tc.pix_off + tc.pix(p);
       T[p] = final_T[q];
       nc[p] = n_contrib[q];
       g0[p] = dL_dimages[3 * q + 0];
@@ -374,12 +346,6 @@ __global__ void __launch_bounds__(64 * kQ) splat_backward_kernel(
   }
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) mx = max(mx, (uint32_t)__shfl_xor((int)mx, off, 64));
-  if (kQ > 1) {                          // every wavefront walks the same batches
-    if (lane == 0) mx_sh[wave] = mx;
-    __syncthreads();
-#pragma unroll
-    for (int q = 0; q < kQ; ++q) mx = max(mx, mx_sh[q]);
-  }
   const int64_t stop = tc.start + (int64_t)mx;
   uint64_t n_tested = 0u, n_blended = 0u, n_slots = 0u, n_entries = 0u;
   uint32_t n_atomics = 0u;
@@ -402,11 +368,13 @@ __global__ void __launch_bounds__(64 * kQ) splat_backward_kernel(
       const int k = 63 - __builtin_clzll(mask);          // back to front
       mask &= ~(1ull << k);
       if (kCount) ++n_entries;
-      const float u = rl(q0.x, k), v = rl(q0.y, k), A = rl(q0.z, k), B = rl(q0.w, k);
-      const float Cc = rl(q1.x, k), o = rl(q1.y, k);
-      const float cr = rl(q1.z, k), cg = rl(q1.w, k), cb = rl(q2.x, k);
-      uint64_t win[kPx];
-      window_masks(rlu(q2.y, k), rlu(q2.z, k), tc.xbase, tc.ybase, win);
+      const float u = bcast(q0.x, k), v = bcast(q0.y, k);
+      const float A = bcast(q0.z, k), B = bcast(q0.w, k);
+      const float Cc = bcast(q1.x, k), o = bcast(q1.y, k);
+      const float cr = bcast(q1.z, k), cg = bcast(q1.w, k);
+      const float cb = bcast(q2.x, k);
+      uint64_t win[kS];
+      window_masks<kS>(rlu(q2.y, k), rlu(q2.z, k), tc.xbase, tc.ybase, win);
       const float dx = u - tc.fi;
       const float adx = (A * dx) * dx;
       const float bdx = B * dx;
@@ -418,9 +386,9 @@ __global__ void __launch_bounds__(64 * kQ) splat_backward_kernel(
       float sr = 0.0f, sg = 0.0f, sb = 0.0f;
       uint64_t any = 0ull;
 #pragma unroll
-      for (int p = 0; p < kPx; ++p) {
+      for (int p = 0; p < kS; ++p) {
         const uint64_t act = win[p] & __builtin_amdgcn_ballot_w64(rel < nc[p]);
-        // no per-slot branch: the four slots form one basic block (independent chains)
+        if (act == 0ull) continue;
         const float dy = v - tc.fj[p];
         const float power = -0.5f * (adx + (Cc * dy) * dy) - bdx * dy;
         const float e = __expf(power);
@@ -462,38 +430,18 @@ __global__ void __launch_bounds__(64 * kQ) splat_backward_kernel(
       const float r3 = row_total(sB), r4 = row_total(sC), r5 = row_total(so);
       const float r6 = row_total(sr), r7 = row_total(sg), r8 = row_total(sb);
       if ((lane & 15) == 15) {
-        float* d = part[wave][lane >> 4][k];
+        float* d = part[lane >> 4][k];
         d[0] = r0; d[1] = r1; d[2] = r2; d[3] = r3; d[4] = r4;
         d[5] = r5; d[6] = r6; d[7] = r7; d[8] = r8;
       }
     }
-    // Merge: the partials of entry k over the rows (and, with kQ = 4, the quadrants) are added
-    // in a fixed order, then issued by lane k of the wavefronts, which share the nine
-    // components (wavefront q takes components q, q + kQ, ...).
-    if (kQ == 1) {
-      if (has == 0ull) continue;
-    } else if (lane == 0) {
-      has_sh[wave] = has;
-    }
+    if (has == 0ull) continue;
     __syncthreads();
-    uint64_t hq[kQ];
-    uint64_t hall = 0ull;
-#pragma unroll
-    for (int q = 0; q < kQ; ++q) {
-      hq[q] = kQ == 1 ? has : has_sh[q];
-      hall |= hq[q];
-    }
-    if ((hall >> lane) & 1ull) {
+    if ((has >> lane) & 1ull) {
       const int64_t gi = tc.g_off + (int64_t)my_id;
-      for (int a = wave; a < 9; a += kQ) {
-        float acc = 0.0f;
 #pragma unroll
-        for (int q = 0; q < kQ; ++q) {
-          if (!((hq[q] >> lane) & 1ull)) continue;
-          const float sq = (part[q][0][lane][a] + part[q][1][lane][a]) +
-                           (part[q][2][lane][a] + part[q][3][lane][a]);
-          acc += sq;
-        }
+      for (int a = 0; a < 9; ++a) {
+        const float acc = (part[0][lane][a] + part[1][lane][a]) + (part[2][lane][a] + part[3][lane][a]);
         const int64_t at = (int64_t)a * G + gi;
         if (mode == kAdjointAtomic) {
           if (acc != 0.0f) {
@@ -571,47 +519,48 @@ __global__ void __launch_bounds__(kOrderThreads) tile_order_kernel(const uint64_
     order[atomicAdd(&cnt[bucket(t)], 1u)] = (uint32_t)t;
 }
 
-template <int kQ>
+template <int kS, int kH>
 void splat_forward_dispatch(hipStream_t st, const Seg* segs, const int64_t* seg_tstart, int S,
                             const DevCam* cams, int64_t n_tiles, const uint64_t* ranges,
                             const uint32_t* values, const SplatRec* rec, float* images,
                             float* final_T, int32_t* last_id, uint32_t* n_contrib,
                             unsigned long long* stats, const uint32_t* order, uint32_t* tile_work,
                             bool count) {
+  const dim3 grid((unsigned)(n_tiles * kH)), block(64);
   if (count && stats)
-    hipLaunchKernelGGL((splat_forward_kernel<true, kQ>), dim3((unsigned)n_tiles), dim3(64 * kQ), 0,
-                       st, segs, seg_tstart, S, cams, ranges, values, rec, images, final_T, last_id,
-                       n_contrib, stats, order, tile_work);
+    hipLaunchKernelGGL((splat_forward_kernel<true, kS, kH>), grid, block, 0, st, segs, seg_tstart,
+                       S, cams, ranges, values, rec, images, final_T, last_id, n_contrib, stats,
+                       order, tile_work);
   else
-    hipLaunchKernelGGL((splat_forward_kernel<false, kQ>), dim3((unsigned)n_tiles), dim3(64 * kQ), 0,
-                       st, segs, seg_tstart, S, cams, ranges, values, rec, images, final_T, last_id,
-                       n_contrib, stats, order, tile_work);
+    hipLaunchKernelGGL((splat_forward_kernel<false, kS, kH>), grid, block, 0, st, segs, seg_tstart,
+                       S, cams, ranges, values, rec, images, final_T, last_id, n_contrib, stats,
+                       order, tile_work);
 }
 
-template <int kQ>
+template <int kS>
 void splat_backward_dispatch(hipStream_t st, const Seg* segs, const int64_t* seg_tstart, int S,
                              const DevCam* cams, int64_t n_tiles, const uint64_t* ranges,
                              const uint32_t* values, const SplatRec* rec, const float* final_T,
                              const uint32_t* n_contrib, const float* dL_dimages, float* grad2d,
                              int64_t G, const uint32_t* order, uint32_t* gmax,
                              unsigned long long* gfix, unsigned long long* stats, bool count) {
-  const dim3 grid((unsigned)n_tiles), block(64 * kQ);
+  const dim3 grid((unsigned)n_tiles), block(64);
   if (!gmax) {
     if (count && stats)
-      hipLaunchKernelGGL((splat_backward_kernel<true, kQ>), grid, block, 0, st, segs, seg_tstart, S,
+      hipLaunchKernelGGL((splat_backward_kernel<true, kS>), grid, block, 0, st, segs, seg_tstart, S,
                          cams, ranges, values, rec, final_T, n_contrib, dL_dimages, grad2d, G,
                          order, (int)kAdjointAtomic, gmax, gfix, stats);
     else
-      hipLaunchKernelGGL((splat_backward_kernel<false, kQ>), grid, block, 0, st, segs, seg_tstart, S,
+      hipLaunchKernelGGL((splat_backward_kernel<false, kS>), grid, block, 0, st, segs, seg_tstart, S,
                          cams, ranges, values, rec, final_T, n_contrib, dL_dimages, grad2d, G,
                          order, (int)kAdjointAtomic, gmax, gfix, stats);
     return;
   }
   // Deterministic: gmax [9][G] and gfix [9][G] must be zero on entry.
-  hipLaunchKernelGGL((splat_backward_kernel<false, kQ>), grid, block, 0, st, segs, seg_tstart, S,
+  hipLaunchKernelGGL((splat_backward_kernel<false, kS>), grid, block, 0, st, segs, seg_tstart, S,
                      cams, ranges, values, rec, final_T, n_contrib, dL_dimages, grad2d, G, order,
                      (int)kAdjointMax, gmax, gfix, stats);
-  hipLaunchKernelGGL((splat_backward_kernel<false, kQ>), grid, block, 0, st, segs, seg_tstart, S,
+  hipLaunchKernelGGL((splat_backward_kernel<false, kS>), grid, block, 0, st, segs, seg_tstart, S,
                      cams, ranges, values, rec, final_T, n_contrib, dL_dimages, grad2d, G, order,
                      (int)kAdjointFixed, gmax, gfix, stats);
   if (G > 0)
@@ -621,19 +570,24 @@ void splat_backward_dispatch(hipStream_t st, const Seg* segs, const int64_t* seg
 
 }  // namespace
 
+// tsy: log2 of the tile height (4: 16x16 tiles, 5: 16x32 tiles).
 hipError_t launch_splat_forward(hipStream_t st, const Seg* segs, const int64_t* seg_tstart, int S,
                                 const DevCam* cams, int64_t n_tiles, const uint64_t* ranges,
                                 const uint32_t* values, const SplatRec* rec, float* images,
                                 float* final_T, int32_t* last_id, uint32_t* n_contrib,
                                 unsigned long long* stats, const uint32_t* order,
-                                uint32_t* tile_work, bool count, int tshift) {
+                                uint32_t* tile_work, bool count, int tsy) {
   if (n_tiles == 0) return hipSuccess;
-  if (tshift == 5)
-    splat_forward_dispatch<4>(st, segs, seg_tstart, S, cams, n_tiles, ranges, values, rec, images,
-                              final_T, last_id, n_contrib, stats, order, tile_work, count);
+  // 16x32 tiles: two independent wavefronts of four slots each (the forward keeps the
+  // occupancy of small register sets); tile_work must then be zero on entry.
+  if (tsy == 5)
+    splat_forward_dispatch<4, 2>(st, segs, seg_tstart, S, cams, n_tiles, ranges, values, rec,
+                                 images, final_T, last_id, n_contrib, stats, order, tile_work,
+                                 count);
   else
-    splat_forward_dispatch<1>(st, segs, seg_tstart, S, cams, n_tiles, ranges, values, rec, images,
-                              final_T, last_id, n_contrib, stats, order, tile_work, count);
+    splat_forward_dispatch<4, 1>(st, segs, seg_tstart, S, cams, n_tiles, ranges, values, rec,
+                                 images, final_T, last_id, n_contrib, stats, order, tile_work,
+                                 count);
   return hipGetLastError();
 }
 
@@ -643,13 +597,13 @@ hipError_t launch_splat_backward(hipStream_t st, const Seg* segs, const int64_t*
                                  const uint32_t* n_contrib, const float* dL_dimages,
                                  float* grad2d, int64_t G, const uint32_t* order, uint32_t* gmax,
                                  unsigned long long* gfix, unsigned long long* stats, bool count,
-                                 int tshift) {
+                                 int tsy) {
   if (n_tiles == 0) return hipSuccess;
-  if (tshift == 5)
-    splat_backward_dispatch<4>(st, segs, seg_tstart, S, cams, n_tiles, ranges, values, rec, final_T,
+  if (tsy == 5)
+    splat_backward_dispatch<8>(st, segs, seg_tstart, S, cams, n_tiles, ranges, values, rec, final_T,
                                n_contrib, dL_dimages, grad2d, G, order, gmax, gfix, stats, count);
   else
-    splat_backward_dispatch<1>(st, segs, seg_tstart, S, cams, n_tiles, ranges, values, rec, final_T,
+    splat_backward_dispatch<4>(st, segs, seg_tstart, S, cams, n_tiles, ranges, values, rec, final_T,
                                n_contrib, dL_dimages, grad2d, G, order, gmax, gfix, stats, count);
   return hipGetLastError();
 }

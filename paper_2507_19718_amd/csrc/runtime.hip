@@ -92,7 +92,7 @@ struct gsc_binning {
   bool forward_done = false;
   int K = 0;
   int TX = 0, TY = 0;
-  int tshift = kTileShift;         // 16x16 tiles (gsc_project_bin) or 32x32 (frames)
+  int tsy = kTileShift;         // log2 tile height: 16x16 tiles (gsc_project_bin), 16x32 (frames)
   // views
   DevBuf view_window, view_screen;
 
@@ -350,9 +350,9 @@ struct ReqSpec {
 };
 
 // Builds (or rebuilds) a binning object's tables for a list of requests and uploads them.
-void plan_batch(gsc_ctx* ctx, gsc_binning* b, const std::vector<ReqSpec>& reqs, int tshift) {
-  b->tshift = tshift;
-  const int ts = 1 << tshift;
+void plan_batch(gsc_ctx* ctx, gsc_binning* b, const std::vector<ReqSpec>& reqs, int tsy) {
+  b->tsy = tsy;
+  const int th = 1 << tsy;                 // tiles are 16 x th pixels
   b->segs.clear();
   b->cams.clear();
   b->seg_gstart.clear();
@@ -361,7 +361,7 @@ void plan_batch(gsc_ctx* ctx, gsc_binning* b, const std::vector<ReqSpec>& reqs, 
   for (size_t r = 0; r < reqs.size(); ++r) {
     const gsc_camera& c = reqs[r].cam;
     b->cams.push_back(to_dev(c));
-    const int TX = (c.w + ts - 1) / ts, TY = (c.h + ts - 1) / ts;
+    const int TX = (c.w + kTile - 1) / kTile, TY = (c.h + th - 1) / th;
     for (size_t l = 0; l < reqs[r].levels.size(); ++l) {
       const gsc_gaussians& lv = reqs[r].levels[l];
       Seg s{};
@@ -374,7 +374,7 @@ void plan_batch(gsc_ctx* ctx, gsc_binning* b, const std::vector<ReqSpec>& reqs, 
       s.TX = TX; s.TY = TY;
       s.level = (int32_t)l;
       s.request = (int32_t)r;
-      s.tshift = tshift;
+      s.tsy = tsy;
       s.n_chunks = (int32_t)((lv.n + kChunk - 1) / kChunk);
       b->segs.push_back(s);
       b->seg_gstart.push_back(g);
@@ -539,12 +539,14 @@ void run_forward(gsc_ctx* ctx, gsc_binning* b, float* images, float* final_T, in
     GSC_TRY(hipMemsetAsync(ctx->d_stats.p, 0, kStatWords * 8, ctx->stream));
   }
   const uint32_t* order = tile_order(ctx, b, nullptr);
+  if (b->tsy != kTileShift)     // taller tiles: the forward sums its blocks' work per tile
+    GSC_TRY(launch_fill_u32(ctx->stream, b->tile_work.as<uint32_t>(), 0u, b->n_tiles));
   { ProfScope ps_(ctx, P_FWD, ctx->stream);
   GSC_TRY(launch_splat_forward(ctx->stream, b->d_segs(), b->d_tstart(), b->S, b->d_cams(), b->n_tiles,
                                b->ranges.as<uint64_t>(), b->values.as<uint32_t>(),
                                b->rec.as<SplatRec>(), images, final_T, last_id,
                                b->n_contrib.as<uint32_t>(), ctx->d_stats.as<unsigned long long>(),
-                               order, b->tile_work.as<uint32_t>(), ctx->work_counters, b->tshift));
+                               order, b->tile_work.as<uint32_t>(), ctx->work_counters, b->tsy));
   }
   b->forward_done = true;
 }
@@ -573,7 +575,7 @@ void run_splat_adjoint(gsc_ctx* ctx, gsc_binning* b, const float* final_T, const
                                 b->rec.as<SplatRec>(), final_T, b->n_contrib.as<uint32_t>(), dL,
                                 b->grad2d.as<float>(), b->G, order, gmax, gfix,
                                 ctx->d_stats.as<unsigned long long>(), ctx->work_counters,
-                                b->tshift));
+                                b->tsy));
   }
 }
 
@@ -1212,42 +1214,60 @@ gsc_status gsc_splat_forward(gsc_ctx* ctx, gsc_binning* bin, float* images, floa
   });
 }
 
+namespace {
+gsc_binning* check_backward_args(gsc_ctx* ctx, const gsc_binning* bin, const gsc_gaussians* levels,
+                                 int32_t num_levels, const gsc_camera* cam, const float* final_T,
+                                 const int32_t* last_id, const float* dL_dimages,
+                                 const gsc_grads* grads) {
+  if (!bin || !final_T || !last_id || !dL_dimages || !grads) invalid(ctx, "NULL argument");
+  gsc_binning* b = const_cast<gsc_binning*>(bin);
+  if (!b->forward_done) invalid(ctx, "gsc_splat_forward has not run on this binning");
+  check_levels(ctx, levels, num_levels);
+  check_camera(ctx, cam);
+  if (num_levels != b->S) invalid(ctx, "num_levels differs from the binning's");
+  for (int l = 0; l < num_levels; ++l) {
+    const Seg& sg = b->segs[l];
+    if (levels[l].n != sg.n || levels[l].pos != sg.pos || levels[l].rot != sg.rot ||
+        levels[l].log_scale != sg.ls || levels[l].rgb != sg.rgb ||
+        levels[l].opacity_logit != sg.logit)
+      invalid(ctx, "levels differ from those given to gsc_project_bin");
+    if (levels[l].n > 0 && (!grads[l].pos || !grads[l].rot || !grads[l].log_scale ||
+                            !grads[l].rgb || !grads[l].opacity_logit))
+      invalid(ctx, "gradient pointer is NULL");
+  }
+  return b;
+}
+
+// Copies each level's 14 gradients ([14 n] in the binning's segment order) to the caller's arrays.
+void copy_out_grads(gsc_ctx* ctx, const gsc_binning* b, const gsc_gaussians* levels, int num_levels,
+                    const float* grads14, const gsc_grads* grads) {
+  for (int l = 0; l < num_levels; ++l) {
+    const int64_t nn = levels[l].n;
+    if (nn == 0) continue;
+    const float* g = grads14 + 14 * b->segs[l].g_off;
+    GSC_TRY(hipMemcpyAsync(grads[l].pos, g, 12 * nn, hipMemcpyDeviceToDevice, ctx->stream));
+    GSC_TRY(hipMemcpyAsync(grads[l].rot, g + 3 * nn, 16 * nn, hipMemcpyDeviceToDevice, ctx->stream));
+    GSC_TRY(hipMemcpyAsync(grads[l].log_scale, g + 7 * nn, 12 * nn, hipMemcpyDeviceToDevice, ctx->stream));
+    GSC_TRY(hipMemcpyAsync(grads[l].rgb, g + 10 * nn, 12 * nn, hipMemcpyDeviceToDevice, ctx->stream));
+    GSC_TRY(hipMemcpyAsync(grads[l].opacity_logit, g + 13 * nn, 4 * nn, hipMemcpyDeviceToDevice, ctx->stream));
+  }
+}
+}  // namespace
+
 gsc_status gsc_splat_backward(gsc_ctx* ctx, const gsc_binning* bin, const gsc_gaussians* levels,
                               int32_t num_levels, const gsc_camera* cam, const float* final_T,
                               const int32_t* last_id, const float* dL_dimages,
                               const gsc_grads* grads) {
   return guarded(ctx, [&]() -> gsc_status {
-    if (!bin || !final_T || !last_id || !dL_dimages || !grads) invalid(ctx, "NULL argument");
-    gsc_binning* b = const_cast<gsc_binning*>(bin);
-    if (!b->forward_done) invalid(ctx, "gsc_splat_forward has not run on this binning");
-    check_levels(ctx, levels, num_levels);
-    check_camera(ctx, cam);
-    if (num_levels != b->S) invalid(ctx, "num_levels differs from the binning's");
-    for (int l = 0; l < num_levels; ++l) {
-      const Seg& sg = b->segs[l];
-      if (levels[l].n != sg.n || levels[l].pos != sg.pos || levels[l].rot != sg.rot ||
-          levels[l].log_scale != sg.ls || levels[l].rgb != sg.rgb ||
-          levels[l].opacity_logit != sg.logit)
-        invalid(ctx, "levels differ from those given to gsc_project_bin");
-      if (levels[l].n > 0 && (!grads[l].pos || !grads[l].rot || !grads[l].log_scale ||
-                              !grads[l].rgb || !grads[l].opacity_logit))
-        invalid(ctx, "gradient pointer is NULL");
-    }
+    gsc_binning* b = check_backward_args(ctx, bin, levels, num_levels, cam, final_T, last_id,
+                                         dL_dimages, grads);
     need(ctx, ctx->grads14, ctx->alloc, 4 * 14 * (size_t)std::max<int64_t>(b->G, 1), "parameter gradients");
     run_backward(ctx, b, final_T, dL_dimages, ctx->grads14.as<float>());
-    for (int l = 0; l < num_levels; ++l) {
-      const int64_t nn = levels[l].n;
-      if (nn == 0) continue;
-      const float* g = ctx->grads14.as<float>() + 14 * b->segs[l].g_off;
-      GSC_TRY(hipMemcpyAsync(grads[l].pos, g, 12 * nn, hipMemcpyDeviceToDevice, ctx->stream));
-      GSC_TRY(hipMemcpyAsync(grads[l].rot, g + 3 * nn, 16 * nn, hipMemcpyDeviceToDevice, ctx->stream));
-      GSC_TRY(hipMemcpyAsync(grads[l].log_scale, g + 7 * nn, 12 * nn, hipMemcpyDeviceToDevice, ctx->stream));
-      GSC_TRY(hipMemcpyAsync(grads[l].rgb, g + 10 * nn, 12 * nn, hipMemcpyDeviceToDevice, ctx->stream));
-      GSC_TRY(hipMemcpyAsync(grads[l].opacity_logit, g + 13 * nn, 4 * nn, hipMemcpyDeviceToDevice, ctx->stream));
-    }
+    copy_out_grads(ctx, b, levels, num_levels, ctx->grads14.as<float>(), grads);
     return GSC_OK;
   });
 }
+
 
 gsc_status gsc_loss_composite(gsc_ctx* ctx, const float* images, const float* targets,
                               const gsc_path_record* records, int32_t spp, int32_t num_levels,
@@ -1513,8 +1533,8 @@ size_t gsc_frame_footprint_bytes(const gsc_scene* sc, int32_t w, int32_t h, uint
   for (int l = 0; l < sc->K; ++l) G += sc->n[l];
   const size_t P = (size_t)w * h;
   const size_t K = (size_t)sc->K;
-  const int ts = 1 << kFrameTileShift;                             // frames bin 32x32 tiles
-  const size_t tiles = K * (size_t)((w + ts - 1) / ts) * ((h + ts - 1) / ts);
+  const int th = 1 << kFrameTileShift;                             // frames bin 16 x 32 tiles
+  const size_t tiles = K * (size_t)((w + 15) / 16) * ((h + th - 1) / th);
   size_t b = 0;
   b += (size_t)G * (48 + 4 + 8 + 4 + 4 * 4 + 8 + 9 * 4 + 14 * 4);   // per-Gaussian buffers
   b += 4 * (size_t)instance_estimate;                              // instance ids
