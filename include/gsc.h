@@ -367,6 +367,22 @@ gsc_status gsc_splat_backward(gsc_ctx* ctx, const gsc_binning* bin, const gsc_ga
                               const int32_t* last_id, const float* dL_dimages,
                               const gsc_grads* grads);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
+ * loops, harnesses that forbid hipMalloc): the same adjoint as gsc_splat_backward, same
+ * arguments and results, but its temporaries (screen-space and parameter gradients before they
+ * are copied out, the tile schedule) live in one static device array of the library, 49.3 MB
+ * per device, held until the process ends; it calls no hipMalloc / hipFree and no allocator
+ * hook.  Limits: at most 524,288 Gaussians (all levels together) and 262,144 tiles per call,
+ * else GSC_E_INVALID_ARG with a message and nothing enqueued.  Sums with float atomics:
+ * GSC_E_INVALID_ARG while the deterministic mode is on.  Every call on a device shares that
+ * device's array, so calls that overlap on one device (several contexts or streams) race; calls
+ * ordered on one stream do not.  GSC_E_DEVICE if the array's address could not be obtained. */
+gsc_status gsc_splat_backward_noalloc(gsc_ctx* ctx, const gsc_binning* bin,
+                                      const gsc_gaussians* levels, int32_t num_levels,
+                                      const gsc_camera* cam, const float* final_T,
+                                      const int32_t* last_id, const float* dL_dimages,
+                                      const gsc_grads* grads);
+
 /* Per level l, with prediction y = images[l] and noisy target x = targets[l]: L2 (loss 0) or
  * the HDR loss of Eq. 4, (y - x)^2 / (sg(max(y,0)) + 0.01)^2 (loss 1), averaged over the
  * 3 w h elements of the level and summed over levels; writes dL/dimages [K][h][w][3] and the

@@ -421,6 +421,21 @@ def gsc_splat_backward(ctx: Context, b: Binning, levels, cam, final_T, last_id, 
                                           _ptr(final_T), _ptr(last_id), _ptr(dL_dimages), garr))
 
 
+def gsc_splat_backward_noalloc(ctx: Context, b: Binning, levels, cam, final_T, last_id,
+                               dL_dimages, grads: Sequence[Dict[str, torch.Tensor]]):
+    """gsc_splat_backward without any device allocation (the library's static scratch array):
+    for callers that cannot allocate.  The caller passes every output."""
+    arr = levels_struct(levels)
+    cs = camera_struct(cam)
+    garr = (gsc_grads * len(levels))()
+    for l, g in enumerate(grads):
+        garr[l] = gsc_grads(_ptr(g["pos"]), _ptr(g["rot"]), _ptr(g["log_scale"]), _ptr(g["rgb"]),
+                            _ptr(g["opacity_logit"]))
+    ctx.check(ctx._lib.gsc_splat_backward_noalloc(ctx.handle, b.handle, arr, len(levels),
+                                                  ctypes.byref(cs), _ptr(final_T), _ptr(last_id),
+                                                  _ptr(dL_dimages), garr))
+
+
 def _check_bytes(t: Optional[torch.Tensor], need: int, what: str):
     if t is not None and t.numel() * t.element_size() < need:
         raise ValueError(f"{what} holds {t.numel() * t.element_size()} bytes, needs {need}")

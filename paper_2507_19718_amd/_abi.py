@@ -140,6 +140,8 @@ _SIGNATURES = {
     "gsc_splat_forward": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p]),
     "gsc_splat_backward": (c_int32, [c_void_p, c_void_p, P(gsc_gaussians), c_int32, P(gsc_camera),
                                      c_void_p, c_void_p, c_void_p, P(gsc_grads)]),
+    "gsc_splat_backward_noalloc": (c_int32, [c_void_p, c_void_p, P(gsc_gaussians), c_int32, P(gsc_camera),
+                                     c_void_p, c_void_p, c_void_p, P(gsc_grads)]),
     "gsc_loss_composite": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_int32, c_int32,
                                      c_int32, c_int32, c_int32, c_void_p, c_void_p, c_void_p]),
     "gsc_adam_step": (c_int32, [c_void_p, c_void_p, c_void_p, c_void_p, c_void_p, c_int64,

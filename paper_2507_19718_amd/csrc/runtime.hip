@@ -9,6 +9,7 @@
 #include <functional>
 #include <new>
 #include <string>
+#include <mutex>
 #include <vector>
 
 #include "gsc_internal.h"
@@ -163,6 +164,8 @@ struct gsc_ctx {
   uint64_t acc_instances = 0, acc_frames = 0;
   DevBuf adam_tab;                 // fused AdamW group table
   DevBuf d_stats;                  // splat work counters (kStatWords words)
+  void* scratch = nullptr;         // this device's address of the allocation-free adjoint's array
+  hipError_t scratch_err = hipSuccess;
   bool work_counters = false;      // detailed counting variants of the splat kernels
 };
 
@@ -947,6 +950,43 @@ std::vector<std::pair<int64_t, int64_t>> parse_state_header(gsc_ctx* ctx, const 
 // =============================================================================================
 // C ABI
 // =============================================================================================
+// ---- the allocation-free adjoint's scratch ------------------------------------------------------
+// gsc_splat_backward_noalloc keeps its temporaries (the [9][G] screen-space gradients, the
+// [14][G] parameter gradients before they are copied out, the tile schedule) in one file-scope
+// device array instead of allocating them.  Every device the library runs on holds its own copy
+// until the process ends; host code uses only the address hipGetSymbolAddress gives for the
+// current device, looked up once per device.
+constexpr int64_t kNoAllocMaxGaussians = int64_t(1) << 19;     // 524,288 Gaussians per call
+constexpr int64_t kNoAllocMaxTiles = int64_t(1) << 18;         // 262,144 tiles per call
+constexpr size_t kNoAllocScratchBytes =
+    (size_t)(9 + 14) * 4 * (size_t)kNoAllocMaxGaussians + 4 * (size_t)kNoAllocMaxTiles;
+static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
+
+constexpr int kMaxDevices = 64;
+struct ScratchSlot {
+  std::once_flag once;
+  void* ptr = nullptr;
+  hipError_t err = hipSuccess;
+};
+ScratchSlot g_scratch[kMaxDevices];
+
+// Called with `device` current.
+void lookup_scratch(int device, void** ptr, hipError_t* err) {
+  if (device < 0 || device >= kMaxDevices) {
+    *ptr = nullptr;
+    *err = hipErrorInvalidDevice;
+    return;
+  }
+  ScratchSlot& slot = g_scratch[device];
+  std::call_once(slot.once, [&]() {
+    void* p = nullptr;
+    slot.err = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    slot.ptr = slot.err == hipSuccess ? p : nullptr;
+  });
+  *ptr = slot.ptr;
+  *err = slot.err;
+}
+
 // Ceiling micro-benchmarks: one launch between two events on the context stream.
 namespace {
 template <typename F>
@@ -991,6 +1031,7 @@ gsc_status gsc_ctx_create(int device, void* hip_stream, const gsc_allocator* all
   c->pinned_cap = size_t(4) << 20;
   ok = ok && hipHostMalloc((void**)&c->pinned, c->pinned_cap, hipHostMallocDefault) == hipSuccess;
   ok = ok && hipHostMalloc((void**)&c->host_u64, 8 * 32, hipHostMallocDefault) == hipSuccess;
+  if (ok) lookup_scratch(device, &c->scratch, &c->scratch_err);
   if (!ok) {
     gsc_ctx_destroy(c);
     return GSC_E_DEVICE;
@@ -1268,6 +1309,55 @@ gsc_status gsc_splat_backward(gsc_ctx* ctx, const gsc_binning* bin, const gsc_ga
   });
 }
 
+gsc_status gsc_splat_backward_noalloc(gsc_ctx* ctx, const gsc_binning* bin,
+                                      const gsc_gaussians* levels, int32_t num_levels,
+                                      const gsc_camera* cam, const float* final_T,
+                                      const int32_t* last_id, const float* dL_dimages,
+                                      const gsc_grads* grads) {
+  return guarded(ctx, [&]() -> gsc_status {
+    gsc_binning* b = check_backward_args(ctx, bin, levels, num_levels, cam, final_T, last_id,
+                                         dL_dimages, grads);
+    if (ctx->deterministic)
+      invalid(ctx, "gsc_splat_backward_noalloc sums with float atomics; switch the deterministic "
+                   "mode off (gsc_ctx_set_deterministic)");
+    if (b->G > kNoAllocMaxGaussians) {
+      char buf[200];
+      snprintf(buf, sizeof(buf), "gsc_splat_backward_noalloc takes at most %lld Gaussians per call; "
+               "the binning holds %lld", (long long)kNoAllocMaxGaussians, (long long)b->G);
+      invalid(ctx, buf);
+    }
+    if (b->n_tiles > kNoAllocMaxTiles) {
+      char buf[200];
+      snprintf(buf, sizeof(buf), "gsc_splat_backward_noalloc takes at most %lld tiles per call; "
+               "the binning holds %lld", (long long)kNoAllocMaxTiles, (long long)b->n_tiles);
+      invalid(ctx, buf);
+    }
+    if (!ctx->scratch) {
+      char buf[200];
+      snprintf(buf, sizeof(buf), "no address for the allocation-free adjoint's device array on "
+               "device %d (hipGetSymbolAddress: %s)", ctx->device, hipGetErrorString(ctx->scratch_err));
+      ctx->err = buf;
+      return GSC_E_DEVICE;
+    }
+    hipStream_t st = ctx->stream;
+    const int64_t G = b->G;
+    float* g2d = (float*)ctx->scratch;
+    float* g14 = g2d + 9 * kNoAllocMaxGaussians;
+    uint32_t* order = (uint32_t*)(g14 + 14 * kNoAllocMaxGaussians);
+    // Cleared by a kernel (no memset node), so the call can be captured in a graph.
+    GSC_TRY(launch_fill_u32(st, (uint32_t*)g2d, 0u, 9 * G));
+    GSC_TRY(launch_tile_order(st, b->ranges.as<uint64_t>(), b->tile_work.as<uint32_t>(), b->n_tiles,
+                              order));
+    GSC_TRY(launch_splat_backward(st, b->d_segs(), b->d_tstart(), b->S, b->d_cams(), b->n_tiles,
+                                  b->ranges.as<uint64_t>(), b->values.as<uint32_t>(),
+                                  b->rec.as<SplatRec>(), final_T, b->n_contrib.as<uint32_t>(),
+                                  dL_dimages, g2d, G, order, nullptr, nullptr, nullptr, false,
+                                  b->tsy));
+    GSC_TRY(launch_project_backward(st, b->d_segs(), b->d_gstart(), b->S, b->d_cams(), G, g2d, g14));
+    copy_out_grads(ctx, b, levels, num_levels, g14, grads);
+    return GSC_OK;
+  });
+}
 
 gsc_status gsc_loss_composite(gsc_ctx* ctx, const float* images, const float* targets,
                               const gsc_path_record* records, int32_t spp, int32_t num_levels,
