@@ -132,6 +132,11 @@ __device__ __forceinline__ void window_masks(uint32_t wx, uint32_t wy, int xbase
   const uint32_t c32 = c16 | (c16 << 16);
   const uint64_t c64 = ((uint64_t)c32 << 32) | (uint64_t)c32;
   const int ylo = (int)(wy & 0xffffu) - ybase, yhi = (int)(wy >> 16) - ybase;
+  if (ylo <= 0 && yhi >= 4 * kS - 1) {   // the window spans every row of the block (most entries)
+#pragma unroll
+    for (int p = 0; p < kS; ++p) m[p] = c64;
+    return;
+  }
 #pragma unroll
   for (int p = 0; p < kS; ++p) {
     const int glo = max(ylo - 4 * p, 0), ghi = min(yhi - 4 * p, 3);
