@@ -467,11 +467,11 @@ def main():
         "ceilings": ceil,
         "kernels": kernels,
         "counters": {"instances_per_frame": int(per_frame_inst), "gaussians": int(c["gaussians"]),
-                     "gaussian_pixel_evals_per_frame": int(cnt["evaluations"] / args.steps),
-                     "blended_pairs_per_frame": int(cnt["blended"] / args.steps),
+                     "gaussian_pixel_evals_per_frame": int(work["evaluations"]),
+                     "blended_pairs_per_frame": int(work["blended"]),
                      "adjoint_walk_pairs_per_frame": int(cnt["contributors"] / args.steps),
                      "tile_entries_per_frame": int(cnt["tile_entries"] / args.steps),
-                     "gaussian_pixel_evals_per_s": round(cnt["evaluations"] / elapsed, 1),
+                     "gaussian_pixel_evals_per_s": round(work["evaluations"] * fps, 1),
                      "tested_pairs_per_frame_forward": int(work["fwd_tested"]),
                      "tested_pairs_per_frame_adjoint": int(work["bwd_tested"]),
                      "blended_pairs_adjoint": int(work["bwd_blended"]),

@@ -260,11 +260,12 @@ gsc_status gsc_ctx_profile(gsc_ctx* ctx, int32_t on);
 gsc_status gsc_ctx_profile_read(gsc_ctx* ctx, int32_t index, char* name, size_t name_len,
                                 double* total_ms, int64_t* launches);
 /* Work counters since profiling was last turned on (HOST struct).  The splat counters count
- * pairs of the cache-image forward (the front-to-back blend): per pixel, `evaluations` sums the
- * list entries it examined before it finished (its termination position, or the list length),
- * `blended` the entries it blended (alpha >= 1/255 before termination) and `contributors` the
+ * pairs of the cache-image forward (the front-to-back blend): per pixel, `contributors` sums the
  * position of its last blended entry (the length of the adjoint's walk); `tile_entries` sums,
- * per 16x16 tile, the entries its wavefront evaluated after the tile-ellipse cull. */
+ * per tile wavefront, the entries it evaluated after the tile-ellipse cull.  While
+ * gsc_ctx_set_work_counters is on, also `evaluations` (per pixel, the list entries it examined
+ * before it finished: its termination position, or the list length), `blended` (the entries it
+ * blended, alpha >= 1/255 before termination) and the fwd_* and bwd_* counters. */
 typedef struct gsc_counters {
   uint64_t instances;      /* (tile, Gaussian) instances binned */
   uint64_t binnings;       /* binnings run */

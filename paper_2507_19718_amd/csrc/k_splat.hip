@@ -148,10 +148,10 @@ __device__ __forceinline__ bool lane_in(uint64_t mask) {
   return __builtin_amdgcn_inverse_ballot_w64(mask);
 }
 
-// Work counters (stats words, all sums over the launch): the forward always adds
-// [0] list positions each pixel examined, [1] blended pairs, [2] each pixel's walk length,
-// [3] entries its wavefront evaluated after the cull; with kCount also [4] (pixel, entry) pairs
-// tested (lanes live in an evaluated slot) and [5] slot evaluations.  The adjoint with kCount
+// Work counters (stats words, all sums over the launch): the forward always adds [2] each
+// pixel's walk length and [3] entries its wavefront evaluated after the cull; with kCount also
+// [0] list positions each pixel examined, [1] blended pairs, [4] (pixel, entry) pairs tested
+// (lanes live in an evaluated slot) and [5] slot evaluations.  The adjoint with kCount
 // adds [6] pairs tested, [7] pairs blended, [8] slot evaluations, [9] entries walked after the
 // cull and [10] float atomics issued.
 enum { kStEval = 0, kStBlend, kStContrib, kStEntries, kStFwdTested, kStFwdSlots, kStBwdTested,
@@ -238,9 +238,11 @@ __global__ void __launch_bounds__(64) splat_forward_kernel(
         C2[p] = fmaf(cb, w, C2[p]);
         T[p] = bl ? Tn : T[p];
         nc[p] = bl ? pos : nc[p];
-        stop[p] = lane_in(finm) ? pos : stop[p];
         done[p] |= finm;
-        n_blend += (uint32_t)__popcll(blm);
+        if (kCount) {
+          stop[p] = lane_in(finm) ? pos : stop[p];
+          n_blend += (uint32_t)__popcll(blm);
+        }
       }
     }
   }
@@ -261,7 +263,7 @@ __global__ void __launch_bounds__(64) splat_forward_kernel(
     final_T[q] = T[p];
     last_id[q] = nc[p] ? (int32_t)values[tc.start + nc[p] - 1u] : -1;
     n_contrib[q] = nc[p];
-    ev += stop[p] ? stop[p] : len;
+    if (kCount) ev += stop[p] ? stop[p] : len;
     ncs += nc[p];
   }
   if (stats) {
@@ -271,11 +273,11 @@ __global__ void __launch_bounds__(64) splat_forward_kernel(
       ncs += __shfl_xor(ncs, off, 64);
     }
     if (lane == 0) {
-      atomicAdd(&stats[kStEval], (unsigned long long)ev);
-      atomicAdd(&stats[kStBlend], (unsigned long long)n_blend);
       atomicAdd(&stats[kStContrib], (unsigned long long)ncs);
       atomicAdd(&stats[kStEntries], (unsigned long long)n_entries);
       if (kCount) {
+        atomicAdd(&stats[kStEval], (unsigned long long)ev);
+        atomicAdd(&stats[kStBlend], (unsigned long long)n_blend);
         atomicAdd(&stats[kStFwdTested], (unsigned long long)n_tested);
         atomicAdd(&stats[kStFwdSlots], (unsigned long long)n_slots);
       }
@@ -383,11 +385,11 @@ __global__ void __launch_bounds__(64) splat_backward_kernel(
       const float dx = u - tc.fi;
       const float adx = (A * dx) * dx;
       const float bdx = B * dx;
-      const float hdx2 = (-0.5f * dx) * dx;
-      const float mAdx = -A * dx, mBdx = -B * dx;
-      const float inv_o = __builtin_amdgcn_rcpf(o);
       const uint32_t rel = rel0 + (uint32_t)k;
-      float su = 0.0f, sv = 0.0f, sA = 0.0f, sB = 0.0f, sC = 0.0f, so = 0.0f;
+      // Per lane, the moments of dL/dpower over its pixels (all in one column, so dx is
+      // common): m0 = sum dpow, m1 = sum dpow dy, m2 = sum dpow dy^2; the conic, mean and
+      // opacity gradients are linear in them.
+      float m0 = 0.0f, m1 = 0.0f, m2 = 0.0f;
       float sr = 0.0f, sg = 0.0f, sb = 0.0f;
       uint64_t any = 0ull;
 #pragma unroll
@@ -422,15 +424,21 @@ __global__ void __launch_bounds__(64) splat_backward_kernel(
         // alpha not clamped: it depends on power and opacity (dL/do = dL/dpower / o).
         const bool unclamped = lane_in(__builtin_amdgcn_ballot_w64(!(oe > kAlphaMax)));
         const float dpow = unclamped ? dal * az : 0.0f;
-        so = fmaf(dpow, inv_o, so);
-        sA = fmaf(dpow, hdx2, sA);
-        sC = fmaf(dpow, (-0.5f * dy) * dy, sC);
-        sB = fmaf(dpow, -dx * dy, sB);
-        su = fmaf(dpow, fmaf(-B, dy, mAdx), su);
-        sv = fmaf(dpow, fmaf(-Cc, dy, mBdx), sv);
+        const float tdy = dpow * dy;
+        m0 += dpow;
+        m1 += tdy;
+        m2 = fmaf(tdy, dy, m2);
       }
       if (any == 0ull) continue;
       has |= 1ull << k;
+      // power = -(A dx^2 + C dy^2) / 2 - B dx dy with dx = u - i, dy = v - j, and dL/do from
+      // alpha = o e^power (the unclamped pairs only, as dpow).
+      const float so = m0 * __builtin_amdgcn_rcpf(o);
+      const float sA = ((-0.5f * dx) * dx) * m0;
+      const float sC = -0.5f * m2;
+      const float sB = -dx * m1;
+      const float su = fmaf(-B, m1, (-A * dx) * m0);
+      const float sv = fmaf(-Cc, m1, (-B * dx) * m0);
       const float r0 = row_total(su), r1 = row_total(sv), r2 = row_total(sA);
       const float r3 = row_total(sB), r4 = row_total(sC), r5 = row_total(so);
       const float r6 = row_total(sr), r7 = row_total(sg), r8 = row_total(sb);

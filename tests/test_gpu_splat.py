@@ -212,7 +212,11 @@ def test_splat_counters_match_oracle(gsc, gctx):
                 want_walk += int(np.nonzero(lst == gid)[0][0]) + 1
     levels = [gsc.level_to_device(g) for g in levels_np]
     gctx.profile(True)
-    forward_levels(gsc, gctx, levels, cam, len(levels))
+    gctx.set_work_counters(True)
+    try:
+        forward_levels(gsc, gctx, levels, cam, len(levels))
+    finally:
+        gctx.set_work_counters(False)
     c = gctx.counters()
     gctx.profile(False)
     assert c["blended"] == want_blend
