@@ -165,14 +165,14 @@ struct Projected {
   float u, v, A, B, Cc, o, z;
   float radius;
   int px0, px1, py0, py1;   // full-frame inclusive window
-  int tx0, tx1, ty0, ty1;   // window-local inclusive tile rect (tiles of 16 x 2^tsy pixels)
+  int tx0, tx1, ty0, ty1;   // window-local inclusive tile rect (tiles of 2^tsx x 2^tsy pixels)
   uint32_t tiles;           // 0 when culled
 };
 
 __device__ __forceinline__ Projected project_one(const float* __restrict__ pos,
                                                  const float* __restrict__ rot,
                                                  const float* __restrict__ ls, float logit,
-                                                 const DevCam& cam, int tsy) {
+                                                 const DevCam& cam, int tsx, int tsy) {
   Projected P;
   P.tiles = 0u;
   P.px0 = P.px1 = P.py0 = P.py1 = 0;
@@ -251,7 +251,7 @@ __device__ __forceinline__ Projected project_one(const float* __restrict__ pos,
   const float fy1 = fminf((float)(cam.y0 + cam.h - 1), floorf(P.v + r));
   if (!(fx0 <= fx1) || !(fy0 <= fy1)) return P;
   P.px0 = (int)fx0; P.px1 = (int)fx1; P.py0 = (int)fy0; P.py1 = (int)fy1;
-  P.tx0 = (P.px0 - cam.x0) >> 4; P.tx1 = (P.px1 - cam.x0) >> 4;
+  P.tx0 = (P.px0 - cam.x0) >> tsx; P.tx1 = (P.px1 - cam.x0) >> tsx;
   P.ty0 = (P.py0 - cam.y0) >> tsy; P.ty1 = (P.py1 - cam.y0) >> tsy;
   P.tiles = (uint32_t)((P.tx1 - P.tx0 + 1) * (P.ty1 - P.ty0 + 1));
   return P;

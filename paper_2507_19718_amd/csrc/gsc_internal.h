@@ -17,10 +17,13 @@ namespace gsc {
 
 constexpr int kTile = 16;               // 16x16 pixel tiles (gsc_project_bin and its views)
 constexpr int kTileShift = 4;
-// Frames bin 16-wide, 32-tall tiles (log2 height 5): each wavefront then splats eight pixels
-// per lane, so the per-entry work (record broadcast, window masks, the adjoint's reductions and
-// atomics) is shared by twice the pixels, and the tile lists hold about half the instances.
-constexpr int kFrameTileShift = 5;
+// Frames bin 32x32 tiles.  The adjoint walks one with a workgroup of two wavefronts, each a
+// 16x32 half with eight pixels per lane (the per-entry work, record broadcast, window masks and
+// reductions, is shared by eight pixels), and adds a Gaussian's partials from both halves in LDS
+// before its atomics; the forward walks it with four independent 16x16 wavefronts.  The tile
+// lists hold about a third of the instances of 16x16 tiles.
+constexpr int kFrameTileShiftX = 5;
+constexpr int kFrameTileShiftY = 5;
 constexpr int kMaxTf = 64;
 constexpr int kMaxLights = 8;
 constexpr int kChunk = 1024;            // depth-ordered Gaussians per binning chunk
@@ -49,8 +52,7 @@ struct Seg {
   int32_t TX, TY;
   int32_t level;
   int32_t request;
-  int32_t tsy;       // log2 of the tile height: 16x16 tiles (4) or, in frames, 16x32 (5)
-  int32_t pad_;
+  int32_t tsx, tsy;     // log2 of the tile width and height: 16x16 (4, 4) or, in frames, 32x32
 };
 
 // Per request of a trace launch.
@@ -162,7 +164,7 @@ hipError_t launch_splat_forward(hipStream_t st, const Seg* segs, const int64_t* 
                                 const uint32_t* values, const SplatRec* rec, float* images,
                                 float* final_T, int32_t* last_id, uint32_t* n_contrib,
                                 unsigned long long* stats, const uint32_t* order,
-                                uint32_t* tile_work, bool count, int tsy);
+                                uint32_t* tile_work, bool count, int tsx, int tsy);
 // Keys ordering tiles by decreasing work (work NULL: list length from ranges).
 hipError_t launch_tile_order(hipStream_t st, const uint64_t* ranges, const uint32_t* work,
                              int64_t n_tiles, uint32_t* order);
@@ -174,7 +176,7 @@ hipError_t launch_splat_backward(hipStream_t st, const Seg* segs, const int64_t*
                                  const uint32_t* n_contrib, const float* dL_dimages,
                                  float* grad2d, int64_t G, const uint32_t* order, uint32_t* gmax,
                                  unsigned long long* gfix, unsigned long long* stats, bool count,
-                                 int tsy);
+                                 int tsx, int tsy);
 
 int64_t trace_align(int64_t pixels);
 hipError_t launch_trace(hipStream_t st, const TraceDesc* descs, const int64_t* req_pstart, int R,

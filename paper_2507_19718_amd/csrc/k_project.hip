@@ -23,7 +23,7 @@ constexpr uint64_t kEmptyRect = 0x0000000100000001ull;   // tx0 = 1 > tx1 = 0: c
 constexpr float kCoreQ = 1.3f;
 
 __device__ __forceinline__ uint64_t saturation_core(const Projected& P, const DevCam& cam,
-                                                    int tsy) {
+                                                    int tsx, int tsy) {
   if (!P.tiles || !(P.o >= (2.0f / 255.0f) * 1.01f)) return 0ull;
   const float rho = fabsf(P.B) / sqrtf(P.A * P.Cc);
   if (!(rho < 0.999f)) return 0ull;
@@ -34,11 +34,11 @@ __device__ __forceinline__ uint64_t saturation_core(const Projected& P, const De
   const int j0 = max(P.py0, (int)ceilf(P.v - hy)), j1 = min(P.py1, (int)floorf(P.v + hy));
   if (i0 > i1 || j0 > j1) return 0ull;
   // Window-local tiles whose pixels (clipped to the render window) lie in [i0, i1] x [j0, j1].
-  const int th = 1 << tsy;                       // tiles are 16 x th pixels
-  const int TX = (cam.w + 15) >> 4, TY = (cam.h + th - 1) >> tsy;
+  const int tw = 1 << tsx, th = 1 << tsy;        // tiles are tw x th pixels
+  const int TX = (cam.w + tw - 1) >> tsx, TY = (cam.h + th - 1) >> tsy;
   const int lx0 = i0 - cam.x0, lx1 = i1 - cam.x0, ly0 = j0 - cam.y0, ly1 = j1 - cam.y0;
-  const int cx0 = (lx0 + 15) >> 4, cy0 = (ly0 + th - 1) >> tsy;
-  const int cx1 = (lx1 >= cam.w - 1) ? TX - 1 : ((lx1 + 1) >> 4) - 1;
+  const int cx0 = (lx0 + tw - 1) >> tsx, cy0 = (ly0 + th - 1) >> tsy;
+  const int cx1 = (lx1 >= cam.w - 1) ? TX - 1 : ((lx1 + 1) >> tsx) - 1;
   const int cy1 = (ly1 >= cam.h - 1) ? TY - 1 : ((ly1 + 1) >> tsy) - 1;
   if (cx0 > cx1 || cy0 > cy1) return 0ull;
   const uint64_t w = (uint64_t)(-logf(1.0f - 0.5f * P.o) * (65536.0f * 0.999f));
@@ -62,7 +62,7 @@ __global__ void __launch_bounds__(256) project_kernel(const Seg* __restrict__ se
   const int64_t lid = i - sg.g_off;
   const DevCam cam = cams[sg.cam];
   const Projected P = project_one(sg.pos + 3 * lid, sg.rot + 4 * lid, sg.ls + 3 * lid,
-                                  sg.logit[lid], cam, sg.tsy);
+                                  sg.logit[lid], cam, sg.tsx, sg.tsy);
   const float* c = sg.rgb + 3 * lid;
   SplatRec r;
   r.q0 = make_float4(P.u, P.v, P.A, P.B);
@@ -77,7 +77,7 @@ __global__ void __launch_bounds__(256) project_kernel(const Seg* __restrict__ se
                     : kEmptyRect;
   tiles[i] = P.tiles;
   ids[i] = (uint32_t)lid;
-  if (core) core[i] = saturation_core(P, cam, sg.tsy);
+  if (core) core[i] = saturation_core(P, cam, sg.tsx, sg.tsy);
 }
 
 // Adjoint of the projection.  grad2d is SoA [9][G]: du, dv, dA, dB, dCc, do, dr, dg, db
@@ -94,7 +94,7 @@ __device__ __forceinline__ void project_grads(const Seg& sg, const DevCam& cam, 
   const float* rot = sg.rot + 4 * lid;
   const float* ls = sg.ls + 3 * lid;
   const float logit = sg.logit[lid];
-  const Projected P = project_one(pos, rot, ls, logit, cam, sg.tsy);
+  const Projected P = project_one(pos, rot, ls, logit, cam, sg.tsx, sg.tsy);
   // Opacity: o = sigmoid(logit).
   *gl = go * (P.o * (1.0f - P.o));
   if (P.tiles == 0u) {

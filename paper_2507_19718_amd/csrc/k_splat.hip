@@ -47,22 +47,23 @@ struct Tile {
   __device__ int64_t pix(int p) const { return (int64_t)(py0 + 4 * p) * cw + px; }
 };
 
-// A wavefront covers the 16 x 4 kS block `part` (0 .. kH - 1, top to bottom) of tile t, whose
-// height is 4 kS kH pixels; the block's rectangle is what may_touch tests.
-template <int kS, int kH = 1>
+// A wavefront covers the 16 x 4 kS block `part` (kW across, kH down, row-major) of tile t, a
+// tile of 16 kW x 4 kS kH pixels; the block's rectangle is what may_touch tests.
+template <int kS, int kW = 1, int kH = 1>
 __device__ __forceinline__ Tile<kS> tile_setup(const Seg* __restrict__ segs,
                                                const int64_t* __restrict__ seg_tstart, int S,
                                                const DevCam* __restrict__ cams,
                                                const uint64_t* __restrict__ ranges, int64_t t,
                                                int part = 0) {
-  static_assert(kS * kH == 4 || kS * kH == 8, "16x16 or 16x32 tiles");
+  static_assert(kS == 4 || kS == 8, "four or eight slots per lane");
   const int s = find_segment(seg_tstart, S, t);
   const Seg& sg = segs[s];
   const DevCam& cam = cams[sg.cam];
   const int64_t lt = t - sg.tile_base;
   const int tx = (int)(lt % sg.TX), ty = (int)(lt / sg.TX);
   const int lane = __lane_id();
-  const int ox = tx * 16, oy = ty * (4 * kS * kH) + part * (4 * kS);
+  const int ox = tx * (16 * kW) + 16 * (part % kW);
+  const int oy = ty * (4 * kS * kH) + (4 * kS) * (part / kW);
   Tile<kS> c;
   c.start = (int64_t)ranges[2 * t];
   c.end = (int64_t)ranges[2 * t + 1];
@@ -157,8 +158,9 @@ __device__ __forceinline__ bool lane_in(uint64_t mask) {
 enum { kStEval = 0, kStBlend, kStContrib, kStEntries, kStFwdTested, kStFwdSlots, kStBwdTested,
        kStBwdBlend, kStBwdSlots, kStBwdEntries, kStBwdAtomics, kStWords };
 
-// Workgroup b takes block b % kH of tile order[b / kH] (kH wavefronts per tile, independent).
-template <bool kCount, int kS, int kH>
+// Workgroup b takes block b % (kW kH) of tile order[b / (kW kH)] (one independent wavefront
+// per block).
+template <bool kCount, int kS, int kW, int kH>
 __global__ void __launch_bounds__(64) splat_forward_kernel(
     const Seg* __restrict__ segs, const int64_t* __restrict__ seg_tstart, int S,
     const DevCam* __restrict__ cams, const uint64_t* __restrict__ ranges,
@@ -166,10 +168,10 @@ __global__ void __launch_bounds__(64) splat_forward_kernel(
     float* __restrict__ images, float* __restrict__ final_T, int32_t* __restrict__ last_id,
     uint32_t* __restrict__ n_contrib, unsigned long long* __restrict__ stats,
     const uint32_t* __restrict__ order, uint32_t* __restrict__ tile_work) {
-  const int64_t b = (int64_t)blockIdx.x / kH;
+  const int64_t b = (int64_t)blockIdx.x / (kW * kH);
   const int64_t t = order ? (int64_t)order[b] : b;
-  const Tile<kS> tc = tile_setup<kS, kH>(segs, seg_tstart, S, cams, ranges, t,
-                                          (int)(blockIdx.x % kH));
+  const Tile<kS> tc = tile_setup<kS, kW, kH>(segs, seg_tstart, S, cams, ranges, t,
+                                              (int)(blockIdx.x % (kW * kH)));
   const int lane = __lane_id();
   float T[kS], C0[kS], C1[kS], C2[kS];
   uint32_t nc[kS], stop[kS];
@@ -246,10 +248,10 @@ __global__ void __launch_bounds__(64) splat_forward_kernel(
       }
     }
   }
-  // The tile's work estimate for the adjoint's schedule (with kH > 1 summed over its blocks
+  // The tile's work estimate for the adjoint's schedule (with several blocks per tile summed
   // into a zeroed array).
   if (tile_work && lane == 0) {
-    if (kH == 1) tile_work[t] = n_entries;
+    if (kW * kH == 1) tile_work[t] = n_entries;
     else atomicAdd(&tile_work[t], n_entries);
   }
   uint64_t ev = 0, ncs = 0;
@@ -318,7 +320,9 @@ __device__ __forceinline__ float row_total(float v) {
   return t;
 }
 
-template <bool kCount, int kS>
+// Workgroup b walks block b % kW (16 x 4 kS, the tile's blocks side by side) of tile
+// order[b / kW], one independent wavefront per block.
+template <bool kCount, int kS, int kW>
 __global__ void __launch_bounds__(64) splat_backward_kernel(
     const Seg* __restrict__ segs, const int64_t* __restrict__ seg_tstart, int S,
     const DevCam* __restrict__ cams, const uint64_t* __restrict__ ranges,
@@ -328,8 +332,10 @@ __global__ void __launch_bounds__(64) splat_backward_kernel(
     const uint32_t* __restrict__ order, int mode, uint32_t* __restrict__ gmax,
     unsigned long long* __restrict__ gfix, unsigned long long* __restrict__ stats) {
   __shared__ float part[4][64][kPartStride];    // [row group][entry][component]
-  const int64_t t = order ? (int64_t)order[blockIdx.x] : (int64_t)blockIdx.x;
-  const Tile<kS> tc = tile_setup<kS>(segs, seg_tstart, S, cams, ranges, t);
+  const int64_t b = (int64_t)blockIdx.x / kW;
+  const int64_t t = order ? (int64_t)order[b] : b;
+  const Tile<kS> tc = tile_setup<kS, kW, 1>(segs, seg_tstart, S, cams, ranges, t,
+                                             (int)(blockIdx.x % kW));
   const int lane = __lane_id();
   // BG: the colour blended behind the current Gaussian (from the entries already walked), dotted
   // with the pixel's image gradient g; it is all the adjoint needs of that colour.
@@ -532,48 +538,48 @@ __global__ void __launch_bounds__(kOrderThreads) tile_order_kernel(const uint64_
     order[atomicAdd(&cnt[bucket(t)], 1u)] = (uint32_t)t;
 }
 
-template <int kS, int kH>
+template <int kS, int kW, int kH>
 void splat_forward_dispatch(hipStream_t st, const Seg* segs, const int64_t* seg_tstart, int S,
                             const DevCam* cams, int64_t n_tiles, const uint64_t* ranges,
                             const uint32_t* values, const SplatRec* rec, float* images,
                             float* final_T, int32_t* last_id, uint32_t* n_contrib,
                             unsigned long long* stats, const uint32_t* order, uint32_t* tile_work,
                             bool count) {
-  const dim3 grid((unsigned)(n_tiles * kH)), block(64);
+  const dim3 grid((unsigned)(n_tiles * kW * kH)), block(64);
   if (count && stats)
-    hipLaunchKernelGGL((splat_forward_kernel<true, kS, kH>), grid, block, 0, st, segs, seg_tstart,
-                       S, cams, ranges, values, rec, images, final_T, last_id, n_contrib, stats,
-                       order, tile_work);
+    hipLaunchKernelGGL((splat_forward_kernel<true, kS, kW, kH>), grid, block, 0, st, segs,
+                       seg_tstart, S, cams, ranges, values, rec, images, final_T, last_id,
+                       n_contrib, stats, order, tile_work);
   else
-    hipLaunchKernelGGL((splat_forward_kernel<false, kS, kH>), grid, block, 0, st, segs, seg_tstart,
-                       S, cams, ranges, values, rec, images, final_T, last_id, n_contrib, stats,
-                       order, tile_work);
+    hipLaunchKernelGGL((splat_forward_kernel<false, kS, kW, kH>), grid, block, 0, st, segs,
+                       seg_tstart, S, cams, ranges, values, rec, images, final_T, last_id,
+                       n_contrib, stats, order, tile_work);
 }
 
-template <int kS>
+template <int kS, int kW>
 void splat_backward_dispatch(hipStream_t st, const Seg* segs, const int64_t* seg_tstart, int S,
                              const DevCam* cams, int64_t n_tiles, const uint64_t* ranges,
                              const uint32_t* values, const SplatRec* rec, const float* final_T,
                              const uint32_t* n_contrib, const float* dL_dimages, float* grad2d,
                              int64_t G, const uint32_t* order, uint32_t* gmax,
                              unsigned long long* gfix, unsigned long long* stats, bool count) {
-  const dim3 grid((unsigned)n_tiles), block(64);
+  const dim3 grid((unsigned)(n_tiles * kW)), block(64);
   if (!gmax) {
     if (count && stats)
-      hipLaunchKernelGGL((splat_backward_kernel<true, kS>), grid, block, 0, st, segs, seg_tstart, S,
-                         cams, ranges, values, rec, final_T, n_contrib, dL_dimages, grad2d, G,
+      hipLaunchKernelGGL((splat_backward_kernel<true, kS, kW>), grid, block, 0, st, segs, seg_tstart,
+                         S, cams, ranges, values, rec, final_T, n_contrib, dL_dimages, grad2d, G,
                          order, (int)kAdjointAtomic, gmax, gfix, stats);
     else
-      hipLaunchKernelGGL((splat_backward_kernel<false, kS>), grid, block, 0, st, segs, seg_tstart, S,
-                         cams, ranges, values, rec, final_T, n_contrib, dL_dimages, grad2d, G,
-                         order, (int)kAdjointAtomic, gmax, gfix, stats);
+      hipLaunchKernelGGL((splat_backward_kernel<false, kS, kW>), grid, block, 0, st, segs,
+                         seg_tstart, S, cams, ranges, values, rec, final_T, n_contrib, dL_dimages,
+                         grad2d, G, order, (int)kAdjointAtomic, gmax, gfix, stats);
     return;
   }
   // Deterministic: gmax [9][G] and gfix [9][G] must be zero on entry.
-  hipLaunchKernelGGL((splat_backward_kernel<false, kS>), grid, block, 0, st, segs, seg_tstart, S,
+  hipLaunchKernelGGL((splat_backward_kernel<false, kS, kW>), grid, block, 0, st, segs, seg_tstart, S,
                      cams, ranges, values, rec, final_T, n_contrib, dL_dimages, grad2d, G, order,
                      (int)kAdjointMax, gmax, gfix, stats);
-  hipLaunchKernelGGL((splat_backward_kernel<false, kS>), grid, block, 0, st, segs, seg_tstart, S,
+  hipLaunchKernelGGL((splat_backward_kernel<false, kS, kW>), grid, block, 0, st, segs, seg_tstart, S,
                      cams, ranges, values, rec, final_T, n_contrib, dL_dimages, grad2d, G, order,
                      (int)kAdjointFixed, gmax, gfix, stats);
   if (G > 0)
@@ -583,24 +589,24 @@ void splat_backward_dispatch(hipStream_t st, const Seg* segs, const int64_t* seg
 
 }  // namespace
 
-// tsy: log2 of the tile height (4: 16x16 tiles, 5: 16x32 tiles).
+// Tiles of 2^tsx x 2^tsy pixels: 16x16 (4, 4) or 32x32 (5, 5); any other shape is rejected.
 hipError_t launch_splat_forward(hipStream_t st, const Seg* segs, const int64_t* seg_tstart, int S,
                                 const DevCam* cams, int64_t n_tiles, const uint64_t* ranges,
                                 const uint32_t* values, const SplatRec* rec, float* images,
                                 float* final_T, int32_t* last_id, uint32_t* n_contrib,
                                 unsigned long long* stats, const uint32_t* order,
-                                uint32_t* tile_work, bool count, int tsy) {
+                                uint32_t* tile_work, bool count, int tsx, int tsy) {
   if (n_tiles == 0) return hipSuccess;
-  // 16x32 tiles: two independent wavefronts of four slots each (the forward keeps the
-  // occupancy of small register sets); tile_work must then be zero on entry.
-  if (tsy == 5)
-    splat_forward_dispatch<4, 2>(st, segs, seg_tstart, S, cams, n_tiles, ranges, values, rec,
-                                 images, final_T, last_id, n_contrib, stats, order, tile_work,
-                                 count);
+  if (tsx == 5 && tsy == 5)        // four independent 16x16 wavefronts per tile
+    splat_forward_dispatch<4, 2, 2>(st, segs, seg_tstart, S, cams, n_tiles, ranges, values, rec,
+                                    images, final_T, last_id, n_contrib, stats, order, tile_work,
+                                    count);
+  else if (tsx == 4 && tsy == 4)
+    splat_forward_dispatch<4, 1, 1>(st, segs, seg_tstart, S, cams, n_tiles, ranges, values, rec,
+                                    images, final_T, last_id, n_contrib, stats, order, tile_work,
+                                    count);
   else
-    splat_forward_dispatch<4, 1>(st, segs, seg_tstart, S, cams, n_tiles, ranges, values, rec,
-                                 images, final_T, last_id, n_contrib, stats, order, tile_work,
-                                 count);
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 
@@ -610,14 +616,18 @@ hipError_t launch_splat_backward(hipStream_t st, const Seg* segs, const int64_t*
                                  const uint32_t* n_contrib, const float* dL_dimages,
                                  float* grad2d, int64_t G, const uint32_t* order, uint32_t* gmax,
                                  unsigned long long* gfix, unsigned long long* stats, bool count,
-                                 int tsy) {
+                                 int tsx, int tsy) {
   if (n_tiles == 0) return hipSuccess;
-  if (tsy == 5)
-    splat_backward_dispatch<8>(st, segs, seg_tstart, S, cams, n_tiles, ranges, values, rec, final_T,
-                               n_contrib, dL_dimages, grad2d, G, order, gmax, gfix, stats, count);
+  if (tsx == 5 && tsy == 5)        // two independent 16x32 wavefronts of eight slots per tile
+    splat_backward_dispatch<8, 2>(st, segs, seg_tstart, S, cams, n_tiles, ranges, values, rec,
+                                  final_T, n_contrib, dL_dimages, grad2d, G, order, gmax, gfix,
+                                  stats, count);
+  else if (tsx == 4 && tsy == 4)
+    splat_backward_dispatch<4, 1>(st, segs, seg_tstart, S, cams, n_tiles, ranges, values, rec,
+                                  final_T, n_contrib, dL_dimages, grad2d, G, order, gmax, gfix,
+                                  stats, count);
   else
-    splat_backward_dispatch<4>(st, segs, seg_tstart, S, cams, n_tiles, ranges, values, rec, final_T,
-                               n_contrib, dL_dimages, grad2d, G, order, gmax, gfix, stats, count);
+    return hipErrorInvalidValue;
   return hipGetLastError();
 }
 

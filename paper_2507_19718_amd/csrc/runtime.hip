@@ -93,7 +93,7 @@ struct gsc_binning {
   bool forward_done = false;
   int K = 0;
   int TX = 0, TY = 0;
-  int tsy = kTileShift;         // log2 tile height: 16x16 tiles (gsc_project_bin), 16x32 (frames)
+  int tsx = kTileShift, tsy = kTileShift;   // log2 tile size: 16x16 (gsc_project_bin), 32x32 (frames)
   // views
   DevBuf view_window, view_screen;
 
@@ -353,9 +353,10 @@ struct ReqSpec {
 };
 
 // Builds (or rebuilds) a binning object's tables for a list of requests and uploads them.
-void plan_batch(gsc_ctx* ctx, gsc_binning* b, const std::vector<ReqSpec>& reqs, int tsy) {
+void plan_batch(gsc_ctx* ctx, gsc_binning* b, const std::vector<ReqSpec>& reqs, int tsx, int tsy) {
+  b->tsx = tsx;
   b->tsy = tsy;
-  const int th = 1 << tsy;                 // tiles are 16 x th pixels
+  const int tw = 1 << tsx, th = 1 << tsy;  // tiles are tw x th pixels
   b->segs.clear();
   b->cams.clear();
   b->seg_gstart.clear();
@@ -364,7 +365,7 @@ void plan_batch(gsc_ctx* ctx, gsc_binning* b, const std::vector<ReqSpec>& reqs, 
   for (size_t r = 0; r < reqs.size(); ++r) {
     const gsc_camera& c = reqs[r].cam;
     b->cams.push_back(to_dev(c));
-    const int TX = (c.w + kTile - 1) / kTile, TY = (c.h + th - 1) / th;
+    const int TX = (c.w + tw - 1) / tw, TY = (c.h + th - 1) / th;
     for (size_t l = 0; l < reqs[r].levels.size(); ++l) {
       const gsc_gaussians& lv = reqs[r].levels[l];
       Seg s{};
@@ -377,6 +378,7 @@ void plan_batch(gsc_ctx* ctx, gsc_binning* b, const std::vector<ReqSpec>& reqs, 
       s.TX = TX; s.TY = TY;
       s.level = (int32_t)l;
       s.request = (int32_t)r;
+      s.tsx = tsx;
       s.tsy = tsy;
       s.n_chunks = (int32_t)((lv.n + kChunk - 1) / kChunk);
       b->segs.push_back(s);
@@ -542,14 +544,14 @@ void run_forward(gsc_ctx* ctx, gsc_binning* b, float* images, float* final_T, in
     GSC_TRY(hipMemsetAsync(ctx->d_stats.p, 0, kStatWords * 8, ctx->stream));
   }
   const uint32_t* order = tile_order(ctx, b, nullptr);
-  if (b->tsy != kTileShift)     // taller tiles: the forward sums its blocks' work per tile
+  if (b->tsx != kTileShift || b->tsy != kTileShift)   // larger tiles: the forward sums its blocks' work
     GSC_TRY(launch_fill_u32(ctx->stream, b->tile_work.as<uint32_t>(), 0u, b->n_tiles));
   { ProfScope ps_(ctx, P_FWD, ctx->stream);
   GSC_TRY(launch_splat_forward(ctx->stream, b->d_segs(), b->d_tstart(), b->S, b->d_cams(), b->n_tiles,
                                b->ranges.as<uint64_t>(), b->values.as<uint32_t>(),
                                b->rec.as<SplatRec>(), images, final_T, last_id,
                                b->n_contrib.as<uint32_t>(), ctx->d_stats.as<unsigned long long>(),
-                               order, b->tile_work.as<uint32_t>(), ctx->work_counters, b->tsy));
+                               order, b->tile_work.as<uint32_t>(), ctx->work_counters, b->tsx, b->tsy));
   }
   b->forward_done = true;
 }
@@ -578,7 +580,7 @@ void run_splat_adjoint(gsc_ctx* ctx, gsc_binning* b, const float* final_T, const
                                 b->rec.as<SplatRec>(), final_T, b->n_contrib.as<uint32_t>(), dL,
                                 b->grad2d.as<float>(), b->G, order, gmax, gfix,
                                 ctx->d_stats.as<unsigned long long>(), ctx->work_counters,
-                                b->tsy));
+                                b->tsx, b->tsy));
   }
 }
 
@@ -742,7 +744,7 @@ gsc_status render_batch(gsc_ctx* ctx, gsc_scene* const* scenes, const gsc_frame_
     pix += (int64_t)sc->K * reqs[i].cam.w * reqs[i].cam.h;
     rpix += (int64_t)reqs[i].trace.spp * reqs[i].cam.w * reqs[i].cam.h;
   }
-  plan_batch(ctx, b, specs, kFrameTileShift);
+  plan_batch(ctx, b, specs, kFrameTileShiftX, kFrameTileShiftY);
   const Alloc& a = ctx->alloc;
   need(ctx, ctx->images, a, 12 * (size_t)pix, "cache images");
   need(ctx, ctx->targets, a, 12 * (size_t)pix, "targets");
@@ -1178,7 +1180,7 @@ gsc_status gsc_project_bin(gsc_ctx* ctx, const gsc_gaussians* levels, int32_t nu
     b->TY = (cam->h + kTile - 1) / kTile;
     gsc_status s;
     try {
-      plan_batch(ctx, b, specs, kTileShift);
+      plan_batch(ctx, b, specs, kTileShift, kTileShift);
       s = run_project_bin(ctx, b, capacity_hint);
     } catch (...) {
       b->free_all();
@@ -1352,7 +1354,7 @@ gsc_status gsc_splat_backward_noalloc(gsc_ctx* ctx, const gsc_binning* bin,
                                   b->ranges.as<uint64_t>(), b->values.as<uint32_t>(),
                                   b->rec.as<SplatRec>(), final_T, b->n_contrib.as<uint32_t>(),
                                   dL_dimages, g2d, G, order, nullptr, nullptr, nullptr, false,
-                                  b->tsy));
+                                  b->tsx, b->tsy));
     GSC_TRY(launch_project_backward(st, b->d_segs(), b->d_gstart(), b->S, b->d_cams(), G, g2d, g14));
     copy_out_grads(ctx, b, levels, num_levels, g14, grads);
     return GSC_OK;
@@ -1623,8 +1625,8 @@ size_t gsc_frame_footprint_bytes(const gsc_scene* sc, int32_t w, int32_t h, uint
   for (int l = 0; l < sc->K; ++l) G += sc->n[l];
   const size_t P = (size_t)w * h;
   const size_t K = (size_t)sc->K;
-  const int th = 1 << kFrameTileShift;                             // frames bin 16 x 32 tiles
-  const size_t tiles = K * (size_t)((w + 15) / 16) * ((h + th - 1) / th);
+  const int tw = 1 << kFrameTileShiftX, th = 1 << kFrameTileShiftY;   // frame tiles
+  const size_t tiles = K * (size_t)((w + tw - 1) / tw) * ((h + th - 1) / th);
   size_t b = 0;
   b += (size_t)G * (48 + 4 + 8 + 4 + 4 * 4 + 8 + 9 * 4 + 14 * 4);   // per-Gaussian buffers
   b += 4 * (size_t)instance_estimate;                              // instance ids
