@@ -246,8 +246,15 @@ gsc_status gsc_ctx_set_deterministic(gsc_ctx* ctx, int32_t on);
  * splat gives alpha >= o/2 over all pixels of a tile multiplies their transmittance by at most
  * 1 - o/2, and once these factors reach 0.5e-4 no later entry can be blended (blending stops
  * below 1e-4), so the cut lists give the same images, gradients and parameter updates as the
- * full ones with fewer instances.  gsc_project_bin always builds full lists. */
+ * full ones with fewer instances.  gsc_project_bin builds full lists unless
+ * gsc_ctx_set_frame_binning is on. */
 gsc_status gsc_ctx_set_list_cut(gsc_ctx* ctx, int32_t on);
+/* on != 0: gsc_project_bin bins the way the frame calls do: 32x32-pixel tiles (the views then
+ * report tiles of that size and the keys carry those tile indices) and, when the list cut is
+ * on, cut tile lists.  The splat forward and adjoint results do not depend on the tiling, so
+ * this is how the frames' binning and kernels are compared with the oracle at full size.
+ * Default off: 16x16 tiles, full lists (the binning the oracle's keys and ranges follow). */
+gsc_status gsc_ctx_set_frame_binning(gsc_ctx* ctx, int32_t on);
 /* After GSC_E_CAPACITY: the instance count the failed call needed. */
 uint64_t gsc_ctx_required_capacity(const gsc_ctx* ctx);
 /* Per-kernel timing: while on, every kernel launch of the context is bracketed by HIP events

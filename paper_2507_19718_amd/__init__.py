@@ -153,6 +153,10 @@ class Context:
         """Frames bin only the list prefixes that can reach a pixel (default on)."""
         self.check(self._lib.gsc_ctx_set_list_cut(self.handle, 1 if on else 0))
 
+    def set_frame_binning(self, on: bool):
+        """gsc_project_bin bins like the frames (32x32 tiles, list cut) (default off)."""
+        self.check(self._lib.gsc_ctx_set_frame_binning(self.handle, 1 if on else 0))
+
     def set_deterministic(self, on: bool):
         """Sum the splat adjoint in fixed point so gradients repeat bit for bit (default off)."""
         self.check(self._lib.gsc_ctx_set_deterministic(self.handle, 1 if on else 0))

@@ -139,6 +139,7 @@ struct gsc_ctx {
   uint64_t required = 0;
   int deterministic = 0;
   int list_cut = 1;                // frames bin only the list prefixes that can reach a pixel
+  int frame_binning = 0;           // gsc_project_bin bins like the frames (32x32 tiles, list cut)
   // pinned staging ring for descriptor uploads
   char* pinned = nullptr;
   size_t pinned_cap = 0, pinned_head = 0;
@@ -1092,6 +1093,12 @@ gsc_status gsc_ctx_set_work_counters(gsc_ctx* ctx, int32_t on) {
   return GSC_OK;
 }
 
+gsc_status gsc_ctx_set_frame_binning(gsc_ctx* ctx, int32_t on) {
+  if (!ctx) return GSC_E_INVALID_ARG;
+  ctx->frame_binning = on != 0;
+  return GSC_OK;
+}
+
 gsc_status gsc_ctx_set_list_cut(gsc_ctx* ctx, int32_t on) {
   if (!ctx) return GSC_E_INVALID_ARG;
   ctx->list_cut = on ? 1 : 0;
@@ -1176,11 +1183,14 @@ gsc_status gsc_project_bin(gsc_ctx* ctx, const gsc_gaussians* levels, int32_t nu
     specs[0].cam = *cam;
     specs[0].levels.assign(levels, levels + num_levels);
     b->K = num_levels;
-    b->TX = (cam->w + kTile - 1) / kTile;
-    b->TY = (cam->h + kTile - 1) / kTile;
+    const bool fb = ctx->frame_binning != 0;
+    const int tsx = fb ? kFrameTileShiftX : kTileShift, tsy = fb ? kFrameTileShiftY : kTileShift;
+    b->TX = (cam->w + (1 << tsx) - 1) >> tsx;
+    b->TY = (cam->h + (1 << tsy) - 1) >> tsy;
+    b->list_cut = fb && ctx->list_cut != 0;
     gsc_status s;
     try {
-      plan_batch(ctx, b, specs, kTileShift, kTileShift);
+      plan_batch(ctx, b, specs, tsx, tsy);
       s = run_project_bin(ctx, b, capacity_hint);
     } catch (...) {
       b->free_all();

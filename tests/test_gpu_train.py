@@ -200,3 +200,43 @@ def test_render_frame_with_an_empty_level(gsc, gctx):
         assert st["step"] == 3
         assert not np.array_equal(to_np(st["params"]), before[i])
     assert np.isfinite(to_np(image)).all()
+
+
+def test_render_frame_three_levels_hdr_paper_rates(gsc, gctx):
+    """The benchmark's training configuration on the small scene: three levels, B = 3, the HDR
+    loss (Eq. 4), the paper's per-group learning rates (scale rate 0) with the Eq. 5 schedule,
+    AdamW weight decay 1e-2 and the frames' binning (32x32 tiles, list cut); two frames, each
+    against the oracle pipeline started from the GPU's state."""
+    wl = synth.workload("tiny", levels=[4096, 2048, 1024], max_bounces=3, loss=1,
+                        lr=synth.P360_LR, weight_decay=1e-2)
+    vol = wl.volume()
+    cam = wl.camera()
+    levels_np = wl.gaussians()
+    K = wl.K
+    scene = gsc.Scene(gctx, gsc.Volume.from_synth(vol), [gsc.level_to_device(g) for g in levels_np])
+    image = torch.empty((cam.h, cam.w, 3), device="cuda")
+    for frame in range(2):
+        state = []
+        for l in range(K):
+            s = scene.state(l)
+            state.append(dict(params=to_np(s["params"]), m=to_np(s["m"]), v=to_np(s["v"]), step=s["step"]))
+        cur = [unpack(state[l]["params"], levels_np[l].n) for l in range(K)]
+        req = gsc.frame_request(cam, wl.seed, frame, K, wl.max_bounces, loss=wl.loss, lr=wl.lr,
+                                weight_decay=wl.weight_decay, C=wl.C, viewport_frames=frame + 1)
+        stats = gsc.gsc_render_frame(gctx, scene, req, image, stats=True)
+        ref = oracle_frame(state, cur, vol, cam, wl, frame, K, wl.loss, wl.lr, wl.weight_decay,
+                           frame + 1)
+        assert abs(stats["loss"] - ref["loss"]) <= 1e-4 * abs(ref["loss"]), (frame, stats["loss"], ref["loss"])
+        okpix = ~ref["boundary"].any(0)
+        assert rel_l2(to_np(image)[okpix], ref["composite"][okpix]) <= 1e-5
+        for l in range(K):
+            s = scene.state(l)
+            rl = ref["levels"][l]
+            assert rl["boundary_gaussians"].mean() <= 0.5, rl["boundary_gaussians"].mean()
+            good, info = adamw_params_close(to_np(s["params"]), rl["params"], state[l]["params"],
+                                            rl["grads"], state[l]["m"], state[l]["v"], state[l]["step"] + 1,
+                                            wl.lr, levels_np[l].n,
+                                            exclude=frame_exclusions(rl["boundary_gaussians"],
+                                                                     cur[l].log_scale))
+            assert good, (frame, l, info)
+            assert s["step"] == frame + 1
