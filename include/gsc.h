@@ -289,6 +289,8 @@ typedef struct gsc_counters {
   uint64_t bwd_slots;      /* adjoint: 64-pixel slot evaluations */
   uint64_t bwd_entries;    /* adjoint: (tile, entry) pairs walked after the tile-ellipse cull */
   uint64_t bwd_atomics;    /* adjoint: float atomics issued into the screen-space gradients */
+  uint64_t frame_retries;  /* frames run again because their binning outgrew the capacity sized
+                              from the previous frame (see gsc_render_frame) */
 } gsc_counters;
 /* Fills *out; synchronises the context's stream.  GSC_E_INVALID_ARG for NULL. */
 gsc_status gsc_ctx_counters(gsc_ctx* ctx, gsc_counters* out);
@@ -490,7 +492,14 @@ size_t gsc_frame_footprint_bytes(const gsc_scene* scene, int32_t w, int32_t h,
  * space, one launch per stage), trace the targets on a second stream meanwhile, then the
  * loss, the cached composite into `image` ([h][w][3]), and -- when req->train -- the splat
  * backward and one AdamW step per parameter group with lr x 1/(1 + ln t) (Eq. 5).  A
- * non-finite loss skips the step.  stats: HOST or NULL (non-NULL synchronises). */
+ * non-finite loss skips the step.  stats: HOST or NULL (non-NULL synchronises).
+ * Sizing: a context's first frame reads its instance count back before placing; later frames
+ * size the tile lists from the previous frame's count plus a quarter, enqueue the whole frame,
+ * and then wait only for the placement's count to reach the host (no stream synchronisation;
+ * the device has the rest of the frame queued).  If the lists did not fit, the splats and the
+ * AdamW step skip themselves on the device and the call runs the frame again with room for
+ * the count (counted in gsc_counters.frame_retries); results equal those of a frame sized
+ * exactly. */
 gsc_status gsc_render_frame(gsc_ctx* ctx, gsc_scene* scene, const gsc_frame_request* req,
                             float* image, gsc_frame_stats* stats);
 

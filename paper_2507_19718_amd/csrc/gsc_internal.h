@@ -164,7 +164,8 @@ hipError_t launch_splat_forward(hipStream_t st, const Seg* segs, const int64_t* 
                                 const uint32_t* values, const SplatRec* rec, float* images,
                                 float* final_T, int32_t* last_id, uint32_t* n_contrib,
                                 unsigned long long* stats, const uint32_t* order,
-                                uint32_t* tile_work, bool count, int tsx, int tsy);
+                                uint32_t* tile_work, bool count, int tsx, int tsy,
+                                const uint64_t* n_inst, uint64_t capacity);
 // Keys ordering tiles by decreasing work (work NULL: list length from ranges).
 hipError_t launch_tile_order(hipStream_t st, const uint64_t* ranges, const uint32_t* work,
                              int64_t n_tiles, uint32_t* order);
@@ -176,7 +177,7 @@ hipError_t launch_splat_backward(hipStream_t st, const Seg* segs, const int64_t*
                                  const uint32_t* n_contrib, const float* dL_dimages,
                                  float* grad2d, int64_t G, const uint32_t* order, uint32_t* gmax,
                                  unsigned long long* gfix, unsigned long long* stats, bool count,
-                                 int tsx, int tsy);
+                                 int tsx, int tsy, const uint64_t* n_inst, uint64_t capacity);
 
 int64_t trace_align(int64_t pixels);
 hipError_t launch_trace(hipStream_t st, const TraceDesc* descs, const int64_t* req_pstart, int R,
@@ -207,6 +208,9 @@ struct AdamGroup {
 hipError_t launch_adam_factors(hipStream_t st, AdamGroup* groups, int n_groups);
 // Advances the step count of each segment's level (groups[5 s]) whose update ran.
 hipError_t launch_adam_commit(hipStream_t st, const AdamGroup* groups, int S);
+// losses[0 .. n) = NaN when *n_inst > capacity, so the AdamW step that follows is skipped.
+hipError_t launch_capacity_guard(hipStream_t st, const uint64_t* n_inst, uint64_t capacity,
+                                 float* losses, int n);
 hipError_t launch_adam(hipStream_t st, float* param, float* m, float* v, const float* grad,
                        int64_t count, float b1, float b2, float omb1, float omb2, float s1,
                        float s2, float wdf, float eps, const float* guard);

@@ -167,7 +167,11 @@ __global__ void __launch_bounds__(64) splat_forward_kernel(
     const uint32_t* __restrict__ values, const SplatRec* __restrict__ rec,
     float* __restrict__ images, float* __restrict__ final_T, int32_t* __restrict__ last_id,
     uint32_t* __restrict__ n_contrib, unsigned long long* __restrict__ stats,
-    const uint32_t* __restrict__ order, uint32_t* __restrict__ tile_work) {
+    const uint32_t* __restrict__ order, uint32_t* __restrict__ tile_work,
+    const uint64_t* __restrict__ n_inst, uint64_t capacity) {
+  // A binning whose instances did not fit its capacity left incomplete lists: do nothing (the
+  // frame is run again with a larger capacity).
+  if (*n_inst > capacity) return;
   const int64_t b = (int64_t)blockIdx.x / (kW * kH);
   const int64_t t = order ? (int64_t)order[b] : b;
   const Tile<kS> tc = tile_setup<kS, kW, kH>(segs, seg_tstart, S, cams, ranges, t,
@@ -330,7 +334,9 @@ __global__ void __launch_bounds__(64) splat_backward_kernel(
     const float* __restrict__ final_T, const uint32_t* __restrict__ n_contrib,
     const float* __restrict__ dL_dimages, float* __restrict__ grad2d, int64_t G,
     const uint32_t* __restrict__ order, int mode, uint32_t* __restrict__ gmax,
-    unsigned long long* __restrict__ gfix, unsigned long long* __restrict__ stats) {
+    unsigned long long* __restrict__ gfix, unsigned long long* __restrict__ stats,
+    const uint64_t* __restrict__ n_inst, uint64_t capacity) {
+  if (*n_inst > capacity) return;               // incomplete lists (see the forward)
   __shared__ float part[4][64][kPartStride];    // [row group][entry][component]
   const int64_t b = (int64_t)blockIdx.x / kW;
   const int64_t t = order ? (int64_t)order[b] : b;
@@ -544,16 +550,16 @@ void splat_forward_dispatch(hipStream_t st, const Seg* segs, const int64_t* seg_
                             const uint32_t* values, const SplatRec* rec, float* images,
                             float* final_T, int32_t* last_id, uint32_t* n_contrib,
                             unsigned long long* stats, const uint32_t* order, uint32_t* tile_work,
-                            bool count) {
+                            bool count, const uint64_t* n_inst, uint64_t capacity) {
   const dim3 grid((unsigned)(n_tiles * kW * kH)), block(64);
   if (count && stats)
     hipLaunchKernelGGL((splat_forward_kernel<true, kS, kW, kH>), grid, block, 0, st, segs,
                        seg_tstart, S, cams, ranges, values, rec, images, final_T, last_id,
-                       n_contrib, stats, order, tile_work);
+                       n_contrib, stats, order, tile_work, n_inst, capacity);
   else
     hipLaunchKernelGGL((splat_forward_kernel<false, kS, kW, kH>), grid, block, 0, st, segs,
                        seg_tstart, S, cams, ranges, values, rec, images, final_T, last_id,
-                       n_contrib, stats, order, tile_work);
+                       n_contrib, stats, order, tile_work, n_inst, capacity);
 }
 
 template <int kS, int kW>
@@ -562,26 +568,27 @@ void splat_backward_dispatch(hipStream_t st, const Seg* segs, const int64_t* seg
                              const uint32_t* values, const SplatRec* rec, const float* final_T,
                              const uint32_t* n_contrib, const float* dL_dimages, float* grad2d,
                              int64_t G, const uint32_t* order, uint32_t* gmax,
-                             unsigned long long* gfix, unsigned long long* stats, bool count) {
+                             unsigned long long* gfix, unsigned long long* stats, bool count,
+                             const uint64_t* n_inst, uint64_t capacity) {
   const dim3 grid((unsigned)(n_tiles * kW)), block(64);
   if (!gmax) {
     if (count && stats)
       hipLaunchKernelGGL((splat_backward_kernel<true, kS, kW>), grid, block, 0, st, segs, seg_tstart,
                          S, cams, ranges, values, rec, final_T, n_contrib, dL_dimages, grad2d, G,
-                         order, (int)kAdjointAtomic, gmax, gfix, stats);
+                         order, (int)kAdjointAtomic, gmax, gfix, stats, n_inst, capacity);
     else
       hipLaunchKernelGGL((splat_backward_kernel<false, kS, kW>), grid, block, 0, st, segs,
                          seg_tstart, S, cams, ranges, values, rec, final_T, n_contrib, dL_dimages,
-                         grad2d, G, order, (int)kAdjointAtomic, gmax, gfix, stats);
+                         grad2d, G, order, (int)kAdjointAtomic, gmax, gfix, stats, n_inst, capacity);
     return;
   }
   // Deterministic: gmax [9][G] and gfix [9][G] must be zero on entry.
   hipLaunchKernelGGL((splat_backward_kernel<false, kS, kW>), grid, block, 0, st, segs, seg_tstart, S,
                      cams, ranges, values, rec, final_T, n_contrib, dL_dimages, grad2d, G, order,
-                     (int)kAdjointMax, gmax, gfix, stats);
+                     (int)kAdjointMax, gmax, gfix, stats, n_inst, capacity);
   hipLaunchKernelGGL((splat_backward_kernel<false, kS, kW>), grid, block, 0, st, segs, seg_tstart, S,
                      cams, ranges, values, rec, final_T, n_contrib, dL_dimages, grad2d, G, order,
-                     (int)kAdjointFixed, gmax, gfix, stats);
+                     (int)kAdjointFixed, gmax, gfix, stats, n_inst, capacity);
   if (G > 0)
     hipLaunchKernelGGL(fixed_to_float_kernel, dim3((unsigned)((9 * G + 255) / 256)), dim3(256), 0,
                        st, gmax, gfix, G, grad2d);
@@ -595,16 +602,17 @@ hipError_t launch_splat_forward(hipStream_t st, const Seg* segs, const int64_t* 
                                 const uint32_t* values, const SplatRec* rec, float* images,
                                 float* final_T, int32_t* last_id, uint32_t* n_contrib,
                                 unsigned long long* stats, const uint32_t* order,
-                                uint32_t* tile_work, bool count, int tsx, int tsy) {
+                                uint32_t* tile_work, bool count, int tsx, int tsy,
+                                const uint64_t* n_inst, uint64_t capacity) {
   if (n_tiles == 0) return hipSuccess;
   if (tsx == 5 && tsy == 5)        // four independent 16x16 wavefronts per tile
     splat_forward_dispatch<4, 2, 2>(st, segs, seg_tstart, S, cams, n_tiles, ranges, values, rec,
                                     images, final_T, last_id, n_contrib, stats, order, tile_work,
-                                    count);
+                                    count, n_inst, capacity);
   else if (tsx == 4 && tsy == 4)
     splat_forward_dispatch<4, 1, 1>(st, segs, seg_tstart, S, cams, n_tiles, ranges, values, rec,
                                     images, final_T, last_id, n_contrib, stats, order, tile_work,
-                                    count);
+                                    count, n_inst, capacity);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();
@@ -616,16 +624,16 @@ hipError_t launch_splat_backward(hipStream_t st, const Seg* segs, const int64_t*
                                  const uint32_t* n_contrib, const float* dL_dimages,
                                  float* grad2d, int64_t G, const uint32_t* order, uint32_t* gmax,
                                  unsigned long long* gfix, unsigned long long* stats, bool count,
-                                 int tsx, int tsy) {
+                                 int tsx, int tsy, const uint64_t* n_inst, uint64_t capacity) {
   if (n_tiles == 0) return hipSuccess;
   if (tsx == 5 && tsy == 5)        // two independent 16x32 wavefronts of eight slots per tile
     splat_backward_dispatch<8, 2>(st, segs, seg_tstart, S, cams, n_tiles, ranges, values, rec,
                                   final_T, n_contrib, dL_dimages, grad2d, G, order, gmax, gfix,
-                                  stats, count);
+                                  stats, count, n_inst, capacity);
   else if (tsx == 4 && tsy == 4)
     splat_backward_dispatch<4, 1>(st, segs, seg_tstart, S, cams, n_tiles, ranges, values, rec,
                                   final_T, n_contrib, dL_dimages, grad2d, G, order, gmax, gfix,
-                                  stats, count);
+                                  stats, count, n_inst, capacity);
   else
     return hipErrorInvalidValue;
   return hipGetLastError();

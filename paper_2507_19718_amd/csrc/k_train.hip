@@ -128,6 +128,12 @@ __global__ void adam_commit_kernel(const AdamGroup* __restrict__ groups, int S) 
   *g.step += 1;
 }
 
+__global__ void capacity_guard_kernel(const uint64_t* __restrict__ n_inst, uint64_t capacity,
+                                      float* __restrict__ losses, int n) {
+  const int i = (int)(blockIdx.x * blockDim.x + threadIdx.x);
+  if (i < n && *n_inst > capacity) losses[i] = __int_as_float(0x7fc00000);
+}
+
 }  // namespace
 
 int loss_num_partials(int64_t pixels) { return (int)((pixels + kLossThreads - 1) / kLossThreads); }
@@ -167,6 +173,14 @@ hipError_t launch_adam_factors(hipStream_t st, AdamGroup* groups, int n_groups) 
 hipError_t launch_adam_commit(hipStream_t st, const AdamGroup* groups, int S) {
   if (S <= 0) return hipSuccess;
   hipLaunchKernelGGL(adam_commit_kernel, dim3((unsigned)((S + 63) / 64)), dim3(64), 0, st, groups, S);
+  return hipGetLastError();
+}
+
+hipError_t launch_capacity_guard(hipStream_t st, const uint64_t* n_inst, uint64_t capacity,
+                                 float* losses, int n) {
+  if (n <= 0) return hipSuccess;
+  hipLaunchKernelGGL(capacity_guard_kernel, dim3((unsigned)((n + 63) / 64)), dim3(64), 0, st, n_inst,
+                     capacity, losses, n);
   return hipGetLastError();
 }
 

@@ -146,6 +146,8 @@ struct gsc_ctx {
   hipEvent_t upload_ev = nullptr;
   bool upload_pending = false;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  hipEvent_t ev_place = nullptr;   // frames: the placement's instance count has reached the host
+  uint64_t frame_capacity = 0;     // frames: instance capacity (0: size the next binning exactly)
   hipEvent_t tev[8] = {};
   // frame workspace
   gsc_binning* frame_bin = nullptr;
@@ -162,7 +164,7 @@ struct gsc_ctx {
   std::vector<hipEvent_t> ev_pool;
   double prof_ms[16] = {};
   int64_t prof_n[16] = {};
-  uint64_t acc_instances = 0, acc_frames = 0;
+  uint64_t acc_instances = 0, acc_frames = 0, acc_retries = 0;
   DevBuf adam_tab;                 // fused AdamW group table
   DevBuf d_stats;                  // splat work counters (kStatWords words)
   void* scratch = nullptr;         // this device's address of the allocation-free adjoint's array
@@ -428,8 +430,10 @@ void plan_batch(gsc_ctx* ctx, gsc_binning* b, const std::vector<ReqSpec>& reqs, 
 // after_count, if set, is called once the per-(chunk, tile) counts are enqueued.  Frames start
 // the tracer there: it then overlaps the scans, the placement and the forward splat, and stays
 // off the LDS-heavy sort and count kernels.
+constexpr int kHostDeferredCount = 16;   // slot of ctx->host_u64 for a frame's instance count
+
 gsc_status run_project_bin(gsc_ctx* ctx, gsc_binning* b, uint64_t capacity_hint,
-                           const std::function<void()>& after_count = {}) {
+                           const std::function<void()>& after_count = {}, bool deferred = false) {
   const Alloc& a = b->alloc;
   const int64_t G = b->G;
   const int64_t Gp = std::max<int64_t>(G, 1);
@@ -512,6 +516,16 @@ gsc_status run_project_bin(gsc_ctx* ctx, gsc_binning* b, uint64_t capacity_hint,
                            b->tile_start.as<uint64_t>(), b->d_ninst(), cap, b->values.as<uint32_t>(),
                            cut));
   }
+  if (deferred && capacity_hint != 0) {
+    // Frames: the count reaches the host while the rest of the frame is enqueued; the splat
+    // kernels and the AdamW step skip a binning that overflowed, and the frame call checks the
+    // count once everything is enqueued (render_batch).
+    GSC_TRY(hipMemcpyAsync(ctx->host_u64 + kHostDeferredCount, b->d_ninst(), 8,
+                           hipMemcpyDeviceToHost, st));
+    GSC_TRY(hipEventRecord(ctx->ev_place, st));
+    b->n_instances = 0;
+    return GSC_OK;
+  }
   if (capacity_hint != 0) n_inst = read_u64(ctx, b->d_ninst());
   b->n_instances = n_inst;
   ctx->acc_instances += n_inst;
@@ -552,7 +566,8 @@ void run_forward(gsc_ctx* ctx, gsc_binning* b, float* images, float* final_T, in
                                b->ranges.as<uint64_t>(), b->values.as<uint32_t>(),
                                b->rec.as<SplatRec>(), images, final_T, last_id,
                                b->n_contrib.as<uint32_t>(), ctx->d_stats.as<unsigned long long>(),
-                               order, b->tile_work.as<uint32_t>(), ctx->work_counters, b->tsx, b->tsy));
+                               order, b->tile_work.as<uint32_t>(), ctx->work_counters, b->tsx, b->tsy,
+                               b->d_ninst(), b->capacity));
   }
   b->forward_done = true;
 }
@@ -581,7 +596,7 @@ void run_splat_adjoint(gsc_ctx* ctx, gsc_binning* b, const float* final_T, const
                                 b->rec.as<SplatRec>(), final_T, b->n_contrib.as<uint32_t>(), dL,
                                 b->grad2d.as<float>(), b->G, order, gmax, gfix,
                                 ctx->d_stats.as<unsigned long long>(), ctx->work_counters,
-                                b->tsx, b->tsy));
+                                b->tsx, b->tsy, b->d_ninst(), b->capacity));
   }
 }
 
@@ -702,8 +717,11 @@ double elapsed(hipEvent_t a, hipEvent_t b) {
 }
 
 // The frame pipeline over a batch of (distinct) scenes.
+// *retry is set when the frame's binning overflowed the capacity sized from the previous frame:
+// nothing persistent was written, and the caller runs the frame again.
 gsc_status render_batch(gsc_ctx* ctx, gsc_scene* const* scenes, const gsc_frame_request* reqs,
-                        float* const* images, int n, gsc_frame_stats* stats) {
+                        float* const* images, int n, gsc_frame_stats* stats, bool* retry) {
+  *retry = false;
   if (n < 1) invalid(ctx, "batch is empty");
   if (!scenes || !reqs || !images) invalid(ctx, "NULL argument");
   for (int i = 0; i < n; ++i) {
@@ -801,7 +819,10 @@ gsc_status render_batch(gsc_ctx* ctx, gsc_scene* const* scenes, const gsc_frame_
   };
   // ---- splat the cache images ---------------------------------------------------------------------
   b->list_cut = ctx->list_cut != 0;
-  gsc_status s = run_project_bin(ctx, b, 0, start_trace);
+  // Sized from the previous frame's count (no host round trip inside the frame); the first
+  // frame of a context is sized exactly.
+  const bool deferred = ctx->frame_capacity != 0;
+  gsc_status s = run_project_bin(ctx, b, ctx->frame_capacity, start_trace, true);
   if (s != GSC_OK) {
     if (traced) GSC_TRY(hipStreamWaitEvent(st, ctx->ev_join, 0));
     return s;
@@ -824,6 +845,8 @@ gsc_status render_batch(gsc_ctx* ctx, gsc_scene* const* scenes, const gsc_frame_
                                   ctx->losses.as<float>() + i, images[i]));
   }
   }
+  // A binning that overflowed its capacity skips the splats; its frame takes no AdamW step.
+  if (deferred) GSC_TRY(launch_capacity_guard(st, b->d_ninst(), b->capacity, ctx->losses.as<float>(), n));
   if (timing) GSC_TRY(hipEventRecord(ctx->tev[3], st));
   // ---- backward + AdamW ---------------------------------------------------------------------------
   bool any_train = false;
@@ -868,6 +891,25 @@ gsc_status render_batch(gsc_ctx* ctx, gsc_scene* const* scenes, const gsc_frame_
   } else if (timing) {
     GSC_TRY(hipEventRecord(ctx->tev[4], st));
   }
+  // The whole frame is enqueued; confirm the capacity (the host waits for the placement's count
+  // only, the device has the rest of the frame queued).  An overflowed frame wrote nothing that
+  // persists (no AdamW step, no step count) and is run again with room for its count.
+  const uint64_t frame_cap = b->capacity;
+  if (deferred) {
+    GSC_TRY(hipEventSynchronize(ctx->ev_place));
+    const uint64_t got = ctx->host_u64[kHostDeferredCount];
+    if (got > frame_cap) {
+      ctx->frame_capacity = got + got / 4 + 1024;
+      ctx->acc_retries += 1;
+      *retry = true;
+      return GSC_OK;
+    }
+    b->n_instances = got;
+    ctx->acc_instances += got;
+    ctx->acc_frames += 1;
+  }
+  if (b->n_instances > ctx->frame_capacity - ctx->frame_capacity / 8)
+    ctx->frame_capacity = b->n_instances + b->n_instances / 4 + 1024;
   if (timing) {
     GSC_TRY(hipEventRecord(ctx->tev[5], st));
     std::vector<float> losses(n);
@@ -1030,6 +1072,7 @@ gsc_status gsc_ctx_create(int device, void* hip_stream, const gsc_allocator* all
   ok = ok && hipEventCreateWithFlags(&c->upload_ev, hipEventDisableTiming) == hipSuccess;
   ok = ok && hipEventCreateWithFlags(&c->ev_fork, hipEventDisableTiming) == hipSuccess;
   ok = ok && hipEventCreateWithFlags(&c->ev_join, hipEventDisableTiming) == hipSuccess;
+  ok = ok && hipEventCreateWithFlags(&c->ev_place, hipEventDisableTiming) == hipSuccess;
   for (int i = 0; i < 8 && ok; ++i) ok = hipEventCreate(&c->tev[i]) == hipSuccess;
   c->pinned_cap = size_t(4) << 20;
   ok = ok && hipHostMalloc((void**)&c->pinned, c->pinned_cap, hipHostMallocDefault) == hipSuccess;
@@ -1061,6 +1104,7 @@ void gsc_ctx_destroy(gsc_ctx* c) {
   if (c->upload_ev) (void)hipEventDestroy(c->upload_ev);
   if (c->ev_fork) (void)hipEventDestroy(c->ev_fork);
   if (c->ev_join) (void)hipEventDestroy(c->ev_join);
+  if (c->ev_place) (void)hipEventDestroy(c->ev_place);
   for (hipEvent_t e : c->tev) if (e) (void)hipEventDestroy(e);
   for (auto& p : c->prof_pending) { (void)hipEventDestroy(p.a); (void)hipEventDestroy(p.b); }
   for (hipEvent_t e : c->ev_pool) (void)hipEventDestroy(e);
@@ -1364,7 +1408,7 @@ gsc_status gsc_splat_backward_noalloc(gsc_ctx* ctx, const gsc_binning* bin,
                                   b->ranges.as<uint64_t>(), b->values.as<uint32_t>(),
                                   b->rec.as<SplatRec>(), final_T, b->n_contrib.as<uint32_t>(),
                                   dL_dimages, g2d, G, order, nullptr, nullptr, nullptr, false,
-                                  b->tsx, b->tsy));
+                                  b->tsx, b->tsy, b->d_ninst(), b->capacity));
     GSC_TRY(launch_project_backward(st, b->d_segs(), b->d_gstart(), b->S, b->d_cams(), G, g2d, g14));
     copy_out_grads(ctx, b, levels, num_levels, g14, grads);
     return GSC_OK;
@@ -1651,13 +1695,21 @@ gsc_status gsc_render_frame(gsc_ctx* ctx, gsc_scene* scene, const gsc_frame_requ
     gsc_scene* const scenes[1] = {scene};
     float* const images[1] = {image};
     if (!req) invalid(ctx, "request is NULL");
-    return render_batch(ctx, scenes, req, images, 1, stats);
+    bool retry = false;
+    gsc_status st = render_batch(ctx, scenes, req, images, 1, stats, &retry);
+    if (st == GSC_OK && retry) st = render_batch(ctx, scenes, req, images, 1, stats, &retry);
+    return (st == GSC_OK && retry) ? GSC_E_CAPACITY : st;
   });
 }
 
 gsc_status gsc_render_frames(gsc_ctx* ctx, gsc_scene* const* scenes, const gsc_frame_request* reqs,
                              float* const* images, int32_t n, gsc_frame_stats* stats) {
-  return guarded(ctx, [&]() -> gsc_status { return render_batch(ctx, scenes, reqs, images, n, stats); });
+  return guarded(ctx, [&]() -> gsc_status {
+    bool retry = false;
+    gsc_status st = render_batch(ctx, scenes, reqs, images, n, stats, &retry);
+    if (st == GSC_OK && retry) st = render_batch(ctx, scenes, reqs, images, n, stats, &retry);
+    return (st == GSC_OK && retry) ? GSC_E_CAPACITY : st;
+  });
 }
 
 }  // extern "C"
@@ -1835,6 +1887,7 @@ gsc_status gsc_ctx_counters(gsc_ctx* ctx, gsc_counters* out) {
     }
     out->instances = ctx->acc_instances;
     out->binnings = ctx->acc_frames;
+    out->frame_retries = ctx->acc_retries;
     out->evaluations = d[0];
     out->blended = d[1];
     out->contributors = d[2];

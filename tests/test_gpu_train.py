@@ -240,3 +240,42 @@ def test_render_frame_three_levels_hdr_paper_rates(gsc, gctx):
                                                                      cur[l].log_scale))
             assert good, (frame, l, info)
             assert s["step"] == frame + 1
+
+
+def test_frame_that_outgrows_its_capacity_is_run_again(gsc):
+    """Frames size their tile lists from the previous frame's instance count.  A far view then a
+    near view makes the second frame's binning overflow that capacity: the frame is run again
+    (one retry counted) and its image, parameters, moments and step count equal, bit for bit
+    (deterministic adjoint), those of the same frame on a fresh context, which sizes exactly."""
+    wl = synth.workload("tiny", levels=[4096, 2048], max_bounces=3, loss=1, lr=synth.P360_LR,
+                        weight_decay=1e-2)
+    vol = gsc.Volume.from_synth(wl.volume())
+    far = synth.orbit_camera(128, 128, 30.0, radius=4.5)
+    near = synth.orbit_camera(128, 128, 30.0, radius=1.3)
+    ctx_a, ctx_b = gsc.Context(0), gsc.Context(0)
+    for c in (ctx_a, ctx_b):
+        c.set_deterministic(True)
+    levels = [gsc.level_to_device(g) for g in wl.gaussians()]
+    sa = gsc.Scene(ctx_a, vol, levels)
+    image = torch.empty((128, 128, 3), device="cuda")
+    req = lambda cam, f: gsc.frame_request(cam, wl.seed, f, wl.K, wl.max_bounces, loss=wl.loss,
+                                           lr=wl.lr, weight_decay=wl.weight_decay, C=wl.C,
+                                           viewport_frames=f + 1)
+    gsc.gsc_render_frame(ctx_a, sa, req(far, 0), image)
+    sb = gsc.Scene(ctx_b, vol, levels)
+    sb.copy_state_from(sa)
+    c0 = ctx_a.counters()
+    got = torch.empty_like(image)
+    gsc.gsc_render_frame(ctx_a, sa, req(near, 1), got)
+    c1 = ctx_a.counters()
+    assert c1["frame_retries"] == c0["frame_retries"] + 1
+    assert c1["instances"] - c0["instances"] > 1.25 * (c0["instances"] / max(c0["binnings"], 1))
+    want = torch.empty_like(image)
+    gsc.gsc_render_frame(ctx_b, sb, req(near, 1), want)
+    assert ctx_b.counters()["frame_retries"] == 0
+    assert torch.equal(got, want)
+    for l in range(wl.K):
+        a, b = sa.state(l), sb.state(l)
+        for k in ("params", "m", "v"):
+            assert torch.equal(a[k], b[k]), (l, k)
+        assert a["step"] == b["step"] == 2
