@@ -73,3 +73,52 @@ def test_fp32_screen_values_bound(ora, name):
         worst_c13 = max(worst_c13, float(np.max(d / (1e-4 * np.maximum(np.abs(r), 1e-2 * rms)))))
     # The bound 1e-4 max(|ref|, 1e-2 rms) is already broken by the input rounding alone.
     assert worst_c13 > 1.0
+
+
+def _quat_rotation(q):
+    q = q / q.norm(dim=-1, keepdim=True)
+    w, x, y, z = q.unbind(-1)
+    return torch.stack([1 - 2 * (y * y + z * z), 2 * (x * y - w * z), 2 * (x * z + w * y),
+                        2 * (x * y + w * z), 1 - 2 * (x * x + z * z), 2 * (y * z - w * x),
+                        2 * (x * z - w * y), 2 * (y * z + w * x), 1 - 2 * (x * x + y * y)],
+                       -1).reshape(-1, 3, 3)
+
+
+def _rotation_grad_fp32_error(anisotropy: float, n: int = 4000, seed: int = 0):
+    """The rotation gradient of Sigma = R(q) S^2 R(q)^T against a fixed dL/dSigma, chained in
+    fp32 and in fp64 from the same fp32 parameters, for log-scales that differ by at most
+    `anisotropy`.  Returns (median relative error, max error / rms of the fp64 gradient)."""
+    g = torch.Generator().manual_seed(seed)
+    q = torch.randn(n, 4, generator=g, dtype=torch.float64).float()
+    ls = torch.full((n, 3), -3.0, dtype=torch.float64)
+    ls[:, 0] += anisotropy * torch.rand(n, generator=g, dtype=torch.float64)
+    ls[:, 1] += anisotropy
+    ls = ls.float()
+    dS = torch.randn(n, 3, 3, generator=g, dtype=torch.float64)
+    dS = dS + dS.transpose(1, 2)
+    out = []
+    for dt in (torch.float32, torch.float64):
+        qq = q.to(dt).clone().requires_grad_(True)
+        R = _quat_rotation(qq)
+        cov = R @ torch.diag_embed(torch.exp(2.0 * ls.to(dt))) @ R.transpose(1, 2)
+        (cov * dS.to(dt)).sum().backward()
+        out.append(qq.grad.double())
+    err = (out[0] - out[1]).abs()
+    return float((err / out[1].abs()).median()), float(err.max() / out[1].pow(2).mean().sqrt())
+
+
+def test_rotation_gradient_of_nearly_isotropic_gaussians_is_ill_conditioned():
+    """The reading behind the rotation exclusion of the training-frame parity checks: a
+    Gaussian whose log-scales differ by a has a rotation gradient that is a sum of terms of the
+    size of its covariance gradient cancelling down to ~a of it, so an fp32 chain rule keeps a
+    relative ~1.4e-7 / a of it.  At a = 1e-2 that is ~1.4e-5, and the worst elements reach
+    ~2e-4 of the group's rms: all of the 2e-4 rms the bar allows, before the splat adjoint's own
+    error is counted.  From a = 5e-2 on the median is below 3e-6 and the worst element below
+    1e-4 rms, half the allowance."""
+    med = {}
+    for a in (1e-3, 1e-2, 5e-2, 1e-1):
+        med[a], worst = _rotation_grad_fp32_error(a)
+        assert 0.3e-7 / a < med[a] < 5e-7 / a, (a, med[a])
+        if a >= 5e-2:
+            assert worst < 1e-4, (a, worst)
+    assert med[1e-3] > 5.0 * med[1e-2] > 25.0 * med[1e-1]
