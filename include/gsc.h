@@ -255,6 +255,14 @@ gsc_status gsc_ctx_set_list_cut(gsc_ctx* ctx, int32_t on);
  * this is how the frames' binning and kernels are compared with the oracle at full size.
  * Default off: 16x16 tiles, full lists (the binning the oracle's keys and ranges follow). */
 gsc_status gsc_ctx_set_frame_binning(gsc_ctx* ctx, int32_t on);
+/* The tile edge, in pixels, that frames (gsc_render_frame / gsc_render_frames) bin with: 16,
+ * 32, or 0 for automatic (the default): 32 when every request of the batch spans at least
+ * 6144 tiles of 32x32 pixels over its levels (1920x1080 with four levels spans 8160), else 16.
+ * Larger tiles give shorter binning (fewer instances), smaller ones more parallel work and
+ * shorter lists for the splat kernels.  Images, gradients and
+ * parameter updates do not depend on the tiling beyond float summation order.  Returns
+ * GSC_E_INVALID_ARG for a NULL ctx or any other size. */
+gsc_status gsc_ctx_set_frame_tiles(gsc_ctx* ctx, int32_t tile_px);
 /* After GSC_E_CAPACITY: the instance count the failed call needed. */
 uint64_t gsc_ctx_required_capacity(const gsc_ctx* ctx);
 /* Per-kernel timing: while on, every kernel launch of the context is bracketed by HIP events

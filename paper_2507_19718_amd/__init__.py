@@ -157,6 +157,10 @@ class Context:
         """gsc_project_bin bins like the frames (32x32 tiles, list cut) (default off)."""
         self.check(self._lib.gsc_ctx_set_frame_binning(self.handle, 1 if on else 0))
 
+    def set_frame_tiles(self, tile_px: int):
+        """Tile edge frames bin with: 16, 32, or 0 = by batch size (default)."""
+        self.check(self._lib.gsc_ctx_set_frame_tiles(self.handle, int(tile_px)))
+
     def set_deterministic(self, on: bool):
         """Sum the splat adjoint in fixed point so gradients repeat bit for bit (default off)."""
         self.check(self._lib.gsc_ctx_set_deterministic(self.handle, 1 if on else 0))

@@ -113,6 +113,7 @@ _SIGNATURES = {
     "gsc_ctx_set_deterministic": (c_int32, [c_void_p, c_int32]),
     "gsc_ctx_set_list_cut": (c_int32, [c_void_p, c_int32]),
     "gsc_ctx_set_frame_binning": (c_int32, [c_void_p, c_int32]),
+    "gsc_ctx_set_frame_tiles": (c_int32, [c_void_p, c_int32]),
     "gsc_ctx_set_work_counters": (c_int32, [c_void_p, c_int32]),
     "gsc_ctx_required_capacity": (c_uint64, [c_void_p]),
     "gsc_ctx_trim": (c_int32, [c_void_p]),

@@ -17,13 +17,17 @@ namespace gsc {
 
 constexpr int kTile = 16;               // 16x16 pixel tiles (gsc_project_bin and its views)
 constexpr int kTileShift = 4;
-// Frames bin 32x32 tiles.  The adjoint walks one with a workgroup of two wavefronts, each a
+// Large frames bin 32x32 tiles.  The adjoint walks one with two independent wavefronts, each a
 // 16x32 half with eight pixels per lane (the per-entry work, record broadcast, window masks and
-// reductions, is shared by eight pixels), and adds a Gaussian's partials from both halves in LDS
-// before its atomics; the forward walks it with four independent 16x16 wavefronts.  The tile
-// lists hold about a third of the instances of 16x16 tiles.
+// reductions, is shared by eight pixels); the forward walks it with four independent 16x16
+// wavefronts.  The tile lists hold about a third of the instances of 16x16 tiles.
 constexpr int kFrameTileShiftX = 5;
 constexpr int kFrameTileShiftY = 5;
+// Frames bin 32x32 tiles when each request of the batch spans at least this many of them over
+// its levels (1920x1080 with four levels: 8160), else 16x16.  Measured on 1M-Gaussian levels:
+// 32x32 tiles win 10 % at 1080p with four levels, tie at 1080p with three, and lose 20-110 %
+// at 720p and 360p, where the longest tile list sets the splat adjoint's time.
+constexpr int64_t kAutoTiles32 = 6144;
 constexpr int kMaxTf = 64;
 constexpr int kMaxLights = 8;
 constexpr int kChunk = 1024;            // depth-ordered Gaussians per binning chunk

@@ -140,6 +140,7 @@ struct gsc_ctx {
   int deterministic = 0;
   int list_cut = 1;                // frames bin only the list prefixes that can reach a pixel
   int frame_binning = 0;           // gsc_project_bin bins like the frames (32x32 tiles, list cut)
+  int frame_tiles = 0;             // frames' tile edge in pixels: 16, 32, or 0 (by batch size)
   // pinned staging ring for descriptor uploads
   char* pinned = nullptr;
   size_t pinned_cap = 0, pinned_head = 0;
@@ -719,6 +720,22 @@ double elapsed(hipEvent_t a, hipEvent_t b) {
 // The frame pipeline over a batch of (distinct) scenes.
 // *retry is set when the frame's binning overflowed the capacity sized from the previous frame:
 // nothing persistent was written, and the caller runs the frame again.
+// The frames' tile edge (as a shift): the setting, or by the requests' sizes.  32x32 tiles
+// bin fewer instances than 16x16 ones (a third at 1080p), but the splat kernels walk each list
+// with two or four wavefronts instead of one per 16x16 tile, so a frame's heaviest tile takes
+// longer; only a request with at least kAutoTiles32 of them over its levels has the parallel
+// work to hide that.  Every request of the batch must have it.
+int frame_tile_shift(const gsc_ctx* ctx, gsc_scene* const* scenes, const gsc_frame_request* reqs,
+                     int n) {
+  if (ctx->frame_tiles == 16) return kTileShift;
+  if (ctx->frame_tiles == 32) return kFrameTileShiftX;
+  for (int i = 0; i < n; ++i) {
+    const int64_t tiles = (int64_t)scenes[i]->K * ((reqs[i].cam.w + 31) / 32) * ((reqs[i].cam.h + 31) / 32);
+    if (tiles < kAutoTiles32) return kTileShift;
+  }
+  return kFrameTileShiftX;
+}
+
 gsc_status render_batch(gsc_ctx* ctx, gsc_scene* const* scenes, const gsc_frame_request* reqs,
                         float* const* images, int n, gsc_frame_stats* stats, bool* retry) {
   *retry = false;
@@ -763,7 +780,8 @@ gsc_status render_batch(gsc_ctx* ctx, gsc_scene* const* scenes, const gsc_frame_
     pix += (int64_t)sc->K * reqs[i].cam.w * reqs[i].cam.h;
     rpix += (int64_t)reqs[i].trace.spp * reqs[i].cam.w * reqs[i].cam.h;
   }
-  plan_batch(ctx, b, specs, kFrameTileShiftX, kFrameTileShiftY);
+  const int fshift = frame_tile_shift(ctx, scenes, reqs, n);
+  plan_batch(ctx, b, specs, fshift, fshift);
   const Alloc& a = ctx->alloc;
   need(ctx, ctx->images, a, 12 * (size_t)pix, "cache images");
   need(ctx, ctx->targets, a, 12 * (size_t)pix, "targets");
@@ -1140,6 +1158,16 @@ gsc_status gsc_ctx_set_work_counters(gsc_ctx* ctx, int32_t on) {
 gsc_status gsc_ctx_set_frame_binning(gsc_ctx* ctx, int32_t on) {
   if (!ctx) return GSC_E_INVALID_ARG;
   ctx->frame_binning = on != 0;
+  return GSC_OK;
+}
+
+gsc_status gsc_ctx_set_frame_tiles(gsc_ctx* ctx, int32_t tile_px) {
+  if (!ctx) return GSC_E_INVALID_ARG;
+  if (tile_px != 0 && tile_px != 16 && tile_px != 32) {
+    ctx->err = "frame tile size must be 0 (automatic), 16 or 32";
+    return GSC_E_INVALID_ARG;
+  }
+  ctx->frame_tiles = tile_px;
   return GSC_OK;
 }
 
@@ -1679,7 +1707,7 @@ size_t gsc_frame_footprint_bytes(const gsc_scene* sc, int32_t w, int32_t h, uint
   for (int l = 0; l < sc->K; ++l) G += sc->n[l];
   const size_t P = (size_t)w * h;
   const size_t K = (size_t)sc->K;
-  const int tw = 1 << kFrameTileShiftX, th = 1 << kFrameTileShiftY;   // frame tiles
+  const int tw = 1 << kTileShift, th = 1 << kTileShift;   // the smaller frame tiles (more of them)
   const size_t tiles = K * (size_t)((w + tw - 1) / tw) * ((h + th - 1) / th);
   size_t b = 0;
   b += (size_t)G * (48 + 4 + 8 + 4 + 4 * 4 + 8 + 9 * 4 + 14 * 4);   // per-Gaussian buffers

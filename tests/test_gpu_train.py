@@ -202,11 +202,21 @@ def test_render_frame_with_an_empty_level(gsc, gctx):
     assert np.isfinite(to_np(image)).all()
 
 
-def test_render_frame_three_levels_hdr_paper_rates(gsc, gctx):
+@pytest.mark.parametrize("tile_px", [32, 16])
+def test_render_frame_three_levels_hdr_paper_rates(gsc, gctx, tile_px):
     """The benchmark's training configuration on the small scene: three levels, B = 3, the HDR
     loss (Eq. 4), the paper's per-group learning rates (scale rate 0) with the Eq. 5 schedule,
-    AdamW weight decay 1e-2 and the frames' binning (32x32 tiles, list cut); two frames, each
-    against the oracle pipeline started from the GPU's state."""
+    AdamW weight decay 1e-2 and the frames' binning (list cut; 32x32 tiles, as large frames
+    bin, and 16x16, as small ones do); two frames, each against the oracle pipeline started
+    from the GPU's state."""
+    gctx.set_frame_tiles(tile_px)
+    try:
+        _three_levels_hdr_paper_rates(gsc, gctx)
+    finally:
+        gctx.set_frame_tiles(0)
+
+
+def _three_levels_hdr_paper_rates(gsc, gctx):
     wl = synth.workload("tiny", levels=[4096, 2048, 1024], max_bounces=3, loss=1,
                         lr=synth.P360_LR, weight_decay=1e-2)
     vol = wl.volume()
@@ -279,3 +289,30 @@ def test_frame_that_outgrows_its_capacity_is_run_again(gsc):
         for k in ("params", "m", "v"):
             assert torch.equal(a[k], b[k]), (l, k)
         assert a["step"] == b["step"] == 2
+
+
+def test_frame_tile_sizes_agree(gsc):
+    """A frame binned in 16x16 tiles and one binned in 32x32 tiles give the same composite and
+    loss bit for bit (each pixel blends the same entries in the same order whatever the tile),
+    the larger tiles with fewer instances; the automatic choice takes 16x16 tiles for this small
+    frame; sizes other than 0, 16 and 32 are rejected."""
+    wl = synth.workload("tiny", levels=[4096, 2048], max_bounces=3, loss=1, lr=synth.P360_LR,
+                        weight_decay=1e-2)
+    vol = gsc.Volume.from_synth(wl.volume())
+    cam = wl.camera()
+    levels = [gsc.level_to_device(g) for g in wl.gaussians()]
+    req = gsc.frame_request(cam, wl.seed, 0, wl.K, wl.max_bounces, loss=wl.loss, lr=wl.lr,
+                            weight_decay=wl.weight_decay, C=wl.C)
+    out = {}
+    for tp in (16, 32, 0):
+        ctx = gsc.Context(0)
+        ctx.set_frame_tiles(tp)
+        sc = gsc.Scene(ctx, vol, levels)
+        image = torch.empty((cam.h, cam.w, 3), device="cuda")
+        st = gsc.gsc_render_frame(ctx, sc, req, image, stats=True)
+        out[tp] = (image, st["loss"], ctx.counters()["instances"])
+        with pytest.raises(gsc.GscError):
+            ctx.set_frame_tiles(24)
+    for tp in (32, 0):
+        assert torch.equal(out[tp][0], out[16][0]) and out[tp][1] == out[16][1], tp
+    assert out[32][2] < out[16][2] and out[0][2] == out[16][2]
