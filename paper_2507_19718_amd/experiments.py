@@ -2,14 +2,15 @@
 sampling coefficient C and of cold-start training (Evaluation), of the hyper-parameter
 ablation (supplement: regularisation and covariance learning rate), and of the image-quality
 comparison against uniform and next-event-estimation path tracing under two small spherical
-area lights (Evaluation: scenes and baselines).
+area lights (Evaluation: scenes and baselines), and of the cache re-adapting when the transfer
+function is replaced and a light is moved while frames keep training (Abstract; Introduction).
 
 Everything runs through the library's entry points: `gsc_cache_init` for volume-shaped initial
 caches, `gsc_render_frame` for cached frames (trace + splat + train + composite), and
 `gsc_trace_targets` for the references (no early termination, many samples per pixel).
 
     python -m paper_2507_19718_amd.experiments [--workload orbit1k] [--lights point|area]
-        [--what C,cold,ablation,estimators,spp]
+        [--what C,cold,ablation,estimators,spp,adapt]
 
 prints one JSON object per study.
 """
@@ -24,23 +25,58 @@ from typing import Dict, List, Sequence
 import torch
 
 from . import (STRATEGY_NEE, STRATEGY_UNIFORM, Context, Scene, Volume, frame_request,
-               gsc_cache_init, gsc_render_frame, gsc_trace_targets, trace_params)
+               gsc_cache_init, gsc_project_bin, gsc_render_frame, gsc_splat_forward,
+               gsc_trace_targets, trace_params)
 
 
-def reference_radiance(ctx: Context, vol: Volume, cam, K: int, B: int, seed: int, spp: int = 1024,
-                       chunk: int = 64) -> torch.Tensor:
-    """Unbiased pixel radiance [h][w][3]: the per-length targets summed over lengths, traced
-    without early termination (C = inf) and averaged over spp samples."""
+def reference_levels(ctx: Context, vol: Volume, cam, K: int, B: int, seed: int, spp: int = 1024,
+                     chunk: int = 64) -> torch.Tensor:
+    """Unbiased per-level radiance [K][h][w][3]: what cache level l should hold at each pixel
+    (the radiance of the paths' segments from vertex l on), traced without early termination
+    (C = inf) and averaged over spp samples."""
     tg = torch.empty((K, cam.h, cam.w, 3), device="cuda")
-    acc = torch.zeros((cam.h, cam.w, 3), device="cuda", dtype=torch.float64)
+    acc = torch.zeros((K, cam.h, cam.w, 3), device="cuda", dtype=torch.float64)
     done = 0
     while done < spp:
         n = min(chunk, spp - done)
         # A distinct frame index per chunk gives independent Philox streams.
         gsc_trace_targets(ctx, vol, cam, trace_params(seed, 1_000_000 + done, n, B, K, C=math.inf), tg)
-        acc += tg.sum(0).double() * n
+        acc += tg.double() * n
         done += n
     return (acc / spp).float()
+
+
+def reference_radiance(ctx: Context, vol: Volume, cam, K: int, B: int, seed: int, spp: int = 1024,
+                       chunk: int = 64) -> torch.Tensor:
+    """Unbiased pixel radiance [h][w][3]: the per-level references summed over levels."""
+    return reference_levels(ctx, vol, cam, K, B, seed, spp, chunk).double().sum(0).float()
+
+
+def cache_images(ctx: Context, scene: Scene, cam) -> torch.Tensor:
+    """The scene's cache as it stands, rendered level by level [K][h][w][3] (projection,
+    binning and the forward splat of its current parameters; no training)."""
+    levels = [scene.level(l) for l in range(scene.K)]
+    b = gsc_project_bin(ctx, levels, cam)
+    images = torch.empty((scene.K, cam.h, cam.w, 3), device="cuda")
+    final_T = torch.empty((scene.K, cam.h, cam.w), device="cuda")
+    last_id = torch.empty((scene.K, cam.h, cam.w), dtype=torch.int32, device="cuda")
+    gsc_splat_forward(ctx, b, images, final_T, last_id)
+    b.release()
+    return images
+
+
+def level_l2(images: torch.Tensor, ref: torch.Tensor) -> List[float]:
+    """Per-level mean squared error of cache images [K][h][w][3] against references."""
+    return [float(x) for x in ((images.double() - ref.double()) ** 2).mean(dim=(1, 2, 3))]
+
+
+def level_hdr_l2(images: torch.Tensor, ref: torch.Tensor) -> List[float]:
+    """Per-level relative error with Eq. 4's normalisation, the reference in place of the
+    prediction: mean of (y - r)^2 / (max(r, 0) + 0.01)^2.  The HDR loss weights dark pixels up,
+    so under a cache too coarse to fit every pixel its optimum is not the plain-L2 optimum; this
+    is the error that loss drives down."""
+    r = ref.double()
+    return [float(x) for x in (((images.double() - r) / (r.clamp(min=0.0) + 0.01)) ** 2).mean(dim=(1, 2, 3))]
 
 
 def path_traced(ctx: Context, vol: Volume, cam, K: int, B: int, seed: int, frame: int,
@@ -218,6 +254,75 @@ def study_spp(ctx, wl, gv, init_levels, ref, cam, spps=(1, 2, 4, 8, 16, 32, 64),
     return {"study": "spp", "warm_frames": warm, "measured_frames": measure, "rows": rows}
 
 
+def study_adapt(ctx, wl, gv, levels, cam, frames: int = 300, changes=(100, 200), ref_spp: int = 1024,
+                light_deg: float = 90.0, every: int = 1) -> Dict:
+    """The cache re-adapting while frames keep training at a static camera (Abstract;
+    Introduction: the cache follows changes of lights and transfer function).  At frame
+    changes[0] the transfer function is replaced by a new random one with as many control
+    points; at changes[1] the first light turns `light_deg` about the vertical axis through the
+    volume's centre.  The viewport counter t of Eq. 5 restarts at both, so the learning rates
+    rise again.  After every `every`-th frame the cache is rendered level by level and compared
+    (mean squared error, and the relative error of Eq. 4's normalisation) with that level's
+    reference under the optics in force, traced at `ref_spp` samples per pixel; just before
+    each change the stale cache is also compared with the new optics' reference."""
+    import synth
+    tf1 = synth.transfer_function(wl.tf_points, wl.seed, 1)
+    lights_rot = synth.point_lights(wl.n_lights, rotate_first_deg=light_deg)
+    optics = [(gv.tf, gv.lights), (tf1, gv.lights), (tf1, lights_rot)][:len(changes) + 1]
+    vols = [Volume(gv.density, gv.density_max, tf, li, gv.spheres) for tf, li in optics]
+    t = time.perf_counter()
+    refs = [reference_levels(ctx, v, cam, wl.K, wl.max_bounces, wl.seed, spp=ref_spp) for v in vols]
+    torch.cuda.synchronize()
+    ref_s = time.perf_counter() - t
+    scene = fresh_scene(ctx, gv, levels)
+    img = torch.empty((cam.h, cam.w, 3), device="cuda")
+    rows, stale = [], []
+    phase, t_view, frame_ms = 0, 0, 0.0
+    for f in range(frames):
+        if phase < len(changes) and f == changes[phase]:
+            im = cache_images(ctx, scene, cam)
+            stale.append((level_l2(im, refs[phase + 1]), level_hdr_l2(im, refs[phase + 1])))
+            phase += 1
+            scene.set_optics(*optics[phase], gv.spheres)
+            t_view = 0
+        t_view += 1
+        req = frame_request(cam, wl.seed, f, wl.K, wl.max_bounces, loss=wl.loss, lr=wl.lr,
+                            weight_decay=wl.weight_decay, C=wl.C, viewport_frames=t_view)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        gsc_render_frame(ctx, scene, req, img)
+        torch.cuda.synchronize()
+        frame_ms += (time.perf_counter() - t) * 1e3
+        if f % every == 0 or f == frames - 1 or (phase < len(changes) and f + 1 == changes[phase]):
+            im = cache_images(ctx, scene, cam)
+            rows.append({"frame": f, "phase": phase, "l2": level_l2(im, refs[phase]),
+                         "hdr_l2": level_hdr_l2(im, refs[phase]),
+                         "composite_mse": mse(img, refs[phase].double().sum(0))})
+    scene.destroy()
+    starts = [0] + list(changes[:len(optics) - 1])
+    phases = []
+    for p in range(len(optics)):
+        pr = [r for r in rows if r["phase"] == p]
+        total = [sum(r["l2"]) for r in pr]
+        info = {"first_frame": starts[p], "l2_first": pr[0]["l2"], "l2_end": pr[-1]["l2"],
+                "l2_min_total": min(total), "hdr_l2_first": pr[0]["hdr_l2"],
+                "hdr_l2_end": pr[-1]["hdr_l2"], "composite_mse_end": pr[-1]["composite_mse"]}
+        if p > 0:
+            info["l2_stale"], info["hdr_l2_stale"] = stale[p - 1]
+            # How far the change moved the references themselves (per level).
+            info["reference_change_l2"] = level_l2(refs[p], refs[p - 1])
+            s0 = sum(stale[p - 1][0])
+            info["frames_to_halve_stale"] = next((r["frame"] - starts[p] + 1 for r, x in zip(pr, total)
+                                                  if x <= 0.5 * s0), None)
+            info["frames_to_within_10pct_of_end"] = next(
+                (r["frame"] - starts[p] + 1 for r, x in zip(pr, total) if x <= 1.1 * total[-1]), None)
+        phases.append(info)
+    return {"study": "adapt", "frames": frames, "changes": {"transfer_function": changes[0],
+            "light_rotated_deg": light_deg, "light_frame": changes[1] if len(changes) > 1 else None},
+            "ref_spp": ref_spp, "ref_seconds": round(ref_s, 2), "ms_per_frame": round(frame_ms / frames, 3),
+            "phases": phases, "per_frame": rows}
+
+
 def main():
     import synth
     ap = argparse.ArgumentParser()
@@ -227,6 +332,9 @@ def main():
     ap.add_argument("--ref-spp", type=int, default=1024)
     ap.add_argument("--orbit", type=int, default=256)
     ap.add_argument("--still", type=int, default=256)
+    ap.add_argument("--frames", type=int, default=300, help="adapt: frames in the run")
+    ap.add_argument("--changes", default="100,200",
+                    help="adapt: frames of the transfer-function swap and of the light move")
     ap.add_argument("--lights", choices=("point", "area"), default="point",
                     help="the workload's point lights, or two spherical area lights instead")
     args = ap.parse_args()
@@ -238,14 +346,26 @@ def main():
     ctx = Context(0)
     gv = Volume.from_synth(vol)
     cam = wl.camera()
+    what = set(args.what.split(","))
+    head = {"workload": wl.name, "lights": args.lights, "width": cam.w, "height": cam.h, "levels": wl.K,
+            "ref_spp": args.ref_spp}
+    if "adapt" in what:
+        # The workload's own random levels (the sizes the adaptation run is specified with).
+        from . import level_to_device
+        lv = [level_to_device(g) for g in wl.gaussians()]
+        print(json.dumps({**head, "gaussians_per_level": list(wl.levels),
+                          **study_adapt(ctx, wl, gv, lv, cam, frames=args.frames, ref_spp=args.ref_spp,
+                                        changes=tuple(int(x) for x in args.changes.split(",")))}),
+              flush=True)
+        what.discard("adapt")
+        if not what:
+            return
     t = time.perf_counter()
     init_levels = gsc_cache_init(ctx, gv, args.init_points, wl.K, wl.seed)
     torch.cuda.synchronize()
     init_ms = (time.perf_counter() - t) * 1e3
     ref = reference_radiance(ctx, gv, cam, wl.K, wl.max_bounces, wl.seed, spp=args.ref_spp)
-    head = {"workload": wl.name, "lights": args.lights, "width": cam.w, "height": cam.h, "levels": wl.K,
-            "init_points": args.init_points, "init_ms": round(init_ms, 2), "ref_spp": args.ref_spp}
-    what = set(args.what.split(","))
+    head.update({"init_points": args.init_points, "init_ms": round(init_ms, 2)})
     if "C" in what:
         print(json.dumps({**head, **study_C(ctx, wl, vol, gv, init_levels, ref, cam)}), flush=True)
     if "cold" in what:

@@ -66,8 +66,10 @@ def percentile(xs: Sequence[float], q: float) -> float:
 
 
 def summarize(reqs: Sequence[Request], t0: float, t_end: float, skip_s: float = 0.0) -> dict:
+    """Frames/s over the whole run; latency percentiles over the requests that arrived at or
+    after skip_s (the warm-up of the first seconds left out)."""
     lat = [1000.0 * (r.t_done - r.t_arrival) for r in reqs if r.t_arrival >= skip_s]
-    return {"frames": len(reqs), "wall_s": t_end - t0,
+    return {"frames": len(reqs), "wall_s": t_end - t0, "latency_from_s": skip_s,
             "frames_per_s": len(reqs) / max(t_end - t0, 1e-9),
             "p50_ms": percentile(lat, 50), "p99_ms": percentile(lat, 99),
             "mean_ms": float(np.mean(lat)) if lat else math.nan}
@@ -80,8 +82,9 @@ def _req_struct(spec: SceneSpec, r: Request):
 
 
 def run_plain(ctx: Context, scenes: Sequence[SceneSpec], reqs: Sequence[Request],
-              realtime: bool = True) -> dict:
-    """One frame at a time in arrival order."""
+              realtime: bool = True, skip_s: float = 0.0) -> dict:
+    """One frame at a time in arrival order.  realtime=False is the closed loop (every request
+    has arrived at time 0): frames/s is then the loop's capacity."""
     images = {}
     t0 = time.perf_counter()
     for r in reqs:
@@ -96,7 +99,7 @@ def run_plain(ctx: Context, scenes: Sequence[SceneSpec], reqs: Sequence[Request]
         gsc_render_frame(ctx, scenes[r.scene].scene, _req_struct(scenes[r.scene], r), images[key])
         ctx.synchronize()
         r.t_done = time.perf_counter() - t0
-    return summarize(reqs, 0.0, time.perf_counter() - t0)
+    return summarize(reqs, 0.0, time.perf_counter() - t0, skip_s)
 
 
 class ContinuousBatcher:
@@ -153,7 +156,10 @@ class ContinuousBatcher:
             if self.after_batch:
                 self.after_batch(slot, batch, images)
 
-    def run(self, reqs: Sequence[Request], realtime: bool = True) -> dict:
+    def run(self, reqs: Sequence[Request], realtime: bool = True, skip_s: float = 0.0) -> dict:
+        """Replays the log (realtime) or serves it as a closed loop (every request has arrived
+        at time 0: frames/s is then the capacity); latencies of requests that arrived before
+        skip_s are left out of the percentiles."""
         pending = collections.deque()                 # arrived, not started (arrival order)
         upcoming = collections.deque(reqs)
         busy_scenes = set()
@@ -233,7 +239,7 @@ class ContinuousBatcher:
             th.join()
         if errors:
             raise errors[0]
-        return summarize(reqs, 0.0, time.perf_counter() - t0)
+        return summarize(reqs, 0.0, time.perf_counter() - t0, skip_s)
 
 
 def make_requests(log: Sequence[dict], cams: Callable[[dict], object], duration_s: Optional[float] = None,
