@@ -232,45 +232,120 @@ def cpu_baseline(wl, vol, levels, crop=256):
 SERVE_SCENES = ((128, 100_000), (256, 300_000), (512, 600_000), (512, 1_000_000))
 
 
-def serving(duration_s: float, rate_hz: float = 240.0, slots: int = 2):
+def serving(duration_s: float, rate_hz: float = 240.0, slots: int = 2, capacity_requests: int = 960,
+            probe_spp: int = 256):
     """Served vs plain on the same Poisson request log: 4 resident scenes (128^3, 256^3, 512^3,
     512^3 fBm; 3 levels of 100k / 300k / 600k / 1M Gaussians), 32 viewers at 640x360 /
-    1280x720 / 1920x1080 on random orbits, 1 spp trace + train step + composite per request."""
+    1280x720 / 1920x1080 on random orbits, 1 spp trace + train step + composite per request.
+
+    Three measurements: (1) the log replayed in real time by both loops (latency percentiles
+    over the requests after the first 2 s); (2) the capacity of each loop, closed loop (the next
+    `capacity_requests` requests all available at once); (3) the cache accuracy the two loops
+    reach: every scene's cache rendered level by level at four probe cameras against
+    probe_spp references, after (1) and (2), and after a replay of the first requests on fresh
+    scenes with the deterministic adjoint, where the two loops' caches are compared bit for
+    bit."""
     import torch
     import synth
     import paper_2507_19718_amd as gsc
     from paper_2507_19718_amd import serve
+    from paper_2507_19718_amd.experiments import cache_images, level_l2, reference_levels
     ctx = gsc.Context(0)
+    t = time.time()
+    inputs = []
+    for i, (res, n) in enumerate(SERVE_SCENES):
+        wl = synth.workload("orbit1k", volume_res=res, levels=[n] * 3, seed=0x47534305 + 10 + i)
+        inputs.append((wl, gsc.Volume.from_synth(wl.volume()), [gsc.level_to_device(g) for g in wl.gaussians()]))
 
     def scenes():
-        out = []
-        for i, (res, n) in enumerate(SERVE_SCENES):
-            wl = synth.workload("orbit1k", volume_res=res, levels=[n] * 3, seed=0x47534305 + 10 + i)
-            vol = wl.volume()
-            sc = gsc.Scene(ctx, gsc.Volume.from_synth(vol), [gsc.level_to_device(g) for g in wl.gaussians()])
-            out.append(serve.SceneSpec(sc, wl.K, wl.max_bounces, 1, wl.lr, wl.weight_decay, wl.C))
-        return out
+        return [serve.SceneSpec(gsc.Scene(ctx, gv, lv), wl.K, wl.max_bounces, 1, wl.lr, wl.weight_decay, wl.C)
+                for wl, gv, lv in inputs]
 
-    log_ = synth.poisson_requests(rate_hz, duration_s, 32, 4, 0x47534305)
+    log_ = synth.poisson_requests(rate_hz, duration_s + capacity_requests / rate_hz + 1.0, 32, 4, 0x47534305)
+    rt_log = [e for e in log_ if e["t_arrival"] < duration_s]
+    cap_log = log_[len(rt_log):len(rt_log) + capacity_requests]
     cam = lambda e: synth.orbit_camera(e["width"], e["height"], e["azimuth"], e["elevation"], e["radius"])
-    t = time.time()
-    specs = scenes()
-    log(f"serving: {len(log_)} requests over {duration_s} s; scenes ready in {time.time() - t:.1f} s")
+    specs = {"plain": scenes(), "served": scenes()}
+    log(f"serving: {len(rt_log)} requests over {duration_s} s; scenes ready in {time.time() - t:.1f} s")
     free, total = torch.cuda.mem_get_info()
     budget = int(0.8 * free)
-    plain = serve.run_plain(ctx, specs, serve.make_requests(log_, cam))
-    log(f"plain: {plain}")
-    specs2 = scenes()
     # Instance estimate for admission: the 1080p / 1M level binning reaches ~1e9 instances.
-    est = lambda r: int(360.0 * r.cam.w * r.cam.h * specs2[r.scene].K)
-    b = serve.ContinuousBatcher(specs2, slots=slots, hbm_budget=budget, instance_estimate=est)
-    served = b.run(serve.make_requests(log_, cam))
-    log(f"served: {served}")
+    est = lambda sp: (lambda r: int(360.0 * r.cam.w * r.cam.h * sp[r.scene].K))
+
+    def requests(part):
+        # Per-scene frame counters continue from the real-time log into the capacity part.
+        start = {}
+        if part is cap_log:
+            for e in rt_log:
+                start[e["scene"]] = start.get(e["scene"], 0) + 1
+        return serve.make_requests(part, cam, scene_frames=start)
+
+    realtime = {"plain": serve.run_plain(ctx, specs["plain"], requests(rt_log), skip_s=2.0)}
+    log(f"plain (real time): {realtime['plain']}")
+    b = serve.ContinuousBatcher(specs["served"], slots=slots, hbm_budget=budget,
+                                instance_estimate=est(specs["served"]))
+    realtime["served"] = b.run(requests(rt_log), skip_s=2.0)
     sizes = [len(x) for x in b.batches]
-    return {"requests": len(log_), "rate_hz": rate_hz, "duration_s": duration_s,
-            "plain": {k: round(v, 3) for k, v in plain.items()},
-            "served": {k: round(v, 3) for k, v in served.items()},
+    log(f"served (real time): {realtime['served']}")
+
+    capacity = {"plain": serve.run_plain(ctx, specs["plain"], requests(cap_log), realtime=False)}
+    b2 = serve.ContinuousBatcher(specs["served"], slots=slots, hbm_budget=budget,
+                                 instance_estimate=est(specs["served"]))
+    capacity["served"] = b2.run(requests(cap_log), realtime=False)
+    log(f"capacity (closed loop): plain {capacity['plain']['frames_per_s']:.1f}, "
+        f"served {capacity['served']['frames_per_s']:.1f} frames/s")
+
+    # Cache accuracy.  The float-atomic adjoint sums in a different order on every run, so the
+    # two loops' caches above differ by that (and by its growth over thousands of noisy training
+    # steps); their error at probe cameras is reported as measured.  With the deterministic
+    # adjoint the same requests give the same caches whichever loop runs them: replayed on fresh
+    # scenes, every parameter is compared bit for bit.
+    probes = [synth.orbit_camera(640, 360, az) for az in (0.0, 90.0, 180.0, 270.0)]
+    refs = [[reference_levels(ctx, gv, cam_, wl.K, wl.max_bounces, wl.seed, spp=probe_spp) for cam_ in probes]
+            for wl, gv, _ in inputs]
+
+    def probe_l2(sp_list):
+        out = []
+        for i, sp in enumerate(sp_list):
+            per = [level_l2(cache_images(ctx, sp.scene, cam_), refs[i][j]) for j, cam_ in enumerate(probes)]
+            out.append([float(f"{sum(p[l] for p in per) / len(per):.6g}") for l in range(len(per[0]))])
+        return out
+
+    l2 = {k: probe_l2(specs[k]) for k in specs}
+    log(f"cache L2 (float atomics, mean of 4 probe cameras): {l2}")
+    for k in specs:
+        for sp in specs[k]:
+            sp.scene.destroy()
+    det_ctx = gsc.Context(0)
+    det_ctx.set_deterministic(True)
+    det = {"plain": scenes(), "served": scenes()}
+    n_det = min(len(rt_log), 480)
+    serve.run_plain(det_ctx, det["plain"], requests(rt_log[:n_det]), realtime=False)
+    serve.ContinuousBatcher(det["served"], slots=slots, hbm_budget=budget, deterministic=True,
+                            instance_estimate=est(det["served"])).run(requests(rt_log[:n_det]), realtime=False)
+    identical = all(torch.equal(a.scene.state(l)[k], b_.scene.state(l)[k])
+                    for a, b_ in zip(det["plain"], det["served"]) for l in range(a.K)
+                    for k in ("params", "m", "v"))
+    l2_det = {k: probe_l2(det[k]) for k in det}
+    log(f"deterministic replay of {n_det} requests: caches bit-identical {identical}; L2 {l2_det}")
+    for k in det:
+        for sp in det[k]:
+            sp.scene.destroy()
+    rnd = lambda d: {k: round(v, 3) for k, v in d.items()}
+    return {"requests": len(rt_log), "rate_hz": rate_hz, "duration_s": duration_s,
+            "plain": rnd(realtime["plain"]), "served": rnd(realtime["served"]),
             "served_batches": len(sizes), "mean_batch": round(float(sum(sizes)) / max(len(sizes), 1), 2),
+            "capacity_closed_loop": {"requests": len(cap_log),
+                                     "plain_frames_per_s": round(capacity["plain"]["frames_per_s"], 2),
+                                     "served_frames_per_s": round(capacity["served"]["frames_per_s"], 2),
+                                     "served_mean_batch": round(float(sum(len(x) for x in b2.batches))
+                                                                / max(len(b2.batches), 1), 2)},
+            "cache_l2": {"probe_cameras": "640x360, azimuths 0/90/180/270, elevation 20 (mean)",
+                         "ref_spp": probe_spp,
+                         "float_atomics_after_real_time_and_capacity_runs": {"plain": l2["plain"],
+                                                                             "served": l2["served"]},
+                         "deterministic_replay": {"requests": n_det, "bit_identical_caches": identical,
+                                                  "plain": l2_det["plain"], "served": l2_det["served"]}},
             "slots": slots, "hbm_budget_GB": round(budget / 1e9, 1)}
 
 
@@ -285,7 +360,7 @@ def main():
                     help="only run a plain 1 GiB device copy 5 times (calibrates HBM counters)")
     ap.add_argument("--deterministic", action="store_true",
                     help="sum the splat adjoint in fixed point (bit-reproducible gradients)")
-    ap.add_argument("--serve-seconds", type=float, default=8.0,
+    ap.add_argument("--serve-seconds", type=float, default=60.0,
                     help="length of the Poisson request log replayed served vs plain (0: skip)")
     args = ap.parse_args()
     if args.gpus != 1:
