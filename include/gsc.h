@@ -388,7 +388,7 @@ gsc_status gsc_splat_backward(gsc_ctx* ctx, const gsc_binning* bin, const gsc_ga
 /* For callers that cannot allocate device memory (code under HIP graph capture, tight serving
  * loops, harnesses that forbid hipMalloc): the same adjoint as gsc_splat_backward, same
  * arguments and results, but its temporaries (screen-space and parameter gradients before they
- * are copied out, the tile schedule) live in one static device array of the library, 49.3 MB
+ * are copied out, the tile schedule) live in one static device array of the library, 64.0 MB
  * per device, held until the process ends; it calls no hipMalloc / hipFree and no allocator
  * hook.  Limits: at most 524,288 Gaussians (all levels together) and 262,144 tiles per call,
  * else GSC_E_INVALID_ARG with a message and nothing enqueued.  Sums with float atomics:

@@ -28,6 +28,11 @@ constexpr int kFrameTileShiftY = 5;
 // 32x32 tiles win 10 % at 1080p with four levels, tie at 1080p with three, and lose 20-110 %
 // at 720p and 360p, where the longest tile list sets the splat adjoint's time.
 constexpr int64_t kAutoTiles32 = 6144;
+// The adjoint's screen-space gradients: one 64-byte record of 16 floats per Gaussian, [G][16]
+// (du, dv, dA, dB, dC, do, dr, dg, db, then 7 unused).  The nine float atomics of a (tile,
+// Gaussian) partial then fall in one aligned 64-byte line, and the adjoint issues them from nine
+// lanes of one instruction, which the memory system carries as one request.
+constexpr int kGrad2dStride = 16;
 constexpr int kMaxTf = 64;
 constexpr int kMaxLights = 8;
 constexpr int kChunk = 1024;            // depth-ordered Gaussians per binning chunk

@@ -80,8 +80,9 @@ __global__ void __launch_bounds__(256) project_kernel(const Seg* __restrict__ se
   if (core) core[i] = saturation_core(P, cam, sg.tsx, sg.tsy);
 }
 
-// Adjoint of the projection.  grad2d is SoA [9][G]: du, dv, dA, dB, dCc, do, dr, dg, db
-// (accumulated by the splat backward).  Writes (overwrites) the gradients of the 14 parameters.
+// Adjoint of the projection.  grad2d holds a 64-byte record per Gaussian, [G][kGrad2dStride]:
+// du, dv, dA, dB, dCc, do, dr, dg, db (accumulated by the splat backward).  Writes (overwrites)
+// the gradients of the 14 parameters.
 // The forward quantities are recomputed in fp32 exactly as the projection computes them.
 // Chain rule of one Gaussian (level-local index lid of segment sg) from the screen-space
 // gradients (u, v, conic A, B, C, opacity o) to its mean, quaternion, log-scales and opacity
@@ -239,6 +240,15 @@ __device__ __forceinline__ void project_grads(const Seg& sg, const DevCam& cam, 
   gq[3] = (dqz - qz * dot) * iq;
 }
 
+// The nine screen-space gradients of Gaussian i (three aligned 16-byte loads of its record).
+__device__ __forceinline__ void load_grad2d(const float* __restrict__ grad2d, int64_t i, float g[12]) {
+  const float4* r = reinterpret_cast<const float4*>(grad2d + i * kGrad2dStride);
+  const float4 a = r[0], b = r[1], c = r[2];
+  g[0] = a.x; g[1] = a.y; g[2] = a.z; g[3] = a.w;
+  g[4] = b.x; g[5] = b.y; g[6] = b.z; g[7] = b.w;
+  g[8] = c.x; g[9] = c.y; g[10] = c.z; g[11] = c.w;
+}
+
 __global__ void __launch_bounds__(256) project_backward_kernel(
     const Seg* __restrict__ segs, const int64_t* __restrict__ seg_gstart, int S,
     const DevCam* __restrict__ cams, int64_t G, const float* __restrict__ grad2d,
@@ -252,11 +262,12 @@ __global__ void __launch_bounds__(256) project_backward_kernel(
   float* base = grads14 + 14 * sg.g_off;
   const int64_t nn = sg.n;
   float* gc = base + 10 * nn + 3 * lid;
-  gc[0] = grad2d[6 * G + i];
-  gc[1] = grad2d[7 * G + i];
-  gc[2] = grad2d[8 * G + i];
-  project_grads(sg, cams[sg.cam], lid, grad2d[0 * G + i], grad2d[1 * G + i], grad2d[2 * G + i],
-                grad2d[3 * G + i], grad2d[4 * G + i], grad2d[5 * G + i], base + 3 * lid,
+  float g[12];
+  load_grad2d(grad2d, i, g);
+  gc[0] = g[6];
+  gc[1] = g[7];
+  gc[2] = g[8];
+  project_grads(sg, cams[sg.cam], lid, g[0], g[1], g[2], g[3], g[4], g[5], base + 3 * lid,
                 base + 3 * nn + 4 * lid, base + 7 * nn + 3 * lid, base + 13 * nn + lid);
 }
 
@@ -289,12 +300,13 @@ __global__ void __launch_bounds__(256) project_backward_adam_kernel(
     if (live) {
       const Seg sg = segs[s];
       const int64_t lid = i - sg.g_off;
-      project_grads(sg, cams[sg.cam], lid, grad2d[0 * G + i], grad2d[1 * G + i], grad2d[2 * G + i],
-                    grad2d[3 * G + i], grad2d[4 * G + i], grad2d[5 * G + i], gr14, gr14 + 3,
+      float g[12];
+      load_grad2d(grad2d, i, g);
+      project_grads(sg, cams[sg.cam], lid, g[0], g[1], g[2], g[3], g[4], g[5], gr14, gr14 + 3,
                     gr14 + 7, gr14 + 13);
-      gr14[10] = grad2d[6 * G + i];
-      gr14[11] = grad2d[7 * G + i];
-      gr14[12] = grad2d[8 * G + i];
+      gr14[10] = g[6];
+      gr14[11] = g[7];
+      gr14[12] = g[8];
     }
   }
   if (s_first != s_last) {                 // straddles a segment boundary: per-thread updates

@@ -304,13 +304,15 @@ __device__ __forceinline__ double fixed_scale(uint32_t max_bits) {
   return m > 0.0f ? ldexp(1.0, 40 - ilogbf(m)) : 0.0;
 }
 
+// gmax, gfix: [9][G]; grad2d: [G][kGrad2dStride].
 __global__ void __launch_bounds__(256) fixed_to_float_kernel(const uint32_t* __restrict__ gmax,
                                                              const unsigned long long* __restrict__ gfix,
                                                              int64_t G, float* __restrict__ grad2d) {
   const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
   if (i >= 9 * G) return;
   const double sc = fixed_scale(gmax[i]);
-  grad2d[i] = sc > 0.0 ? (float)((double)(long long)gfix[i] / sc) : 0.0f;
+  const int64_t a = i / G, g = i - a * G;
+  grad2d[g * kGrad2dStride + a] = sc > 0.0 ? (float)((double)(long long)gfix[i] / sc) : 0.0f;
 }
 
 // Sum over each 16-lane row; lane 15 of the row receives it (a prefix sum by row shifts of
@@ -338,6 +340,7 @@ __global__ void __launch_bounds__(64) splat_backward_kernel(
     const uint64_t* __restrict__ n_inst, uint64_t capacity) {
   if (*n_inst > capacity) return;               // incomplete lists (see the forward)
   __shared__ float part[4][64][kPartStride];    // [row group][entry][component]
+  __shared__ uint32_t sent[64], sid[64];        // entries with partials: batch position, id
   const int64_t b = (int64_t)blockIdx.x / kW;
   const int64_t t = order ? (int64_t)order[b] : b;
   const Tile<kS> tc = tile_setup<kS, kW, 1>(segs, seg_tstart, S, cams, ranges, t,
@@ -461,22 +464,33 @@ __global__ void __launch_bounds__(64) splat_backward_kernel(
       }
     }
     if (has == 0ull) continue;
-    __syncthreads();
+    // The entries with partials, in order, then their nine sums: lane 9 j + a adds component a
+    // of the (j0 + j)-th of them, seven entries per instruction, so the nine atomics of an entry
+    // go out together and land in one 64-byte record.
     if ((has >> lane) & 1ull) {
-      const int64_t gi = tc.g_off + (int64_t)my_id;
-#pragma unroll
-      for (int a = 0; a < 9; ++a) {
-        const float acc = (part[0][lane][a] + part[1][lane][a]) + (part[2][lane][a] + part[3][lane][a]);
-        const int64_t at = (int64_t)a * G + gi;
+      const int r = __popcll(has & ((1ull << lane) - 1ull));
+      sent[r] = (uint32_t)lane;
+      sid[r] = my_id;
+    }
+    __syncthreads();
+    const int E = __popcll(has);
+    const int jl = lane / 9, a = lane - 9 * jl;
+    for (int j0 = 0; j0 < E; j0 += 7) {
+      const int j = j0 + jl;
+      if (lane < 63 && j < E) {
+        const uint32_t k = sent[j];
+        const float acc = (part[0][k][a] + part[1][k][a]) + (part[2][k][a] + part[3][k][a]);
+        const int64_t gi = tc.g_off + (int64_t)sid[j];
         if (mode == kAdjointAtomic) {
           if (acc != 0.0f) {
-            unsafeAtomicAdd(&grad2d[at], acc);
+            unsafeAtomicAdd(&grad2d[gi * kGrad2dStride + a], acc);
             if (kCount) ++n_atomics;
           }
         } else if (mode == kAdjointMax) {
-          if (acc != 0.0f) atomicMax(&gmax[at], __float_as_uint(fabsf(acc)));
+          if (acc != 0.0f) atomicMax(&gmax[(int64_t)a * G + gi], __float_as_uint(fabsf(acc)));
         } else {
           // Integer sums do not depend on the order in which the atomics land.
+          const int64_t at = (int64_t)a * G + gi;
           const long long qv = llrint((double)acc * fixed_scale(gmax[at]));
           if (qv) atomicAdd(&gfix[at], (unsigned long long)qv);
         }

@@ -573,9 +573,10 @@ void run_forward(gsc_ctx* ctx, gsc_binning* b, float* images, float* final_T, in
   b->forward_done = true;
 }
 
-// The splat adjoint into b->grad2d ([9][G] screen-space gradients).
+// The splat adjoint into b->grad2d ([G][kGrad2dStride] screen-space gradients).
 void run_splat_adjoint(gsc_ctx* ctx, gsc_binning* b, const float* final_T, const float* dL) {
-  need(ctx, b->grad2d, b->alloc, 4 * 9 * (size_t)std::max<int64_t>(b->G, 1), "2D gradients");
+  need(ctx, b->grad2d, b->alloc, 4 * kGrad2dStride * (size_t)std::max<int64_t>(b->G, 1),
+       "2D gradients");
   uint32_t* gmax = nullptr;
   unsigned long long* gfix = nullptr;
   if (ctx->deterministic) {
@@ -584,7 +585,7 @@ void run_splat_adjoint(gsc_ctx* ctx, gsc_binning* b, const float* final_T, const
     gfix = b->gfix.as<unsigned long long>();
     gmax = (uint32_t*)(gfix + 9 * (size_t)b->G);
   } else {
-    GSC_TRY(hipMemsetAsync(b->grad2d.p, 0, 4 * 9 * (size_t)b->G, ctx->stream));
+    GSC_TRY(hipMemsetAsync(b->grad2d.p, 0, 4 * kGrad2dStride * (size_t)b->G, ctx->stream));
   }
   const uint32_t* order = tile_order(ctx, b, b->tile_work.as<uint32_t>());
   if (ctx->work_counters && !ctx->d_stats.p) {
@@ -1014,7 +1015,7 @@ std::vector<std::pair<int64_t, int64_t>> parse_state_header(gsc_ctx* ctx, const 
 // C ABI
 // =============================================================================================
 // ---- the allocation-free adjoint's scratch ------------------------------------------------------
-// gsc_splat_backward_noalloc keeps its temporaries (the [9][G] screen-space gradients, the
+// gsc_splat_backward_noalloc keeps its temporaries (the [G][16] screen-space gradients, the
 // [14][G] parameter gradients before they are copied out, the tile schedule) in one file-scope
 // device array instead of allocating them.  Every device the library runs on holds its own copy
 // until the process ends; host code uses only the address hipGetSymbolAddress gives for the
@@ -1022,7 +1023,7 @@ std::vector<std::pair<int64_t, int64_t>> parse_state_header(gsc_ctx* ctx, const 
 constexpr int64_t kNoAllocMaxGaussians = int64_t(1) << 19;     // 524,288 Gaussians per call
 constexpr int64_t kNoAllocMaxTiles = int64_t(1) << 18;         // 262,144 tiles per call
 constexpr size_t kNoAllocScratchBytes =
-    (size_t)(9 + 14) * 4 * (size_t)kNoAllocMaxGaussians + 4 * (size_t)kNoAllocMaxTiles;
+    (size_t)(kGrad2dStride + 14) * 4 * (size_t)kNoAllocMaxGaussians + 4 * (size_t)kNoAllocMaxTiles;
 static __device__ __align__(256) unsigned char scratch[kNoAllocScratchBytes];
 
 constexpr int kMaxDevices = 64;
@@ -1426,10 +1427,10 @@ gsc_status gsc_splat_backward_noalloc(gsc_ctx* ctx, const gsc_binning* bin,
     hipStream_t st = ctx->stream;
     const int64_t G = b->G;
     float* g2d = (float*)ctx->scratch;
-    float* g14 = g2d + 9 * kNoAllocMaxGaussians;
+    float* g14 = g2d + kGrad2dStride * kNoAllocMaxGaussians;
     uint32_t* order = (uint32_t*)(g14 + 14 * kNoAllocMaxGaussians);
     // Cleared by a kernel (no memset node), so the call can be captured in a graph.
-    GSC_TRY(launch_fill_u32(st, (uint32_t*)g2d, 0u, 9 * G));
+    GSC_TRY(launch_fill_u32(st, (uint32_t*)g2d, 0u, kGrad2dStride * G));
     GSC_TRY(launch_tile_order(st, b->ranges.as<uint64_t>(), b->tile_work.as<uint32_t>(), b->n_tiles,
                               order));
     GSC_TRY(launch_splat_backward(st, b->d_segs(), b->d_tstart(), b->S, b->d_cams(), b->n_tiles,
