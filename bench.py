@@ -468,9 +468,13 @@ def main():
                     "measured_ceiling_TFLOPs": ceil["valu_fma_TFLOPs"],
                     "frac_vs_measured": round(achieved / ceil["valu_fma_TFLOPs"], 4)}
         if dominant == "splat_backward":
+            # Atomic requests: each (tile, Gaussian) partial goes out as up to nine adds into one
+            # 64-byte record, one request; the probe's scattered adds are one request each.
             at = work["bwd_atomics"] / launches_per_frame / (per_launch_ms * 1e-3)
-            roofline["atomics_per_s"] = round(at, 1)
-            roofline["atomics_frac_vs_measured"] = round(at / ceil["atomic_add_f32_per_s"], 4)
+            rq = work["bwd_records"] / launches_per_frame / (per_launch_ms * 1e-3)
+            roofline["atomic_adds_per_s"] = round(at, 1)
+            roofline["atomic_requests_per_s"] = round(rq, 1)
+            roofline["atomic_requests_frac_vs_measured"] = round(rq / ceil["atomic_add_f32_per_s"], 4)
     else:
         per_launch = algorithmic_bytes(dominant, c) / launches_per_frame
         achieved = per_launch / (per_launch_ms * 1e-3) / 1e9
@@ -554,6 +558,7 @@ def main():
                      "slot_evaluations_adjoint": int(work["bwd_slots"]),
                      "adjoint_entries_walked": int(work["bwd_entries"]),
                      "adjoint_atomics": int(work["bwd_atomics"]),
+                     "adjoint_atomic_requests": int(work["bwd_records"]),
                      "tested_pairs_forward_per_s": round(work["fwd_tested"] * fps, 1),
                      "paths_per_frame": int(c["paths"]),
                      "path_vertices_per_frame": int(stats["path_vertices"]),

@@ -297,6 +297,8 @@ typedef struct gsc_counters {
   uint64_t bwd_slots;      /* adjoint: 64-pixel slot evaluations */
   uint64_t bwd_entries;    /* adjoint: (tile, entry) pairs walked after the tile-ellipse cull */
   uint64_t bwd_atomics;    /* adjoint: float atomics issued into the screen-space gradients */
+  uint64_t bwd_records;    /* adjoint: (tile, Gaussian) partials flushed, each as up to nine
+                              atomics into one 64-byte record (one memory request) */
   uint64_t frame_retries;  /* frames run again because their binning outgrew the capacity sized
                               from the previous frame (see gsc_render_frame) */
 } gsc_counters;

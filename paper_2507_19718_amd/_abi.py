@@ -94,7 +94,7 @@ class gsc_counters(Structure):
                 ("blended", c_uint64), ("contributors", c_uint64), ("tile_entries", c_uint64),
                 ("fwd_tested", c_uint64), ("fwd_slots", c_uint64), ("bwd_tested", c_uint64),
                 ("bwd_blended", c_uint64), ("bwd_slots", c_uint64), ("bwd_entries", c_uint64),
-                ("bwd_atomics", c_uint64), ("frame_retries", c_uint64)]
+                ("bwd_atomics", c_uint64), ("bwd_records", c_uint64), ("frame_retries", c_uint64)]
 
     def as_dict(self):
         return {k: int(getattr(self, k)) for k, _ in self._fields_}

@@ -156,7 +156,7 @@ __device__ __forceinline__ bool lane_in(uint64_t mask) {
 // adds [6] pairs tested, [7] pairs blended, [8] slot evaluations, [9] entries walked after the
 // cull and [10] float atomics issued.
 enum { kStEval = 0, kStBlend, kStContrib, kStEntries, kStFwdTested, kStFwdSlots, kStBwdTested,
-       kStBwdBlend, kStBwdSlots, kStBwdEntries, kStBwdAtomics, kStWords };
+       kStBwdBlend, kStBwdSlots, kStBwdEntries, kStBwdAtomics, kStBwdRecords, kStWords };
 
 // Workgroup b takes block b % (kW kH) of tile order[b / (kW kH)] (one independent wavefront
 // per block).
@@ -369,7 +369,7 @@ __global__ void __launch_bounds__(64) splat_backward_kernel(
 #pragma unroll
   for (int off = 32; off > 0; off >>= 1) mx = max(mx, (uint32_t)__shfl_xor((int)mx, off, 64));
   const int64_t stop = tc.start + (int64_t)mx;
-  uint64_t n_tested = 0u, n_blended = 0u, n_slots = 0u, n_entries = 0u;
+  uint64_t n_tested = 0u, n_blended = 0u, n_slots = 0u, n_entries = 0u, n_records = 0u;
   uint32_t n_atomics = 0u;
   for (int64_t be = stop; be > tc.start; be -= 64) {
     const int64_t bs = (be - 64) > tc.start ? (be - 64) : tc.start;
@@ -474,6 +474,7 @@ __global__ void __launch_bounds__(64) splat_backward_kernel(
     }
     __syncthreads();
     const int E = __popcll(has);
+    if (kCount) n_records += (uint64_t)E;
     const int jl = lane / 9, a = lane - 9 * jl;
     for (int j0 = 0; j0 < E; j0 += 7) {
       const int j = j0 + jl;
@@ -508,6 +509,7 @@ __global__ void __launch_bounds__(64) splat_backward_kernel(
       atomicAdd(&stats[kStBwdSlots], (unsigned long long)n_slots);
       atomicAdd(&stats[kStBwdEntries], (unsigned long long)n_entries);
       atomicAdd(&stats[kStBwdAtomics], (unsigned long long)na);
+      atomicAdd(&stats[kStBwdRecords], (unsigned long long)n_records);
     }
   }
 }

@@ -266,7 +266,7 @@ const char* const kProfNames[] = {"project", "depth_sort", "bin_count", "bin_sca
                                   "project_backward", "adam", "gather_rect",
                                   "project_backward_adam"};
 constexpr int kProfCount = 13;
-constexpr int kStatWords = 11;  // splat work counters (gsc_counters; see k_splat.hip)
+constexpr int kStatWords = 12;  // splat work counters (gsc_counters; see k_splat.hip)
 enum { P_PROJECT, P_SORT, P_COUNT, P_SCAN, P_PLACE, P_FWD, P_TRACE, P_LOSS, P_BWD, P_PBWD, P_ADAM,
        P_GATHER, P_PBADAM };
 
@@ -1928,6 +1928,7 @@ gsc_status gsc_ctx_counters(gsc_ctx* ctx, gsc_counters* out) {
     out->bwd_slots = d[8];
     out->bwd_entries = d[9];
     out->bwd_atomics = d[10];
+    out->bwd_records = d[11];
     return GSC_OK;
   });
 }

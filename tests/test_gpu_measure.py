@@ -50,8 +50,10 @@ def test_work_counters_of_a_training_frame(gsc, gctx):
     # contributor, so they may walk more entries than the forward's wavefronts evaluated.)
     assert d["bwd_entries"] > 0
     # At most nine float atomics per walked (tile, entry) pair, at least one per pair that
-    # blended anything.
+    # blended anything; they go out as one record of up to nine adds per such pair.
     assert 0 < d["bwd_atomics"] <= 9 * d["bwd_entries"]
+    assert 0 < d["bwd_records"] <= d["bwd_entries"]
+    assert d["bwd_records"] <= d["bwd_atomics"] <= 9 * d["bwd_records"]
 
 
 def test_ceiling_probes(gsc, gctx):
