@@ -36,7 +36,6 @@ sys.path.insert(0, ROOT)
 METRIC = "GS-cache frames/s @1080p (trace+splat fwd/bwd) & p50/p99 ms, served vs plain"
 HBM_PEAK_GBS = 8000.0
 FP32_PEAK_TFLOPS = 157.3          # published: packed fp32 FMA, 256 CUs x 2.4 GHz x 128 lanes x 2 x 2
-FP32_NONPACKED_TFLOPS = 78.6      # the same without packed fp32 (the build disables it)
 
 
 def log(msg):
@@ -464,7 +463,6 @@ def main():
         achieved = per_launch / (per_launch_ms * 1e-3) / 1e12
         roofline = {"bound": "alu", "achieved": round(achieved, 2), "peak": FP32_PEAK_TFLOPS,
                     "unit": "TFLOP/s", "frac": round(achieved / FP32_PEAK_TFLOPS, 4),
-                    "frac_vs_nonpacked_78.6": round(achieved / FP32_NONPACKED_TFLOPS, 4),
                     "measured_ceiling_TFLOPs": ceil["valu_fma_TFLOPs"],
                     "frac_vs_measured": round(achieved / ceil["valu_fma_TFLOPs"], 4)}
         if dominant == "splat_backward":
