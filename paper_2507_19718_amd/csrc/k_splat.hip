@@ -31,7 +31,7 @@ namespace {
 constexpr float kAlphaMin = 1.0f / 255.0f;
 constexpr float kAlphaMax = 0.99f;
 constexpr float kTmin = 1e-4f;
-constexpr int kPartStride = 10;   // floats per (row group, entry) of the adjoint's LDS partials
+constexpr int kPartStride = 10;   // floats per entry of the adjoint's LDS sums
 
 template <int kS>
 struct Tile {
@@ -315,17 +315,6 @@ __global__ void __launch_bounds__(256) fixed_to_float_kernel(const uint32_t* __r
   grad2d[g * kGrad2dStride + a] = sc > 0.0 ? (float)((double)(long long)gfix[i] / sc) : 0.0f;
 }
 
-// Sum over each 16-lane row; lane 15 of the row receives it (a prefix sum by row shifts of
-// 1, 2, 4 and 8 lanes with zero fill).
-__device__ __forceinline__ float row_total(float v) {
-  float t = v;
-  t = t + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(t), 0x111, 0xf, 0xf, true));
-  t = t + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(t), 0x112, 0xf, 0xf, true));
-  t = t + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(t), 0x114, 0xf, 0xf, true));
-  t = t + __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(t), 0x118, 0xf, 0xf, true));
-  return t;
-}
-
 // Workgroup b walks block b % kW (16 x 4 kS, the tile's blocks side by side) of tile
 // order[b / kW], one independent wavefront per block.
 template <bool kCount, int kS, int kW>
@@ -339,7 +328,8 @@ __global__ void __launch_bounds__(64) splat_backward_kernel(
     unsigned long long* __restrict__ gfix, unsigned long long* __restrict__ stats,
     const uint64_t* __restrict__ n_inst, uint64_t capacity) {
   if (*n_inst > capacity) return;               // incomplete lists (see the forward)
-  __shared__ float part[4][64][kPartStride];    // [row group][entry][component]
+  __shared__ float part[64][kPartStride];       // [entry][component]: the wave's sums
+  __shared__ __align__(16) float red[9][64];    // one entry's per-lane values, by component
   __shared__ uint32_t sent[64], sid[64];        // entries with partials: batch position, id
   const int64_t b = (int64_t)blockIdx.x / kW;
   const int64_t t = order ? (int64_t)order[b] : b;
@@ -454,13 +444,23 @@ __global__ void __launch_bounds__(64) splat_backward_kernel(
       const float sB = -dx * m1;
       const float su = fmaf(-B, m1, (-A * dx) * m0);
       const float sv = fmaf(-Cc, m1, (-B * dx) * m0);
-      const float r0 = row_total(su), r1 = row_total(sv), r2 = row_total(sA);
-      const float r3 = row_total(sB), r4 = row_total(sC), r5 = row_total(so);
-      const float r6 = row_total(sr), r7 = row_total(sg), r8 = row_total(sb);
-      if ((lane & 15) == 15) {
-        float* d = part[lane >> 4][k];
-        d[0] = r0; d[1] = r1; d[2] = r2; d[3] = r3; d[4] = r4;
-        d[5] = r5; d[6] = r6; d[7] = r7; d[8] = r8;
+      // The wave's nine sums through LDS (a transpose instead of per-row DPP steps): every lane
+      // parks its nine values by component; lane 16 r + a then adds the sixteen values of
+      // component a in row r (lanes with a >= 9 add a copy of component 8 and are ignored),
+      // and two shuffles add the four rows.  A single wave runs the workgroup and its LDS
+      // accesses complete in order, so no barrier is needed.
+      red[0][lane] = su; red[1][lane] = sv; red[2][lane] = sA;
+      red[3][lane] = sB; red[4][lane] = sC; red[5][lane] = so;
+      red[6][lane] = sr; red[7][lane] = sg; red[8][lane] = sb;
+      {
+        const int ra = (lane & 15) < 9 ? (lane & 15) : 8;
+        const float4* q = reinterpret_cast<const float4*>(&red[ra][lane & 48]);
+        const float4 x0 = q[0], x1 = q[1], x2 = q[2], x3 = q[3];
+        float t = ((x0.x + x0.y) + (x0.z + x0.w)) + ((x1.x + x1.y) + (x1.z + x1.w)) +
+                  (((x2.x + x2.y) + (x2.z + x2.w)) + ((x3.x + x3.y) + (x3.z + x3.w)));
+        t += __shfl_xor(t, 32, 64);
+        t += __shfl_xor(t, 16, 64);
+        if (lane < 9) part[k][lane] = t;
       }
     }
     if (has == 0ull) continue;
@@ -480,7 +480,7 @@ __global__ void __launch_bounds__(64) splat_backward_kernel(
       const int j = j0 + jl;
       if (lane < 63 && j < E) {
         const uint32_t k = sent[j];
-        const float acc = (part[0][k][a] + part[1][k][a]) + (part[2][k][a] + part[3][k][a]);
+        const float acc = part[k][a];
         const int64_t gi = tc.g_off + (int64_t)sid[j];
         if (mode == kAdjointAtomic) {
           if (acc != 0.0f) {
