@@ -220,7 +220,10 @@ __global__ void __launch_bounds__(64) splat_forward_kernel(
       uint64_t win[kS];
       window_masks<kS>(rlu(q2.y, k), rlu(q2.z, k), tc.xbase, tc.ybase, win);
       const float dx = u - tc.fi;
-      const float adx = (A * dx) * dx;
+      // power = -(A dx^2 + C dy^2) / 2 - B dx dy, with the halving applied to A dx^2 and C
+      // beforehand: scaling by -1/2 is exact, so every rounding, and the result, are unchanged.
+      const float adxh = -0.5f * ((A * dx) * dx);
+      const float Ch = -0.5f * Cc;
       const float bdx = B * dx;
       const uint32_t pos = rel0 + (uint32_t)k + 1u;
 #pragma unroll
@@ -229,7 +232,7 @@ __global__ void __launch_bounds__(64) splat_forward_kernel(
         if (act == 0ull) continue;
         if (kCount) { n_tested += (uint64_t)__popcll(act); ++n_slots; }
         const float dy = v - tc.fj[p];
-        const float power = -0.5f * (adx + (Cc * dy) * dy) - bdx * dy;
+        const float power = (adxh + (Ch * dy) * dy) - bdx * dy;
         const float alpha = fminf(kAlphaMax, o * __expf(power));
         // Lane masks on the scalar unit: ballots of single compares cost no vector work.
         const uint64_t okm = act & __builtin_amdgcn_ballot_w64(!(power > 0.0f)) &
@@ -329,7 +332,9 @@ __global__ void __launch_bounds__(64) splat_backward_kernel(
     const uint64_t* __restrict__ n_inst, uint64_t capacity) {
   if (*n_inst > capacity) return;               // incomplete lists (see the forward)
   __shared__ float part[64][kPartStride];       // [entry][component]: the wave's sums
-  __shared__ __align__(16) float red[9][64];    // one entry's per-lane values, by component
+  // One entry's per-lane values by component; rows padded to 68 floats so that the sixteen-float
+  // reads of the nine components start in different banks.
+  __shared__ __align__(16) float red[9][68];
   __shared__ uint32_t sent[64], sid[64];        // entries with partials: batch position, id
   const int64_t b = (int64_t)blockIdx.x / kW;
   const int64_t t = order ? (int64_t)order[b] : b;
@@ -388,7 +393,9 @@ __global__ void __launch_bounds__(64) splat_backward_kernel(
       uint64_t win[kS];
       window_masks<kS>(rlu(q2.y, k), rlu(q2.z, k), tc.xbase, tc.ybase, win);
       const float dx = u - tc.fi;
-      const float adx = (A * dx) * dx;
+      // The halving of the quadratic form applied beforehand (exact; see the forward).
+      const float adxh = -0.5f * ((A * dx) * dx);
+      const float Ch = -0.5f * Cc;
       const float bdx = B * dx;
       const uint32_t rel = rel0 + (uint32_t)k;
       // Per lane, the moments of dL/dpower over its pixels (all in one column, so dx is
@@ -402,7 +409,7 @@ __global__ void __launch_bounds__(64) splat_backward_kernel(
         const uint64_t act = win[p] & __builtin_amdgcn_ballot_w64(rel < nc[p]);
         if (act == 0ull) continue;
         const float dy = v - tc.fj[p];
-        const float power = -0.5f * (adx + (Cc * dy) * dy) - bdx * dy;
+        const float power = (adxh + (Ch * dy) * dy) - bdx * dy;
         const float e = __expf(power);
         const float oe = o * e;
         const float alpha = fminf(kAlphaMax, oe);
