@@ -115,11 +115,6 @@ __device__ __forceinline__ uint32_t rlu(float v, int k) {
   return (uint32_t)__builtin_amdgcn_readlane(__float_as_int(v), k);
 }
 
-// Lane k's value in every lane, in a vector register (ds_bpermute with a uniform address).
-// Broadcasting through v_readlane into scalar registers measured slower in both kernels.
-__device__ __forceinline__ float bcast(float v, int k) {
-  return __int_as_float(__builtin_amdgcn_ds_bpermute(k << 2, __float_as_int(v)));
-}
 
 // Lane masks of the tile's pixels inside a Gaussian's integer window (packed full-frame bounds
 // wx = px0 | px1 << 16, wy = py0 | py1 << 16), one per slot.  Uniform arithmetic: it runs on
@@ -177,6 +172,10 @@ __global__ void __launch_bounds__(64) splat_forward_kernel(
   const Tile<kS> tc = tile_setup<kS, kW, kH>(segs, seg_tstart, S, cams, ranges, t,
                                               (int)(blockIdx.x % (kW * kH)));
   const int lane = __lane_id();
+  // The batch's records, one per lane.  Each entry's values reach every lane as LDS reads at one
+  // address (broadcasts): three loads instead of nine lane-to-lane permutes (ds_bpermute), and
+  // broadcasting through v_readlane into scalar registers measured slower still.
+  __shared__ float4 srec[3][64];
   float T[kS], C0[kS], C1[kS], C2[kS];
   uint32_t nc[kS], stop[kS];
   uint64_t done[kS];                     // lanes finished (terminated, or outside the image)
@@ -205,6 +204,7 @@ __global__ void __launch_bounds__(64) splat_forward_kernel(
       q0 = r.q0; q1 = r.q1; q2 = r.q2;
       keep = may_touch(q0, q1, q2, tc);
     }
+    srec[0][lane] = q0; srec[1][lane] = q1; srec[2][lane] = q2;
     uint64_t mask = __ballot(keep);
     const uint32_t rel0 = (uint32_t)(bs - tc.start);
     while (mask) {
@@ -212,11 +212,12 @@ __global__ void __launch_bounds__(64) splat_forward_kernel(
       const int k = __builtin_ctzll(mask);
       mask &= mask - 1ull;
       ++n_entries;
-      const float u = bcast(q0.x, k), v = bcast(q0.y, k);
-      const float A = bcast(q0.z, k), B = bcast(q0.w, k);
-      const float Cc = bcast(q1.x, k), o = bcast(q1.y, k);
-      const float cr = bcast(q1.z, k), cg = bcast(q1.w, k);
-      const float cb = bcast(q2.x, k);
+      // Entry k's record from LDS, read at one address by every lane (a broadcast): three
+      // loads instead of nine lane-to-lane permutes.
+      const float4 e0 = srec[0][k], e1 = srec[1][k];
+      const float cb = srec[2][k].x;
+      const float u = e0.x, v = e0.y, A = e0.z, B = e0.w;
+      const float Cc = e1.x, o = e1.y, cr = e1.z, cg = e1.w;
       uint64_t win[kS];
       window_masks<kS>(rlu(q2.y, k), rlu(q2.z, k), tc.xbase, tc.ybase, win);
       const float dx = u - tc.fi;
@@ -336,6 +337,7 @@ __global__ void __launch_bounds__(64) splat_backward_kernel(
   // reads of the nine components start in different banks.
   __shared__ __align__(16) float red[9][68];
   __shared__ uint32_t sent[64], sid[64];        // entries with partials: batch position, id
+  __shared__ float4 srec[3][64];                // the batch's records, one per lane
   const int64_t b = (int64_t)blockIdx.x / kW;
   const int64_t t = order ? (int64_t)order[b] : b;
   const Tile<kS> tc = tile_setup<kS, kW, 1>(segs, seg_tstart, S, cams, ranges, t,
@@ -378,6 +380,7 @@ __global__ void __launch_bounds__(64) splat_backward_kernel(
       q0 = r.q0; q1 = r.q1; q2 = r.q2;
       keep = may_touch(q0, q1, q2, tc);
     }
+    srec[0][lane] = q0; srec[1][lane] = q1; srec[2][lane] = q2;
     uint64_t mask = __ballot(keep);
     uint64_t has = 0ull;                       // entries whose row sums are parked in LDS
     const uint32_t rel0 = (uint32_t)(bs - tc.start);
@@ -385,11 +388,12 @@ __global__ void __launch_bounds__(64) splat_backward_kernel(
       const int k = 63 - __builtin_clzll(mask);          // back to front
       mask &= ~(1ull << k);
       if (kCount) ++n_entries;
-      const float u = bcast(q0.x, k), v = bcast(q0.y, k);
-      const float A = bcast(q0.z, k), B = bcast(q0.w, k);
-      const float Cc = bcast(q1.x, k), o = bcast(q1.y, k);
-      const float cr = bcast(q1.z, k), cg = bcast(q1.w, k);
-      const float cb = bcast(q2.x, k);
+      // Entry k's record from LDS, read at one address by every lane (a broadcast): three
+      // loads instead of nine lane-to-lane permutes.
+      const float4 e0 = srec[0][k], e1 = srec[1][k];
+      const float cb = srec[2][k].x;
+      const float u = e0.x, v = e0.y, A = e0.z, B = e0.w;
+      const float Cc = e1.x, o = e1.y, cr = e1.z, cg = e1.w;
       uint64_t win[kS];
       window_masks<kS>(rlu(q2.y, k), rlu(q2.z, k), tc.xbase, tc.ybase, win);
       const float dx = u - tc.fi;
