@@ -609,10 +609,16 @@ void splat_backward_dispatch(hipStream_t st, const Seg* segs, const int64_t* seg
                          grad2d, G, order, (int)kAdjointAtomic, gmax, gfix, stats, n_inst, capacity);
     return;
   }
-  // Deterministic: gmax [9][G] and gfix [9][G] must be zero on entry.
-  hipLaunchKernelGGL((splat_backward_kernel<false, kS, kW>), grid, block, 0, st, segs, seg_tstart, S,
-                     cams, ranges, values, rec, final_T, n_contrib, dL_dimages, grad2d, G, order,
-                     (int)kAdjointMax, gmax, gfix, stats, n_inst, capacity);
+  // Deterministic: gmax [9][G] and gfix [9][G] must be zero on entry.  The first pass counts
+  // the work when asked (the second walks the same pairs).
+  if (count && stats)
+    hipLaunchKernelGGL((splat_backward_kernel<true, kS, kW>), grid, block, 0, st, segs, seg_tstart,
+                       S, cams, ranges, values, rec, final_T, n_contrib, dL_dimages, grad2d, G,
+                       order, (int)kAdjointMax, gmax, gfix, stats, n_inst, capacity);
+  else
+    hipLaunchKernelGGL((splat_backward_kernel<false, kS, kW>), grid, block, 0, st, segs, seg_tstart,
+                       S, cams, ranges, values, rec, final_T, n_contrib, dL_dimages, grad2d, G,
+                       order, (int)kAdjointMax, gmax, gfix, stats, n_inst, capacity);
   hipLaunchKernelGGL((splat_backward_kernel<false, kS, kW>), grid, block, 0, st, segs, seg_tstart, S,
                      cams, ranges, values, rec, final_T, n_contrib, dL_dimages, grad2d, G, order,
                      (int)kAdjointFixed, gmax, gfix, stats, n_inst, capacity);
