@@ -371,52 +371,113 @@ __global__ void __launch_bounds__(256) bin_place_kernel(const BinWork* __restric
 // Per tile: exclusive scan over chunks (in place) and the tile total.  With wsum, chunks after
 // the one at which the running saturation weight reaches kCutWeight add nothing.  cut[tile] is
 // the last kept chunk that has entries for the tile (-1: none), so placement can skip the rest.
-__global__ void __launch_bounds__(256) chunk_scan_kernel(const BinWork* __restrict__ work,
-                                                         const int64_t* __restrict__ seg_tstart,
-                                                         int S, int64_t n_tiles,
-                                                         uint32_t* __restrict__ counts,
-                                                         uint32_t* __restrict__ tile_total,
-                                                         const uint32_t* __restrict__ wsum,
-                                                         int32_t* __restrict__ cut,
-                                                         int32_t* __restrict__ region_n) {
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (t >= n_tiles) return;
-  const int s = find_segment(seg_tstart, S, t);
-  const BinWork W = work[s];
-  const int64_t lt = t - W.tile_base;
-  const int64_t T = (int64_t)W.TX * W.TY;
-  uint32_t run = 0u, weight = 0u;
-  int last = W.n_chunks - 1, last_nz = -1;
-  // Sixteen chunks' loads in flight at a time (the loop is latency-bound otherwise).
-  constexpr int kAhead = 16;
-  for (int cb = 0; cb < W.n_chunks; cb += kAhead) {
-    uint32_t v[kAhead], ws[kAhead];
+//
+// A workgroup takes 64 consecutive tiles (lane = tile, so every load and store is coalesced
+// over tiles) and splits each tile's chunks into kScanParts contiguous parts, one per wave, so
+// the launch has enough waves to hide the loads.  Three passes over the parts, with the parts'
+// sums combined in LDS between them: (A) saturation weights, whose prefix over the parts tells
+// each part the weight before it and so where the cut falls; (B) the counts of the chunks up to
+// the cut, whose prefix gives each part its starting offset; (C) the exclusive scan written in
+// place.  The result equals the sequential scan over the chunks.
+constexpr int kScanParts = 16;
+
+__global__ void __launch_bounds__(64 * kScanParts) chunk_scan_kernel(
+    const BinWork* __restrict__ work, const int64_t* __restrict__ seg_tstart, int S,
+    int64_t n_tiles, uint32_t* __restrict__ counts, uint32_t* __restrict__ tile_total,
+    const uint32_t* __restrict__ wsum, int32_t* __restrict__ cut, int32_t* __restrict__ region_n) {
+  __shared__ uint32_t sh_w[kScanParts][64];   // weight, then count, sums of each part
+  __shared__ int32_t sh_nz[kScanParts][64];   // each part's last kept chunk with entries
+  const int lane = threadIdx.x & 63, part = threadIdx.x >> 6;
+  const int64_t t = (int64_t)blockIdx.x * 64 + lane;
+  const bool live = t < n_tiles;
+  BinWork W{};
+  int64_t lt = 0, T = 1;
+  int c0 = 0, c1 = 0;
+  if (live) {
+    W = work[find_segment(seg_tstart, S, t)];
+    lt = t - W.tile_base;
+    T = (int64_t)W.TX * W.TY;
+    const int q = (W.n_chunks + kScanParts - 1) / kScanParts;
+    c0 = min(part * q, W.n_chunks);
+    c1 = min(c0 + q, W.n_chunks);
+  }
+  uint32_t* col = counts + W.ct_off + lt;            // chunk c at col[c * T]
+  const uint32_t* wcol = wsum ? wsum + W.ct_off + lt : nullptr;
+  constexpr int kAhead = 8;
+  // (A) the part's saturation weight.
+  uint32_t wpart = 0u;
+  if (wcol) {
+    for (int cb = c0; cb < c1; cb += kAhead) {
+      uint32_t ws[kAhead];
 #pragma unroll
-    for (int j = 0; j < kAhead; ++j) {
-      const int64_t k = W.ct_off + (int64_t)(cb + j) * T + lt;
-      v[j] = (cb + j < W.n_chunks) ? counts[k] : 0u;
-      ws[j] = (wsum && cb + j < W.n_chunks) ? wsum[k] : 0u;
+      for (int j = 0; j < kAhead; ++j) ws[j] = (cb + j < c1) ? wcol[(int64_t)(cb + j) * T] : 0u;
+#pragma unroll
+      for (int j = 0; j < kAhead; ++j) wpart += ws[j];
     }
+  }
+  sh_w[part][lane] = wpart;
+  __syncthreads();
+  uint32_t weight = 0u;                      // the weight of the chunks before this part
+  for (int p = 0; p < part; ++p) weight += sh_w[p][lane];
+  __syncthreads();
+  // (B) the counts of the part's chunks up to the cut, and its last kept chunk with entries.
+  // `last` is the cut chunk once the running weight reaches kCutWeight (inclusive).
+  int last = (wcol && weight >= kCutWeight) ? c0 - 1 : W.n_chunks - 1;
+  uint32_t cpart = 0u;
+  int last_nz = -1;
+  {
+    uint32_t wr = weight;
+    for (int cb = c0; cb < c1 && cb <= last; cb += kAhead) {
+      uint32_t v[kAhead], ws[kAhead];
 #pragma unroll
-    for (int j = 0; j < kAhead; ++j) {
-      const int c = cb + j;
-      if (c >= W.n_chunks) break;
-      counts[W.ct_off + (int64_t)c * T + lt] = run;
-      if (c <= last) {
-        run += v[j];
+      for (int j = 0; j < kAhead; ++j) {
+        const bool in = cb + j < c1;
+        v[j] = in ? col[(int64_t)(cb + j) * T] : 0u;
+        ws[j] = (in && wcol) ? wcol[(int64_t)(cb + j) * T] : 0u;
+      }
+#pragma unroll
+      for (int j = 0; j < kAhead; ++j) {
+        const int c = cb + j;
+        if (c >= c1 || c > last) break;
+        cpart += v[j];
         if (v[j]) last_nz = c;
-        weight += ws[j];
-        if (wsum && weight >= kCutWeight) last = c;
+        wr += ws[j];
+        if (wcol && wr >= kCutWeight) last = c;
       }
     }
   }
-  tile_total[t] = run;
-  cut[t] = last_nz;
+  sh_w[part][lane] = cpart;
+  sh_nz[part][lane] = last_nz;
+  __syncthreads();
+  uint32_t run = 0u, total = 0u;
+  int nz = -1;
+  for (int p = 0; p < kScanParts; ++p) {
+    const uint32_t x = sh_w[p][lane];
+    if (p < part) run += x;
+    total += x;
+    nz = max(nz, sh_nz[p][lane]);
+  }
+  // (C) the exclusive scan, in place; chunks after the cut keep the offset of the tile's end.
+  for (int cb = c0; cb < c1; cb += kAhead) {
+    uint32_t v[kAhead];
+#pragma unroll
+    for (int j = 0; j < kAhead; ++j) v[j] = (cb + j < c1 && cb + j <= last) ? col[(int64_t)(cb + j) * T] : 0u;
+#pragma unroll
+    for (int j = 0; j < kAhead; ++j) {
+      const int c = cb + j;
+      if (c >= c1) break;
+      col[(int64_t)c * T] = run;
+      run += v[j];
+    }
+  }
+  if (!live || part != 0) return;
+  tile_total[t] = total;
+  cut[t] = nz;
   // The region's chunk count for placement: 1 + the largest cut of its tiles (zeroed before).
   const int RX = (W.TX + kRegion - 1) / kRegion;
   const int tx = (int)(lt % W.TX), ty = (int)(lt / W.TX);
-  if (last_nz >= 0)
-    atomicMax(&region_n[W.region_base + (int64_t)(ty / kRegion) * RX + tx / kRegion], last_nz + 1);
+  if (nz >= 0)
+    atomicMax(&region_n[W.region_base + (int64_t)(ty / kRegion) * RX + tx / kRegion], nz + 1);
 }
 
 // Exclusive scan of u32 into u64, three phases over blocks of 1024 items.
@@ -627,8 +688,8 @@ hipError_t launch_bin_scan(hipStream_t st, const void* work_dev, int S, const in
                            int32_t* region_n) {
   const BinWork* W = (const BinWork*)work_dev;
   if (n_tiles == 0) return hipSuccess;
-  hipLaunchKernelGGL(chunk_scan_kernel, dim3(nblk(n_tiles, 256)), dim3(256), 0, st, W, seg_tstart,
-                     S, n_tiles, counts, tile_total, wsum, cut, region_n);
+  hipLaunchKernelGGL(chunk_scan_kernel, dim3(nblk(n_tiles, 64)), dim3(64 * kScanParts), 0, st, W,
+                     seg_tstart, S, n_tiles, counts, tile_total, wsum, cut, region_n);
   const int64_t nb = (n_tiles + kScanBlock - 1) / kScanBlock;
   hipLaunchKernelGGL(scan_reduce_kernel, dim3((unsigned)nb), dim3(kScanThreads), 0, st, tile_total,
                      n_tiles, partial);
