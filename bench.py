@@ -136,6 +136,27 @@ def measured_traffic(kernel: str):
     return None
 
 
+LDS_FILE = os.path.join(ROOT, "profiles", "lds_traffic_fhd_1080p_4x1M.txt")
+
+
+def measured_lds(kernel: str):
+    """LDS bytes per launch of `kernel` from the committed rocprofv3 summary
+    (SQ_INSTS_LDS_{LOAD,STORE}_BANDWIDTH); None when missing or the source changed since."""
+    if not os.path.exists(LDS_FILE):
+        return None
+    sha = source_sha(kernel)
+    with open(LDS_FILE) as f:
+        for line in f:
+            parts = line.split()
+            if len(parts) >= 9 and parts[0] == kernel and not line.startswith("#"):
+                try:
+                    nbytes = float(parts[4])
+                except ValueError:
+                    return None
+                return nbytes if sha is not None and parts[-1] == sha else None
+    return None
+
+
 def ceilings(ctx, volume_res: int, gaussians: int):
     """Measured ceilings of the kernels' bounds (the survey's micro-benchmarks): a plain device
     copy (HBM), random 32-byte reads over a working set the size of the scene's cell-corner
@@ -480,6 +501,13 @@ def main():
                     "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4)}
     roofline.update({"traffic": traffic, "kernel": dominant, "avg_launch_ms": round(per_launch_ms, 4),
                      "algorithmic_per_launch": per_launch})
+    lds = measured_lds(dominant)
+    if lds is not None:
+        # LDS bytes moved per launch (rocprofv3 counters), per CU and clock: CDNA3's LDS moves
+        # 128 B per clock per CU.
+        roofline["lds"] = {"bytes_per_launch": lds,
+                           "achieved_GBs": round(lds / (per_launch_ms * 1e-3) / 1e9, 1),
+                           "bytes_per_clk_per_cu": round(lds / (per_launch_ms * 1e-3) / (2.4e9 * 256), 2)}
     # Frame-level fraction: sum over kernels of the time their algorithmic work needs at the
     # vendor peak (bytes at HBM peak, or fp32 operations at the vector peak) over the frame time.
     t_min = t_min_meas = 0.0
