@@ -140,6 +140,33 @@ __device__ __forceinline__ void window_masks(uint32_t wx, uint32_t wy, int xbase
   }
 }
 
+// Per batch lane (one list entry): the window's columns among the block's 16 (bits 0-15) and
+// bit 16 set when the window spans every row of the block, so that an entry's masks mostly
+// come from one lane read and a few scalar operations.
+template <int kS>
+__device__ __forceinline__ uint32_t window_pack(uint32_t wx, uint32_t wy, int xbase, int ybase) {
+  const int lo = max((int)(wx & 0xffffu) - xbase, 0);
+  const int hi = min((int)(wx >> 16) - xbase, 15);
+  const uint32_t c16 = (lo <= hi) ? ((2u << hi) - (1u << lo)) : 0u;
+  const int ylo = (int)(wy & 0xffffu) - ybase, yhi = (int)(wy >> 16) - ybase;
+  return c16 | ((ylo <= 0 && yhi >= 4 * kS - 1) ? 0x10000u : 0u);
+}
+
+// An entry's slot masks from its packed window (and, when the window does not span every row,
+// its full bounds).
+template <int kS>
+__device__ __forceinline__ void entry_masks(uint32_t pk, float q2y, float q2z, int k, int xbase,
+                                            int ybase, uint64_t m[kS]) {
+  if (pk & 0x10000u) {
+    const uint32_t c32 = (pk & 0xffffu) * 0x10001u;
+    const uint64_t c64 = ((uint64_t)c32 << 32) | (uint64_t)c32;
+#pragma unroll
+    for (int p = 0; p < kS; ++p) m[p] = c64;
+  } else {
+    window_masks<kS>(rlu(q2y, k), rlu(q2z, k), xbase, ybase, m);
+  }
+}
+
 __device__ __forceinline__ bool lane_in(uint64_t mask) {
   return __builtin_amdgcn_inverse_ballot_w64(mask);
 }
@@ -205,6 +232,7 @@ __global__ void __launch_bounds__(64) splat_forward_kernel(
       keep = may_touch(q0, q1, q2, tc);
     }
     srec[0][lane] = q0; srec[1][lane] = q1; srec[2][lane] = q2;
+    const uint32_t wpk = window_pack<kS>(__float_as_uint(q2.y), __float_as_uint(q2.z), tc.xbase, tc.ybase);
     uint64_t mask = __ballot(keep);
     const uint32_t rel0 = (uint32_t)(bs - tc.start);
     while (mask) {
@@ -219,7 +247,7 @@ __global__ void __launch_bounds__(64) splat_forward_kernel(
       const float u = e0.x, v = e0.y, A = e0.z, B = e0.w;
       const float Cc = e1.x, o = e1.y, cr = e1.z, cg = e1.w;
       uint64_t win[kS];
-      window_masks<kS>(rlu(q2.y, k), rlu(q2.z, k), tc.xbase, tc.ybase, win);
+      entry_masks<kS>(__builtin_amdgcn_readlane(wpk, k), q2.y, q2.z, k, tc.xbase, tc.ybase, win);
       const float dx = u - tc.fi;
       // power = -(A dx^2 + C dy^2) / 2 - B dx dy, with the halving applied to A dx^2 and C
       // beforehand: scaling by -1/2 is exact, so every rounding, and the result, are unchanged.
@@ -381,6 +409,7 @@ __global__ void __launch_bounds__(64) splat_backward_kernel(
       keep = may_touch(q0, q1, q2, tc);
     }
     srec[0][lane] = q0; srec[1][lane] = q1; srec[2][lane] = q2;
+    const uint32_t wpk = window_pack<kS>(__float_as_uint(q2.y), __float_as_uint(q2.z), tc.xbase, tc.ybase);
     uint64_t mask = __ballot(keep);
     uint64_t has = 0ull;                       // entries whose row sums are parked in LDS
     const uint32_t rel0 = (uint32_t)(bs - tc.start);
@@ -395,7 +424,7 @@ __global__ void __launch_bounds__(64) splat_backward_kernel(
       const float u = e0.x, v = e0.y, A = e0.z, B = e0.w;
       const float Cc = e1.x, o = e1.y, cr = e1.z, cg = e1.w;
       uint64_t win[kS];
-      window_masks<kS>(rlu(q2.y, k), rlu(q2.z, k), tc.xbase, tc.ybase, win);
+      entry_masks<kS>(__builtin_amdgcn_readlane(wpk, k), q2.y, q2.z, k, tc.xbase, tc.ybase, win);
       const float dx = u - tc.fi;
       // The halving of the quadratic form applied beforehand (exact; see the forward).
       const float adxh = -0.5f * ((A * dx) * dx);
