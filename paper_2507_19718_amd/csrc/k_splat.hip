@@ -464,11 +464,10 @@ __global__ void __launch_bounds__(64) splat_backward_kernel(
         // dL/dalpha = T (c - background) . g; the background moves towards c by alpha.
         const float cgp = fmaf(cr, g0[p], fmaf(cg, g1[p], cb * g2[p]));
         const float dd = cgp - BG[p];
-        const float dal = T[p] * dd;
         BG[p] = fmaf(az, dd, BG[p]);
-        // alpha not clamped: it depends on power and opacity (dL/do = dL/dpower / o).
-        const bool unclamped = lane_in(__builtin_amdgcn_ballot_w64(!(oe > kAlphaMax)));
-        const float dpow = unclamped ? dal * az : 0.0f;
+        // dL/dpower = alpha dL/dalpha = (alpha T) dd where alpha is not clamped (it then depends
+        // on power and opacity; dL/do = dL/dpower / o).
+        const float dpow = !(oe > kAlphaMax) ? w * dd : 0.0f;
         const float tdy = dpow * dy;
         m0 += dpow;
         m1 += tdy;
