@@ -254,7 +254,10 @@ __global__ void __launch_bounds__(64) splat_forward_kernel(
       const float adxh = -0.5f * ((A * dx) * dx);
       const float Ch = -0.5f * Cc;
       const float bdx = B * dx;
-      const uint32_t pos = rel0 + (uint32_t)k + 1u;
+      uint32_t pos = rel0 + (uint32_t)k + 1u;
+      // Held in a vector register once per entry (the slots' selects would otherwise each copy
+      // it from its scalar register).
+      asm volatile("" : "+v"(pos));
 #pragma unroll
       for (int p = 0; p < kS; ++p) {
         const uint64_t act = win[p] & ~done[p];
