@@ -481,7 +481,10 @@ def main():
     dominant = max((k for k in kernels if k != "trace"), key=lambda k: kernels[k]["ms_per_frame"])
     per_launch_ms = prof[dominant]["ms"] / prof[dominant]["launches"]
     launches_per_frame = prof[dominant]["launches"] / args.steps
-    traffic = measured_traffic(dominant)
+    # The committed counter summaries were taken on the 1080p workload with the float-atomic
+    # adjoint: other workloads and the deterministic adjoint report none.
+    profiled = args.workload == "fhd" and not args.deterministic
+    traffic = measured_traffic(dominant) if profiled else None
     if dominant in ALU_KERNELS:
         per_launch = algorithmic_flops(dominant, work) / launches_per_frame
         achieved = per_launch / (per_launch_ms * 1e-3) / 1e12
@@ -506,7 +509,7 @@ def main():
                      "algorithmic_per_launch": per_launch,
                      "selection": "largest per-frame time on the frame's main stream (the trace runs "
                                   "concurrently on a second stream and is listed under kernels)"})
-    lds = measured_lds(dominant)
+    lds = measured_lds(dominant) if profiled else None
     if lds is not None:
         # LDS bytes moved per launch (rocprofv3 counters), per CU and clock: CDNA3's LDS moves
         # 128 B per clock per CU.

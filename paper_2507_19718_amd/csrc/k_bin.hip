@@ -238,7 +238,7 @@ __device__ __forceinline__ void place_batch(uint32_t* __restrict__ values, uint6
       const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(cur >> 32), t);
       const uint64_t base = ((uint64_t)hi << 32) | lo;
       if (cov) values[base + lane_rank(m)] = id;
-      if (lane == t) cur = base + (uint64_t)__popcll(m);
+      cur = (lane == t) ? base + (uint64_t)__popcll(m) : cur;
     }
   }
 }
@@ -268,7 +268,7 @@ __global__ void __launch_bounds__(256) bin_place_kernel(const BinWork* __restric
   if (blk >= *n_blocks) return;
   if (*n_instances > capacity) return;
   const int lane = __lane_id();
-  const int wave = threadIdx.x >> 6;
+  const int wave = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));   // uniform per wave
   const int64_t g = find_segment(region_start, (int)n_regions, blk);
   const int s = find_segment(seg_rbase, S, g);
   const BinWork W = work[s];
