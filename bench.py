@@ -253,7 +253,7 @@ SERVE_SCENES = ((128, 100_000), (256, 300_000), (512, 600_000), (512, 1_000_000)
 
 
 def serving(duration_s: float, rate_hz: float = 240.0, slots: int = 2, capacity_requests: int = 960,
-            probe_spp: int = 256):
+            probe_spp: int = 256, request_log=None):
     """Served vs plain on the same Poisson request log: 4 resident scenes (128^3, 256^3, 512^3,
     512^3 fBm; 3 levels of 100k / 300k / 600k / 1M Gaussians), 32 viewers at 640x360 /
     1280x720 / 1920x1080 on random orbits, 1 spp trace + train step + composite per request.
@@ -264,11 +264,12 @@ def serving(duration_s: float, rate_hz: float = 240.0, slots: int = 2, capacity_
     reach: every scene's cache rendered level by level at four probe cameras against
     probe_spp references, after (1) and (2), and after a replay of the first requests on fresh
     scenes with the deterministic adjoint, where the two loops' caches are compared bit for
-    bit."""
+    bit.  With `request_log`, the real-time runs' requests are written there as JSON Lines (one
+    record per request and loop: arrival, start and completion times, latency)."""
     import torch
     import synth
     import paper_2507_19718_amd as gsc
-    from paper_2507_19718_amd import serve
+    from paper_2507_19718_amd import metrics, serve
     from paper_2507_19718_amd.experiments import cache_images, level_l2, reference_levels
     ctx = gsc.Context(0)
     t = time.time()
@@ -300,13 +301,20 @@ def serving(duration_s: float, rate_hz: float = 240.0, slots: int = 2, capacity_
                 start[e["scene"]] = start.get(e["scene"], 0) + 1
         return serve.make_requests(part, cam, scene_frames=start)
 
-    realtime = {"plain": serve.run_plain(ctx, specs["plain"], requests(rt_log), skip_s=2.0)}
+    rq = {"plain": requests(rt_log), "served": requests(rt_log)}
+    realtime = {"plain": serve.run_plain(ctx, specs["plain"], rq["plain"], skip_s=2.0)}
     log(f"plain (real time): {realtime['plain']}")
     b = serve.ContinuousBatcher(specs["served"], slots=slots, hbm_budget=budget,
                                 instance_estimate=est(specs["served"]))
-    realtime["served"] = b.run(requests(rt_log), skip_s=2.0)
+    realtime["served"] = b.run(rq["served"], skip_s=2.0)
     sizes = [len(x) for x in b.batches]
     log(f"served (real time): {realtime['served']}")
+    if request_log:
+        with metrics.JsonlLog(request_log) as jl:
+            for loop in ("plain", "served"):
+                for r in rq[loop]:
+                    jl.write({**metrics.request_record(r), "loop": loop})
+        log(f"request records: {request_log}")
 
     capacity = {"plain": serve.run_plain(ctx, specs["plain"], requests(cap_log), realtime=False)}
     b2 = serve.ContinuousBatcher(specs["served"], slots=slots, hbm_budget=budget,
@@ -382,6 +390,8 @@ def main():
                     help="sum the splat adjoint in fixed point (bit-reproducible gradients)")
     ap.add_argument("--serve-seconds", type=float, default=60.0,
                     help="length of the Poisson request log replayed served vs plain (0: skip)")
+    ap.add_argument("--request-log", default=None,
+                    help="write the real-time serving runs' per-request records (JSON Lines)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (the GSCache hot path is single-GPU here); "
@@ -553,7 +563,7 @@ def main():
         del scene
         ctx.trim()
         torch.cuda.empty_cache()
-        serve_res = serving(args.serve_seconds)
+        serve_res = serving(args.serve_seconds, request_log=args.request_log)
 
     out = {
         "metric": METRIC,

@@ -54,5 +54,44 @@ def build(verbose: bool = True) -> str:
     return LIB
 
 
+# The host-ASan check: the library's sources and a driver of its C ABI linked into one
+# executable whose host code is built with AddressSanitizer (device code as in the library; the
+# GPU code itself is not instrumented).  Run by tests/test_gpu_host_asan.py.
+ASAN_DIR = os.path.join(BUILD, "asan")
+ASAN_EXE = os.path.join(ASAN_DIR, "gsc_host_asan")
+ASAN_DRIVER = os.path.join(HERE, "..", "tests", "native", "host_asan_check.hip")
+ASAN_FLAGS = ["-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fno-omit-frame-pointer",
+              "-Xarch_host", "-g"]
+
+
+def _compile_asan(src: str) -> str:
+    out = os.path.join(ASAN_DIR, os.path.basename(src).replace(".hip", ".o"))
+    cmd = [HIPCC] + FLAGS + ASAN_FLAGS + ["-I", os.path.join(HERE, "..", "include"), "-c", src,
+                                          "-o", out]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"hipcc (host ASan) failed for {src}:\n{r.stdout + r.stderr}")
+    return out
+
+
+def build_host_asan_check(verbose: bool = True) -> str:
+    """Builds the host-ASan check executable (always recompiles)."""
+    os.makedirs(ASAN_DIR, exist_ok=True)
+    srcs = [os.path.join(CSRC, s) for s in SOURCES] + [ASAN_DRIVER]
+    with concurrent.futures.ThreadPoolExecutor(max_workers=min(8, len(srcs))) as ex:
+        objs = list(ex.map(_compile_asan, srcs))
+    tmp = ASAN_EXE + ".tmp"
+    cmd = [HIPCC, "--offload-arch=gfx950", "-Xarch_host", "-fsanitize=address", "-o", tmp] + objs
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("host ASan link failed:\n" + r.stdout + r.stderr)
+    os.replace(tmp, ASAN_EXE)
+    if verbose:
+        print(f"built {ASAN_EXE}")
+    return ASAN_EXE
+
+
 if __name__ == "__main__":
     build()
+    if "--host-asan" in sys.argv[1:]:
+        build_host_asan_check()

@@ -10,9 +10,10 @@ caches, `gsc_render_frame` for cached frames (trace + splat + train + composite)
 `gsc_trace_targets` for the references (no early termination, many samples per pixel).
 
     python -m paper_2507_19718_amd.experiments [--workload orbit1k] [--lights point|area]
-        [--what C,cold,ablation,estimators,spp,adapt]
+        [--what C,cold,ablation,estimators,spp,adapt] [--frame-log adapt_frames.jsonl]
 
-prints one JSON object per study.
+prints one JSON object per study; --frame-log writes the adaptation run's per-frame records
+(stage times, counters, loss, per-level cache error) as JSON Lines.
 """
 from __future__ import annotations
 
@@ -26,7 +27,7 @@ import torch
 
 from . import (STRATEGY_NEE, STRATEGY_UNIFORM, Context, Scene, Volume, frame_request,
                gsc_cache_init, gsc_project_bin, gsc_render_frame, gsc_splat_forward,
-               gsc_trace_targets, trace_params)
+               gsc_trace_targets, metrics, trace_params)
 
 
 def reference_levels(ctx: Context, vol: Volume, cam, K: int, B: int, seed: int, spp: int = 1024,
@@ -255,7 +256,7 @@ def study_spp(ctx, wl, gv, init_levels, ref, cam, spps=(1, 2, 4, 8, 16, 32, 64),
 
 
 def study_adapt(ctx, wl, gv, levels, cam, frames: int = 300, changes=(100, 200), ref_spp: int = 1024,
-                light_deg: float = 90.0, every: int = 1) -> Dict:
+                light_deg: float = 90.0, every: int = 1, log=None) -> Dict:
     """The cache re-adapting while frames keep training at a static camera (Abstract;
     Introduction: the cache follows changes of lights and transfer function).  At frame
     changes[0] the transfer function is replaced by a new random one with as many control
@@ -264,7 +265,9 @@ def study_adapt(ctx, wl, gv, levels, cam, frames: int = 300, changes=(100, 200),
     rise again.  After every `every`-th frame the cache is rendered level by level and compared
     (mean squared error, and the relative error of Eq. 4's normalisation) with that level's
     reference under the optics in force, traced at `ref_spp` samples per pixel; just before
-    each change the stale cache is also compared with the new optics' reference."""
+    each change the stale cache is also compared with the new optics' reference.  With `log` (a
+    metrics.JsonlLog) every frame also writes one record: stage times, counters, loss and the
+    per-level error when it was measured (the frame then collects its statistics)."""
     import synth
     tf1 = synth.transfer_function(wl.tf_points, wl.seed, 1)
     lights_rot = synth.point_lights(wl.n_lights, rotate_first_deg=light_deg)
@@ -290,14 +293,19 @@ def study_adapt(ctx, wl, gv, levels, cam, frames: int = 300, changes=(100, 200),
                             weight_decay=wl.weight_decay, C=wl.C, viewport_frames=t_view)
         torch.cuda.synchronize()
         t = time.perf_counter()
-        gsc_render_frame(ctx, scene, req, img)
+        st = gsc_render_frame(ctx, scene, req, img, stats=log is not None)
         torch.cuda.synchronize()
         frame_ms += (time.perf_counter() - t) * 1e3
+        row = None
         if f % every == 0 or f == frames - 1 or (phase < len(changes) and f + 1 == changes[phase]):
             im = cache_images(ctx, scene, cam)
-            rows.append({"frame": f, "phase": phase, "l2": level_l2(im, refs[phase]),
-                         "hdr_l2": level_hdr_l2(im, refs[phase]),
-                         "composite_mse": mse(img, refs[phase].double().sum(0))})
+            row = {"frame": f, "phase": phase, "l2": level_l2(im, refs[phase]),
+                   "hdr_l2": level_hdr_l2(im, refs[phase]),
+                   "composite_mse": mse(img, refs[phase].double().sum(0))}
+            rows.append(row)
+        if log is not None:
+            log.write(metrics.frame_record(f, st, l2=row["l2"] if row else None, phase=phase,
+                                           t_view=t_view))
     scene.destroy()
     starts = [0] + list(changes[:len(optics) - 1])
     phases = []
@@ -337,6 +345,8 @@ def main():
                     help="adapt: frames of the transfer-function swap and of the light move")
     ap.add_argument("--lights", choices=("point", "area"), default="point",
                     help="the workload's point lights, or two spherical area lights instead")
+    ap.add_argument("--frame-log", default=None,
+                    help="adapt: write one JSON line per frame to this file")
     args = ap.parse_args()
     wl = synth.workload(args.workload)
     vol = wl.volume()
@@ -353,10 +363,14 @@ def main():
         # The workload's own random levels (the sizes the adaptation run is specified with).
         from . import level_to_device
         lv = [level_to_device(g) for g in wl.gaussians()]
-        print(json.dumps({**head, "gaussians_per_level": list(wl.levels),
-                          **study_adapt(ctx, wl, gv, lv, cam, frames=args.frames, ref_spp=args.ref_spp,
-                                        changes=tuple(int(x) for x in args.changes.split(",")))}),
-              flush=True)
+        log = metrics.JsonlLog(args.frame_log) if args.frame_log else None
+        try:
+            res = study_adapt(ctx, wl, gv, lv, cam, frames=args.frames, ref_spp=args.ref_spp,
+                              changes=tuple(int(x) for x in args.changes.split(",")), log=log)
+        finally:
+            if log is not None:
+                log.close()
+        print(json.dumps({**head, "gaussians_per_level": list(wl.levels), **res}), flush=True)
         what.discard("adapt")
         if not what:
             return

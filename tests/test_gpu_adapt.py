@@ -9,15 +9,25 @@ import synth
 pytestmark = pytest.mark.gpu
 
 
-def test_cache_readapts_after_transfer_function_swap_and_light_move():
+def test_cache_readapts_after_transfer_function_swap_and_light_move(tmp_path):
     import paper_2507_19718_amd as gsc
+    from paper_2507_19718_amd import metrics
     from paper_2507_19718_amd.experiments import study_adapt
     ctx = gsc.Context(0)
     wl = synth.workload("tiny")
     cam = wl.camera()
     gv = gsc.Volume.from_synth(wl.volume())
     lv = [gsc.level_to_device(g) for g in wl.gaussians()]
-    r = study_adapt(ctx, wl, gv, lv, cam, frames=360, changes=(160, 260), ref_spp=256)
+    path = str(tmp_path / "adapt_frames.jsonl")
+    with metrics.JsonlLog(path) as log:
+        r = study_adapt(ctx, wl, gv, lv, cam, frames=360, changes=(160, 260), ref_spp=256, log=log)
+    # One record per frame: the frame's statistics and the per-level error measured after it.
+    recs = list(metrics.read_jsonl(path))
+    assert [x["frame"] for x in recs] == list(range(360))
+    assert [x["l2"] for x in recs] == [x["l2"] for x in r["per_frame"]]
+    assert all(x["counters"]["instances"] > 0 and x["ms"]["total"] > 0 and x["loss"] is not None
+               and not x["adam_skipped"] for x in recs)
+    assert [x["t_view"] for x in recs if x["frame"] in (159, 160, 259, 260)] == [160, 1, 100, 1]
     ph = r["phases"]
     print({"phases": ph})
     print({"per_frame_total_l2": [round(sum(x["l2"]), 6) for x in r["per_frame"]]})
