@@ -56,7 +56,7 @@ typedef enum {
                             * how many were needed; retry with a larger hint                */
   GSC_E_OUT_OF_MEMORY = 3, /* the allocator returned NULL                                   */
   GSC_E_DEVICE = 4,        /* a HIP runtime error; sticky for the context                   */
-  GSC_E_UNSUPPORTED = 5     /* reserved: no call of this version returns it                  */
+  GSC_E_UNSUPPORTED = 5     /* the call needs a debug build (gsc_debug_selftest)            */
 } gsc_status;
 
 typedef struct gsc_ctx gsc_ctx;
@@ -527,6 +527,18 @@ gsc_status gsc_render_frames(gsc_ctx* ctx, gsc_scene* const* scenes,
 gsc_status gsc_copy(gsc_ctx* ctx, void* dst, const void* src, size_t bytes);
 /* Waits for all work enqueued on the context's stream. */
 gsc_status gsc_ctx_synchronize(gsc_ctx* ctx);
+
+/* ---- debug builds ---------------------------------------------------------------------- */
+/* A library built with -DGSC_DEBUG (libgsc_debug.so) checks on the device the accesses whose
+ * indices come from data: each instance store of the binning against the tile lists' capacity,
+ * the placement's compaction queue against its ring, and each tile-list entry the splat kernels
+ * read against the capacity and its level's Gaussian count.  A failed check skips the access and
+ * records itself; after every call the library waits for the device, and a call during which a
+ * check failed returns GSC_E_DEVICE with gsc_ctx_last_error() naming the checks.  Other builds
+ * compile no check.  This call makes the check path fire on purpose (one flag set by a kernel,
+ * no access skipped): GSC_E_DEVICE naming "self-test" in a debug build, GSC_E_UNSUPPORTED in
+ * others. */
+gsc_status gsc_debug_selftest(gsc_ctx* ctx);
 
 /* HOST, side-effect free: sizes of the structs above, for bindings to check their layouts:
  * which = 0 camera, 1 gaussians, 2 grads, 3 volume, 4 trace_params, 5 path_record,

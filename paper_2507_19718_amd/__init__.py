@@ -165,6 +165,13 @@ class Context:
         """Sum the splat adjoint in fixed point so gradients repeat bit for bit (default off)."""
         self.check(self._lib.gsc_ctx_set_deterministic(self.handle, 1 if on else 0))
 
+    def debug_selftest(self):
+        """Fires the device bounds-check path on purpose (gsc_debug_selftest); returns the status
+        and message instead of raising: GSC_E_DEVICE naming "self-test" with the debug library
+        (GSC_DEBUG=1), GSC_E_UNSUPPORTED with the release one."""
+        st = self._lib.gsc_debug_selftest(self.handle)
+        return st, self._lib.gsc_ctx_last_error(self.handle).decode()
+
     def probe_gather(self, cells: torch.Tensor, threads: int, per_thread: int) -> float:
         """ms for threads x per_thread random 32-byte reads of `cells` (a uint8/float tensor whose
         size is a multiple of 32 bytes)."""

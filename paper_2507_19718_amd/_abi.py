@@ -8,6 +8,7 @@ from ctypes import (POINTER, Structure, c_double, c_float, c_int32, c_int64, c_s
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libgsc.so")
+DEBUG_LIB_PATH = os.path.join(_HERE, "libgsc_debug.so")
 
 GSC_OK, GSC_E_INVALID_ARG, GSC_E_CAPACITY, GSC_E_OUT_OF_MEMORY, GSC_E_DEVICE, GSC_E_UNSUPPORTED = range(6)
 STATUS_NAMES = {0: "GSC_OK", 1: "GSC_E_INVALID_ARG", 2: "GSC_E_CAPACITY", 3: "GSC_E_OUT_OF_MEMORY",
@@ -118,6 +119,7 @@ _SIGNATURES = {
     "gsc_ctx_required_capacity": (c_uint64, [c_void_p]),
     "gsc_ctx_trim": (c_int32, [c_void_p]),
     "gsc_ctx_synchronize": (c_int32, [c_void_p]),
+    "gsc_debug_selftest": (c_int32, [c_void_p]),
     "gsc_copy": (c_int32, [c_void_p, c_void_p, c_void_p, c_size_t]),
     "gsc_ctx_profile": (c_int32, [c_void_p, c_int32]),
     "gsc_ctx_profile_read": (c_int32, [c_void_p, c_int32, ctypes.c_char_p, c_size_t, P(c_double),
@@ -170,15 +172,22 @@ _SIGNATURES = {
 _lib = None
 
 
+def library_path() -> str:
+    """The in-tree libgsc.so, or with GSC_DEBUG=1 in the environment the debug build
+    libgsc_debug.so (device bounds checks; see gsc_debug_selftest)."""
+    return DEBUG_LIB_PATH if os.environ.get("GSC_DEBUG") == "1" else LIB_PATH
+
+
 def load():
-    """Loads the in-tree libgsc.so.  There is no fallback: without the library nothing runs."""
+    """Loads the in-tree library.  There is no fallback: without it nothing runs."""
     global _lib
     if _lib is None:
-        if not os.path.exists(LIB_PATH):
+        path = library_path()
+        if not os.path.exists(path):
             raise ImportError(
-                f"{LIB_PATH} is missing: build it with `python __graft_entry__.py` or "
+                f"{path} is missing: build it with `python __graft_entry__.py` or "
                 "`python -m paper_2507_19718_amd.build_lib`; the GSCache path has no CPU fallback")
-        lib = ctypes.CDLL(LIB_PATH)
+        lib = ctypes.CDLL(path)
         for name, (res, args) in _SIGNATURES.items():
             fn = getattr(lib, name)
             fn.restype = res

@@ -11,6 +11,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libgsc.so")
+DEBUG_LIB = os.path.join(HERE, "libgsc_debug.so")
 SOURCES = ["k_project.hip", "k_sort.hip", "k_bin.hip", "k_splat.hip", "k_trace.hip",
            "k_train.hip", "k_init.hip", "k_probe.hip", "runtime.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
@@ -22,10 +23,10 @@ FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=o
          "-packed-fp32-ops", "-Wall", "-Wno-unused-function"]
 
 
-def _compile(src: str) -> str:
-    out = os.path.join(BUILD, src.replace(".hip", ".o"))
-    cmd = [HIPCC] + FLAGS + ["-I", os.path.join(HERE, "..", "include"), "-c",
-                             os.path.join(CSRC, src), "-o", out]
+def _compile(src: str, debug: bool = False) -> str:
+    out = os.path.join(BUILD, "debug" if debug else "", src.replace(".hip", ".o"))
+    cmd = [HIPCC] + FLAGS + (["-DGSC_DEBUG"] if debug else []) + [
+        "-I", os.path.join(HERE, "..", "include"), "-c", os.path.join(CSRC, src), "-o", out]
     r = subprocess.run(cmd, capture_output=True, text=True)
     noise = ("packed-fp32-ops", "ignoring feature")
     msg = "\n".join(l for l in (r.stdout + r.stderr).splitlines() if not any(n in l for n in noise))
@@ -36,22 +37,24 @@ def _compile(src: str) -> str:
     return out
 
 
-def build(verbose: bool = True) -> str:
-    """Compiles every HIP source and links libgsc.so.  Always recompiles."""
+def build(verbose: bool = True, debug: bool = False) -> str:
+    """Compiles every HIP source and links libgsc.so (debug: libgsc_debug.so, with the device
+    bounds checks of -DGSC_DEBUG).  Always recompiles."""
     if not os.path.exists(HIPCC):
         raise RuntimeError(f"hipcc not found at {HIPCC}")
-    os.makedirs(BUILD, exist_ok=True)
+    os.makedirs(os.path.join(BUILD, "debug" if debug else ""), exist_ok=True)
     with concurrent.futures.ThreadPoolExecutor(max_workers=min(8, len(SOURCES))) as ex:
-        objs = list(ex.map(_compile, SOURCES))
-    tmp = LIB + ".tmp"
+        objs = list(ex.map(lambda src: _compile(src, debug), SOURCES))
+    target = DEBUG_LIB if debug else LIB
+    tmp = target + ".tmp"
     cmd = [HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", "-o", tmp] + objs
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("link failed:\n" + r.stdout + r.stderr)
-    os.replace(tmp, LIB)
+    os.replace(tmp, target)
     if verbose:
-        print(f"built {LIB}")
-    return LIB
+        print(f"built {target}")
+    return target
 
 
 # The host-ASan check: the library's sources and a driver of its C ABI linked into one
@@ -93,5 +96,7 @@ def build_host_asan_check(verbose: bool = True) -> str:
 
 if __name__ == "__main__":
     build()
+    if "--debug" in sys.argv[1:]:
+        build(debug=True)
     if "--host-asan" in sys.argv[1:]:
         build_host_asan_check()

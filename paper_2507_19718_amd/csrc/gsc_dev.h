@@ -12,6 +12,32 @@
 
 namespace gsc {
 
+// Device bounds checks of a debug build (compiled with -DGSC_DEBUG).  GSC_DCHECK(cond, bit)
+// guards an access whose index comes from data (a list entry, a cursor, a count) and yields
+// cond; in a debug build a false cond also sets `bit` in this translation unit's flag word, the
+// guarded access is skipped, and the call that ran the kernel fails (the runtime reads and
+// clears the words after every call).  In other builds it is the constant true and cond is not
+// compiled at all.
+#ifdef GSC_DEBUG
+static __device__ uint32_t g_debug_flags;
+__device__ __forceinline__ bool dcheck(bool ok, uint32_t bit) {
+  if (!ok) atomicOr(&g_debug_flags, bit);
+  return ok;
+}
+#define GSC_DCHECK(cond, bit) ::gsc::dcheck((cond), (bit))
+#define GSC_DEBUG_FLAGS_READER(fn)                                                          \
+  uint32_t fn() {                                                                           \
+    uint32_t v = 0u, z = 0u;                                                                \
+    if (hipMemcpyFromSymbol(&v, HIP_SYMBOL(g_debug_flags), 4) != hipSuccess) return ~0u;     \
+    if (hipMemcpyToSymbol(HIP_SYMBOL(g_debug_flags), &z, 4) != hipSuccess) return ~0u;       \
+    return v;                                                                               \
+  }
+#else
+#define GSC_DCHECK(cond, bit) true
+#define GSC_DEBUG_FLAGS_READER(fn) \
+  uint32_t fn() { return 0u; }
+#endif
+
 // AdamW on element i of one parameter group (decoupled weight decay folded into wdf = 1 - lr wd,
 // bias corrections into s1 = lr / (1 - b1^t) and s2 = 1 / sqrt(1 - b2^t)); every operation is
 // separately rounded, in this order, wherever the step runs.

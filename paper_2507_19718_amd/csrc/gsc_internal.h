@@ -231,4 +231,18 @@ hipError_t launch_probe_atomic(hipStream_t st, float* buf, uint64_t n, uint32_t 
                                int per_thread);
 hipError_t launch_probe_valu(hipStream_t st, float* out, uint32_t threads, int iters, int mode);
 
+// Device bounds checks of a debug build (-DGSC_DEBUG): the bits a failed check sets, and per
+// translation unit that holds checks, the reader of its flag word (returns the bits set since
+// the last read and clears them; ~0u if the word could not be read; always 0 in other builds).
+enum : uint32_t {
+  kDbgInstanceStore = 1u << 0,   // an instance id stored past the tile lists' capacity
+  kDbgPlaceQueue = 1u << 1,      // the placement's compaction queue held more than its ring
+  kDbgListEntry = 1u << 2,       // a tile list past the capacity, or naming a Gaussian past its level
+  kDbgSelfTest = 1u << 31,       // set on purpose by gsc_debug_selftest
+};
+uint32_t debug_flags_bin();
+uint32_t debug_flags_splat();
+uint32_t debug_flags_probe();
+hipError_t launch_debug_selftest(hipStream_t st);
+
 }  // namespace gsc

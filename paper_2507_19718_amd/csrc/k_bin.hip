@@ -205,9 +205,10 @@ __device__ __forceinline__ uint32_t lane_rank(uint64_t m) {
 // Places n <= 64 queued Gaussians (lane i holds entry i) into the runs of the wave's live tiles
 // (bit t of `live_t`: tile (ox + (t & 15), oy + (t >> 4)), whose cursor lane t holds), all
 // inside [bx0, bx1] x [by0, by1].
-__device__ __forceinline__ void place_batch(uint32_t* __restrict__ values, uint64_t& cur, int lane,
-                                            int n, uint64_t r, uint32_t id, int ox, int oy,
-                                            uint64_t live_t, int bx0, int by0, int bx1, int by1) {
+__device__ __forceinline__ void place_batch(uint32_t* __restrict__ values, uint64_t capacity,
+                                            uint64_t& cur, int lane, int n, uint64_t r, uint32_t id,
+                                            int ox, int oy, uint64_t live_t, int bx0, int by0,
+                                            int bx1, int by1) {
   const bool live = lane < n;
   const uint32_t xr = (uint32_t)r, yr = (uint32_t)(r >> 32);
   const int tx0 = (int)(xr & 0xffffu), tx1 = (int)(xr >> 16);
@@ -237,7 +238,8 @@ __device__ __forceinline__ void place_batch(uint32_t* __restrict__ values, uint6
       const uint32_t lo = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)cur, t);
       const uint32_t hi = (uint32_t)__builtin_amdgcn_readlane((int)(uint32_t)(cur >> 32), t);
       const uint64_t base = ((uint64_t)hi << 32) | lo;
-      if (cov) values[base + lane_rank(m)] = id;
+      const uint64_t at = base + lane_rank(m);
+      if (cov && GSC_DCHECK(at < capacity, kDbgInstanceStore)) values[at] = id;
       cur = (lane == t) ? base + (uint64_t)__popcll(m) : cur;
     }
   }
@@ -346,12 +348,14 @@ __global__ void __launch_bounds__(256) bin_place_kernel(const BinWork* __restric
         qi[slot] = id;
       }
       tail += __popcll(m);
+      (void)GSC_DCHECK(tail - head <= kQueue, kDbgPlaceQueue);
       while (tail - head >= 64) {
         __builtin_amdgcn_wave_barrier();
         const uint64_t qrr = qr[(head + lane) & (kQueue - 1)];
         const uint32_t qid = qi[(head + lane) & (kQueue - 1)];
         head += 64;
-        place_batch(values, cur, lane, 64, qrr, qid, ox, oy, live_tiles, bx0, by0, bx1, by1);
+        place_batch(values, capacity, cur, lane, 64, qrr, qid, ox, oy, live_tiles, bx0, by0, bx1,
+                    by1);
       }
     }
   }
@@ -364,7 +368,7 @@ __global__ void __launch_bounds__(256) bin_place_kernel(const BinWork* __restric
       qrr = qr[(head + lane) & (kQueue - 1)];
       qid = qi[(head + lane) & (kQueue - 1)];
     }
-    place_batch(values, cur, lane, n, qrr, qid, ox, oy, live_tiles, bx0, by0, bx1, by1);
+    place_batch(values, capacity, cur, lane, n, qrr, qid, ox, oy, live_tiles, bx0, by0, bx1, by1);
   }
 }
 
@@ -743,5 +747,7 @@ hipError_t launch_view(hipStream_t st, int64_t G, const SplatRec* rec, const uin
                      screen);
   return hipGetLastError();
 }
+
+GSC_DEBUG_FLAGS_READER(debug_flags_bin)
 
 }  // namespace gsc

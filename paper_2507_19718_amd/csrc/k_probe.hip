@@ -75,7 +75,19 @@ __global__ void __launch_bounds__(256) probe_valu_kernel(float* __restrict__ out
   out[tid] = s;
 }
 
+// Sets the self-test bit through the debug-check path, from one lane (debug builds only).
+__global__ void __launch_bounds__(64) debug_selftest_kernel() {
+  if (threadIdx.x == 0) (void)GSC_DCHECK(false, kDbgSelfTest);
+}
+
 }  // namespace
+
+hipError_t launch_debug_selftest(hipStream_t st) {
+  hipLaunchKernelGGL(debug_selftest_kernel, dim3(1), dim3(64), 0, st);
+  return hipGetLastError();
+}
+
+GSC_DEBUG_FLAGS_READER(debug_flags_probe)
 
 hipError_t launch_probe_gather(hipStream_t st, const float4* cells, uint64_t n_cells,
                                uint32_t threads, int per_thread, float* out) {

@@ -43,6 +43,9 @@ struct Tile {
   int cw, ch;                // render window size
   int xbase, ybase;          // full-frame coordinates of the tile's first pixel
   float ti0, ti1, tj0, tj1;  // the tile's pixel rectangle inside the render window
+#ifdef GSC_DEBUG
+  int64_t n;                 // the level's Gaussians (for the list-entry checks)
+#endif
   __device__ bool inside(int p) const { return px < cw && py0 + 4 * p < ch; }
   __device__ int64_t pix(int p) const { return (int64_t)(py0 + 4 * p) * cw + px; }
 };
@@ -82,6 +85,9 @@ __device__ __forceinline__ Tile<kS> tile_setup(const Seg* __restrict__ segs,
   c.ti1 = (float)(cam.x0 + min(ox + 16, cam.w) - 1);
   c.tj0 = (float)(cam.y0 + oy);
   c.tj1 = (float)(cam.y0 + min(oy + 4 * kS, cam.h) - 1);
+#ifdef GSC_DEBUG
+  c.n = sg.n;
+#endif
   return c;
 }
 
@@ -226,7 +232,8 @@ __global__ void __launch_bounds__(64) splat_forward_kernel(
     const int64_t idx = bs + lane;
     float4 q0 = make_float4(0, 0, 0, 0), q1 = q0, q2 = q0;
     bool keep = false;
-    if (idx < tc.end) {
+    if (idx < tc.end && GSC_DCHECK((uint64_t)idx < capacity && (int64_t)values[idx] < tc.n,
+                                   kDbgListEntry)) {
       const SplatRec r = rec[tc.g_off + values[idx]];
       q0 = r.q0; q1 = r.q1; q2 = r.q2;
       keep = may_touch(q0, q1, q2, tc);
@@ -405,7 +412,8 @@ __global__ void __launch_bounds__(64) splat_backward_kernel(
     float4 q0 = make_float4(0, 0, 0, 0), q1 = q0, q2 = q0;
     bool keep = false;
     uint32_t my_id = 0u;
-    if (lane < n) {
+    if (lane < n && GSC_DCHECK((uint64_t)(bs + lane) < capacity &&
+                               (int64_t)values[bs + lane] < tc.n, kDbgListEntry)) {
       my_id = values[bs + lane];
       const SplatRec r = rec[tc.g_off + my_id];
       q0 = r.q0; q1 = r.q1; q2 = r.q2;
@@ -710,5 +718,7 @@ hipError_t launch_tile_order(hipStream_t st, const uint64_t* ranges, const uint3
                      order);
   return hipGetLastError();
 }
+
+GSC_DEBUG_FLAGS_READER(debug_flags_splat)
 
 }  // namespace gsc

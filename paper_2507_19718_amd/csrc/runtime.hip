@@ -206,6 +206,26 @@ void need(gsc_ctx* ctx, DevBuf& b, const Alloc& a, size_t bytes, const char* wha
   if (!b.ensure(a, bytes)) oom(ctx, what, bytes);
 }
 
+#ifdef GSC_DEBUG
+// Debug builds: after every call, wait for the device and read (and clear) the flag words of
+// the device bounds checks; a failed check fails the call with GSC_E_DEVICE, naming the checks.
+void debug_after_call(gsc_ctx* ctx) {
+  GSC_TRY(hipDeviceSynchronize());
+  const uint32_t f = debug_flags_bin() | debug_flags_splat() | debug_flags_probe();
+  if (f == 0u) return;
+  std::string msg = "device bounds check failed:";
+  if (f == ~0u) msg += " (flag word unreadable)";
+  else {
+    if (f & kDbgInstanceStore) msg += " instance store past the list capacity;";
+    if (f & kDbgPlaceQueue) msg += " placement queue overflow;";
+    if (f & kDbgListEntry) msg += " tile-list entry out of range;";
+    if (f & kDbgSelfTest) msg += " self-test;";
+  }
+  ctx->err = msg;
+  throw Fail{GSC_E_DEVICE};
+}
+#endif
+
 template <typename F>
 gsc_status guarded(gsc_ctx* ctx, F&& f) {
   if (!ctx) return GSC_E_INVALID_ARG;
@@ -213,7 +233,13 @@ gsc_status guarded(gsc_ctx* ctx, F&& f) {
   try {
     ctx->err.clear();
     GSC_TRY(hipSetDevice(ctx->device));
+#ifdef GSC_DEBUG
+    const gsc_status st = f();
+    if (st == GSC_OK) debug_after_call(ctx);
+    return st;
+#else
     return f();
+#endif
   } catch (const Fail& fl) {
     return fl.st;
   } catch (const std::bad_alloc&) {
@@ -1976,6 +2002,19 @@ gsc_status gsc_probe_valu(gsc_ctx* ctx, float* out, uint32_t threads, int32_t it
     check_probe_threads(ctx, threads, iters);
     return timed_probe(ctx, ms, [&]() { return launch_probe_valu(ctx->stream, out, threads, iters, mode); });
   });
+}
+
+gsc_status gsc_debug_selftest(gsc_ctx* ctx) {
+#ifdef GSC_DEBUG
+  return guarded(ctx, [&]() -> gsc_status {
+    GSC_TRY(launch_debug_selftest(ctx->stream));
+    return GSC_OK;
+  });
+#else
+  if (!ctx) return GSC_E_INVALID_ARG;
+  ctx->err = "not a debug build (GSC_DEBUG)";
+  return GSC_E_UNSUPPORTED;
+#endif
 }
 
 gsc_status gsc_ctx_synchronize(gsc_ctx* ctx) {
