@@ -1737,7 +1737,7 @@ size_t gsc_frame_footprint_bytes(const gsc_scene* sc, int32_t w, int32_t h, uint
   const int tw = 1 << kTileShift, th = 1 << kTileShift;   // the smaller frame tiles (more of them)
   const size_t tiles = K * (size_t)((w + tw - 1) / tw) * ((h + th - 1) / th);
   size_t b = 0;
-  b += (size_t)G * (48 + 4 + 8 + 4 + 4 * 4 + 8 + 9 * 4 + 14 * 4);   // per-Gaussian buffers
+  b += (size_t)G * (48 + 4 + 8 + 4 + 4 * 4 + 8 + 4 * kGrad2dStride + 14 * 4);  // per Gaussian
   b += 4 * (size_t)instance_estimate;                              // instance ids
   b += tiles * (8 + 16 + 4) + 4 * tiles * (size_t)((G / (int64_t)K + kChunk - 1) / kChunk);
   b += P * K * (12 * 3 + 4 + 4 + 4) + P * (20 + 12);              // images, targets, dL, T, ids
