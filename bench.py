@@ -158,7 +158,7 @@ def measured_lds(kernel: str):
 
 
 def ceilings(ctx, volume_res: int, gaussians: int):
-    """Measured ceilings of the kernels' bounds (the survey's micro-benchmarks): a plain device
+    """Measured ceilings of the kernels' bounds (micro-benchmarks): a plain device
     copy (HBM), random 32-byte reads over a working set the size of the scene's cell-corner
     grid (the tracer), float atomic adds to random elements of a [9][G] gradient array (the
     adjoint), and the vector ALU's fp32 FMA and exp rates (the splat kernels)."""
